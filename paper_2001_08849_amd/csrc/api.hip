@@ -1,0 +1,469 @@
+// extern "C" entry points of include/sfem.h.  Every call catches the
+// library's internal errors and turns them into an sfem_status plus a
+// message kept on the context.
+#include "ctx.h"
+
+using sfem::Ctx;
+using sfem::Error;
+
+struct sfem_ctx {
+  Ctx c;
+};
+
+namespace {
+
+template <typename F>
+int guarded(sfem_ctx* h, F&& fn) {
+  if (!h) return SFEM_EINVAL;
+  h->c.err.clear();
+  try {
+    SFEM_HIP(hipSetDevice(h->c.device));
+    return fn(h->c);
+  } catch (const Error& e) {
+    h->c.err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    h->c.err = e.what();
+    return SFEM_EINVAL;
+  }
+}
+
+// Copy n elements from a caller buffer into a device buffer.
+template <typename T>
+void upload(Ctx& c, T* dst, const T* src, int64_t n, int ptr_kind) {
+  SFEM_REQUIRE(src != nullptr || n == 0, SFEM_EINVAL, "null input pointer");
+  SFEM_REQUIRE(ptr_kind == SFEM_PTR_HOST || ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL,
+               "ptr_kind must be SFEM_PTR_HOST or SFEM_PTR_DEVICE");
+  if (n == 0) return;
+  SFEM_HIP(hipMemcpyAsync(dst, src, sizeof(T) * n,
+                          ptr_kind == SFEM_PTR_HOST ? hipMemcpyHostToDevice
+                                                    : hipMemcpyDeviceToDevice,
+                          c.stream));
+  if (ptr_kind == SFEM_PTR_HOST) SFEM_HIP(hipStreamSynchronize(c.stream));
+}
+
+template <typename T>
+void download(Ctx& c, T* dst, const T* src, int64_t n, int ptr_kind) {
+  SFEM_REQUIRE(ptr_kind == SFEM_PTR_HOST || ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL,
+               "ptr_kind must be SFEM_PTR_HOST or SFEM_PTR_DEVICE");
+  if (!dst || n == 0) return;
+  SFEM_HIP(hipMemcpyAsync(dst, src, sizeof(T) * n,
+                          ptr_kind == SFEM_PTR_HOST ? hipMemcpyDeviceToHost
+                                                    : hipMemcpyDeviceToDevice,
+                          c.stream));
+  if (ptr_kind == SFEM_PTR_HOST) SFEM_HIP(hipStreamSynchronize(c.stream));
+}
+
+__global__ void k_check_index(const int32_t* idx, int64_t n, int64_t lim, int32_t* err) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && (idx[i] < 0 || idx[i] >= lim)) atomicOr(err, 1);
+}
+
+bool indices_ok(Ctx& c, const int32_t* dev_idx, int64_t n, int64_t lim) {
+  if (n == 0) return true;
+  int32_t* err = nullptr;
+  SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), c.stream));
+  SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c.stream));
+  k_check_index<<<sfem::div_up(n, 256), 256, 0, c.stream>>>(dev_idx, n, lim, err);
+  SFEM_HIP(hipGetLastError());
+  int32_t h = 0;
+  SFEM_HIP(hipMemcpyAsync(&h, err, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  SFEM_HIP(hipStreamSynchronize(c.stream));
+  SFEM_HIP(hipFreeAsync(err, c.stream));
+  return h == 0;
+}
+
+__global__ void k_lame(int64_t T, const double* E, const double* nu, double* lam, double* mu,
+                       int32_t* err) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double e = E[t], v = nu[t];
+  if (!(e > 0.0) || !(v > -1.0 && v < 0.5)) atomicOr(err, 1);
+  lam[t] = e * v / ((1.0 + v) * (1.0 - 2.0 * v));
+  mu[t] = e / (2.0 * (1.0 + v));
+}
+
+__global__ void k_set_fixed(int64_t n, const int32_t* dof, const double* value, uint8_t* fixed,
+                            double* ubar, int32_t* flags) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = dof[i];
+  const double v = value ? value[i] : 0.0;
+  fixed[d] = 1;
+  ubar[d] = v;
+  if (v != 0.0) atomicOr(flags, 1);
+}
+
+void reset_problem(Ctx& c) {
+  c.have_material = false;
+  c.per_tet = false;
+  c.any_fixed = c.any_nonzero_bc = false;
+  c.penalty = 0.0;
+  c.assembled = false;
+  c.val_has_bc = false;
+  c.have_f32 = false;
+  const int64_t n = c.n_dof();
+  c.fixed.reserve(n);
+  c.ubar.reserve(n);
+  c.f_user.reserve(n);
+  SFEM_HIP(hipMemsetAsync(c.fixed.get(), 0, n, c.stream));
+  SFEM_HIP(hipMemsetAsync(c.ubar.get(), 0, n * sizeof(double), c.stream));
+  SFEM_HIP(hipMemsetAsync(c.f_user.get(), 0, n * sizeof(double), c.stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfem_create(sfem_ctx** out, int device, void* hip_stream) {
+  if (!out) return SFEM_EINVAL;
+  *out = nullptr;
+  sfem_ctx* h = new (std::nothrow) sfem_ctx;
+  if (!h) return SFEM_ENOMEM;
+  h->c.device = device;
+  int st = guarded(h, [&](Ctx& c) {
+    int count = 0;
+    SFEM_HIP(hipGetDeviceCount(&count));
+    SFEM_REQUIRE(device >= 0 && device < count, SFEM_EINVAL, "bad device ordinal");
+    if (hip_stream) {
+      c.stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      SFEM_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+      c.own_stream = true;
+    }
+    SFEM_HIP(hipEventCreate(&c.ev0));
+    SFEM_HIP(hipEventCreate(&c.ev1));
+    SFEM_HIP(hipHostMalloc((void**)&c.sc_host, sizeof(sfem::CgScalars), hipHostMallocDefault));
+    c.sc.reserve(1);
+    SFEM_HIP(hipMemsetAsync(c.sc.get(), 0, sizeof(sfem::CgScalars), c.stream));
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+  if (st != SFEM_OK) {
+    sfem_destroy(h);
+    return st;
+  }
+  *out = h;
+  return SFEM_OK;
+}
+
+void sfem_destroy(sfem_ctx* h) {
+  if (!h) return;
+  Ctx& c = h->c;
+  (void)hipSetDevice(c.device);
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  if (c.ev0) (void)hipEventDestroy(c.ev0);
+  if (c.ev1) (void)hipEventDestroy(c.ev1);
+  if (c.sc_host) (void)hipHostFree(c.sc_host);
+  if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
+  delete h;
+}
+
+const char* sfem_last_error(const sfem_ctx* h) { return h ? h->c.err.c_str() : "null context"; }
+
+int sfem_set_stream(sfem_ctx* h, void* hip_stream) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(hip_stream != nullptr, SFEM_EINVAL, "null stream");
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    if (c.own_stream) SFEM_HIP(hipStreamDestroy(c.stream));
+    c.own_stream = false;
+    c.stream = static_cast<hipStream_t>(hip_stream);
+    return SFEM_OK;
+  });
+}
+
+int sfem_set_mesh(sfem_ctx* h, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                  const int32_t* tets, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(n_nodes > 0 && n_tets > 0 && xyz && tets, SFEM_EINVAL, "empty or null mesh");
+    SFEM_REQUIRE(n_nodes < (int64_t(1) << 21), SFEM_EINVAL, "n_nodes must be < 2^21");
+    SFEM_REQUIRE(double(n_nodes) * double(n_nodes) * 4.0 * double(n_tets) < 9.2e18, SFEM_EINVAL,
+                 "n_nodes^2 * 4 n_tets must be < 2^63");
+    c.topo.valid = false;
+    c.N = n_nodes;
+    c.T = n_tets;
+    c.xyz.reserve(3 * n_nodes);
+    c.tets.reserve(4 * n_tets);
+    upload(c, c.xyz.get(), xyz, 3 * n_nodes, ptr_kind);
+    upload(c, c.tets.get(), tets, 4 * n_tets, ptr_kind);
+    if (!indices_ok(c, c.tets.get(), 4 * n_tets, n_nodes)) {
+      c.N = c.T = 0;
+      throw Error{SFEM_EINVAL, "tet node index out of range"};
+    }
+    reset_problem(c);
+    SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+    try {
+      sfem::build_topology(c);
+    } catch (...) {
+      c.N = c.T = 0;
+      throw;
+    }
+    SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+    SFEM_HIP(hipEventSynchronize(c.ev1));
+    float ms = 0;
+    SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    c.ms_topology = ms;
+    return SFEM_OK;
+  });
+}
+
+int sfem_set_material(sfem_ctx* h, double E, double nu) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(E > 0.0 && nu > -1.0 && nu < 0.5, SFEM_EINVAL, "need E > 0 and -1 < nu < 0.5");
+    c.lam0 = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    c.mu0 = E / (2.0 * (1.0 + nu));
+    c.per_tet = false;
+    c.have_material = true;
+    c.assembled = false;
+    return SFEM_OK;
+  });
+}
+
+int sfem_set_material_per_tet(sfem_ctx* h, const double* E, const double* nu, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    double *dE = nullptr, *dn = nullptr;
+    int32_t* err = nullptr;
+    SFEM_HIP(hipMallocAsync((void**)&dE, sizeof(double) * c.T, c.stream));
+    SFEM_HIP(hipMallocAsync((void**)&dn, sizeof(double) * c.T, c.stream));
+    SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), c.stream));
+    SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c.stream));
+    c.lam_t.reserve(c.T);
+    c.mu_t.reserve(c.T);
+    upload(c, dE, E, c.T, ptr_kind);
+    upload(c, dn, nu, c.T, ptr_kind);
+    k_lame<<<sfem::div_up(c.T, 256), 256, 0, c.stream>>>(c.T, dE, dn, c.lam_t.get(), c.mu_t.get(),
+                                                          err);
+    SFEM_HIP(hipGetLastError());
+    int32_t he = 0;
+    SFEM_HIP(hipMemcpyAsync(&he, err, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    SFEM_HIP(hipFreeAsync(dE, c.stream));
+    SFEM_HIP(hipFreeAsync(dn, c.stream));
+    SFEM_HIP(hipFreeAsync(err, c.stream));
+    SFEM_REQUIRE(he == 0, SFEM_EINVAL, "need E > 0 and -1 < nu < 0.5 for every tet");
+    c.per_tet = true;
+    c.have_material = true;
+    c.assembled = false;
+    return SFEM_OK;
+  });
+}
+
+int sfem_set_dirichlet(sfem_ctx* h, int64_t n, const int32_t* dof, const double* value,
+                       int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(n >= 0, SFEM_EINVAL, "negative count");
+    int32_t* ddof = nullptr;
+    double* dval = nullptr;
+    int32_t* flags = nullptr;
+    SFEM_HIP(hipMallocAsync((void**)&ddof, sizeof(int32_t) * (n ? n : 1), c.stream));
+    SFEM_HIP(hipMallocAsync((void**)&dval, sizeof(double) * (n ? n : 1), c.stream));
+    SFEM_HIP(hipMallocAsync((void**)&flags, sizeof(int32_t) * 4, c.stream));
+    SFEM_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, c.stream));
+    upload(c, ddof, dof, n, ptr_kind);
+    if (value) upload(c, dval, value, n, ptr_kind);
+    const bool ok = indices_ok(c, ddof, n, c.n_dof());
+    if (ok) {
+      SFEM_HIP(hipMemsetAsync(c.fixed.get(), 0, c.n_dof(), c.stream));
+      SFEM_HIP(hipMemsetAsync(c.ubar.get(), 0, c.n_dof() * sizeof(double), c.stream));
+      if (n)
+        k_set_fixed<<<sfem::div_up(n, 256), 256, 0, c.stream>>>(n, ddof, value ? dval : nullptr,
+                                                                 c.fixed.get(), c.ubar.get(), flags);
+      SFEM_HIP(hipGetLastError());
+    }
+    int32_t hf[4] = {0, 0, 0, 0};
+    SFEM_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c.stream));
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    SFEM_HIP(hipFreeAsync(ddof, c.stream));
+    SFEM_HIP(hipFreeAsync(dval, c.stream));
+    SFEM_HIP(hipFreeAsync(flags, c.stream));
+    SFEM_REQUIRE(ok, SFEM_EINVAL, "Dirichlet DOF index out of range");
+    c.any_fixed = n > 0;
+    c.any_nonzero_bc = hf[0] != 0;
+    c.assembled = false;
+    return SFEM_OK;
+  });
+}
+
+int sfem_set_bc_penalty(sfem_ctx* h, double alpha) {
+  return guarded(h, [&](Ctx& c) {
+    c.penalty = alpha > 0.0 ? alpha : 0.0;
+    c.assembled = false;
+    return SFEM_OK;
+  });
+}
+
+int sfem_set_nodal_load(sfem_ctx* h, const double* f, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    upload(c, c.f_user.get(), f, c.n_dof(), ptr_kind);
+    c.assembled = false;
+    return SFEM_OK;
+  });
+}
+
+int sfem_add_traction(sfem_ctx* h, int64_t n_tri, const int32_t* tri, const double t[3],
+                      int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(n_tri >= 0 && t && (tri || n_tri == 0), SFEM_EINVAL, "bad traction arguments");
+    if (n_tri == 0) return SFEM_OK;
+    int32_t* dtri = nullptr;
+    SFEM_HIP(hipMallocAsync((void**)&dtri, sizeof(int32_t) * 3 * n_tri, c.stream));
+    upload(c, dtri, tri, 3 * n_tri, ptr_kind);
+    try {
+      sfem::traction_load(c, n_tri, dtri, t);
+    } catch (...) {
+      (void)hipFreeAsync(dtri, c.stream);
+      throw;
+    }
+    SFEM_HIP(hipFreeAsync(dtri, c.stream));
+    c.assembled = false;
+    return SFEM_OK;
+  });
+}
+
+int sfem_assemble(sfem_ctx* h, int flags) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(c.have_material, SFEM_ESTATE, "set a material first");
+    const int64_t nnz = 9 * c.topo.nb;
+    c.val.reserve(nnz);
+    const bool f32 = (flags & SFEM_ASM_F32_COPY) != 0;
+    if (f32) c.val32.reserve(nnz);
+    c.have_f32 = f32;
+    c.w.reserve(c.n_dof());
+    c.q.reserve(c.n_dof());
+    const bool two_step = c.any_fixed && c.any_nonzero_bc && c.penalty <= 0.0;
+    SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+    sfem::assemble_values(c, c.val.get(), f32 ? c.val32.get() : nullptr, !two_step);
+    SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+    sfem::rhs_with_bc(c);
+    if (two_step) sfem::bc_mask_values(c);
+    sfem::extract_dinv(c);
+    SFEM_HIP(hipEventSynchronize(c.ev1));
+    float ms = 0;
+    SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    c.ms_assemble = ms;
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    c.assembled = true;
+    c.val_has_bc = c.any_fixed;
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_sizes(sfem_ctx* h, int64_t* n_faces, int64_t* n_exterior, int64_t* n_rows,
+                   int64_t* nnz, int64_t* n_blocks) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    if (n_faces) *n_faces = c.topo.nf;
+    if (n_exterior) *n_exterior = c.topo.ne;
+    if (n_rows) *n_rows = c.n_dof();
+    if (nnz) *nnz = 9 * c.topo.nb;
+    if (n_blocks) *n_blocks = c.topo.nb;
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_faces(sfem_ctx* h, int32_t* table, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(table != nullptr, SFEM_EINVAL, "null output");
+    sfem::DBuf<int32_t> tmp;
+    tmp.reserve(7 * c.topo.nf);
+    sfem::face_table_public(c, tmp.get());
+    download(c, table, tmp.get(), 7 * c.topo.nf, ptr_kind);
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_csr(sfem_ctx* h, int32_t* row_ptr, int32_t* col_idx, double* val, int which,
+                 int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(which == SFEM_K_UNCONSTRAINED || which == SFEM_K_WITH_BC, SFEM_EINVAL,
+                 "bad `which`");
+    const int64_t nnz = 9 * c.topo.nb, n = c.n_dof();
+    if (row_ptr || col_idx) {
+      sfem::DBuf<int32_t> rp, ci;
+      if (row_ptr) rp.reserve(n + 1);
+      if (col_idx) ci.reserve(nnz);
+      sfem::scalar_csr_pattern(c, rp.get(), ci.get());
+      download(c, row_ptr, rp.get(), n + 1, ptr_kind);
+      download(c, col_idx, ci.get(), nnz, ptr_kind);
+      SFEM_HIP(hipStreamSynchronize(c.stream));
+    }
+    if (val) {
+      SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+      if (which == SFEM_K_WITH_BC || !c.val_has_bc) {
+        download(c, val, c.val.get(), nnz, ptr_kind);
+      } else {
+        sfem::DBuf<double> tmp;
+        tmp.reserve(nnz);
+        sfem::assemble_values(c, tmp.get(), nullptr, false);
+        download(c, val, tmp.get(), nnz, ptr_kind);
+      }
+      SFEM_HIP(hipStreamSynchronize(c.stream));
+    }
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_rhs(sfem_ctx* h, double* f, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    download(c, f, c.f_bc.get(), c.n_dof(), ptr_kind);
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_spmv(sfem_ctx* h, const double* x, double* y, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    SFEM_REQUIRE(x && y, SFEM_EINVAL, "null vector");
+    const int64_t n = c.n_dof();
+    if (ptr_kind == SFEM_PTR_DEVICE) {
+      sfem::spmv_f64(c, c.val.get(), x, y, c.stream);
+      SFEM_HIP(hipStreamSynchronize(c.stream));
+    } else {
+      sfem::DBuf<double> dx, dy;
+      dx.reserve(n);
+      dy.reserve(n);
+      upload(c, dx.get(), x, n, ptr_kind);
+      sfem::spmv_f64(c, c.val.get(), dx.get(), dy.get(), c.stream);
+      download(c, y, dy.get(), n, ptr_kind);
+    }
+    return SFEM_OK;
+  });
+}
+
+int sfem_solve(sfem_ctx* h, const sfem_solve_opts* opts, double* u, int ptr_kind,
+               sfem_solve_info* info) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    SFEM_REQUIRE(opts && u, SFEM_EINVAL, "null opts or u");
+    SFEM_REQUIRE(opts->rtol > 0.0, SFEM_EINVAL, "rtol must be > 0");
+    SFEM_REQUIRE(opts->precond == SFEM_PRECOND_JACOBI, SFEM_EINVAL,
+                 "preconditioner not available in this build");
+    sfem_solve_info tmp{};
+    int st = sfem::solve(c, *opts, tmp);
+    download(c, u, c.x.get(), c.n_dof(), ptr_kind);
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    if (info) *info = tmp;
+    return st;
+  });
+}
+
+int sfem_get_timings(sfem_ctx* h, double* ms_topology, double* ms_assemble) {
+  return guarded(h, [&](Ctx& c) {
+    if (ms_topology) *ms_topology = c.ms_topology;
+    if (ms_assemble) *ms_assemble = c.ms_assemble;
+    return SFEM_OK;
+  });
+}
+
+}  // extern "C"

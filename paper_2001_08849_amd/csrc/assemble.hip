@@ -1,0 +1,497 @@
+// Numeric FS-FEM assembly and the right-hand side.
+//
+// Per face k (Sec. 2.1 STEP 2-4): the smoothing domain is the sub-tet (face
+// + centroid) of each adjacent tet, holding a quarter of that tet's volume,
+// so V_k = (V_1 + V_2)/4.  Because the shape functions are linear in each
+// tet and the Table-1 centroid rule is exact on each boundary triangle, the
+// boundary sum of Eq. 7 equals (divergence theorem) the volume-weighted mean
+// of the tet gradients:  b_I = (V_1 grad N_I^1 + V_2 grad N_I^2)/(V_1+V_2).
+// The kernel evaluates that closed form in FP64 registers (tet volumes and
+// inverse Jacobians by cross products, Eq. 10), then the 3x3 blocks of
+// K_k = V_k B^T c B (Eq. 9) for isotropic c:
+//   K_IJ = V_k [ lam b_I b_J^T + mu b_J b_I^T + mu (b_I . b_J) I_3 ].
+//
+// Scatter-assembly (Eq. 12 summed into CSR) is owner-computes by tile: a
+// workgroup owns a run of consecutive node rows, holds their CSR values in
+// LDS, visits every face whose support touches the run (each such face once
+// per tile, found through the node->face incidence), adds its blocks for the
+// rows it owns with LDS atomics, then streams the finished rows to HBM once,
+// coalesced, with the essential BCs applied on the way out.
+#include "ctx.h"
+
+namespace sfem {
+
+namespace {
+
+constexpr int kAsmThreads = 512;
+constexpr int kAsmFaces = 2048;  // faces staged per round in LDS
+
+struct Vec3 {
+  double x, y, z;
+};
+__device__ __forceinline__ Vec3 sub(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ Vec3 cross(Vec3 a, Vec3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double dot(Vec3 a, Vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ Vec3 load3(const double* __restrict__ xyz, int n) {
+  const double* p = xyz + 3 * int64_t(n);
+  return {p[0], p[1], p[2]};
+}
+
+// Gradients of the barycentric shape functions of tet (P0, P1, P2, P3) and
+// its volume (Eq. 10, orientation-free).
+__device__ __forceinline__ void tet_grads(Vec3 P0, Vec3 P1, Vec3 P2, Vec3 P3, Vec3 g[4],
+                                          double& vol) {
+  Vec3 e1 = sub(P1, P0), e2 = sub(P2, P0), e3 = sub(P3, P0);
+  Vec3 c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
+  double det = dot(e1, c23);
+  double inv = 1.0 / det;
+  g[1] = {c23.x * inv, c23.y * inv, c23.z * inv};
+  g[2] = {c31.x * inv, c31.y * inv, c31.z * inv};
+  g[3] = {c12.x * inv, c12.y * inv, c12.z * inv};
+  g[0] = {-(g[1].x + g[2].x + g[3].x), -(g[1].y + g[2].y + g[3].y), -(g[1].z + g[2].z + g[3].z)};
+  vol = fabs(det) * (1.0 / 6.0);
+}
+
+// Smoothed gradients b[0..n-1] of the face's support nodes (A, B, C, D[, E]),
+// V_k, and the domain's Lame constants.
+template <bool HET>
+__device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
+                                             const double* __restrict__ xyz, double lam0,
+                                             double mu0, const double* __restrict__ lam_t,
+                                             const double* __restrict__ mu_t, int sup[5],
+                                             Vec3 b[5], double& Vk, double& lam, double& mu) {
+  int4 r0 = *reinterpret_cast<const int4*>(row);
+  int4 r1 = *reinterpret_cast<const int4*>(row + 4);
+  sup[0] = r0.x;
+  sup[1] = r0.y;
+  sup[2] = r0.z;
+  sup[3] = r0.w;
+  sup[4] = r1.x;
+  const bool interior = r1.x >= 0;
+  Vec3 A = load3(xyz, r0.x), B = load3(xyz, r0.y), C = load3(xyz, r0.z), D = load3(xyz, r0.w);
+  Vec3 g1[4];
+  double V1;
+  tet_grads(A, B, C, D, g1, V1);
+  if (!interior) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = g1[i];
+    b[4] = {0, 0, 0};
+    Vk = 0.25 * V1;
+    if (HET) {
+      lam = lam_t[r1.y];
+      mu = mu_t[r1.y];
+    } else {
+      lam = lam0;
+      mu = mu0;
+    }
+    return 4;
+  }
+  Vec3 E = load3(xyz, r1.x);
+  Vec3 g2[4];
+  double V2;
+  tet_grads(A, B, C, E, g2, V2);
+  const double W = V1 + V2;
+  const double w1 = V1 / W, w2 = V2 / W;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    b[i] = {w1 * g1[i].x + w2 * g2[i].x, w1 * g1[i].y + w2 * g2[i].y, w1 * g1[i].z + w2 * g2[i].z};
+  b[3] = {w1 * g1[3].x, w1 * g1[3].y, w1 * g1[3].z};
+  b[4] = {w2 * g2[3].x, w2 * g2[3].y, w2 * g2[3].z};
+  Vk = 0.25 * W;
+  if (HET) {
+    lam = w1 * lam_t[r1.y] + w2 * lam_t[r1.z];
+    mu = w1 * mu_t[r1.y] + w2 * mu_t[r1.z];
+  } else {
+    lam = lam0;
+    mu = mu0;
+  }
+  return 5;
+}
+
+// Position of node J among the ascending block columns cols[0..deg).
+__device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
+  int lo = 0, hi = deg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (cols[mid] < J) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <bool HET>
+__global__ void __launch_bounds__(kAsmThreads)
+    k_assemble(const double* __restrict__ xyz, const int32_t* __restrict__ face,
+               const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
+               const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+               const int32_t* __restrict__ tile_first, double lam0, double mu0,
+               const double* __restrict__ lam_t, const double* __restrict__ mu_t,
+               const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
+               float* __restrict__ val32) {
+  __shared__ double sval[kTileBlocks * 9];
+  __shared__ int32_t scol[kTileBlocks];
+  __shared__ int32_t sptr[kTileBlocks + 1];
+  __shared__ int32_t sface[kAsmFaces];
+  __shared__ int32_t nface;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = tid / kWave;
+  const int nwaves = kAsmThreads / kWave;
+  const int n0 = tile_first[blockIdx.x], n1 = tile_first[blockIdx.x + 1];
+  const int nn = n1 - n0;
+  const int b0 = bptr[n0];
+  const int nblk = bptr[n1] - b0;
+
+  for (int i = tid; i < 9 * nblk; i += kAsmThreads) sval[i] = 0.0;
+  for (int i = tid; i < nblk; i += kAsmThreads) scol[i] = bcol[b0 + i];
+  for (int i = tid; i <= nn; i += kAsmThreads) sptr[i] = bptr[n0 + i] - b0;
+
+  // incidence entries of the tile's rows, processed in rounds of at most
+  // kAsmFaces entries: a face is taken at the entry of its smallest support
+  // node inside [n0, n1), so each touching face is handled once per tile
+  const int e0 = inc_ptr[n0], e1 = inc_ptr[n1];
+  for (int c0 = e0; c0 < e1; c0 += kAsmFaces) {
+    const int c1 = min(e1, c0 + kAsmFaces);
+    if (tid == 0) nface = 0;
+    __syncthreads();
+    // entry e belongs to node I: walk rows with waves, entries with lanes
+    for (int li = wid; li < nn; li += nwaves) {
+      const int I = n0 + li;
+      const int lo = max(inc_ptr[I], c0), hi = min(inc_ptr[I + 1], c1);
+      for (int e = lo + lane; e < hi; e += kWave) {
+        const int f = inc[e];
+        const int32_t* row = face + int64_t(f) * kFaceStride;
+        int4 r0 = *reinterpret_cast<const int4*>(row);
+        int s4 = row[4];
+        int m = 0x7fffffff;
+        m = (r0.x >= n0 && r0.x < n1) ? min(m, r0.x) : m;
+        m = (r0.y >= n0 && r0.y < n1) ? min(m, r0.y) : m;
+        m = (r0.z >= n0 && r0.z < n1) ? min(m, r0.z) : m;
+        m = (r0.w >= n0 && r0.w < n1) ? min(m, r0.w) : m;
+        m = (s4 >= n0 && s4 < n1) ? min(m, s4) : m;
+        if (m == I) sface[atomicAdd(&nface, 1)] = f;
+      }
+    }
+    __syncthreads();
+    const int nf = nface;
+    for (int k = tid; k < nf; k += kAsmThreads) {
+      const int f = sface[k];
+      int sup[5];
+      Vec3 b[5];
+      double Vk, lam, mu;
+      const int n = face_geometry<HET>(face + int64_t(f) * kFaceStride, xyz, lam0, mu0, lam_t,
+                                       mu_t, sup, b, Vk, lam, mu);
+      const double lV = lam * Vk, mV = mu * Vk;
+#pragma unroll
+      for (int p = 0; p < 5; ++p) {
+        const int I = sup[p];
+        if (p >= n || I < n0 || I >= n1) continue;
+        const int li = I - n0;
+        const int rb = sptr[li];
+        const int deg = sptr[li + 1] - rb;
+        double* rowv = sval + 9 * rb;
+        const double bpa[3] = {b[p].x, b[p].y, b[p].z};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          if (q >= n) continue;
+          const int jj = find_col(scol + rb, deg, sup[q]);
+          const double bqa[3] = {b[q].x, b[q].y, b[q].z};
+          const double d = mV * (bpa[0] * bqa[0] + bpa[1] * bqa[1] + bpa[2] * bqa[2]);
+          double* dst = rowv + 3 * jj;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const double v = lV * bpa[a] * bqa[c] + mV * bpa[c] * bqa[a] + (a == c ? d : 0.0);
+              atomicAdd(dst + a * 3 * deg + c, v);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // stream the finished rows out, applying the essential BCs
+  __syncthreads();  // (also covers a tile without incidences)
+  for (int li = wid; li < nn; li += nwaves) {
+    const int I = n0 + li;
+    const int rb = sptr[li];
+    const int deg = sptr[li + 1] - rb;
+    const int three_deg = 3 * deg;
+    const float inv3d = 1.0f / float(three_deg);
+    const int64_t gbase = 9 * (int64_t(b0) + rb);
+    for (int k = lane; k < 9 * deg; k += kWave) {
+      double v = sval[9 * rb + k];
+      if (fixed) {
+        const int a = int((float(k) + 0.5f) * inv3d);
+        const int r = k - a * three_deg;
+        const int jj = r / 3;
+        const int c = r - 3 * jj;
+        const int row = 3 * I + a;
+        const int col = 3 * scol[rb + jj] + c;
+        const bool fr = fixed[row], fc = fixed[col];
+        if (penalty > 0.0) {
+          if (fr && row == col) v += penalty;
+        } else if ((fr || fc) && row != col) {
+          v = 0.0;
+        }
+      }
+      val[gbase + k] = v;
+      if (val32) val32[gbase + k] = float(v);
+    }
+  }
+}
+
+// In-place elimination on an assembled unconstrained matrix (used when the
+// prescribed values are nonzero: K_unc ubar is needed first).
+__global__ void k_bc_mask(int64_t N, const int32_t* __restrict__ bptr,
+                          const int32_t* __restrict__ bcol, const uint8_t* __restrict__ fixed,
+                          double penalty, double* __restrict__ val, float* __restrict__ val32) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  if (I >= N) return;
+  const int rb = bptr[I];
+  const int deg = bptr[I + 1] - rb;
+  const int three_deg = 3 * deg;
+  const float inv3d = 1.0f / float(three_deg);
+  for (int k = lane; k < 9 * deg; k += kWave) {
+    const int a = int((float(k) + 0.5f) * inv3d);
+    const int r = k - a * three_deg;
+    const int jj = r / 3;
+    const int c = r - 3 * jj;
+    const int row = 3 * int(I) + a;
+    const int col = 3 * bcol[rb + jj] + c;
+    const int64_t idx = 9 * int64_t(rb) + k;
+    double v = val[idx];
+    if (penalty > 0.0) {
+      if (fixed[row] && row == col) v += penalty;
+    } else if ((fixed[row] || fixed[col]) && row != col) {
+      v = 0.0;
+    }
+    val[idx] = v;
+    if (val32) val32[idx] = float(v);
+  }
+}
+
+// f_bc: free rows f - (K_unc ubar) (kub may be null when ubar == 0), fixed
+// rows K_ii ubar_i (elimination) or penalty * ubar_i.
+__global__ void k_rhs_bc(int64_t n, const double* __restrict__ f, const double* __restrict__ kub,
+                         const uint8_t* __restrict__ fixed, const double* __restrict__ ubar,
+                         const double* __restrict__ diag_unc, double penalty,
+                         double* __restrict__ out) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = f[i];
+  if (fixed && fixed[i]) {
+    v = penalty > 0.0 ? penalty * ubar[i] : diag_unc[i] * ubar[i];
+  } else if (kub && penalty <= 0.0) {
+    v -= kub[i];
+  }
+  out[i] = v;
+}
+
+// diag[3I+a] = K(3I+a, 3I+a) from the node's own block.
+__global__ void k_diag(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+                       const double* __restrict__ val, double* __restrict__ diag) {
+  int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int rb = bptr[I];
+  const int deg = bptr[I + 1] - rb;
+  const int jj = find_col(bcol + rb, deg, int(I));
+  for (int a = 0; a < 3; ++a) diag[3 * I + a] = val[9 * int64_t(rb) + a * 3 * deg + 3 * jj + a];
+}
+
+__global__ void k_invert(int64_t n, const double* __restrict__ d, double* __restrict__ inv,
+                         float* __restrict__ inv32) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 1.0 / d[i];
+  inv[i] = v;
+  inv32[i] = float(v);
+}
+
+// Scalar CSR arrays implied by the block pattern.
+__global__ void k_scalar_pattern(int64_t N, const int32_t* __restrict__ bptr,
+                                 const int32_t* __restrict__ bcol, int32_t* __restrict__ row_ptr,
+                                 int32_t* __restrict__ col_idx) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  if (I >= N) return;
+  const int rb = bptr[I];
+  const int deg = bptr[I + 1] - rb;
+  if (row_ptr && lane < 3) row_ptr[3 * I + lane] = 9 * rb + lane * 3 * deg;
+  if (row_ptr && I == N - 1 && lane == 0) row_ptr[3 * N] = 9 * bptr[N];
+  if (!col_idx) return;
+  for (int k = lane; k < 9 * deg; k += kWave) {
+    const int r = k % (3 * deg);
+    col_idx[9 * int64_t(rb) + k] = 3 * bcol[rb + r / 3] + r % 3;
+  }
+}
+
+__global__ void k_face_public(int64_t nf, const int32_t* __restrict__ face,
+                              int32_t* __restrict__ out) {
+  int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int32_t* r = face + f * kFaceStride;
+  int32_t* o = out + 7 * f;
+  o[0] = r[0];
+  o[1] = r[1];
+  o[2] = r[2];
+  o[3] = r[5];
+  o[4] = r[6];
+  o[5] = r[3];
+  o[6] = r[4];
+}
+
+// Traction load, deterministic: per node, the triangles touching it are
+// visited in ascending order; each adds t * area / 3 (Eq. 11 area).
+__global__ void k_tri_entries(int64_t n_tri, const int32_t* __restrict__ tri, int64_t N,
+                              int32_t* __restrict__ bucket, uint32_t* __restrict__ vals,
+                              int32_t* __restrict__ err) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= 3 * n_tri) return;
+  int v = tri[i];
+  if (v < 0 || v >= N) {
+    atomicOr(err, 1);
+    v = 0;
+  }
+  bucket[i] = v;
+  vals[i] = uint32_t(i / 3);
+}
+
+__global__ void k_traction_gather(int64_t N, const int32_t* __restrict__ ptr,
+                                  const uint32_t* __restrict__ tris_of, const int32_t* __restrict__ tri,
+                                  const double* __restrict__ xyz, double tx, double ty, double tz,
+                                  double* __restrict__ f) {
+  int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  double sx = 0, sy = 0, sz = 0;
+  for (int k = ptr[I]; k < ptr[I + 1]; ++k) {
+    const int32_t* t = tri + 3 * int64_t(tris_of[k]);
+    Vec3 A = load3(xyz, t[0]), B = load3(xyz, t[1]), C = load3(xyz, t[2]);
+    Vec3 n = cross(sub(B, A), sub(C, A));
+    double area = 0.5 * sqrt(dot(n, n));
+    sx += tx * area / 3.0;
+    sy += ty * area / 3.0;
+    sz += tz * area / 3.0;
+  }
+  f[3 * I + 0] += sx;
+  f[3 * I + 1] += sy;
+  f[3 * I + 2] += sz;
+}
+
+}  // namespace
+
+void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask) {
+  const Topology& tp = c.topo;
+  const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
+  dim3 grid(tp.n_tiles), block(kAsmThreads);
+  if (c.per_tet)
+    k_assemble<true><<<grid, block, 0, c.stream>>>(
+        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.bptr.get(), tp.bcol.get(),
+        tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), fixed, c.penalty,
+        val_out, val32_out);
+  else
+    k_assemble<false><<<grid, block, 0, c.stream>>>(
+        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.bptr.get(), tp.bcol.get(),
+        tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, fixed, c.penalty, val_out,
+        val32_out);
+  SFEM_HIP(hipGetLastError());
+}
+
+void bc_mask_values(Ctx& c) {
+  const Topology& tp = c.topo;
+  const int B = 256;
+  k_bc_mask<<<div_up(tp.N * kWave, B), B, 0, c.stream>>>(
+      tp.N, tp.bptr.get(), tp.bcol.get(), c.fixed.get(), c.penalty, c.val.get(),
+      c.have_f32 ? c.val32.get() : nullptr);
+  SFEM_HIP(hipGetLastError());
+}
+
+// Builds c.f_bc from c.f_user; c.val must hold the UNCONSTRAINED matrix when
+// there are nonzero prescribed values (the caller orders the calls so).
+void rhs_with_bc(Ctx& c) {
+  const int64_t n = c.n_dof();
+  const int B = 256;
+  c.f_bc.reserve(n);
+  if (!c.any_fixed) {
+    SFEM_HIP(hipMemcpyAsync(c.f_bc.get(), c.f_user.get(), n * sizeof(double),
+                            hipMemcpyDeviceToDevice, c.stream));
+    return;
+  }
+  double* kub = nullptr;
+  double* diag = c.w.reserve(n);  // unconstrained diagonal
+  k_diag<<<div_up(c.N, B), B, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
+                                            c.val.get(), diag);
+  SFEM_HIP(hipGetLastError());
+  if (c.any_nonzero_bc && c.penalty <= 0.0) {
+    kub = c.q.reserve(n);
+    spmv_f64(c, c.val.get(), c.ubar.get(), kub, c.stream);
+  }
+  k_rhs_bc<<<div_up(n, B), B, 0, c.stream>>>(n, c.f_user.get(), kub, c.fixed.get(), c.ubar.get(),
+                                            diag, c.penalty, c.f_bc.get());
+  SFEM_HIP(hipGetLastError());
+}
+
+void extract_dinv(Ctx& c) {
+  const int64_t n = c.n_dof();
+  const int B = 256;
+  c.dinv.reserve(n);
+  c.dinv32.reserve(n);
+  double* diag = c.w.reserve(n);
+  k_diag<<<div_up(c.N, B), B, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
+                                            c.val.get(), diag);
+  SFEM_HIP(hipGetLastError());
+  k_invert<<<div_up(n, B), B, 0, c.stream>>>(n, diag, c.dinv.get(), c.dinv32.get());
+  SFEM_HIP(hipGetLastError());
+}
+
+void scalar_csr_pattern(Ctx& c, int32_t* row_ptr, int32_t* col_idx) {
+  const int B = 256;
+  k_scalar_pattern<<<div_up(c.N * kWave, B), B, 0, c.stream>>>(c.N, c.topo.bptr.get(),
+                                                               c.topo.bcol.get(), row_ptr, col_idx);
+  SFEM_HIP(hipGetLastError());
+}
+
+void face_table_public(Ctx& c, int32_t* out) {
+  const int B = 256;
+  k_face_public<<<div_up(c.topo.nf, B), B, 0, c.stream>>>(c.topo.nf, c.topo.face.get(), out);
+  SFEM_HIP(hipGetLastError());
+}
+
+void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t[3]) {
+  if (n_tri <= 0) return;
+  hipStream_t s = c.stream;
+  const int B = 256;
+  int32_t *bucket = nullptr, *ptr = nullptr, *err = nullptr;
+  uint32_t *vals = nullptr, *sorted = nullptr;
+  SFEM_HIP(hipMallocAsync((void**)&bucket, sizeof(int32_t) * 3 * n_tri, s));
+  SFEM_HIP(hipMallocAsync((void**)&vals, sizeof(uint32_t) * 3 * n_tri, s));
+  SFEM_HIP(hipMallocAsync((void**)&sorted, sizeof(uint32_t) * 3 * n_tri, s));
+  SFEM_HIP(hipMallocAsync((void**)&ptr, sizeof(int32_t) * (c.N + 1), s));
+  SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), s));
+  SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+  k_tri_entries<<<div_up(3 * n_tri, B), B, 0, s>>>(n_tri, tri_dev, c.N, bucket, vals, err);
+  SFEM_HIP(hipGetLastError());
+  int32_t h_err = 0;
+  SFEM_HIP(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SFEM_HIP(hipStreamSynchronize(s));
+  if (!h_err) {
+    bucket_sort_u32(bucket, vals, 3 * n_tri, int(c.N), ptr, sorted, s);
+    k_traction_gather<<<div_up(c.N, B), B, 0, s>>>(c.N, ptr, sorted, tri_dev, c.xyz.get(), t[0],
+                                                   t[1], t[2], c.f_user.get());
+    SFEM_HIP(hipGetLastError());
+  }
+  SFEM_HIP(hipFreeAsync(bucket, s));
+  SFEM_HIP(hipFreeAsync(vals, s));
+  SFEM_HIP(hipFreeAsync(sorted, s));
+  SFEM_HIP(hipFreeAsync(ptr, s));
+  SFEM_HIP(hipFreeAsync(err, s));
+  SFEM_REQUIRE(!h_err, SFEM_EINVAL, "traction triangle node index out of range");
+}
+
+}  // namespace sfem

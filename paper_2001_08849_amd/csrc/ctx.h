@@ -1,0 +1,105 @@
+// The library context: every device buffer of one mesh / problem.
+#pragma once
+#include "common.h"
+
+namespace sfem {
+
+// Numeric-assembly tile: a run of consecutive node rows whose 3x3 blocks
+// (and their FP64 values) fit in LDS.  kTileBlocks is the block capacity.
+constexpr int kTileBlocks = 800;
+
+// Face record in HBM: support nodes (a, b, c, o1, o2) then tets (t1, t2),
+// padded to 32 bytes.  o2 = t2 = -1 for an exterior face.
+constexpr int kFaceStride = 8;
+
+struct Topology {
+  int64_t N = 0, T = 0;
+  int64_t nf = 0, ne = 0;        // faces, exterior faces
+  int64_t n_inc = 0;             // node-face incidences (sum of support sizes)
+  int64_t nb = 0;                // 3x3 blocks of the pattern
+  int maxdeg = 0;                // most blocks in one node row
+  int n_tiles = 0;
+  DBuf<int32_t> face;            // [nf][kFaceStride]
+  DBuf<int32_t> inc_ptr;         // [N+2] (bucket N collects exterior padding)
+  DBuf<int32_t> inc;             // face ids per node, ascending
+  DBuf<int32_t> bptr;            // [N+1] block-row offsets
+  DBuf<int32_t> bcol;            // [nb] block column (node) ids, ascending per row
+  DBuf<int32_t> tile_first;      // [n_tiles+1] first node of each tile
+  bool valid = false;
+};
+
+struct CgScalars {
+  double rz, rz_new, pq, alpha, beta, rr, rr_true, ff;
+  double aux[8];
+  int converged;
+  int pad;
+  unsigned int counter[8];
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // mesh
+  int64_t N = 0, T = 0;
+  DBuf<double> xyz;
+  DBuf<int32_t> tets;
+  Topology topo;
+
+  // material
+  bool have_material = false;
+  bool per_tet = false;
+  double lam0 = 0, mu0 = 0;
+  DBuf<double> lam_t, mu_t;
+
+  // BCs and loads
+  DBuf<uint8_t> fixed;           // [3N] 1 if the DOF is prescribed
+  DBuf<double> ubar;             // [3N] prescribed values (0 where free)
+  bool any_fixed = false, any_nonzero_bc = false;
+  double penalty = 0.0;          // > 0: penalty form instead of elimination
+  DBuf<double> f_user;           // [3N] loads as given
+  DBuf<double> f_bc;             // [3N] right-hand side after BCs
+
+  // assembled matrix (values in the scalar CSR order of the block pattern)
+  bool assembled = false;
+  bool val_has_bc = false;
+  bool have_f32 = false;
+  DBuf<double> val;
+  DBuf<float> val32;
+  DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
+  DBuf<float> dinv32;
+
+  // solver work vectors
+  DBuf<double> x, r, z, p, q, w;
+  DBuf<float> x32, r32, z32, p32, q32;
+  DBuf<double> partials;
+  DBuf<CgScalars> sc;
+  CgScalars* sc_host = nullptr;  // pinned mirror
+
+  // timings
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double ms_topology = 0, ms_assemble = 0;
+
+  int64_t n_dof() const { return 3 * N; }
+};
+
+// topology.hip
+void build_topology(Ctx& c);
+// assemble.hip
+void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
+void bc_mask_values(Ctx& c);
+void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t[3]);
+void scalar_csr_pattern(Ctx& c, int32_t* row_ptr, int32_t* col_idx);
+void face_table_public(Ctx& c, int32_t* out);
+void extract_dinv(Ctx& c);
+void rhs_with_bc(Ctx& c);
+// spmv.hip
+void spmv_f64(Ctx& c, const double* val, const double* x, double* y, hipStream_t s);
+void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s);
+// solve.hip
+int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info);
+double true_residual(Ctx& c, const double* u);
+
+}  // namespace sfem

@@ -1,0 +1,278 @@
+"""Python binding of libsfem.so (include/sfem.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  This module converts
+numpy arrays (host) and torch tensors (device memory of the context's GPU)
+into pointers and raises ``SfemError`` on a non-zero status.  If the library has not been built,
+``lib()`` raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfem.so")
+
+PTR_HOST, PTR_DEVICE = 0, 1
+K_UNCONSTRAINED, K_WITH_BC = 0, 1
+ASM_F64, ASM_F32_COPY = 0, 1
+PRECOND_JACOBI, PRECOND_LEARNED = 0, 1
+MODE_F64, MODE_F32_IR = 0, 1
+
+STATUS = {0: "SFEM_OK", -1: "SFEM_EINVAL", -2: "SFEM_EMESH", -3: "SFEM_ENOMEM",
+          -4: "SFEM_EHIP", -5: "SFEM_ENOCONV", -6: "SFEM_ESTATE"}
+
+EXPORTS = [
+    "sfem_create", "sfem_destroy", "sfem_last_error", "sfem_set_stream", "sfem_set_mesh",
+    "sfem_set_material", "sfem_set_material_per_tet", "sfem_set_dirichlet",
+    "sfem_set_bc_penalty", "sfem_set_nodal_load", "sfem_add_traction", "sfem_assemble",
+    "sfem_get_sizes", "sfem_get_faces", "sfem_get_csr", "sfem_get_rhs", "sfem_spmv",
+    "sfem_solve", "sfem_get_timings",
+]
+
+
+class SfemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precond", C.c_int), ("mode", C.c_int), ("rtol", C.c_double),
+                ("max_iter", C.c_int), ("check_every", C.c_int), ("inner_rtol", C.c_double),
+                ("max_outer", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer_steps", C.c_int), ("fell_back", C.c_int),
+                ("converged", C.c_int), ("true_relres", C.c_double), ("ms_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    """Load libsfem.so (once).  Raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run paper_2001_08849_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+        sig = {
+            "sfem_create": (i32, [C.POINTER(vp), i32, vp]),
+            "sfem_destroy": (None, [vp]),
+            "sfem_last_error": (C.c_char_p, [vp]),
+            "sfem_set_stream": (i32, [vp, vp]),
+            "sfem_set_mesh": (i32, [vp, i64, vp, i64, vp, i32]),
+            "sfem_set_material": (i32, [vp, dbl, dbl]),
+            "sfem_set_material_per_tet": (i32, [vp, vp, vp, i32]),
+            "sfem_set_dirichlet": (i32, [vp, i64, vp, vp, i32]),
+            "sfem_set_bc_penalty": (i32, [vp, dbl]),
+            "sfem_set_nodal_load": (i32, [vp, vp, i32]),
+            "sfem_add_traction": (i32, [vp, i64, vp, C.POINTER(dbl), i32]),
+            "sfem_assemble": (i32, [vp, i32]),
+            "sfem_get_sizes": (i32, [vp] + [C.POINTER(i64)] * 5),
+            "sfem_get_faces": (i32, [vp, vp, i32]),
+            "sfem_get_csr": (i32, [vp, vp, vp, vp, i32, i32]),
+            "sfem_get_rhs": (i32, [vp, vp, i32]),
+            "sfem_spmv": (i32, [vp, vp, vp, i32]),
+            "sfem_solve": (i32, [vp, C.POINTER(SolveOpts), vp, i32, C.POINTER(SolveInfo)]),
+            "sfem_get_timings": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _arg(a, dtype):
+    """(pointer, ptr_kind, keepalive) for a numpy array or a torch tensor."""
+    if a is None:
+        return None, PTR_HOST, None
+    if _is_torch(a):
+        import torch
+        want = {np.float64: torch.float64, np.int32: torch.int32}[dtype]
+        if a.dtype != want:
+            raise TypeError(f"expected {want}, got {a.dtype}")
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(a.data_ptr()), (PTR_DEVICE if a.is_cuda else PTR_HOST), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data_as(C.c_void_p), PTR_HOST, arr
+
+
+@dataclass
+class Sizes:
+    n_faces: int
+    n_exterior: int
+    n_rows: int
+    nnz: int
+    n_blocks: int
+
+
+class Context:
+    """One sfem_ctx on `device`.  `stream` is a hipStream_t handle (an int,
+    e.g. ``torch.cuda.current_stream().cuda_stream``); by default the library
+    creates and owns a stream.
+
+    This module never imports torch itself: a process must hold a single
+    HIP runtime, and torch wheels bundle their own.  Processes that use torch
+    tensors with this library import torch first, and the library then runs
+    on torch's runtime."""
+
+    def __init__(self, device: int = 0, stream: int = 0):
+        L = lib()
+        h = C.c_void_p()
+        st = L.sfem_create(C.byref(h), device, C.c_void_p(stream) if stream else None)
+        if st != 0:
+            raise SfemError(st, "sfem_create failed")
+        self._h = h
+        self._L = L
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sfem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise SfemError(st, self._L.sfem_last_error(self._h).decode())
+        return st
+
+    # ------------------------------------------------------------ inputs
+    def set_stream(self, stream_handle: int):
+        self._check(self._L.sfem_set_stream(self._h, C.c_void_p(stream_handle)))
+
+    def set_mesh(self, xyz, tets):
+        px, kx, a1 = _arg(xyz, np.float64)
+        pt, kt, a2 = _arg(tets, np.int32)
+        if kx != kt:
+            raise ValueError("xyz and tets must both be host or both be device arrays")
+        n, t = int(xyz.shape[0]), int(tets.shape[0])
+        self._check(self._L.sfem_set_mesh(self._h, n, px, t, pt, kx))
+
+    def set_material(self, E, nu):
+        if np.ndim(E) == 0 and np.ndim(nu) == 0:
+            self._check(self._L.sfem_set_material(self._h, float(E), float(nu)))
+        else:
+            pe, ke, a1 = _arg(E, np.float64)
+            pn, kn, a2 = _arg(nu, np.float64)
+            self._check(self._L.sfem_set_material_per_tet(self._h, pe, pn, ke))
+
+    def set_dirichlet(self, dofs, values=None):
+        pd, kd, a1 = _arg(dofs, np.int32)
+        pv, kv, a2 = _arg(values, np.float64)
+        self._check(self._L.sfem_set_dirichlet(self._h, int(len(dofs)), pd, pv, kd))
+
+    def set_bc_penalty(self, alpha: float):
+        self._check(self._L.sfem_set_bc_penalty(self._h, float(alpha)))
+
+    def set_nodal_load(self, f):
+        pf, kf, a = _arg(f, np.float64)
+        self._check(self._L.sfem_set_nodal_load(self._h, pf, kf))
+
+    def add_traction(self, tris, t):
+        pt, kt, a = _arg(tris, np.int32)
+        tv = (C.c_double * 3)(*[float(v) for v in t])
+        self._check(self._L.sfem_add_traction(self._h, int(len(tris)), pt, tv, kt))
+
+    # ------------------------------------------------------------ compute
+    def assemble(self, f32_copy: bool = False):
+        self._check(self._L.sfem_assemble(self._h, ASM_F32_COPY if f32_copy else ASM_F64))
+
+    def sizes(self) -> Sizes:
+        v = [C.c_int64() for _ in range(5)]
+        self._check(self._L.sfem_get_sizes(self._h, *[C.byref(x) for x in v]))
+        return Sizes(*[int(x.value) for x in v])
+
+    def faces(self) -> np.ndarray:
+        s = self.sizes()
+        out = np.empty((s.n_faces, 7), dtype=np.int32)
+        self._check(self._L.sfem_get_faces(self._h, out.ctypes.data_as(C.c_void_p), PTR_HOST))
+        return out
+
+    def csr(self, which: int = K_WITH_BC, values: bool = True):
+        s = self.sizes()
+        rp = np.empty(s.n_rows + 1, dtype=np.int32)
+        ci = np.empty(s.nnz, dtype=np.int32)
+        va = np.empty(s.nnz, dtype=np.float64) if values else None
+        self._check(self._L.sfem_get_csr(
+            self._h, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+            va.ctypes.data_as(C.c_void_p) if values else None, which, PTR_HOST))
+        return rp, ci, va
+
+    def csr_values_into(self, out, which: int = K_WITH_BC):
+        """Copy the CSR values into a device tensor (float64, nnz)."""
+        p, k, a = _arg(out, np.float64)
+        self._check(self._L.sfem_get_csr(self._h, None, None, p, which, k))
+
+    def rhs(self) -> np.ndarray:
+        out = np.empty(self.sizes().n_rows, dtype=np.float64)
+        self._check(self._L.sfem_get_rhs(self._h, out.ctypes.data_as(C.c_void_p), PTR_HOST))
+        return out
+
+    def spmv(self, x, y=None):
+        if y is None:
+            y = np.empty_like(np.asarray(x, dtype=np.float64)) if not _is_torch(x) else x.clone()
+        px, kx, a1 = _arg(x, np.float64)
+        py, ky, a2 = _arg(y, np.float64)
+        if kx != ky:
+            raise ValueError("x and y must live on the same side")
+        self._check(self._L.sfem_spmv(self._h, px, py, kx))
+        return y
+
+    def solve(self, rtol: float = 1e-8, mode: int = MODE_F64, precond: int = PRECOND_JACOBI,
+              max_iter: int = 0, check_every: int = 0, inner_rtol: float = 0.0,
+              max_outer: int = 0, out=None, raise_on_noconv: bool = False):
+        opts = SolveOpts(precond, mode, rtol, max_iter, check_every, inner_rtol, max_outer)
+        info = SolveInfo()
+        if out is None:
+            out = np.empty(self.sizes().n_rows, dtype=np.float64)
+        pu, ku, a = _arg(out, np.float64)
+        st = self._L.sfem_solve(self._h, C.byref(opts), pu, ku, C.byref(info))
+        if st != 0 and (st != -5 or raise_on_noconv):
+            self._check(st)
+        return out, info.as_dict()
+
+    def timings(self):
+        a, b = C.c_double(), C.c_double()
+        self._check(self._L.sfem_get_timings(self._h, C.byref(a), C.byref(b)))
+        return {"ms_topology": a.value, "ms_assemble": b.value}
+
+
+def setup_problem(ctx: Context, problem, f32_copy: bool = False, load_tris=None):
+    """Mesh + material + clamp + end traction of a meshgen Problem, then
+    assemble.  Returns the context."""
+    m = problem.mesh
+    ctx.set_mesh(m.xyz, m.tets)
+    ctx.set_material(problem.E, problem.nu)
+    ctx.set_dirichlet(problem.fixed_dofs())
+    tris = m.end_tris if load_tris is None else load_tris
+    ctx.add_traction(tris, np.asarray(problem.traction, dtype=np.float64).reshape(-1)[:3])
+    ctx.assemble(f32_copy=f32_copy)
+    return ctx

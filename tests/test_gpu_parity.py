@@ -1,0 +1,294 @@
+"""GPU (HIP, gfx950) vs FP64 oracle parity, through the C ABI.
+
+Integer outputs (face table, CSR pattern) must match bit for bit; K values
+to 1e-12 of each row's largest magnitude; displacements to 1e-8 relative L2.
+Every test prints the error it measured.
+"""
+import numpy as np
+import pytest
+
+from oracle import fsfem as O
+from paper_2001_08849_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def _sfem():
+    from paper_2001_08849_amd import sfem
+    return sfem
+
+
+def row_rel_err(rp, A_val, B_csr):
+    """max over rows of max_j |A - B|_ij / max_j |B|_ij."""
+    worst = 0.0
+    d = np.abs(A_val - B_csr.data)
+    for i in range(len(rp) - 1):
+        s = slice(rp[i], rp[i + 1])
+        m = np.abs(B_csr.data[s]).max()
+        if m > 0:
+            worst = max(worst, d[s].max() / m)
+        else:
+            worst = max(worst, d[s].max())
+    return worst
+
+
+class Case:
+    def __init__(self, problem, bc=True):
+        self.p = problem
+        m = problem.mesh
+        self.faces = O.extract_faces(m.tets)
+        self.K = O.assemble(m.xyz, m.tets, problem.E, problem.nu, self.faces)
+        self.f = O.traction_load(m.xyz, m.end_tris, np.asarray(problem.traction, float))
+        self.Kb, self.fb = O.apply_dirichlet(self.K, self.f, problem.fixed_dofs())
+
+
+def gpu_ctx(problem, f32=False):
+    sfem = _sfem()
+    ctx = sfem.Context(0)
+    sfem.setup_problem(ctx, problem, f32_copy=f32)
+    return ctx
+
+
+SMALL = {
+    "c0": mg.cantilever_c0,
+    "jit_7x3x4": lambda: mg.cantilever_scaled(7, 3, 4, jitter=0.2, seed=9, L=(3.0, 1.0, 1.5)),
+    "jit_23x5x3": lambda: mg.cantilever_scaled(23, 5, 3, jitter=0.15, seed=21),
+}
+
+
+@pytest.fixture(scope="module", params=list(SMALL))
+def small(request):
+    return request.param, Case(SMALL[request.param]())
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return Case(mg.cantilever_c1())
+
+
+def test_face_table_bit_exact(small):
+    name, cs = small
+    ctx = gpu_ctx(cs.p)
+    got = ctx.faces()
+    ref = cs.faces["table"].astype(np.int32)
+    s = ctx.sizes()
+    print(f"{name}: faces {s.n_faces} ({s.n_exterior} exterior); mismatched rows "
+          f"{int((got != ref).any(axis=1).sum()) if got.shape == ref.shape else 'shape'}")
+    assert s.n_exterior == cs.faces["face_out"].shape[0]
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_csr_pattern_and_values(small):
+    name, cs = small
+    sfem = _sfem()
+    ctx = gpu_ctx(cs.p)
+    rp, ci, va = ctx.csr(sfem.K_UNCONSTRAINED)
+    np.testing.assert_array_equal(rp, cs.K.indptr)
+    np.testing.assert_array_equal(ci, cs.K.indices)
+    e_unc = row_rel_err(rp, va, cs.K)
+    rp2, ci2, vb = ctx.csr(sfem.K_WITH_BC)
+    Kb = cs.Kb.tocsr()
+    Kb.sort_indices()
+    np.testing.assert_array_equal(rp2, Kb.indptr)
+    np.testing.assert_array_equal(ci2, Kb.indices)
+    e_bc = row_rel_err(rp2, vb, Kb)
+    print(f"{name}: nnz {len(ci)}; K row-relative error unconstrained {e_unc:.2e}, with BC {e_bc:.2e}")
+    assert e_unc <= 1e-12 and e_bc <= 1e-12
+
+
+def test_rhs_and_spmv(small):
+    name, cs = small
+    ctx = gpu_ctx(cs.p)
+    f = ctx.rhs()
+    ef = np.abs(f - cs.fb).max() / np.abs(cs.fb).max()
+    x = np.random.default_rng(3).standard_normal(cs.K.shape[0])
+    y = ctx.spmv(x)
+    yr = cs.Kb @ x
+    ey = np.abs(y - yr).max() / np.abs(yr).max()
+    print(f"{name}: rhs error {ef:.2e}, spmv error {ey:.2e}")
+    assert ef <= 1e-14 and ey <= 1e-13
+
+
+def test_solve_small(small):
+    name, cs = small
+    ctx = gpu_ctx(cs.p)
+    u, info = ctx.solve(rtol=1e-10)
+    ud = O.solve_dense(cs.Kb, cs.fb)
+    err = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+    print(f"{name}: iters {info['iters']} true relres {info['true_relres']:.2e}; "
+          f"u rel L2 error vs dense {err:.2e}")
+    assert info["converged"] and info["true_relres"] <= 1e-10
+    assert err <= 1e-8
+
+
+def test_c1_csr_solve_f64(c1):
+    sfem = _sfem()
+    ctx = gpu_ctx(c1.p)
+    rp, ci, va = ctx.csr(sfem.K_WITH_BC)
+    np.testing.assert_array_equal(rp, c1.Kb.indptr)
+    np.testing.assert_array_equal(ci, c1.Kb.indices)
+    ek = row_rel_err(rp, va, c1.Kb)
+    u, info = ctx.solve(rtol=1e-8)
+    ub = O.solve_banded(c1.Kb, c1.fb)
+    err = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+    print(f"c1: nnz {len(ci)} K error {ek:.2e}; Jacobi PCG FP64 iters {info['iters']} "
+          f"relres {info['true_relres']:.2e}; u error vs banded Cholesky {err:.2e}")
+    assert ek <= 1e-12
+    assert info["converged"] and err <= 1e-8
+
+
+def test_c1_f32_refinement(c1):
+    sfem = _sfem()
+    ctx = gpu_ctx(c1.p, f32=True)
+    u, info = ctx.solve(rtol=1e-8, mode=sfem.MODE_F32_IR)
+    ub = O.solve_banded(c1.Kb, c1.fb)
+    err = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+    print(f"c1: FP32+FP64-IR iters {info['iters']} outer {info['outer_steps']} "
+          f"relres {info['true_relres']:.2e}; u error vs banded {err:.2e}")
+    assert info["converged"] and info["true_relres"] <= 1e-8
+    assert err <= 1e-8
+
+
+def test_heterogeneous_material():
+    p = mg.learned_small(0, grid=(12, 4, 4))
+    cs = Case(p)
+    sfem = _sfem()
+    ctx = gpu_ctx(p)
+    rp, ci, va = ctx.csr(sfem.K_WITH_BC)
+    np.testing.assert_array_equal(ci, cs.Kb.indices)
+    e = row_rel_err(rp, va, cs.Kb)
+    u, info = ctx.solve(rtol=1e-10)
+    ud = O.solve_dense(cs.Kb, cs.fb)
+    eu = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+    print(f"per-tet E,nu: K error {e:.2e}; u error {eu:.2e}")
+    assert e <= 1e-12 and eu <= 1e-8
+
+
+def test_patch_test_nonzero_dirichlet():
+    """Linear field prescribed on the boundary, none inside: reproduced."""
+    sfem = _sfem()
+    m = mg.box_mesh(5, 4, 3, 1.0, 1.0, 1.0, jitter=0.2, seed=11)
+    A = np.array([[1e-3, 2e-4, -3e-4], [5e-4, -1e-3, 1e-4], [2e-4, 3e-4, 7e-4]])
+    uex = (m.xyz @ A.T + np.array([1e-4, -2e-4, 3e-4])).reshape(-1)
+    bn = np.flatnonzero(np.any(np.isclose(m.xyz, 0.0) | np.isclose(m.xyz, 1.0), axis=1))
+    dofs = (3 * bn[:, None] + np.arange(3)).reshape(-1).astype(np.int32)
+    ctx = sfem.Context(0)
+    ctx.set_mesh(m.xyz, m.tets)
+    ctx.set_material(1e9, 0.3)
+    ctx.set_dirichlet(dofs, uex[dofs])
+    ctx.assemble()
+    K = O.assemble(m.xyz, m.tets, 1e9, 0.3)
+    Kb, fb = O.apply_dirichlet(K, np.zeros(K.shape[0]), dofs, uex[dofs])
+    ef = np.abs(ctx.rhs() - fb).max() / np.abs(fb).max()
+    u, info = ctx.solve(rtol=1e-12)
+    err = np.abs(u - uex).max() / np.abs(uex).max()
+    print(f"patch test: rhs error {ef:.2e}; max error {err:.2e} (relres {info['true_relres']:.2e})")
+    assert ef <= 1e-13 and err <= 1e-10
+
+
+def test_penalty_bc_matches_oracle():
+    sfem = _sfem()
+    cs = Case(mg.cantilever_c0())
+    alpha = 1e3 * cs.K.diagonal().max()
+    Kp, fp = O.apply_penalty(cs.K, cs.f, cs.p.fixed_dofs(), alpha)
+    ctx = sfem.Context(0)
+    m = cs.p.mesh
+    ctx.set_mesh(m.xyz, m.tets)
+    ctx.set_material(cs.p.E, cs.p.nu)
+    ctx.set_dirichlet(cs.p.fixed_dofs())
+    ctx.set_bc_penalty(alpha)
+    ctx.add_traction(m.end_tris, cs.p.traction)
+    ctx.assemble()
+    rp, ci, va = ctx.csr(sfem.K_WITH_BC)
+    e = row_rel_err(rp, va, Kp)
+    u, info = ctx.solve(rtol=1e-10)
+    ud = O.solve_dense(Kp, fp)
+    eu = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+    print(f"penalty BC: K error {e:.2e}; u error {eu:.2e}")
+    assert e <= 1e-12 and eu <= 1e-8
+
+
+def test_mesh_errors():
+    sfem = _sfem()
+    ctx = sfem.Context(0)
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]], float)
+    with pytest.raises(sfem.SfemError) as e:   # face 0-1-2 in three tets
+        ctx.set_mesh(xyz, np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]], np.int32))
+    assert e.value.status == -2
+    with pytest.raises(sfem.SfemError) as e:   # node index out of range
+        ctx.set_mesh(xyz, np.array([[0, 1, 2, 9]], np.int32))
+    assert e.value.status == -1
+    flat = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], float)
+    with pytest.raises(sfem.SfemError) as e:   # zero-volume tet
+        ctx.set_mesh(flat, np.array([[0, 1, 2, 3]], np.int32))
+    assert e.value.status == -2
+    with pytest.raises(sfem.SfemError) as e:   # node 4, 5 in no tet
+        ctx.set_mesh(xyz, np.array([[0, 1, 2, 3]], np.int32))
+    assert e.value.status == -2
+    with pytest.raises(sfem.SfemError) as e:   # solve before a mesh
+        ctx.solve()
+    assert e.value.status == -6
+    print("mesh errors: non-manifold, bad index, zero volume, isolated node, order -> rejected")
+
+
+def test_zero_load_and_empty_inputs():
+    sfem = _sfem()
+    p = mg.cantilever_c0()
+    ctx = sfem.Context(0)
+    ctx.set_mesh(p.mesh.xyz, p.mesh.tets)
+    ctx.set_material(p.E, p.nu)
+    ctx.set_dirichlet(p.fixed_dofs())
+    ctx.add_traction(np.zeros((0, 3), np.int32), [0, 0, -1.0])   # no triangles
+    ctx.assemble()
+    u, info = ctx.solve(rtol=1e-8)
+    assert info["converged"] and not np.any(u)
+    ctx.set_dirichlet(np.zeros(0, np.int32))                     # no BCs: K singular
+    ctx.assemble()
+    rp, ci, va = ctx.csr(sfem.K_WITH_BC)
+    K = O.assemble(p.mesh.xyz, p.mesh.tets, p.E, p.nu)
+    assert row_rel_err(rp, va, K) <= 1e-12
+    print("empty traction list, zero load, empty Dirichlet set: handled")
+
+
+def test_single_tet():
+    sfem = _sfem()
+    P = np.array([[0, 0, 0], [1.1, 0.1, 0], [0.2, 0.9, 0.1], [0.1, 0.3, 1.2]])
+    tets = np.array([[0, 2, 1, 3]], np.int32)   # negatively oriented
+    ctx = sfem.Context(0)
+    ctx.set_mesh(P, tets)
+    ctx.set_material(1e9, 0.27)
+    ctx.assemble()
+    rp, ci, va = ctx.csr(sfem.K_UNCONSTRAINED)
+    Kt = O.fem_t4_assemble(P, tets, 1e9, 0.27)
+    e = row_rel_err(rp, va, Kt)
+    print(f"single tet vs FEM-T4 element matrix: {e:.2e}")
+    assert ctx.sizes().n_faces == 4 and e <= 1e-12
+
+
+def test_c2_sampled_rows():
+    """Full 1.92M-tet cantilever in the benchmark's configuration: rows of a
+    sample of nodes (clamped face, loaded end, edges, interior) against the
+    oracle computed row by row."""
+    sfem = _sfem()
+    p = mg.cantilever_c2()
+    m = p.mesh
+    ctx = gpu_ctx(p)
+    s = ctx.sizes()
+    assert (s.n_faces, s.n_exterior, s.nnz) == (3875200, 70400, 78876369)
+    rp, ci, va = ctx.csr(sfem.K_UNCONSTRAINED)
+    rng = np.random.default_rng(0)
+    nx, ny, nz = m.grid
+    picks = [0, mg.node_id(nx, ny, nz, ny, nz), mg.node_id(nx, 0, nz // 2, ny, nz),
+             mg.node_id(0, ny // 2, nz // 2, ny, nz), mg.node_id(nx // 2, ny // 2, nz // 2, ny, nz),
+             mg.node_id(nx // 3, 0, 0, ny, nz)]
+    picks += list(rng.integers(0, m.n_nodes, 10))
+    rows = O.assemble_rows(m.xyz, m.tets, p.E, p.nu, picks)
+    worst = 0.0
+    for I, (cols, vals) in rows.items():
+        for a in range(3):
+            r = 3 * I + a
+            sl = slice(rp[r], rp[r + 1])
+            np.testing.assert_array_equal(ci[sl], cols)
+            worst = max(worst, np.abs(va[sl] - vals[a]).max() / np.abs(vals[a]).max())
+    print(f"c2: faces {s.n_faces}, nnz {s.nnz}; sampled-row K error {worst:.2e}")
+    assert worst <= 1e-12

@@ -1,0 +1,229 @@
+"""Benchmark: FS-FEM stiffness assembly + PCG solve of the 1.92M-tet cantilever.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = the whole hot path on one synthetic problem already resident in
+HBM: numeric assembly of K (per-face smoothed stiffness summed into CSR, BCs
+applied) and the solve of K u = f to an FP64 true relative residual of 1e-8.
+Topology (faces, CSR pattern) is built once before timing, as the metric
+counts assembly with cached topology.
+
+Prints ONE JSON line.  `value` is the K-assembly throughput in faces/s
+(median over the timed steps); solve seconds are reported beside it.
+`roofline` covers the step's dominant kernel (the CG SpMV), with its
+duration measured per launch by HIP events on the library's stream;
+`roofline_assembly` covers the assembly kernel.  `cpu_baseline` times the
+FP64 oracle (single thread) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "K-assembly faces/s; solve s to 1e-8 rel-res @1.9M tets: learned vs Jacobi PCG"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(N, T, nf, nnz, nb, f32_copy=False, per_tet=False):
+    """Bytes the method itself must move per launch (no re-reads, no
+    intermediates): assembly reads coordinates and the face table and writes
+    every CSR value once; the CG SpMV reads each value once, the block
+    column list, the row offsets, x, and writes y."""
+    n = 3 * N
+    asm = 24 * N + 32 * nf + 8 * nnz + (4 * nnz if f32_copy else 0) + (16 * T if per_tet else 0)
+    spmv64 = 8 * nnz + 4 * nb + 4 * (N + 1) + 8 * n + 8 * n
+    spmv32 = 4 * nnz + 4 * nb + 4 * (N + 1) + 4 * n + 4 * n
+    return asm, spmv64, spmv32
+
+
+def read_traffic(kernel_tag):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if
+    one exists for this kernel and its source has not changed since."""
+    path = os.path.join(PROFILE_DIR, f"{kernel_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        import hashlib
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+CPU_SNIPPET = r"""
+import os, sys, time, json
+sys.path.insert(0, {root!r})
+import numpy as np
+from oracle import fsfem as O
+from paper_2001_08849_amd import meshgen as mg
+p = mg.cantilever_c2()
+m = p.mesh
+faces = O.extract_faces(m.tets)["table"]          # topology, not timed
+S = {sample}
+sub = faces[:S]
+t0 = time.perf_counter()
+vol = O.tet_volume(m.xyz[m.tets])
+parts = []
+for blk in (sub[sub[:, 4] < 0], sub[sub[:, 4] >= 0]):
+    if blk.shape[0]:
+        K, nodes = O.face_stiffness(m.xyz, m.tets, blk, p.E, p.nu, vol)
+        parts.append(O._coo_block(K, nodes))
+import scipy.sparse as sp
+I = np.concatenate([q[0] for q in parts]); J = np.concatenate([q[1] for q in parts])
+V = np.concatenate([q[2] for q in parts])
+Ks = sp.coo_matrix((V, (I, J)), shape=(3 * m.n_nodes,) * 2).tocsr()
+dt = time.perf_counter() - t0
+print(json.dumps({{"faces": int(S), "seconds": dt, "faces_per_s": S / dt}}))
+"""
+
+
+def cpu_baseline(sample_faces: int):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1", NUMEXPR_NUM_THREADS="1")
+    code = CPU_SNIPPET.format(root=ROOT, sample=sample_faces)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if res.returncode != 0:
+        log("cpu baseline failed:", res.stderr[-2000:])
+        return None
+    rec = json.loads(res.stdout.strip().splitlines()[-1])
+    return {
+        "value": rec["faces_per_s"], "unit": "faces/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 oracle numeric assembly (Eq. 7 + Table 1 smoothed gradients, "
+                   f"Eq. 9 face stiffness, Eq. 12 COO -> CSR) of the first {rec['faces']} "
+                   f"faces of the 1.92M-tet cantilever, topology excluded; "
+                   f"{rec['seconds']:.1f} s on one host thread"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=300000)
+    ap.add_argument("--skip-solve", action="store_true", help="assembly only (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"design is described, not built.", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+
+    from paper_2001_08849_amd import meshgen as mg
+    from paper_2001_08849_amd import sfem
+
+    t0 = time.time()
+    prob = mg.cantilever_c2()
+    m = prob.mesh
+    log(f"[bench] mesh {m.grid} N={m.n_nodes} T={m.n_tets} generated in {time.time() - t0:.1f}s")
+    ctx = sfem.Context(0)
+    ctx.set_mesh(m.xyz, m.tets)
+    ctx.set_material(prob.E, prob.nu)
+    ctx.set_dirichlet(prob.fixed_dofs())
+    ctx.add_traction(m.end_tris, prob.traction)
+    s = ctx.sizes()
+    ms_topo = ctx.timings()["ms_topology"]
+    log(f"[bench] topology {ms_topo:.1f} ms: faces {s.n_faces} ({s.n_exterior} ext), "
+        f"nnz {s.nnz}, blocks {s.n_blocks}")
+
+    u = np.empty(s.n_rows)
+
+    def step(profile=False):
+        ctx.assemble(f32_copy=False)
+        ms_asm = ctx.timings()["ms_assemble"]
+        if args.skip_solve:
+            return ms_asm, None
+        _, info = ctx.solve(rtol=1e-8, out=u, profile=profile)
+        return ms_asm, info
+
+    for w in range(args.warmup):
+        ms_asm, info = step()
+        log(f"[bench] warmup {w}: assembly {ms_asm:.3f} ms" +
+            (f", solve {info['ms_solve']:.1f} ms ({info['iters']} it)" if info else ""))
+
+    ctx.synchronize()
+    ctx.timer_start()
+    asm_ms, solves = [], []
+    for k in range(args.steps):
+        ms_asm, info = step(profile=True)
+        asm_ms.append(ms_asm)
+        if info:
+            solves.append(info)
+        log(f"[bench] step {k}: assembly {ms_asm:.3f} ms" +
+            (f", solve {info['ms_solve']:.1f} ms, {info['iters']} it, relres "
+             f"{info['true_relres']:.2e}, spmv {info['ms_spmv_avg'] * 1e3:.1f} us" if info else ""))
+    total_ms = ctx.timer_stop()
+    ctx.synchronize()
+
+    asm_med = float(np.median(asm_ms))
+    faces_per_s = s.n_faces / (asm_med * 1e-3)
+    asm_bytes, spmv_bytes, _ = algorithmic_bytes(m.n_nodes, m.n_tets, s.n_faces, s.nnz,
+                                                 s.n_blocks)
+    out = {
+        "metric": METRIC,
+        "value": faces_per_s,
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "cantilever 40x4x4 m, 200x40x40 cells x 6 Kuhn T4 (1.92M tets), "
+                        "+/-10% jitter seed 2, E=210e9, nu=0.3, clamp x=0, end traction 1e6 Pa",
+            "tets": m.n_tets, "nodes": m.n_nodes, "faces": s.n_faces, "nnz": s.nnz,
+            "solver": "Jacobi PCG FP64, x0=0, true relres <= 1e-8",
+        },
+        "assembly_ms": asm_med,
+        "topology_ms": ms_topo,
+    }
+    if solves:
+        out["solve_s"] = {"jacobi_f64": float(np.median([i["ms_solve"] for i in solves])) / 1e3,
+                          "learned_f32ir": None}
+        out["solve_iters"] = {"jacobi_f64": solves[-1]["iters"]}
+        out["solve_true_relres"] = {"jacobi_f64": solves[-1]["true_relres"]}
+        spmv_ms = float(np.mean([i["ms_spmv_avg"] for i in solves]))
+        ach = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+        out["roofline"] = {"kernel": "k_cg_spmv<double,double>", "bound": "hbm",
+                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS,
+                           "traffic": read_traffic("cg_spmv_f64_c2"),
+                           "bytes_per_launch": spmv_bytes, "us_per_launch": spmv_ms * 1e3}
+    ach_a = asm_bytes / (asm_med * 1e-3) / 1e9
+    out["roofline_assembly"] = {"kernel": "k_assemble<false>", "bound": "hbm", "achieved": ach_a,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_a / HBM_PEAK_GBS,
+                                "traffic": read_traffic("assemble_c2"),
+                                "bytes_per_launch": asm_bytes, "us_per_launch": asm_med * 1e3}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle, 1 thread) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    out["context"] = {"paper_assembly_faces_per_s_24core": 4.2e5,
+                      "paper_note": "derived: ~4.15M faces / ~10 s on a 24-core Xeon 5118, "
+                                    "TetGen mesh of 2.08M tets, direct solver; not comparable"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

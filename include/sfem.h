@@ -169,6 +169,7 @@ typedef struct {
   int check_every;    /* true-residual period in iterations (0: 50) */
   double inner_rtol;  /* F32_IR inner tolerance (0: 1e-3) */
   int max_outer;      /* F32_IR outer-step cap (0: 30) */
+  int profile;        /* nonzero: time every SpMV launch with HIP events */
 } sfem_solve_opts;
 
 typedef struct {
@@ -178,6 +179,8 @@ typedef struct {
   int converged;      /* 1 if true_relres <= rtol */
   double true_relres; /* FP64 ||f - K u|| / ||f|| at return */
   double ms_solve;    /* device time of the solve (HIP events) */
+  double ms_spmv_avg; /* mean device time of one CG SpMV launch (profile) */
+  int n_spmv;         /* SpMV launches timed (profile) */
 } sfem_solve_info;
 
 int sfem_solve(sfem_ctx* ctx, const sfem_solve_opts* opts, double* u, int ptr_kind,
@@ -186,6 +189,14 @@ int sfem_solve(sfem_ctx* ctx, const sfem_solve_opts* opts, double* u, int ptr_ki
 /* Device time in milliseconds of the most recent topology build and the
  * most recent numeric assembly (HIP events on the context stream). */
 int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
+
+/* Wall-clock device timer on the context stream: start records an event,
+ * stop records a second one, waits for it and returns the elapsed ms. */
+int sfem_timer_start(sfem_ctx* ctx);
+int sfem_timer_stop(sfem_ctx* ctx, double* ms);
+
+/* Waits until all work queued on the context stream has finished. */
+int sfem_synchronize(sfem_ctx* ctx);
 
 #ifdef __cplusplus
 }

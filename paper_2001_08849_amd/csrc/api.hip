@@ -133,6 +133,8 @@ int sfem_create(sfem_ctx** out, int device, void* hip_stream) {
     }
     SFEM_HIP(hipEventCreate(&c.ev0));
     SFEM_HIP(hipEventCreate(&c.ev1));
+    SFEM_HIP(hipEventCreate(&c.tev0));
+    SFEM_HIP(hipEventCreate(&c.tev1));
     SFEM_HIP(hipHostMalloc((void**)&c.sc_host, sizeof(sfem::CgScalars), hipHostMallocDefault));
     c.sc.reserve(1);
     SFEM_HIP(hipMemsetAsync(c.sc.get(), 0, sizeof(sfem::CgScalars), c.stream));
@@ -154,6 +156,9 @@ void sfem_destroy(sfem_ctx* h) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   if (c.ev0) (void)hipEventDestroy(c.ev0);
   if (c.ev1) (void)hipEventDestroy(c.ev1);
+  if (c.tev0) (void)hipEventDestroy(c.tev0);
+  if (c.tev1) (void)hipEventDestroy(c.tev1);
+  for (hipEvent_t e : c.prof_ev) (void)hipEventDestroy(e);
   if (c.sc_host) (void)hipHostFree(c.sc_host);
   if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
   delete h;
@@ -462,6 +467,32 @@ int sfem_get_timings(sfem_ctx* h, double* ms_topology, double* ms_assemble) {
   return guarded(h, [&](Ctx& c) {
     if (ms_topology) *ms_topology = c.ms_topology;
     if (ms_assemble) *ms_assemble = c.ms_assemble;
+    return SFEM_OK;
+  });
+}
+
+int sfem_timer_start(sfem_ctx* h) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_HIP(hipEventRecord(c.tev0, c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_timer_stop(sfem_ctx* h, double* ms) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(ms != nullptr, SFEM_EINVAL, "null output");
+    SFEM_HIP(hipEventRecord(c.tev1, c.stream));
+    SFEM_HIP(hipEventSynchronize(c.tev1));
+    float t = 0;
+    SFEM_HIP(hipEventElapsedTime(&t, c.tev0, c.tev1));
+    *ms = t;
+    return SFEM_OK;
+  });
+}
+
+int sfem_synchronize(sfem_ctx* h) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_HIP(hipStreamSynchronize(c.stream));
     return SFEM_OK;
   });
 }

@@ -12,11 +12,12 @@
 //   K_IJ = V_k [ lam b_I b_J^T + mu b_J b_I^T + mu (b_I . b_J) I_3 ].
 //
 // Scatter-assembly (Eq. 12 summed into CSR) is owner-computes by tile: a
-// workgroup owns a run of consecutive node rows, holds their CSR values in
-// LDS, visits every face whose support touches the run (each such face once
-// per tile, found through the node->face incidence), adds its blocks for the
-// rows it owns with LDS atomics, then streams the finished rows to HBM once,
-// coalesced, with the essential BCs applied on the way out.
+// workgroup owns a run of consecutive node rows and holds their CSR values in
+// LDS.  Its work items are the (row, face) incidences of those rows: each
+// evaluates the face in registers and adds the row's blocks with LDS
+// atomics at column slots precomputed with the topology.  The finished rows
+// are streamed to HBM once, coalesced, with the essential BCs applied on the
+// way out.
 #include "ctx.h"
 
 namespace sfem {
@@ -24,7 +25,6 @@ namespace sfem {
 namespace {
 
 constexpr int kAsmThreads = 512;
-constexpr int kAsmFaces = 2048;  // faces staged per round in LDS
 
 struct Vec3 {
   double x, y, z;
@@ -121,20 +121,33 @@ __device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
   return lo;
 }
 
+// Largest index i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
+__device__ __forceinline__ int upper_index(const int32_t* a, int n, int v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One workgroup per tile of node rows.  Work item = incidence entry e of a
+// row I in the tile, i.e. a (row, face) pair: the face's smoothed gradients
+// are evaluated in registers and the row's 4 or 5 blocks K_{I,J} are added
+// into the LDS copy of the rows with the column slots from the slot map.
 template <bool HET>
 __global__ void __launch_bounds__(kAsmThreads)
     k_assemble(const double* __restrict__ xyz, const int32_t* __restrict__ face,
                const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
-               const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-               const int32_t* __restrict__ tile_first, double lam0, double mu0,
-               const double* __restrict__ lam_t, const double* __restrict__ mu_t,
-               const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
-               float* __restrict__ val32) {
+               const uint32_t* __restrict__ slot, const int32_t* __restrict__ bptr,
+               const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
+               double lam0, double mu0, const double* __restrict__ lam_t,
+               const double* __restrict__ mu_t, const uint8_t* __restrict__ fixed,
+               double penalty, double* __restrict__ val, float* __restrict__ val32) {
   __shared__ double sval[kTileBlocks * 9];
-  __shared__ int32_t scol[kTileBlocks];
-  __shared__ int32_t sptr[kTileBlocks + 1];
-  __shared__ int32_t sface[kAsmFaces];
-  __shared__ int32_t nface;
+  __shared__ int32_t sptr[kTileBlocks + 1];  // block offsets of the tile's rows
+  __shared__ int32_t sinc[kTileBlocks + 1];  // incidence offsets of the tile's rows
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -144,79 +157,53 @@ __global__ void __launch_bounds__(kAsmThreads)
   const int nn = n1 - n0;
   const int b0 = bptr[n0];
   const int nblk = bptr[n1] - b0;
+  const int e0 = inc_ptr[n0], e1 = inc_ptr[n1];
 
   for (int i = tid; i < 9 * nblk; i += kAsmThreads) sval[i] = 0.0;
-  for (int i = tid; i < nblk; i += kAsmThreads) scol[i] = bcol[b0 + i];
-  for (int i = tid; i <= nn; i += kAsmThreads) sptr[i] = bptr[n0 + i] - b0;
+  for (int i = tid; i <= nn; i += kAsmThreads) {
+    sptr[i] = bptr[n0 + i] - b0;
+    sinc[i] = inc_ptr[n0 + i] - e0;
+  }
+  __syncthreads();
 
-  // incidence entries of the tile's rows, processed in rounds of at most
-  // kAsmFaces entries: a face is taken at the entry of its smallest support
-  // node inside [n0, n1), so each touching face is handled once per tile
-  const int e0 = inc_ptr[n0], e1 = inc_ptr[n1];
-  for (int c0 = e0; c0 < e1; c0 += kAsmFaces) {
-    const int c1 = min(e1, c0 + kAsmFaces);
-    if (tid == 0) nface = 0;
-    __syncthreads();
-    // entry e belongs to node I: walk rows with waves, entries with lanes
-    for (int li = wid; li < nn; li += nwaves) {
-      const int I = n0 + li;
-      const int lo = max(inc_ptr[I], c0), hi = min(inc_ptr[I + 1], c1);
-      for (int e = lo + lane; e < hi; e += kWave) {
-        const int f = inc[e];
-        const int32_t* row = face + int64_t(f) * kFaceStride;
-        int4 r0 = *reinterpret_cast<const int4*>(row);
-        int s4 = row[4];
-        int m = 0x7fffffff;
-        m = (r0.x >= n0 && r0.x < n1) ? min(m, r0.x) : m;
-        m = (r0.y >= n0 && r0.y < n1) ? min(m, r0.y) : m;
-        m = (r0.z >= n0 && r0.z < n1) ? min(m, r0.z) : m;
-        m = (r0.w >= n0 && r0.w < n1) ? min(m, r0.w) : m;
-        m = (s4 >= n0 && s4 < n1) ? min(m, s4) : m;
-        if (m == I) sface[atomicAdd(&nface, 1)] = f;
-      }
-    }
-    __syncthreads();
-    const int nf = nface;
-    for (int k = tid; k < nf; k += kAsmThreads) {
-      const int f = sface[k];
-      int sup[5];
-      Vec3 b[5];
-      double Vk, lam, mu;
-      const int n = face_geometry<HET>(face + int64_t(f) * kFaceStride, xyz, lam0, mu0, lam_t,
-                                       mu_t, sup, b, Vk, lam, mu);
-      const double lV = lam * Vk, mV = mu * Vk;
+  for (int e = e0 + tid; e < e1; e += kAsmThreads) {
+    const int li = upper_index(sinc, nn, e - e0);
+    const int I = n0 + li;
+    const int rb = sptr[li];
+    const int deg = sptr[li + 1] - rb;
+    const uint32_t code = slot[e];
+    int sup[5];
+    Vec3 b[5];
+    double Vk, lam, mu;
+    const int n = face_geometry<HET>(face + int64_t(inc[e]) * kFaceStride, xyz, lam0, mu0, lam_t,
+                                     mu_t, sup, b, Vk, lam, mu);
+    const double lV = lam * Vk, mV = mu * Vk;
+    Vec3 bp = b[0];
 #pragma unroll
-      for (int p = 0; p < 5; ++p) {
-        const int I = sup[p];
-        if (p >= n || I < n0 || I >= n1) continue;
-        const int li = I - n0;
-        const int rb = sptr[li];
-        const int deg = sptr[li + 1] - rb;
-        double* rowv = sval + 9 * rb;
-        const double bpa[3] = {b[p].x, b[p].y, b[p].z};
+    for (int p = 1; p < 5; ++p)
+      if (sup[p] == I) bp = b[p];
+    const double bpa[3] = {bp.x, bp.y, bp.z};
+    double* rowv = sval + 9 * rb;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          if (q >= n) continue;
-          const int jj = find_col(scol + rb, deg, sup[q]);
-          const double bqa[3] = {b[q].x, b[q].y, b[q].z};
-          const double d = mV * (bpa[0] * bqa[0] + bpa[1] * bqa[1] + bpa[2] * bqa[2]);
-          double* dst = rowv + 3 * jj;
+    for (int q = 0; q < 5; ++q) {
+      if (q >= n) continue;
+      const int jj = int((code >> (6 * q)) & 63u);
+      const double bqa[3] = {b[q].x, b[q].y, b[q].z};
+      const double d = mV * (bpa[0] * bqa[0] + bpa[1] * bqa[1] + bpa[2] * bqa[2]);
+      double* dst = rowv + 3 * jj;
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
+      for (int a = 0; a < 3; ++a) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const double v = lV * bpa[a] * bqa[c] + mV * bpa[c] * bqa[a] + (a == c ? d : 0.0);
-              atomicAdd(dst + a * 3 * deg + c, v);
-            }
-          }
+        for (int c = 0; c < 3; ++c) {
+          const double v = lV * bpa[a] * bqa[c] + mV * bpa[c] * bqa[a] + (a == c ? d : 0.0);
+          atomicAdd(dst + a * 3 * deg + c, v);
         }
       }
     }
-    __syncthreads();
   }
 
   // stream the finished rows out, applying the essential BCs
-  __syncthreads();  // (also covers a tile without incidences)
+  __syncthreads();
   for (int li = wid; li < nn; li += nwaves) {
     const int I = n0 + li;
     const int rb = sptr[li];
@@ -232,7 +219,7 @@ __global__ void __launch_bounds__(kAsmThreads)
         const int jj = r / 3;
         const int c = r - 3 * jj;
         const int row = 3 * I + a;
-        const int col = 3 * scol[rb + jj] + c;
+        const int col = 3 * bcol[b0 + rb + jj] + c;
         const bool fr = fixed[row], fc = fixed[col];
         if (penalty > 0.0) {
           if (fr && row == col) v += penalty;
@@ -392,14 +379,14 @@ void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask)
   dim3 grid(tp.n_tiles), block(kAsmThreads);
   if (c.per_tet)
     k_assemble<true><<<grid, block, 0, c.stream>>>(
-        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.bptr.get(), tp.bcol.get(),
-        tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), fixed, c.penalty,
-        val_out, val32_out);
+        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
+        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), fixed,
+        c.penalty, val_out, val32_out);
   else
     k_assemble<false><<<grid, block, 0, c.stream>>>(
-        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.bptr.get(), tp.bcol.get(),
-        tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, fixed, c.penalty, val_out,
-        val32_out);
+        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
+        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, fixed, c.penalty,
+        val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

@@ -102,12 +102,13 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 
 // Counting sort of n items by bucket (0 <= bucket < n_buckets), then a sort
-// of the values inside every bucket (values must be distinct within a
-// bucket).  ptr gets n_buckets+1 offsets; out the sorted values.
+// of the values inside each of the first n_sorted buckets (all if < 0;
+// values must be distinct within a bucket).  ptr gets n_buckets+1 offsets;
+// out the values, bucket by bucket.
 void bucket_sort_u64(const int32_t* bucket, const uint64_t* vals, int64_t n, int n_buckets,
-                     int32_t* ptr, uint64_t* out, hipStream_t s);
+                     int32_t* ptr, uint64_t* out, hipStream_t s, int n_sorted = -1);
 void bucket_sort_u32(const int32_t* bucket, const uint32_t* vals, int64_t n, int n_buckets,
-                     int32_t* ptr, uint32_t* out, hipStream_t s);
+                     int32_t* ptr, uint32_t* out, hipStream_t s, int n_sorted = -1);
 
 // Sort the values of every segment [ptr[i], ptr[i+1]) of `in` into `out`.
 void segmented_sort_u64(const int32_t* ptr, int n_seg, const uint64_t* in, uint64_t* out,

@@ -6,7 +6,9 @@ namespace sfem {
 
 // Numeric-assembly tile: a run of consecutive node rows whose 3x3 blocks
 // (and their FP64 values) fit in LDS.  kTileBlocks is the block capacity.
-constexpr int kTileBlocks = 800;
+constexpr int kTileBlocks = 640;
+// Largest node degree (3x3 blocks in a row) the slot map can encode.
+constexpr int kMaxDeg = 64;
 
 // Face record in HBM: support nodes (a, b, c, o1, o2) then tets (t1, t2),
 // padded to 32 bytes.  o2 = t2 = -1 for an exterior face.
@@ -22,6 +24,7 @@ struct Topology {
   DBuf<int32_t> face;            // [nf][kFaceStride]
   DBuf<int32_t> inc_ptr;         // [N+2] (bucket N collects exterior padding)
   DBuf<int32_t> inc;             // face ids per node, ascending
+  DBuf<uint32_t> slot;           // per incidence: block slots of the face's support
   DBuf<int32_t> bptr;            // [N+1] block-row offsets
   DBuf<int32_t> bcol;            // [nb] block column (node) ids, ascending per row
   DBuf<int32_t> tile_first;      // [n_tiles+1] first node of each tile
@@ -72,14 +75,19 @@ struct Ctx {
   DBuf<float> dinv32;
 
   // solver work vectors
-  DBuf<double> x, r, z, p, q, w;
-  DBuf<float> x32, r32, z32, p32, q32;
+  DBuf<double> x, r, z, p, p2, q, w;
+  DBuf<float> x32, r32, z32, p32, p32b, q32, b32;
   DBuf<double> partials;
   DBuf<CgScalars> sc;
   CgScalars* sc_host = nullptr;  // pinned mirror
 
   // timings
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t tev0 = nullptr, tev1 = nullptr;  // sfem_timer_*
+  std::vector<hipEvent_t> prof_ev;             // per-launch SpMV timing
+  bool profile = false;
+  double prof_ms = 0;
+  int prof_n = 0;
   double ms_topology = 0, ms_assemble = 0;
 
   int64_t n_dof() const { return 3 * N; }

@@ -153,6 +153,8 @@ __global__ void __launch_bounds__(kSegWaves * kWave)
 
 template <typename V>
 void segmented_sort_impl(const int32_t* ptr, int n_seg, const V* in, V* out, hipStream_t s) {
+  // (segments are sorted independently; callers may pass fewer segments
+  // than the buckets they counted to leave trailing buckets unsorted)
   if (n_seg <= 0) return;
   k_segsort<V><<<div_up(n_seg, kSegWaves), kSegWaves * kWave, 0, s>>>(ptr, n_seg, in, out);
   SFEM_HIP(hipGetLastError());
@@ -160,7 +162,7 @@ void segmented_sort_impl(const int32_t* ptr, int n_seg, const V* in, V* out, hip
 
 template <typename V>
 void bucket_sort_impl(const int32_t* bucket, const V* vals, int64_t n, int n_buckets, int32_t* ptr,
-                      V* out, hipStream_t s) {
+                      V* out, hipStream_t s, int n_sorted) {
   int32_t *cnt = nullptr, *cursor = nullptr;
   V* tmp = nullptr;
   SFEM_HIP(hipMallocAsync((void**)&cnt, sizeof(int32_t) * (n_buckets + 1), s));
@@ -178,7 +180,15 @@ void bucket_sort_impl(const int32_t* bucket, const V* vals, int64_t n, int n_buc
     k_scatter<V><<<div_up(n, 256), 256, 0, s>>>(bucket, vals, n, cursor, tmp);
     SFEM_HIP(hipGetLastError());
   }
-  segmented_sort_impl<V>(ptr, n_buckets, tmp, out, s);
+  segmented_sort_impl<V>(ptr, n_sorted, tmp, out, s);
+  if (n_sorted < n_buckets) {  // unsorted trailing buckets: plain copy
+    int32_t first = 0;
+    SFEM_HIP(hipMemcpyAsync(&first, ptr + n_sorted, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SFEM_HIP(hipStreamSynchronize(s));
+    if (n > first)
+      SFEM_HIP(hipMemcpyAsync(out + first, tmp + first, sizeof(V) * (n - first),
+                              hipMemcpyDeviceToDevice, s));
+  }
   SFEM_HIP(hipFreeAsync(cnt, s));
   SFEM_HIP(hipFreeAsync(cursor, s));
   SFEM_HIP(hipFreeAsync(tmp, s));
@@ -191,13 +201,15 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
 }
 
 void bucket_sort_u64(const int32_t* bucket, const uint64_t* vals, int64_t n, int n_buckets,
-                     int32_t* ptr, uint64_t* out, hipStream_t s) {
-  bucket_sort_impl<uint64_t>(bucket, vals, n, n_buckets, ptr, out, s);
+                     int32_t* ptr, uint64_t* out, hipStream_t s, int n_sorted) {
+  bucket_sort_impl<uint64_t>(bucket, vals, n, n_buckets, ptr, out, s,
+                             n_sorted < 0 ? n_buckets : n_sorted);
 }
 
 void bucket_sort_u32(const int32_t* bucket, const uint32_t* vals, int64_t n, int n_buckets,
-                     int32_t* ptr, uint32_t* out, hipStream_t s) {
-  bucket_sort_impl<uint32_t>(bucket, vals, n, n_buckets, ptr, out, s);
+                     int32_t* ptr, uint32_t* out, hipStream_t s, int n_sorted) {
+  bucket_sort_impl<uint32_t>(bucket, vals, n, n_buckets, ptr, out, s,
+                             n_sorted < 0 ? n_buckets : n_sorted);
 }
 
 void segmented_sort_u64(const int32_t* ptr, int n_seg, const uint64_t* in, uint64_t* out,

@@ -21,42 +21,84 @@ namespace sfem {
 
 namespace {
 
-constexpr int kRowWaves = 4;               // node rows per workgroup
+constexpr int kRowWaves = 4;               // waves per row-kernel workgroup
+constexpr int kLPR = 32;                   // lanes per node row in the row kernels
 constexpr int kVecThreads = 256;
 
-// The three sums of node row I (valid in every lane after the reduction).
-template <typename VT, typename XT>
-__device__ __forceinline__ void row_product(int I, int lane, const int32_t* __restrict__ bptr,
-                                            const int32_t* __restrict__ bcol,
-                                            const VT* __restrict__ val, const XT* __restrict__ x,
-                                            double& y0, double& y1, double& y2) {
-  const int rb = bptr[I];
-  const int deg = bptr[I + 1] - rb;
-  const int three_deg = 3 * deg;
-  const float inv3d = 1.0f / float(three_deg);
+// The three sums of node row I, computed by a group of LPR lanes (a
+// power of two dividing 64): lane c of the group takes column positions c,
+// c+LPR, ... of the row and multiplies the SAME x entry with the values of
+// all three scalar rows (one gather per column), then the group reduces with
+// shuffles.  Rows with valid == false contribute zeros but still shuffle.
+template <int LPR>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename VT, int LPR, class XF>
+__device__ __forceinline__ void row3(int I, bool valid, int sub, const int32_t* __restrict__ bptr,
+                                     const int32_t* __restrict__ bcol,
+                                     const VT* __restrict__ val, const XF& x, double& y0,
+                                     double& y1, double& y2) {
+  int rb = 0, deg = 0;
+  if (valid) {
+    rb = bptr[I];
+    deg = bptr[I + 1] - rb;
+  }
+  const int td = 3 * deg;
   const VT* v = val + 9 * int64_t(rb);
   const int32_t* cols = bcol + rb;
   using AT = typename std::conditional<sizeof(VT) == 8, double, float>::type;
   AT a0 = 0, a1 = 0, a2 = 0;
-  for (int k = lane; k < 9 * deg; k += kWave) {
-    const int a = int((float(k) + 0.5f) * inv3d);
-    const int r = k - a * three_deg;
-    const int jj = r / 3;
-    const int c = r - 3 * jj;
-    const AT prod = AT(v[k]) * AT(x[3 * cols[jj] + c]);
-    a0 += a == 0 ? prod : AT(0);
-    a1 += a == 1 ? prod : AT(0);
-    a2 += a == 2 ? prod : AT(0);
+  for (int c = sub; c < td; c += LPR) {
+    const int jj = c / 3;
+    const int b = c - 3 * jj;
+    const AT xv = AT(x(3 * int64_t(cols[jj]) + b));
+    a0 += AT(v[c]) * xv;
+    a1 += AT(v[td + c]) * xv;
+    a2 += AT(v[2 * td + c]) * xv;
   }
-  y0 = wave_sum(double(a0));
-  y1 = wave_sum(double(a1));
-  y2 = wave_sum(double(a2));
+  y0 = group_sum<LPR>(double(a0));
+  y1 = group_sum<LPR>(double(a1));
+  y2 = group_sum<LPR>(double(a2));
 }
 
-// Block reduction of NV doubles (each thread passes its values; thread 0
-// gets the block totals).
+template <typename T>
+struct PlainX {
+  const T* __restrict__ p;
+  __device__ __forceinline__ T operator()(int64_t i) const { return p[i]; }
+};
+
+// x-operand of the CG product: p_new = z + beta * p_old, formed on the fly.
+template <typename P>
+struct PNewX {
+  const P* __restrict__ z;
+  const P* __restrict__ p;
+  P beta;
+  __device__ __forceinline__ P operator()(int64_t i) const { return z[i] + beta * p[i]; }
+};
+
+// Row loop shared by the row kernels: each wave serves 64/LPR rows at a time,
+// grid-stride over all node rows; body(I, valid, sub) runs in every lane.
+template <int LPR, class Body>
+__device__ __forceinline__ void for_rows(int64_t N, Body&& body) {
+  constexpr int G = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / LPR, sub = lane % LPR;
+  const int64_t wave = int64_t(blockIdx.x) * kRowWaves + threadIdx.x / kWave;
+  const int64_t stride = int64_t(gridDim.x) * kRowWaves * G;
+  for (int64_t base = wave * G; base < N; base += stride) {
+    const int64_t I = base + g;
+    body(int(I < N ? I : 0), I < N, sub);
+  }
+}
+
+// Block reduction of NV doubles (thread 0 gets the block totals).
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double lds[16 * NV];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
@@ -73,143 +115,101 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
       for (int i = 0; i < NV; ++i) v[i] += lds[w * NV + i];
 }
 
-// Writes this block's partial sums; returns true (in every thread) for the
-// last block to arrive, whose thread 0 then holds the grand totals in v.
+// Each workgroup stores its NV partial sums; a one-workgroup k_finalize
+// launched next adds them in a fixed order (no device-scope fences: the
+// kernel boundary orders the writes).
 template <int NV>
-__device__ __forceinline__ bool last_block_reduce(double (&v)[NV], double* partials,
-                                                  unsigned int* counter) {
-  __shared__ double lds[16 * NV];
-  __shared__ int is_last;
-  block_sum<NV>(v, lds);
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ void store_partials(double (&v)[NV], double* partials) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0)
 #pragma unroll
     for (int i = 0; i < NV; ++i) partials[blockIdx.x * NV + i] = v[i];
-    __threadfence();
-    unsigned int ticket = atomicAdd(counter, 1u);
-    is_last = (ticket == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (int b = threadIdx.x; b < int(gridDim.x); b += blockDim.x)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += partials[b * NV + i];
-  block_sum<NV>(acc, lds);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = acc[i];
-    atomicExch(counter, 0u);
-  }
-  return true;
 }
 
-template <typename VT, typename XT>
+template <typename VT, typename XT, int LPR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
            const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t I = int64_t(blockIdx.x) * kRowWaves + threadIdx.x / kWave;
-  if (I >= N) return;
-  double y0, y1, y2;
-  row_product<VT, XT>(int(I), lane, bptr, bcol, val, x, y0, y1, y2);
-  if (lane == 0) {
-    y[3 * I + 0] = XT(y0);
-    y[3 * I + 1] = XT(y1);
-    y[3 * I + 2] = XT(y2);
-  }
+  const PlainX<XT> xf{x};
+  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
+    double y0, y1, y2;
+    row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y0, y1, y2);
+    if (valid && sub == 0) {
+      y[3 * int64_t(I) + 0] = XT(y0);
+      y[3 * int64_t(I) + 1] = XT(y1);
+      y[3 * int64_t(I) + 2] = XT(y2);
+    }
+  });
 }
 
 // ---------------------------------------------------------------- CG kernels
-// p = z + beta p
-template <typename P>
-__global__ void k_cg_p(int64_t n, const P* __restrict__ z, P* __restrict__ p,
-                       const CgScalars* __restrict__ sc) {
-  if (sc->converged) return;
-  const P beta = P(sc->beta);
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + beta * p[i];
-}
-
-// q = K p; alpha = rz / (p . q); breakdown (p.q <= 0 or not finite) sets
-// converged = 2.
-template <typename VT, typename P>
+// p_new = z + beta p_old (own rows written), q = K p_new, partial (p_new.q).
+template <typename VT, typename P, int LPR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-              const VT* __restrict__ val, const P* __restrict__ p, P* __restrict__ q,
-              CgScalars* __restrict__ sc, double* __restrict__ partials) {
+              const VT* __restrict__ val, const P* __restrict__ z, const P* __restrict__ p_old,
+              P* __restrict__ p_new, P* __restrict__ q, const CgScalars* __restrict__ sc,
+              double* __restrict__ partials) {
   if (sc->converged) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t I = int64_t(blockIdx.x) * kRowWaves + threadIdx.x / kWave;
+  const PNewX<P> xf{z, p_old, P(sc->beta)};
   double v[1] = {0.0};
-  if (I < N) {
-    double y0, y1, y2;
-    row_product<VT, P>(int(I), lane, bptr, bcol, val, p, y0, y1, y2);
-    const P q0 = P(y0), q1 = P(y1), q2 = P(y2);
-    if (lane == 0) {
-      q[3 * I + 0] = q0;
-      q[3 * I + 1] = q1;
-      q[3 * I + 2] = q2;
-      v[0] = double(p[3 * I]) * double(q0) + double(p[3 * I + 1]) * double(q1) +
-             double(p[3 * I + 2]) * double(q2);
+  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
+    double y[3];
+    row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+    if (valid && sub == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = 3 * int64_t(I) + a;
+        const P pi = xf(i);
+        const P qi = P(y[a]);
+        p_new[i] = pi;
+        q[i] = qi;
+        v[0] += double(pi) * double(qi);
+      }
     }
-  }
-  if (last_block_reduce<1>(v, partials, &sc->counter[0]) && threadIdx.x == 0) {
-    sc->pq = v[0];
-    sc->alpha = sc->rz / v[0];
-    if (!(v[0] > 0.0) || !isfinite(sc->alpha)) sc->converged = 2;
-  }
+  });
+  store_partials<1>(v, partials);
 }
 
-// x += alpha p; r -= alpha q; z = dinv r; (r.z), (r.r) -> beta, rz, rr
+// x += alpha p; r -= alpha q; z = dinv r; partials (r.z), (r.r)
 template <typename P>
 __global__ void __launch_bounds__(kVecThreads)
     k_cg_update(int64_t n, P* __restrict__ x, P* __restrict__ r, P* __restrict__ z,
                 const P* __restrict__ p, const P* __restrict__ q, const P* __restrict__ dinv,
-                CgScalars* __restrict__ sc, double* __restrict__ partials) {
+                const CgScalars* __restrict__ sc, double* __restrict__ partials) {
   if (sc->converged) return;
-  const double alpha = sc->alpha;
+  const P alpha = P(sc->alpha);
   double v[2] = {0.0, 0.0};
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
-    P xi = x[i] + P(alpha) * p[i];
-    P ri = r[i] - P(alpha) * q[i];
-    P zi = dinv[i] * ri;
+    const P xi = x[i] + alpha * p[i];
+    const P ri = r[i] - alpha * q[i];
+    const P zi = dinv[i] * ri;
     x[i] = xi;
     r[i] = ri;
     z[i] = zi;
     v[0] += double(ri) * double(zi);
     v[1] += double(ri) * double(ri);
   }
-  if (last_block_reduce<2>(v, partials, &sc->counter[1]) && threadIdx.x == 0) {
-    sc->beta = v[0] / sc->rz;
-    sc->rz = v[0];
-    sc->rr = v[1];
-    sc->aux[0] += 1.0;  // iteration count
-    if (v[1] <= sc->aux[1]) sc->converged = 1;  // aux[1] = tolerance^2 on r.r
-    if (!isfinite(v[1])) sc->converged = 2;
-  }
+  store_partials<2>(v, partials);
 }
 
-// Residual replacement: r = b - K x, z = dinv r; (r.r) -> rr_true, (r.z) -> rz.
-template <typename VT, typename P>
+// Residual replacement: r = b - K x, z = dinv r; partials (r.r), (r.z).
+template <typename VT, typename P, int LPR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_replace(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                  const VT* __restrict__ val, const P* __restrict__ b, const P* __restrict__ x,
                  P* __restrict__ r, P* __restrict__ z, const P* __restrict__ dinv,
-                 CgScalars* __restrict__ sc, double* __restrict__ partials) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t I = int64_t(blockIdx.x) * kRowWaves + threadIdx.x / kWave;
+                 double* __restrict__ partials) {
+  const PlainX<P> xf{x};
   double v[2] = {0.0, 0.0};
-  if (I < N) {
+  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
     double y[3];
-    row_product<VT, P>(int(I), lane, bptr, bcol, val, x, y[0], y[1], y[2]);
-    if (lane == 0) {
+    row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+    if (valid && sub == 0) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * I + a;
+        const int64_t i = 3 * int64_t(I) + a;
         const P ri = P(double(b[i]) - y[a]);
         const P zi = dinv[i] * ri;
         r[i] = ri;
@@ -218,52 +218,44 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
         v[1] += double(ri) * double(zi);
       }
     }
-  }
-  if (last_block_reduce<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-    sc->rr_true = v[0];
-    sc->rz = v[1];
-    sc->rr = v[0];
-  }
+  });
+  store_partials<2>(v, partials);
 }
 
-// FP64 residual of the outer problem: r = f - K u and ||r||^2 -> rr_true.
+// FP64 residual of the outer problem: r = f - K u; partials ||r||^2, ||f||^2.
+template <int LPR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_resid64(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
               const double* __restrict__ val, const double* __restrict__ f,
-              const double* __restrict__ u, double* __restrict__ r, CgScalars* __restrict__ sc,
+              const double* __restrict__ u, double* __restrict__ r,
               double* __restrict__ partials) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t I = int64_t(blockIdx.x) * kRowWaves + threadIdx.x / kWave;
+  const PlainX<double> xf{u};
   double v[2] = {0.0, 0.0};
-  if (I < N) {
+  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
     double y[3];
-    row_product<double, double>(int(I), lane, bptr, bcol, val, u, y[0], y[1], y[2]);
-    if (lane == 0) {
+    row3<double, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+    if (valid && sub == 0) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * I + a;
+        const int64_t i = 3 * int64_t(I) + a;
         const double ri = f[i] - y[a];
         if (r) r[i] = ri;
         v[0] += ri * ri;
         v[1] += f[i] * f[i];
       }
     }
-  }
-  if (last_block_reduce<2>(v, partials, &sc->counter[3]) && threadIdx.x == 0) {
-    sc->rr_true = v[0];
-    sc->ff = v[1];
-  }
+  });
+  store_partials<2>(v, partials);
 }
 
-// CG start from x = 0 with right-hand side b: x = 0, r = b, z = dinv b,
-// p = 0, beta = 0; (r.z) -> rz, (r.r) -> rr.  b may be FP64 while P is FP32
-// (inner solve of the refinement), in which case b is scaled by 1/scale.
+// CG start from x = 0 with right-hand side b (FP64, scaled by inv_scale and
+// converted to P; bp receives the converted copy when non-null): x = 0,
+// r = b, z = dinv b, p = 0; partials (r.z), (r.r).
 template <typename P>
 __global__ void __launch_bounds__(kVecThreads)
     k_cg_start(int64_t n, const double* __restrict__ b, double inv_scale, P* __restrict__ bp,
-               P* __restrict__ x, P* __restrict__ r, P* __restrict__ z, P* __restrict__ p,
-               const P* __restrict__ dinv, CgScalars* __restrict__ sc,
-               double* __restrict__ partials) {
+               P* __restrict__ x, P* __restrict__ r, P* __restrict__ z, P* __restrict__ p0,
+               P* __restrict__ p1, const P* __restrict__ dinv, double* __restrict__ partials) {
   double v[2] = {0.0, 0.0};
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -273,16 +265,59 @@ __global__ void __launch_bounds__(kVecThreads)
     x[i] = P(0);
     r[i] = bi;
     z[i] = zi;
-    p[i] = P(0);
+    p0[i] = P(0);
+    p1[i] = P(0);
     v[0] += double(bi) * double(zi);
     v[1] += double(bi) * double(bi);
   }
-  if (last_block_reduce<2>(v, partials, &sc->counter[4]) && threadIdx.x == 0) {
-    sc->rz = v[0];
-    sc->rr = v[1];
-    sc->rr_true = v[1];
-    sc->beta = 0.0;
-    sc->converged = 0;
+  store_partials<2>(v, partials);
+}
+
+enum FinalizeOp { kFinAlpha = 0, kFinBeta = 1, kFinReplace = 2, kFinResid = 3, kFinStart = 4 };
+
+// One workgroup: adds the partials of the previous kernel in a fixed order
+// and updates the CG scalars.
+__global__ void __launch_bounds__(1024)
+    k_finalize(int op, const double* __restrict__ partials, int nparts, CgScalars* __restrict__ sc) {
+  if ((op == kFinAlpha || op == kFinBeta) && sc->converged) return;
+  const int nv = op == kFinAlpha ? 1 : 2;
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    v[0] += partials[b * nv];
+    if (nv == 2) v[1] += partials[b * nv + 1];
+  }
+  block_sum<2>(v);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case kFinAlpha:
+      sc->pq = v[0];
+      sc->alpha = sc->rz / v[0];
+      if (!(v[0] > 0.0) || !isfinite(sc->alpha)) sc->converged = 2;
+      break;
+    case kFinBeta:
+      sc->beta = v[0] / sc->rz;
+      sc->rz = v[0];
+      sc->rr = v[1];
+      sc->aux[0] += 1.0;                         // iteration count
+      if (v[1] <= sc->aux[1]) sc->converged = 1;  // aux[1]: tolerance^2 on r.r
+      if (!isfinite(v[1])) sc->converged = 2;
+      break;
+    case kFinReplace:
+      sc->rr_true = v[0];
+      sc->rr = v[0];
+      sc->rz = v[1];
+      break;
+    case kFinResid:
+      sc->rr_true = v[0];
+      sc->ff = v[1];
+      break;
+    case kFinStart:
+      sc->rz = v[0];
+      sc->rr = v[1];
+      sc->rr_true = v[1];
+      sc->beta = 0.0;
+      sc->converged = 0;
+      break;
   }
 }
 
@@ -298,45 +333,85 @@ __global__ void k_zero(int64_t n, double* __restrict__ u) {
   if (i < n) u[i] = 0.0;
 }
 
+constexpr int kRowGridMax = 4096;
+constexpr int kVecGridMax = 2048;
+
+int row_grid(int64_t N) {
+  int g = div_up(N, int64_t(kRowWaves) * (kWave / kLPR));
+  return g < kRowGridMax ? g : kRowGridMax;
+}
+
 int vec_grid(int64_t n) {
   int g = div_up(n, kVecThreads);
-  return g < 2048 ? g : 2048;
+  return g < kVecGridMax ? g : kVecGridMax;
+}
+
+void finalize(Ctx& c, FinalizeOp op, int nparts) {
+  k_finalize<<<1, 1024, 0, c.stream>>>(int(op), c.partials.get(), nparts, c.sc.get());
+  SFEM_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------- host driver
 struct CgBuffers {
-  // P-typed vectors and matrix
   const void* val;
   const void* dinv;
-  void *b, *x, *r, *z, *p, *q;
+  void *b, *x, *r, *z, *p0, *p1, *q;  // p0/p1: ping-pong search directions
 };
 
+// With c.profile set, every SpMV launch is bracketed by a pair of events;
+// their elapsed times are summed once the chunk has finished.  `parity`
+// tracks which of p0/p1 holds the current direction.
 template <typename VT, typename P>
-void cg_iterations(Ctx& c, const CgBuffers& B, int iters) {
+void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   const int64_t N = c.N, n = c.n_dof();
   hipStream_t s = c.stream;
-  const int rg = div_up(N, kRowWaves);
+  const int rg = row_grid(N);
   const int vg = vec_grid(n);
+  if (c.profile)
+    while (int(c.prof_ev.size()) < 2 * iters) {
+      hipEvent_t e;
+      SFEM_HIP(hipEventCreate(&e));
+      c.prof_ev.push_back(e);
+    }
   for (int k = 0; k < iters; ++k) {
-    k_cg_p<P><<<div_up(n, kVecThreads), kVecThreads, 0, s>>>(n, (const P*)B.z, (P*)B.p,
-                                                              c.sc.get());
-    k_cg_spmv<VT, P><<<rg, kRowWaves * kWave, 0, s>>>(N, c.topo.bptr.get(), c.topo.bcol.get(),
-                                                       (const VT*)B.val, (const P*)B.p, (P*)B.q,
-                                                       c.sc.get(), c.partials.get());
-    k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, (const P*)B.p,
-                                              (const P*)B.q, (const P*)B.dinv, c.sc.get(),
-                                              c.partials.get());
+    P* p_old = (P*)(parity ? B.p1 : B.p0);
+    P* p_new = (P*)(parity ? B.p0 : B.p1);
+    if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k], s));
+    k_cg_spmv<VT, P, kLPR><<<rg, kRowWaves * kWave, 0, s>>>(
+        N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.z, p_old, p_new,
+        (P*)B.q, c.sc.get(), c.partials.get());
+    if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k + 1], s));
+    finalize(c, kFinAlpha, rg);
+    k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p_new, (const P*)B.q,
+                                              (const P*)B.dinv, c.sc.get(), c.partials.get());
+    finalize(c, kFinBeta, vg);
+    parity ^= 1;
   }
   SFEM_HIP(hipGetLastError());
 }
 
+// Adds the SpMV launches of the last chunk that did work (a launch that
+// returned at once because the solve had converged is not counted).
+void collect_profile(Ctx& c, int iters, int done_before, int done_after) {
+  if (!c.profile) return;
+  SFEM_HIP(hipStreamSynchronize(c.stream));
+  const int worked = std::min(iters, done_after - done_before);
+  for (int k = 0; k < worked; ++k) {
+    float ms = 0;
+    SFEM_HIP(hipEventElapsedTime(&ms, c.prof_ev[2 * k], c.prof_ev[2 * k + 1]));
+    c.prof_ms += ms;
+    c.prof_n += 1;
+  }
+}
+
 template <typename VT, typename P>
 void cg_replace(Ctx& c, const CgBuffers& B) {
-  const int64_t N = c.N;
-  k_cg_replace<VT, P><<<div_up(N, kRowWaves), kRowWaves * kWave, 0, c.stream>>>(
-      N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.b, (const P*)B.x,
-      (P*)B.r, (P*)B.z, (const P*)B.dinv, c.sc.get(), c.partials.get());
+  const int rg = row_grid(c.N);
+  k_cg_replace<VT, P, kLPR><<<rg, kRowWaves * kWave, 0, c.stream>>>(
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.b, (const P*)B.x,
+      (P*)B.r, (P*)B.z, (const P*)B.dinv, c.partials.get());
   SFEM_HIP(hipGetLastError());
+  finalize(c, kFinReplace, rg);
 }
 
 void read_scalars(Ctx& c) {
@@ -359,8 +434,8 @@ __global__ void k_cg_clear(CgScalars* sc) {
 
 // One PCG solve of A x = b from x = 0, stopping when the true residual (the
 // replacement residual, computed in the solve's own precision) satisfies
-// ||r|| <= tol_abs, or after max_iter iterations.  b is FP64 (scaled into P).
-// Returns the iterations done and whether the tolerance was met.
+// ||r|| <= tol_abs, after max_iter iterations, or on stagnation near the
+// tolerance.  b is FP64 (scaled into P).  Returns the iterations done.
 template <typename VT, typename P>
 int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double tol_abs,
         int max_iter, int check_every, bool& met, bool& breakdown) {
@@ -369,30 +444,36 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
   // B.b is the P-typed right-hand side the replacement uses; when it is b64
   // itself (FP64 solve) there is nothing to convert
   P* bconv = (static_cast<const void*>(B.b) == static_cast<const void*>(b64)) ? nullptr : (P*)B.b;
-  k_cg_start<P><<<vec_grid(n), kVecThreads, 0, s>>>(
-      n, b64, inv_scale, bconv, (P*)B.x, (P*)B.r, (P*)B.z, (P*)B.p, (const P*)B.dinv,
-      c.sc.get(), c.partials.get());
+  const int vg = vec_grid(n);
+  k_cg_start<P><<<vg, kVecThreads, 0, s>>>(n, b64, inv_scale, bconv, (P*)B.x, (P*)B.r, (P*)B.z,
+                                           (P*)B.p0, (P*)B.p1, (const P*)B.dinv,
+                                           c.partials.get());
   SFEM_HIP(hipGetLastError());
+  finalize(c, kFinStart, vg);
   const double tol2 = tol_abs * tol_abs;
   k_cg_arm<<<1, 64, 0, s>>>(c.sc.get(), tol2);
   SFEM_HIP(hipGetLastError());
   read_scalars(c);
   met = c.sc_host->rr <= tol2;
   breakdown = false;
-  int done = 0;
+  int done = 0, parity = 0;
   double best = c.sc_host->rr;
-  int stale = 0;  // checks without a new best true residual
+  int stale = 0;  // checks without a new best, counted once near the tolerance
   while (!met && done < max_iter && stale < 40) {
     const int chunk = std::min(check_every, max_iter - done);
-    cg_iterations<VT, P>(c, B, chunk);
+    cg_iterations<VT, P>(c, B, chunk, parity);
     cg_replace<VT, P>(c, B);
     read_scalars(c);
+    const int before = done;
     done = int(c.sc_host->aux[0]);
+    // iterations skipped on the device after a candidate stop did not move p
+    parity = done & 1;
+    collect_profile(c, chunk, before, done);
     met = c.sc_host->rr_true <= tol2;
     if (c.sc_host->rr_true < best) {
       best = c.sc_host->rr_true;
       stale = 0;
-    } else {
+    } else if (best <= 1e4 * tol2) {
       ++stale;
     }
     if (c.sc_host->converged == 2) {
@@ -403,6 +484,7 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
       k_cg_clear<<<1, 64, 0, s>>>(c.sc.get());
       SFEM_HIP(hipGetLastError());
     }
+    if (done == before && !met) break;  // no progress possible
   }
   return done;
 }
@@ -410,23 +492,24 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
 }  // namespace
 
 void spmv_f64(Ctx& c, const double* val, const double* x, double* y, hipStream_t s) {
-  k_spmv<double, double><<<div_up(c.N, kRowWaves), kRowWaves * kWave, 0, s>>>(
+  k_spmv<double, double, kLPR><<<row_grid(c.N), kRowWaves * kWave, 0, s>>>(
       c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y);
   SFEM_HIP(hipGetLastError());
 }
 
 void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s) {
-  k_spmv<float, float><<<div_up(c.N, kRowWaves), kRowWaves * kWave, 0, s>>>(
+  k_spmv<float, float, kLPR><<<row_grid(c.N), kRowWaves * kWave, 0, s>>>(
       c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y);
   SFEM_HIP(hipGetLastError());
 }
 
 double true_residual(Ctx& c, const double* u) {
-  const int64_t N = c.N;
-  k_resid64<<<div_up(N, kRowWaves), kRowWaves * kWave, 0, c.stream>>>(
-      N, c.topo.bptr.get(), c.topo.bcol.get(), c.val.get(), c.f_bc.get(), u, c.w.get(),
-      c.sc.get(), c.partials.get());
+  const int rg = row_grid(c.N);
+  k_resid64<kLPR><<<rg, kRowWaves * kWave, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
+                                                    c.val.get(), c.f_bc.get(), u, c.w.get(),
+                                                    c.partials.get());
   SFEM_HIP(hipGetLastError());
+  finalize(c, kFinResid, rg);
   read_scalars(c);
   const double ff = c.sc_host->ff;
   return ff > 0 ? std::sqrt(c.sc_host->rr_true / ff) : std::sqrt(c.sc_host->rr_true);
@@ -438,6 +521,7 @@ static void ensure_work(Ctx& c, bool f32) {
   c.r.reserve(n);
   c.z.reserve(n);
   c.p.reserve(n);
+  c.p2.reserve(n);
   c.q.reserve(n);
   c.w.reserve(n);
   if (f32) {
@@ -445,10 +529,11 @@ static void ensure_work(Ctx& c, bool f32) {
     c.r32.reserve(n);
     c.z32.reserve(n);
     c.p32.reserve(n);
+    c.p32b.reserve(n);
     c.q32.reserve(n);
+    c.b32.reserve(n);
   }
-  const int64_t nparts = std::max<int64_t>(div_up(c.N, kRowWaves), vec_grid(n)) * 2 + 16;
-  c.partials.reserve(nparts);
+  c.partials.reserve(2 * std::max(kRowGridMax, kVecGridMax) + 16);
 }
 
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
@@ -457,6 +542,9 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   ensure_work(c, f32);
   const int check_every = o.check_every > 0 ? o.check_every : 50;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 100000;
+  c.profile = o.profile != 0;
+  c.prof_ms = 0;
+  c.prof_n = 0;
   SFEM_HIP(hipEventRecord(c.ev0, c.stream));
 
   // ||f||: the residual of u = 0
@@ -465,21 +553,12 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   (void)true_residual(c, c.x.get());
   const double fnorm = std::sqrt(c.sc_host->ff);
   info = sfem_solve_info{};
+  int status = SFEM_OK;
   if (fnorm == 0.0) {
     info.converged = 1;
-    info.outer_steps = 0;
-    SFEM_HIP(hipEventRecord(c.ev1, c.stream));
-    SFEM_HIP(hipEventSynchronize(c.ev1));
-    float ms = 0;
-    SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-    info.ms_solve = ms;
-    return SFEM_OK;
-  }
-
-  int status = SFEM_OK;
-  if (!f32) {
+  } else if (!f32) {
     CgBuffers B{c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(), c.z.get(),
-                c.p.get(), c.q.get()};
+                c.p.get(), c.p2.get(), c.q.get()};
     bool met = false, brk = false;
     info.iters = pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
                                      check_every, met, brk);
@@ -493,29 +572,27 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
     const int max_outer = o.max_outer > 0 ? o.max_outer : 30;
     double* u = c.x.get();
     k_zero<<<div_up(n, 256), 256, 0, c.stream>>>(n, u);
-    CgBuffers B{c.val32.get(), c.dinv32.get(), c.q32.get(), nullptr, c.r32.get(), c.z32.get(),
-                c.p32.get(), nullptr};
-    // inner vectors: x32 is the correction d, q reused as float storage
-    B.x = c.x32.get();
-    float* qf = reinterpret_cast<float*>(c.q.get());
-    B.q = qf;
+    SFEM_HIP(hipGetLastError());
+    // inner solve K32 d = r / scale in FP32; d accumulates in x32
+    CgBuffers B{c.val32.get(), c.dinv32.get(), c.b32.get(), c.x32.get(), c.r32.get(),
+                c.z32.get(), c.p32.get(), c.p32b.get(), c.q32.get()};
     double relres = 1.0;
     int iters = 0, outer = 0;
     double* r64 = c.w.get();
+    const int rg = row_grid(c.N);
     while (outer < max_outer && iters < max_iter) {
-      // FP64 outer residual into r64
-      k_resid64<<<div_up(c.N, kRowWaves), kRowWaves * kWave, 0, c.stream>>>(
-          c.N, c.topo.bptr.get(), c.topo.bcol.get(), c.val.get(), c.f_bc.get(), u, r64,
-          c.sc.get(), c.partials.get());
+      k_resid64<kLPR><<<rg, kRowWaves * kWave, 0, c.stream>>>(c.N, c.topo.bptr.get(),
+                                                        c.topo.bcol.get(), c.val.get(),
+                                                        c.f_bc.get(), u, r64, c.partials.get());
       SFEM_HIP(hipGetLastError());
+      finalize(c, kFinResid, rg);
       read_scalars(c);
       const double rnorm = std::sqrt(c.sc_host->rr_true);
       relres = rnorm / fnorm;
       if (relres <= o.rtol) break;
-      // inner FP32 solve of K d = r64 / scale (scale keeps values O(1))
-      const double scale = rnorm / std::sqrt(double(n));
+      const double scale = rnorm / std::sqrt(double(n));  // keeps FP32 values O(1)
       bool met = false, brk = false;
-      const double tol = inner * std::sqrt(double(n));  // ||r/scale|| = sqrt(n)
+      const double tol = inner * std::sqrt(double(n));  // ||r / scale|| = sqrt(n)
       iters += pcg<float, float>(c, B, r64, 1.0 / scale, tol, max_iter - iters, check_every, met,
                                  brk);
       k_axpy_f32<<<div_up(n, 256), 256, 0, c.stream>>>(n, scale, c.x32.get(), u);
@@ -536,6 +613,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   float ms = 0;
   SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
   info.ms_solve = ms;
+  info.n_spmv = c.prof_n;
+  info.ms_spmv_avg = c.prof_n ? c.prof_ms / c.prof_n : 0.0;
   if (!info.converged && status == SFEM_OK) status = SFEM_ENOCONV;
   return status;
 }

@@ -227,6 +227,36 @@ __global__ void k_tiles(const int32_t* __restrict__ bptr, int64_t N, int C,
   if (I == N - 1) tile_first[n_tiles] = int(N);
 }
 
+// Slot map: for incidence entry e = (row node I, face f), the positions of
+// f's support nodes among row I's block columns, 6 bits each (slot q in
+// bits 6q..6q+5).  One wave per node row.
+__global__ void k_slot_map(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
+                           const int32_t* __restrict__ face, const int32_t* __restrict__ bptr,
+                           const int32_t* __restrict__ bcol, int64_t N,
+                           uint32_t* __restrict__ slots) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  if (I >= N) return;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb;
+  const int32_t* cols = bcol + rb;
+  for (int e = inc_ptr[I] + lane; e < inc_ptr[I + 1]; e += kWave) {
+    const int32_t* row = face + int64_t(inc[e]) * kFaceStride;
+    uint32_t code = 0;
+    for (int q = 0; q < 5; ++q) {
+      const int J = row[q];
+      if (J < 0) continue;
+      int lo = 0, hi = deg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cols[mid] < J) lo = mid + 1;
+        else hi = mid;
+      }
+      code |= uint32_t(lo) << (6 * q);
+    }
+    slots[e] = code;
+  }
+}
+
 // Degenerate tet check: |det| must exceed a tiny fraction of the product of
 // its edge lengths from vertex 0.
 __global__ void k_check_tets(const double* __restrict__ xyz, const int32_t* __restrict__ tets,
@@ -335,8 +365,9 @@ void build_topology(Ctx& c) {
   SFEM_HIP(hipGetLastError());
   tp.inc_ptr.reserve(N + 2);
   tp.inc.reserve(n5);
+  // the spare bucket N only collects padding and is never read: left unsorted
   bucket_sort_u32(ib, iv, n5, int(N + 1), tp.inc_ptr.get(), reinterpret_cast<uint32_t*>(tp.inc.get()),
-                  s);
+                  s, int(N));
   SFEM_HIP(hipFreeAsync(ib, s));
   SFEM_HIP(hipFreeAsync(iv, s));
   tp.n_inc = read_scalar(tp.inc_ptr.get() + N, s);
@@ -370,9 +401,12 @@ void build_topology(Ctx& c) {
   int isolated = read_scalar(md + 1, s);
   SFEM_HIP(hipFreeAsync(md, s));
   SFEM_REQUIRE(!isolated, SFEM_EMESH, "a node belongs to no tetrahedron");
-  SFEM_REQUIRE(2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,
-               "a node has too many neighbours for the assembly tile (" +
-                   std::to_string(tp.maxdeg) + ")");
+  SFEM_REQUIRE(tp.maxdeg <= kMaxDeg && 2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,
+               "a node has more than 64 neighbours (" + std::to_string(tp.maxdeg) + ")");
+  tp.slot.reserve(tp.n_inc);
+  k_slot_map<<<div_up(N * kWave, B), B, 0, s>>>(tp.inc_ptr.get(), tp.inc.get(), tp.face.get(),
+                                                tp.bptr.get(), tp.bcol.get(), N, tp.slot.get());
+  SFEM_HIP(hipGetLastError());
   const int C = kTileBlocks - tp.maxdeg;
   int last = read_scalar(tp.bptr.get() + (N - 1), s);
   tp.n_tiles = last / C + 1;

@@ -30,7 +30,8 @@ EXPORTS = [
     "sfem_set_material", "sfem_set_material_per_tet", "sfem_set_dirichlet",
     "sfem_set_bc_penalty", "sfem_set_nodal_load", "sfem_add_traction", "sfem_assemble",
     "sfem_get_sizes", "sfem_get_faces", "sfem_get_csr", "sfem_get_rhs", "sfem_spmv",
-    "sfem_solve", "sfem_get_timings",
+    "sfem_solve", "sfem_get_timings", "sfem_timer_start", "sfem_timer_stop",
+    "sfem_synchronize",
 ]
 
 
@@ -43,12 +44,13 @@ class SfemError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("precond", C.c_int), ("mode", C.c_int), ("rtol", C.c_double),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int)]
+                ("max_outer", C.c_int), ("profile", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer_steps", C.c_int), ("fell_back", C.c_int),
-                ("converged", C.c_int), ("true_relres", C.c_double), ("ms_solve", C.c_double)]
+                ("converged", C.c_int), ("true_relres", C.c_double), ("ms_solve", C.c_double),
+                ("ms_spmv_avg", C.c_double), ("n_spmv", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +87,9 @@ def lib() -> C.CDLL:
             "sfem_spmv": (i32, [vp, vp, vp, i32]),
             "sfem_solve": (i32, [vp, C.POINTER(SolveOpts), vp, i32, C.POINTER(SolveInfo)]),
             "sfem_get_timings": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl)]),
+            "sfem_timer_start": (i32, [vp]),
+            "sfem_timer_stop": (i32, [vp, C.POINTER(dbl)]),
+            "sfem_synchronize": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -248,8 +253,10 @@ class Context:
 
     def solve(self, rtol: float = 1e-8, mode: int = MODE_F64, precond: int = PRECOND_JACOBI,
               max_iter: int = 0, check_every: int = 0, inner_rtol: float = 0.0,
-              max_outer: int = 0, out=None, raise_on_noconv: bool = False):
-        opts = SolveOpts(precond, mode, rtol, max_iter, check_every, inner_rtol, max_outer)
+              max_outer: int = 0, out=None, raise_on_noconv: bool = False,
+              profile: bool = False):
+        opts = SolveOpts(precond, mode, rtol, max_iter, check_every, inner_rtol, max_outer,
+                         int(profile))
         info = SolveInfo()
         if out is None:
             out = np.empty(self.sizes().n_rows, dtype=np.float64)
@@ -258,6 +265,17 @@ class Context:
         if st != 0 and (st != -5 or raise_on_noconv):
             self._check(st)
         return out, info.as_dict()
+
+    def timer_start(self):
+        self._check(self._L.sfem_timer_start(self._h))
+
+    def timer_stop(self) -> float:
+        ms = C.c_double()
+        self._check(self._L.sfem_timer_stop(self._h, C.byref(ms)))
+        return ms.value
+
+    def synchronize(self):
+        self._check(self._L.sfem_synchronize(self._h))
 
     def timings(self):
         a, b = C.c_double(), C.c_double()

@@ -111,6 +111,20 @@ def cpu_baseline(sample_faces: int):
     }
 
 
+def copy_calibration():
+    """A plain device-to-device copy of 2^27 float64 (1 GiB read + 1 GiB
+    written) five times: what FETCH_SIZE / WRITE_SIZE read for known bytes.
+    Runs in its own process (torch only here; the library is not loaded)."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                      "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,7 +133,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=300000)
     ap.add_argument("--skip-solve", action="store_true", help="assembly only (profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               f"design is described, not built.", flush=True)
@@ -144,6 +163,10 @@ def main():
     log(f"[bench] topology {ms_topo:.1f} ms: faces {s.n_faces} ({s.n_exterior} ext), "
         f"nnz {s.nnz}, blocks {s.n_blocks}")
 
+    ctx.assemble(f32_copy=False)
+    tuned = ctx.autotune(reps=10)
+    log(f"[bench] autotuned row schedule (variant, grid cap) {tuned['f64'][0]}: "
+        f"{tuned['f64'][1]:.1f} us per SpMV")
     u = np.empty(s.n_rows)
 
     def step(profile=False):
@@ -196,6 +219,8 @@ def main():
             "tets": m.n_tets, "nodes": m.n_nodes, "faces": s.n_faces, "nnz": s.nnz,
             "solver": "Jacobi PCG FP64, x0=0, true relres <= 1e-8",
         },
+        "row_schedule": {"variant": tuned["f64"][0][0], "grid_cap": tuned["f64"][0][1],
+                         "autotuned_spmv_us": tuned["f64"][1]},
         "assembly_ms": asm_med,
         "topology_ms": ms_topo,
     }

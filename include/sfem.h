@@ -190,6 +190,22 @@ int sfem_solve(sfem_ctx* ctx, const sfem_solve_opts* opts, double* u, int ptr_ki
  * most recent numeric assembly (HIP events on the context stream). */
 int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
 
+/* Row-kernel schedules (SpMV, residual and CG product kernels): `variant`
+ * in [0, 8) picks the lanes per node row {8,16,32,64} (variant % 4) and one
+ * or two rows per lane group per step (variant / 4); `grid_cap` caps the
+ * workgroups launched.  precision: SFEM_ASM_F64 or SFEM_ASM_F32_COPY (the
+ * schedule of the FP32 matrix).  All schedules compute the same products up
+ * to floating-point summation order. */
+int sfem_set_schedule(sfem_ctx* ctx, int precision, int variant, int grid_cap);
+int sfem_get_schedule(sfem_ctx* ctx, int precision, int* variant, int* grid_cap);
+
+/* Autotuner: times every schedule (variant x grid cap in {1024, 2048, 4096,
+ * 8192}) on the context's assembled matrix, `reps` launches each (0: 10),
+ * with HIP events, and keeps the fastest for FP64 and, if an FP32 copy
+ * exists, for FP32.  Returns the best microseconds per SpMV (pointers may
+ * be NULL).  Needs sfem_assemble. */
+int sfem_autotune(sfem_ctx* ctx, int reps, double* best_us_f64, double* best_us_f32);
+
 /* Wall-clock device timer on the context stream: start records an event,
  * stop records a second one, waits for it and returns the elapsed ms. */
 int sfem_timer_start(sfem_ctx* ctx);

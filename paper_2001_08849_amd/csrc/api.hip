@@ -471,6 +471,35 @@ int sfem_get_timings(sfem_ctx* h, double* ms_topology, double* ms_assemble) {
   });
 }
 
+int sfem_set_schedule(sfem_ctx* h, int precision, int variant, int grid_cap) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(variant >= 0 && variant < sfem::kNumSched && grid_cap >= 8, SFEM_EINVAL,
+                 "bad schedule");
+    const sfem::RowSched rs{variant, grid_cap};
+    if (precision == SFEM_ASM_F32_COPY) c.sched32 = rs;
+    else c.sched64 = rs;
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_schedule(sfem_ctx* h, int precision, int* variant, int* grid_cap) {
+  return guarded(h, [&](Ctx& c) {
+    const sfem::RowSched rs = precision == SFEM_ASM_F32_COPY ? c.sched32 : c.sched64;
+    if (variant) *variant = rs.variant;
+    if (grid_cap) *grid_cap = rs.grid_cap;
+    return SFEM_OK;
+  });
+}
+
+int sfem_autotune(sfem_ctx* h, int reps, double* best_us_f64, double* best_us_f32) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    sfem::autotune_rows(c, reps > 0 ? reps : 10, best_us_f64, best_us_f32);
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
 int sfem_timer_start(sfem_ctx* h) {
   return guarded(h, [&](Ctx& c) {
     SFEM_HIP(hipEventRecord(c.tev0, c.stream));

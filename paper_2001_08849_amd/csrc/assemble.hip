@@ -13,7 +13,7 @@
 //
 // Scatter-assembly (Eq. 12 summed into CSR) is owner-computes by tile: a
 // workgroup owns a run of consecutive node rows and holds their CSR values in
-// LDS.  Its work items are the (row, face) incidences of those rows: each
+// LDS (as 64-bit fixed-point integers, see below).  Its work items are the (row, face) incidences of those rows: each
 // evaluates the face in registers and adds the row's blocks with LDS
 // atomics at column slots precomputed with the topology.  The finished rows
 // are streamed to HBM once, coalesced, with the essential BCs applied on the
@@ -121,6 +121,66 @@ __device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
   return lo;
 }
 
+// ---------------------------------------------------------- fixed-point unit
+// The tile accumulates in 64-bit integers (LDS integer atomics are about
+// twice as fast as FP64 ones on this chip, and integer sums do not depend
+// on the order of the additions, so the matrix is bit-reproducible).  A
+// contribution V_k [lam b_p b_q^T + mu b_q b_p^T + mu (b_p.b_q) I] is at most
+// (lam + 2 mu) V_k |b_p| |b_q| in magnitude; b_p is a convex combination of
+// tet gradients and V_k <= max V_e / 2, so every partial sum of the <= C
+// contributions an entry receives is below
+//   C * max(lam + 2 mu) * max V_e / 2 * max |grad N|^2  =: 2^62 u.
+// Rounding each contribution to a multiple of u then costs at most C u / 2
+// per entry, about 1e-15 of that bound.
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) {
+  atomicMax(p, (unsigned long long)__double_as_longlong(v));  // v >= 0: bits order as values
+}
+
+__global__ void k_fix_bound(const double* __restrict__ xyz, const int32_t* __restrict__ tets,
+                            int64_t T, double lam0, double mu0, const double* __restrict__ lam_t,
+                            const double* __restrict__ mu_t,
+                            unsigned long long* __restrict__ maxes) {
+  double mF = 0, mV = 0, mG = 0;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < T;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int4 v = reinterpret_cast<const int4*>(tets)[t];
+    Vec3 g[4];
+    double vol;
+    tet_grads(load3(xyz, v.x), load3(xyz, v.y), load3(xyz, v.z), load3(xyz, v.w), g, vol);
+    double gg = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gg = fmax(gg, dot(g[a], g[a]));
+    const double F = lam_t ? lam_t[t] + 2.0 * mu_t[t] : lam0 + 2.0 * mu0;
+    mF = fmax(mF, F);
+    mV = fmax(mV, vol * gg);
+    mG = 1.0;
+  }
+  mF = wave_max(mF);
+  mV = wave_max(mV);
+  mG = wave_max(mG);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomic_max_pos(maxes + 0, mF);
+    atomic_max_pos(maxes + 1, mV);
+    atomic_max_pos(maxes + 2, mG);
+  }
+}
+
+// unit[0] = u, unit[1] = 1/u from the three maxima and C.
+__global__ void k_fix_unit(const unsigned long long* __restrict__ maxes, int C,
+                           double* __restrict__ unit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double F = __longlong_as_double((long long)maxes[0]);
+  const double VG = __longlong_as_double((long long)maxes[1]);
+  const double bound = double(C) * F * 0.5 * VG;
+  const double u = bound * 0x1p-62;
+  unit[0] = u;
+  unit[1] = 1.0 / u;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
 // Largest index i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
 __device__ __forceinline__ int upper_index(const int32_t* a, int n, int v) {
   int lo = 0, hi = n - 1;
@@ -143,9 +203,10 @@ __global__ void __launch_bounds__(kAsmThreads)
                const uint32_t* __restrict__ slot, const int32_t* __restrict__ bptr,
                const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
                double lam0, double mu0, const double* __restrict__ lam_t,
-               const double* __restrict__ mu_t, const uint8_t* __restrict__ fixed,
-               double penalty, double* __restrict__ val, float* __restrict__ val32) {
-  __shared__ double sval[kTileBlocks * 9];
+               const double* __restrict__ mu_t, const double* __restrict__ unit,
+               const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
+               float* __restrict__ val32) {
+  __shared__ unsigned long long sval[kTileBlocks * 9];  // fixed point, units of u
   __shared__ int32_t sptr[kTileBlocks + 1];  // block offsets of the tile's rows
   __shared__ int32_t sinc[kTileBlocks + 1];  // incidence offsets of the tile's rows
 
@@ -159,7 +220,8 @@ __global__ void __launch_bounds__(kAsmThreads)
   const int nblk = bptr[n1] - b0;
   const int e0 = inc_ptr[n0], e1 = inc_ptr[n1];
 
-  for (int i = tid; i < 9 * nblk; i += kAsmThreads) sval[i] = 0.0;
+  for (int i = tid; i < 9 * nblk; i += kAsmThreads) sval[i] = 0ull;
+  const double u = unit[0], inv_u = unit[1];
   for (int i = tid; i <= nn; i += kAsmThreads) {
     sptr[i] = bptr[n0 + i] - b0;
     sinc[i] = inc_ptr[n0 + i] - e0;
@@ -177,26 +239,26 @@ __global__ void __launch_bounds__(kAsmThreads)
     double Vk, lam, mu;
     const int n = face_geometry<HET>(face + int64_t(inc[e]) * kFaceStride, xyz, lam0, mu0, lam_t,
                                      mu_t, sup, b, Vk, lam, mu);
-    const double lV = lam * Vk, mV = mu * Vk;
+    const double lV = lam * Vk * inv_u, mV = mu * Vk * inv_u;  // in units of u
     Vec3 bp = b[0];
 #pragma unroll
     for (int p = 1; p < 5; ++p)
       if (sup[p] == I) bp = b[p];
     const double bpa[3] = {bp.x, bp.y, bp.z};
-    double* rowv = sval + 9 * rb;
+    unsigned long long* rowv = sval + 9 * rb;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       if (q >= n) continue;
       const int jj = int((code >> (6 * q)) & 63u);
       const double bqa[3] = {b[q].x, b[q].y, b[q].z};
       const double d = mV * (bpa[0] * bqa[0] + bpa[1] * bqa[1] + bpa[2] * bqa[2]);
-      double* dst = rowv + 3 * jj;
+      unsigned long long* dst = rowv + 3 * jj;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const double v = lV * bpa[a] * bqa[c] + mV * bpa[c] * bqa[a] + (a == c ? d : 0.0);
-          atomicAdd(dst + a * 3 * deg + c, v);
+          atomicAdd(dst + a * 3 * deg + c, (unsigned long long)__double2ll_rn(v));
         }
       }
     }
@@ -212,7 +274,7 @@ __global__ void __launch_bounds__(kAsmThreads)
     const float inv3d = 1.0f / float(three_deg);
     const int64_t gbase = 9 * (int64_t(b0) + rb);
     for (int k = lane; k < 9 * deg; k += kWave) {
-      double v = sval[9 * rb + k];
+      double v = double((long long)sval[9 * rb + k]) * u;
       if (fixed) {
         const int a = int((float(k) + 0.5f) * inv3d);
         const int r = k - a * three_deg;
@@ -376,17 +438,26 @@ __global__ void k_traction_gather(int64_t N, const int32_t* __restrict__ ptr,
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask) {
   const Topology& tp = c.topo;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
+  // fixed-point unit of this assembly (device side, no host round trip)
+  unsigned long long* maxes = reinterpret_cast<unsigned long long*>(c.fix.reserve(8));
+  double* unit = c.fix.get() + 4;
+  k_zero_u64<<<1, 64, 0, c.stream>>>(maxes, 3);
+  k_fix_bound<<<std::min<int64_t>(div_up(c.T, 256), 2048), 256, 0, c.stream>>>(
+      c.xyz.get(), c.tets.get(), c.T, c.lam0, c.mu0, c.per_tet ? c.lam_t.get() : nullptr,
+      c.per_tet ? c.mu_t.get() : nullptr, maxes);
+  k_fix_unit<<<1, 64, 0, c.stream>>>(maxes, tp.max_inc, unit);
+  SFEM_HIP(hipGetLastError());
   dim3 grid(tp.n_tiles), block(kAsmThreads);
   if (c.per_tet)
     k_assemble<true><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), fixed,
-        c.penalty, val_out, val32_out);
+        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), unit,
+        fixed, c.penalty, val_out, val32_out);
   else
     k_assemble<false><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, fixed, c.penalty,
-        val_out, val32_out);
+        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, unit, fixed,
+        c.penalty, val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

@@ -20,6 +20,7 @@ struct Topology {
   int64_t n_inc = 0;             // node-face incidences (sum of support sizes)
   int64_t nb = 0;                // 3x3 blocks of the pattern
   int maxdeg = 0;                // most blocks in one node row
+  int max_inc = 0;               // most incident faces of one node
   int n_tiles = 0;
   DBuf<int32_t> face;            // [nf][kFaceStride]
   DBuf<int32_t> inc_ptr;         // [N+2] (bucket N collects exterior padding)
@@ -29,6 +30,14 @@ struct Topology {
   DBuf<int32_t> bcol;            // [nb] block column (node) ids, ascending per row
   DBuf<int32_t> tile_first;      // [n_tiles+1] first node of each tile
   bool valid = false;
+};
+
+// Row-kernel schedule: variant index (lanes per row, rows per group step)
+// and a cap on the grid size.
+constexpr int kNumSched = 8;
+struct RowSched {
+  int variant;
+  int grid_cap;
 };
 
 struct CgScalars {
@@ -72,6 +81,7 @@ struct Ctx {
   DBuf<double> val;
   DBuf<float> val32;
   DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
+  DBuf<double> fix;              // assembly fixed-point maxima [0..3) and unit [4..6)
   DBuf<float> dinv32;
 
   // solver work vectors
@@ -80,6 +90,10 @@ struct Ctx {
   DBuf<double> partials;
   DBuf<CgScalars> sc;
   CgScalars* sc_host = nullptr;  // pinned mirror
+
+  // row-kernel schedules (FP64 and FP32 matrices), set by the autotuner
+  RowSched sched64{2, 4096};
+  RowSched sched32{2, 4096};
 
   // timings
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -109,5 +123,6 @@ void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s)
 // solve.hip
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info);
 double true_residual(Ctx& c, const double* u);
+void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32);
 
 }  // namespace sfem

@@ -8,7 +8,7 @@
 // node's block-column list (9 values share one entry), and the three row
 // sums are reduced with wavefront shuffles.
 //
-// PCG: x0 = 0; each iteration is three kernels
+// PCG: x0 = 0; each iteration is
 //   p = z + beta p;   q = K p with (p.q) -> alpha;   x, r, z updates with
 //   (r.z), (r.r) -> beta and a device-side convergence flag.
 // Dot products are FP64 partial sums per workgroup; the last workgroup to
@@ -22,7 +22,6 @@ namespace sfem {
 namespace {
 
 constexpr int kRowWaves = 4;               // waves per row-kernel workgroup
-constexpr int kLPR = 32;                   // lanes per node row in the row kernels
 constexpr int kVecThreads = 256;
 
 // The three sums of node row I, computed by a group of LPR lanes (a
@@ -35,6 +34,71 @@ __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// Two rows per group at a time, column loop unrolled by kUnroll: all block
+// column loads, then all x gathers and value loads are issued before any
+// result is used, so each lane keeps many independent loads in flight.
+constexpr int kUnroll = 3;
+
+template <typename VT, int LPR, class XF>
+__device__ __forceinline__ void row3x2(const int (&I)[2], const bool (&valid)[2], int sub,
+                                       const int32_t* __restrict__ bptr,
+                                       const int32_t* __restrict__ bcol,
+                                       const VT* __restrict__ val, const XF& x, double (&y)[2][3]) {
+  using AT = typename std::conditional<sizeof(VT) == 8, double, float>::type;
+  int rb[2], td[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    int b = 0, e = 0;
+    if (valid[r]) {
+      b = bptr[I[r]];
+      e = bptr[I[r] + 1];
+    }
+    rb[r] = b;
+    td[r] = 3 * (e - b);
+  }
+  AT acc[2][3];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) acc[r][0] = acc[r][1] = acc[r][2] = AT(0);
+  const int tdmax = td[0] > td[1] ? td[0] : td[1];
+  for (int c0 = 0; c0 < tdmax; c0 += kUnroll * LPR) {
+    int col[2][kUnroll];
+    bool on[2][kUnroll];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int c = c0 + u * LPR + sub;
+        on[r][u] = c < td[r];
+        const int jj = c / 3;
+        col[r][u] = on[r][u] ? 3 * bcol[rb[r] + jj] + (c - 3 * jj) : 0;
+      }
+    AT xv[2][kUnroll], v0[2][kUnroll], v1[2][kUnroll], v2[2][kUnroll];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int c = c0 + u * LPR + sub;
+        const VT* v = val + 9 * int64_t(rb[r]) + c;
+        xv[r][u] = on[r][u] ? AT(x(int64_t(col[r][u]))) : AT(0);
+        v0[r][u] = on[r][u] ? AT(v[0]) : AT(0);
+        v1[r][u] = on[r][u] ? AT(v[td[r]]) : AT(0);
+        v2[r][u] = on[r][u] ? AT(v[2 * td[r]]) : AT(0);
+      }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        acc[r][0] += v0[r][u] * xv[r][u];
+        acc[r][1] += v1[r][u] * xv[r][u];
+        acc[r][2] += v2[r][u] * xv[r][u];
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[r][a] = group_sum<LPR>(double(acc[r][a]));
 }
 
 template <typename VT, int LPR, class XF>
@@ -71,27 +135,79 @@ struct PlainX {
   __device__ __forceinline__ T operator()(int64_t i) const { return p[i]; }
 };
 
-// x-operand of the CG product: p_new = z + beta * p_old, formed on the fly.
-template <typename P>
-struct PNewX {
-  const P* __restrict__ z;
-  const P* __restrict__ p;
-  P beta;
-  __device__ __forceinline__ P operator()(int64_t i) const { return z[i] + beta * p[i]; }
-};
+// Row loop shared by the row kernels.  Workgroups are dealt round-robin to
+// the 8 XCDs (block b runs on XCD b mod 8), so XCD x is given the x-th
+// contiguous eighth of the node rows and its groups of LPR lanes sweep that
+// range grid-stride: each XCD's L2 then holds the band of x entries its rows
+// gather (neighbour node ids are close), while the rows in flight at any
+// moment stay in one band per XCD.  body(I, valid, sub) runs in every lane
+// (invalid rows still take part in the group shuffles).
+constexpr int kXcds = 8;
 
-// Row loop shared by the row kernels: each wave serves 64/LPR rows at a time,
-// grid-stride over all node rows; body(I, valid, sub) runs in every lane.
 template <int LPR, class Body>
 __device__ __forceinline__ void for_rows(int64_t N, Body&& body) {
   constexpr int G = kWave / LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int g = lane / LPR, sub = lane % LPR;
-  const int64_t wave = int64_t(blockIdx.x) * kRowWaves + threadIdx.x / kWave;
-  const int64_t stride = int64_t(gridDim.x) * kRowWaves * G;
-  for (int64_t base = wave * G; base < N; base += stride) {
-    const int64_t I = base + g;
-    body(int(I < N ? I : 0), I < N, sub);
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t groups_per_xcd = int64_t(gridDim.x / kXcds) * kRowWaves * G;  // grid % 8 == 0
+  const int64_t lgroup = (int64_t(blockIdx.x / kXcds) * kRowWaves + threadIdx.x / kWave) * G + g;
+  const int64_t span = (N + kXcds - 1) / kXcds;
+  const int64_t lo = xcd * span;
+  const int64_t hi = lo + span < N ? lo + span : N;
+  const int64_t steps = (span + groups_per_xcd - 1) / groups_per_xcd;
+  for (int64_t k = 0; k < steps; ++k) {
+    const int64_t I = lo + lgroup + k * groups_per_xcd;
+    body(int(I < hi ? I : 0), I < hi, sub);
+  }
+}
+
+// As for_rows, two rows per group per step (rows k and k + half of the
+// group's sweep), handed to body2(I[2], valid[2], sub).
+template <int LPR, class Body2>
+__device__ __forceinline__ void for_rows2(int64_t N, Body2&& body2) {
+  constexpr int G = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / LPR, sub = lane % LPR;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t groups_per_xcd = int64_t(gridDim.x / kXcds) * kRowWaves * G;
+  const int64_t lgroup = (int64_t(blockIdx.x / kXcds) * kRowWaves + threadIdx.x / kWave) * G + g;
+  const int64_t span = (N + kXcds - 1) / kXcds;
+  const int64_t lo = xcd * span;
+  const int64_t hi = lo + span < N ? lo + span : N;
+  const int64_t steps = (span + groups_per_xcd - 1) / groups_per_xcd;
+  const int64_t half = (steps + 1) / 2;
+  for (int64_t k = 0; k < half; ++k) {
+    const int64_t I0 = lo + lgroup + k * groups_per_xcd;
+    const int64_t I1 = lo + lgroup + (k + half) * groups_per_xcd;
+    const bool v0 = I0 < hi, v1 = (k + half) < steps && I1 < hi;
+    const int I[2] = {int(v0 ? I0 : 0), int(v1 ? I1 : 0)};
+    const bool valid[2] = {v0, v1};
+    body2(I, valid, sub);
+  }
+}
+
+// Row schedule: LPR lanes per node row; PAIR: two rows per group per step
+// (more loads in flight, more registers).  epi(I, y) runs for each valid row
+// in the group's first lane.
+template <typename VT, int LPR, bool PAIR, class XF, class Epi>
+__device__ __forceinline__ void row_apply(int64_t N, const int32_t* __restrict__ bptr,
+                                          const int32_t* __restrict__ bcol,
+                                          const VT* __restrict__ val, const XF& xf, Epi&& epi) {
+  if constexpr (PAIR) {
+    for_rows2<LPR>(N, [&](const int (&I)[2], const bool (&valid)[2], int sub) {
+      double yy[2][3];
+      row3x2<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, yy);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (valid[r] && sub == 0) epi(I[r], yy[r]);
+    });
+  } else {
+    for_rows<LPR>(N, [&](int I, bool valid, int sub) {
+      double y[3];
+      row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+      if (valid && sub == 0) epi(I, y);
+    });
   }
 }
 
@@ -126,46 +242,46 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double* partials
     for (int i = 0; i < NV; ++i) partials[blockIdx.x * NV + i] = v[i];
 }
 
-template <typename VT, typename XT, int LPR>
+template <typename VT, typename XT, int LPR, bool PAIR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
            const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y) {
   const PlainX<XT> xf{x};
-  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
-    double y0, y1, y2;
-    row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y0, y1, y2);
-    if (valid && sub == 0) {
-      y[3 * int64_t(I) + 0] = XT(y0);
-      y[3 * int64_t(I) + 1] = XT(y1);
-      y[3 * int64_t(I) + 2] = XT(y2);
-    }
+  row_apply<VT, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&yy)[3]) {
+    y[3 * int64_t(I) + 0] = XT(yy[0]);
+    y[3 * int64_t(I) + 1] = XT(yy[1]);
+    y[3 * int64_t(I) + 2] = XT(yy[2]);
   });
 }
 
 // ---------------------------------------------------------------- CG kernels
-// p_new = z + beta p_old (own rows written), q = K p_new, partial (p_new.q).
-template <typename VT, typename P, int LPR>
+// p = z + beta p (beta = 0 on the first iteration)
+template <typename P>
+__global__ void __launch_bounds__(kVecThreads)
+    k_cg_p(int64_t n, const P* __restrict__ z, P* __restrict__ p, const CgScalars* __restrict__ sc) {
+  if (sc->converged) return;
+  const P beta = P(sc->beta);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// q = K p, partial (p.q).
+template <typename VT, typename P, int LPR, bool PAIR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-              const VT* __restrict__ val, const P* __restrict__ z, const P* __restrict__ p_old,
-              P* __restrict__ p_new, P* __restrict__ q, const CgScalars* __restrict__ sc,
-              double* __restrict__ partials) {
+              const VT* __restrict__ val, const P* __restrict__ p, P* __restrict__ q,
+              const CgScalars* __restrict__ sc, double* __restrict__ partials) {
   if (sc->converged) return;
-  const PNewX<P> xf{z, p_old, P(sc->beta)};
+  const PlainX<P> xf{p};
   double v[1] = {0.0};
-  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
-    double y[3];
-    row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
-    if (valid && sub == 0) {
+  row_apply<VT, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * int64_t(I) + a;
-        const P pi = xf(i);
-        const P qi = P(y[a]);
-        p_new[i] = pi;
-        q[i] = qi;
-        v[0] += double(pi) * double(qi);
-      }
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = 3 * int64_t(I) + a;
+      const P qi = P(y[a]);
+      q[i] = qi;
+      v[0] += double(p[i]) * double(qi);
     }
   });
   store_partials<1>(v, partials);
@@ -195,7 +311,7 @@ __global__ void __launch_bounds__(kVecThreads)
 }
 
 // Residual replacement: r = b - K x, z = dinv r; partials (r.r), (r.z).
-template <typename VT, typename P, int LPR>
+template <typename VT, typename P, int LPR, bool PAIR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_replace(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                  const VT* __restrict__ val, const P* __restrict__ b, const P* __restrict__ x,
@@ -203,27 +319,23 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
                  double* __restrict__ partials) {
   const PlainX<P> xf{x};
   double v[2] = {0.0, 0.0};
-  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
-    double y[3];
-    row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
-    if (valid && sub == 0) {
+  row_apply<VT, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * int64_t(I) + a;
-        const P ri = P(double(b[i]) - y[a]);
-        const P zi = dinv[i] * ri;
-        r[i] = ri;
-        z[i] = zi;
-        v[0] += double(ri) * double(ri);
-        v[1] += double(ri) * double(zi);
-      }
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = 3 * int64_t(I) + a;
+      const P ri = P(double(b[i]) - y[a]);
+      const P zi = dinv[i] * ri;
+      r[i] = ri;
+      z[i] = zi;
+      v[0] += double(ri) * double(ri);
+      v[1] += double(ri) * double(zi);
     }
   });
   store_partials<2>(v, partials);
 }
 
 // FP64 residual of the outer problem: r = f - K u; partials ||r||^2, ||f||^2.
-template <int LPR>
+template <int LPR, bool PAIR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_resid64(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
               const double* __restrict__ val, const double* __restrict__ f,
@@ -231,18 +343,14 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
               double* __restrict__ partials) {
   const PlainX<double> xf{u};
   double v[2] = {0.0, 0.0};
-  for_rows<LPR>(N, [&](int I, bool valid, int sub) {
-    double y[3];
-    row3<double, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
-    if (valid && sub == 0) {
+  row_apply<double, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * int64_t(I) + a;
-        const double ri = f[i] - y[a];
-        if (r) r[i] = ri;
-        v[0] += ri * ri;
-        v[1] += f[i] * f[i];
-      }
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = 3 * int64_t(I) + a;
+      const double ri = f[i] - y[a];
+      if (r) r[i] = ri;
+      v[0] += ri * ri;
+      v[1] += f[i] * f[i];
     }
   });
   store_partials<2>(v, partials);
@@ -336,10 +444,35 @@ __global__ void k_zero(int64_t n, double* __restrict__ u) {
 constexpr int kRowGridMax = 4096;
 constexpr int kVecGridMax = 2048;
 
-int row_grid(int64_t N) {
-  int g = div_up(N, int64_t(kRowWaves) * (kWave / kLPR));
-  return g < kRowGridMax ? g : kRowGridMax;
+// Row-kernel schedules: lanes per row and one/two rows per group step.
+struct SchedShape {
+  int lpr;
+  bool pair;
+};
+constexpr SchedShape kSched[kNumSched] = {{8, false},  {16, false}, {32, false}, {64, false},
+                                          {8, true},   {16, true},  {32, true},  {64, true}};
+
+int row_grid(int64_t N, const RowSched& rs) {
+  const SchedShape sh = kSched[rs.variant];
+  const int64_t rows_per_block = int64_t(kRowWaves) * (kWave / sh.lpr) * (sh.pair ? 2 : 1);
+  int g = div_up(N, rows_per_block);
+  const int cap = std::min(rs.grid_cap, kRowGridMax);
+  g = g < cap ? g : cap;
+  return div_up(g, kXcds) * kXcds;  // for_rows needs a multiple of kXcds
 }
+
+// Launch KERNEL<prefix..., LPR, PAIR> for the schedule's variant.
+#define SFEM_SCHED_SWITCH(variant, LAUNCH) \
+  switch (variant) {                        \
+    case 0: LAUNCH(8, false); break;        \
+    case 1: LAUNCH(16, false); break;       \
+    case 2: LAUNCH(32, false); break;       \
+    case 3: LAUNCH(64, false); break;       \
+    case 4: LAUNCH(8, true); break;         \
+    case 5: LAUNCH(16, true); break;        \
+    case 6: LAUNCH(32, true); break;        \
+    default: LAUNCH(64, true); break;       \
+  }
 
 int vec_grid(int64_t n) {
   int g = div_up(n, kVecThreads);
@@ -355,17 +488,17 @@ void finalize(Ctx& c, FinalizeOp op, int nparts) {
 struct CgBuffers {
   const void* val;
   const void* dinv;
-  void *b, *x, *r, *z, *p0, *p1, *q;  // p0/p1: ping-pong search directions
+  void *b, *x, *r, *z, *p0, *p1, *q;  // p0: search direction (p1 unused)
 };
 
 // With c.profile set, every SpMV launch is bracketed by a pair of events;
-// their elapsed times are summed once the chunk has finished.  `parity`
-// tracks which of p0/p1 holds the current direction.
+// their elapsed times are summed once the chunk has finished.
 template <typename VT, typename P>
 void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   const int64_t N = c.N, n = c.n_dof();
   hipStream_t s = c.stream;
-  const int rg = row_grid(N);
+  const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
+  const int rg = row_grid(N, rs);
   const int vg = vec_grid(n);
   if (c.profile)
     while (int(c.prof_ev.size()) < 2 * iters) {
@@ -373,19 +506,22 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
       SFEM_HIP(hipEventCreate(&e));
       c.prof_ev.push_back(e);
     }
+  (void)parity;
+  P* p = (P*)B.p0;
   for (int k = 0; k < iters; ++k) {
-    P* p_old = (P*)(parity ? B.p1 : B.p0);
-    P* p_new = (P*)(parity ? B.p0 : B.p1);
+    k_cg_p<P><<<vg, kVecThreads, 0, s>>>(n, (const P*)B.z, p, c.sc.get());
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k], s));
-    k_cg_spmv<VT, P, kLPR><<<rg, kRowWaves * kWave, 0, s>>>(
-        N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.z, p_old, p_new,
-        (P*)B.q, c.sc.get(), c.partials.get());
+#define L_(LPR, PAIR)                                                                          \
+  k_cg_spmv<VT, P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(                                 \
+      N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, p, (P*)B.q, c.sc.get(),        \
+      c.partials.get())
+    SFEM_SCHED_SWITCH(rs.variant, L_)
+#undef L_
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k + 1], s));
     finalize(c, kFinAlpha, rg);
-    k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p_new, (const P*)B.q,
+    k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p, (const P*)B.q,
                                               (const P*)B.dinv, c.sc.get(), c.partials.get());
     finalize(c, kFinBeta, vg);
-    parity ^= 1;
   }
   SFEM_HIP(hipGetLastError());
 }
@@ -406,10 +542,14 @@ void collect_profile(Ctx& c, int iters, int done_before, int done_after) {
 
 template <typename VT, typename P>
 void cg_replace(Ctx& c, const CgBuffers& B) {
-  const int rg = row_grid(c.N);
-  k_cg_replace<VT, P, kLPR><<<rg, kRowWaves * kWave, 0, c.stream>>>(
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.b, (const P*)B.x,
-      (P*)B.r, (P*)B.z, (const P*)B.dinv, c.partials.get());
+  const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
+  const int rg = row_grid(c.N, rs);
+#define L_(LPR, PAIR)                                                                          \
+  k_cg_replace<VT, P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                     \
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.b, (const P*)B.x, \
+      (P*)B.r, (P*)B.z, (const P*)B.dinv, c.partials.get())
+  SFEM_SCHED_SWITCH(rs.variant, L_)
+#undef L_
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinReplace, rg);
 }
@@ -466,8 +606,6 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
     read_scalars(c);
     const int before = done;
     done = int(c.sc_host->aux[0]);
-    // iterations skipped on the device after a candidate stop did not move p
-    parity = done & 1;
     collect_profile(c, chunk, before, done);
     met = c.sc_host->rr_true <= tol2;
     if (c.sc_host->rr_true < best) {
@@ -491,25 +629,94 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
 
 }  // namespace
 
-void spmv_f64(Ctx& c, const double* val, const double* x, double* y, hipStream_t s) {
-  k_spmv<double, double, kLPR><<<row_grid(c.N), kRowWaves * kWave, 0, s>>>(
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y);
+void spmv_f64_sched(Ctx& c, const RowSched& rs, const double* val, const double* x, double* y,
+                    hipStream_t s) {
+  const int rg = row_grid(c.N, rs);
+#define L_(LPR, PAIR)                                                        \
+  k_spmv<double, double, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(        \
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
+  SFEM_SCHED_SWITCH(rs.variant, L_)
+#undef L_
   SFEM_HIP(hipGetLastError());
+}
+
+void spmv_f32_sched(Ctx& c, const RowSched& rs, const float* val, const float* x, float* y,
+                    hipStream_t s) {
+  const int rg = row_grid(c.N, rs);
+#define L_(LPR, PAIR)                                                      \
+  k_spmv<float, float, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(        \
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
+  SFEM_SCHED_SWITCH(rs.variant, L_)
+#undef L_
+  SFEM_HIP(hipGetLastError());
+}
+
+void spmv_f64(Ctx& c, const double* val, const double* x, double* y, hipStream_t s) {
+  spmv_f64_sched(c, c.sched64, val, x, y, s);
 }
 
 void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s) {
-  k_spmv<float, float, kLPR><<<row_grid(c.N), kRowWaves * kWave, 0, s>>>(
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y);
+  spmv_f32_sched(c, c.sched32, val, x, y, s);
+}
+
+// Times every row schedule (variant x grid cap) on this context's matrix
+// with HIP events and keeps the fastest for FP64 and, if present, FP32.
+void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
+  const int64_t n = c.n_dof();
+  c.x.reserve(n);
+  c.q.reserve(n);
+  c.x32.reserve(n);
+  c.q32.reserve(n);
+  k_zero<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.x.get());
   SFEM_HIP(hipGetLastError());
+  const int caps[] = {1024, 2048, 4096, 8192};
+  for (int prec = 0; prec < (c.have_f32 ? 2 : 1); ++prec) {
+    double best = 1e30;
+    RowSched pick = prec ? c.sched32 : c.sched64;
+    for (int v = 0; v < kNumSched; ++v)
+      for (int cap : caps) {
+        const RowSched rs{v, cap};
+        auto run = [&] {
+          if (prec == 0) spmv_f64_sched(c, rs, c.val.get(), c.x.get(), c.q.get(), c.stream);
+          else spmv_f32_sched(c, rs, c.val32.get(), c.x32.get(), c.q32.get(), c.stream);
+        };
+        run();  // warm
+        SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+        for (int r = 0; r < reps; ++r) run();
+        SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+        SFEM_HIP(hipEventSynchronize(c.ev1));
+        float ms = 0;
+        SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        const double us = 1e3 * ms / reps;
+        if (us < best) {
+          best = us;
+          pick = rs;
+        }
+      }
+    if (prec == 0) {
+      c.sched64 = pick;
+      if (best_us64) *best_us64 = best;
+    } else {
+      c.sched32 = pick;
+      if (best_us32) *best_us32 = best;
+    }
+  }
+}
+
+void resid64(Ctx& c, const double* u, double* r) {
+  const int rg = row_grid(c.N, c.sched64);
+#define L_(LPR, PAIR)                                                                 \
+  k_resid64<LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                       \
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), c.val.get(), c.f_bc.get(), u, r, \
+      c.partials.get())
+  SFEM_SCHED_SWITCH(c.sched64.variant, L_)
+#undef L_
+  SFEM_HIP(hipGetLastError());
+  finalize(c, kFinResid, rg);
 }
 
 double true_residual(Ctx& c, const double* u) {
-  const int rg = row_grid(c.N);
-  k_resid64<kLPR><<<rg, kRowWaves * kWave, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
-                                                    c.val.get(), c.f_bc.get(), u, c.w.get(),
-                                                    c.partials.get());
-  SFEM_HIP(hipGetLastError());
-  finalize(c, kFinResid, rg);
+  resid64(c, u, c.w.get());
   read_scalars(c);
   const double ff = c.sc_host->ff;
   return ff > 0 ? std::sqrt(c.sc_host->rr_true / ff) : std::sqrt(c.sc_host->rr_true);
@@ -579,13 +786,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
     double relres = 1.0;
     int iters = 0, outer = 0;
     double* r64 = c.w.get();
-    const int rg = row_grid(c.N);
     while (outer < max_outer && iters < max_iter) {
-      k_resid64<kLPR><<<rg, kRowWaves * kWave, 0, c.stream>>>(c.N, c.topo.bptr.get(),
-                                                        c.topo.bcol.get(), c.val.get(),
-                                                        c.f_bc.get(), u, r64, c.partials.get());
-      SFEM_HIP(hipGetLastError());
-      finalize(c, kFinResid, rg);
+      resid64(c, u, r64);
       read_scalars(c);
       const double rnorm = std::sqrt(c.sc_host->rr_true);
       relres = rnorm / fnorm;

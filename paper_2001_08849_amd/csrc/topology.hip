@@ -207,12 +207,15 @@ __global__ void __launch_bounds__(kPatWaves * kWave)
   }
 }
 
-// out[0] = largest node degree; out[1] = 1 if some node is in no tet.
-__global__ void k_maxdeg(const int32_t* __restrict__ bptr, int64_t N, int* __restrict__ out) {
+// out[0] = largest node degree; out[1] = 1 if some node is in no tet;
+// out[2] = most incident faces of one node.
+__global__ void k_maxdeg(const int32_t* __restrict__ bptr, const int32_t* __restrict__ inc_ptr,
+                         int64_t N, int* __restrict__ out) {
   int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (I >= N) return;
   int d = bptr[I + 1] - bptr[I];
   atomicMax(out, d);
+  atomicMax(out + 2, inc_ptr[I + 1] - inc_ptr[I]);
   if (d == 0) atomicOr(out + 1, 1);
 }
 
@@ -393,12 +396,13 @@ void build_topology(Ctx& c) {
 
   // 4. assembly tiles
   int* md = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&md, 2 * sizeof(int), s));
-  SFEM_HIP(hipMemsetAsync(md, 0, 2 * sizeof(int), s));
-  k_maxdeg<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), N, md);
+  SFEM_HIP(hipMallocAsync((void**)&md, 3 * sizeof(int), s));
+  SFEM_HIP(hipMemsetAsync(md, 0, 3 * sizeof(int), s));
+  k_maxdeg<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), tp.inc_ptr.get(), N, md);
   SFEM_HIP(hipGetLastError());
   tp.maxdeg = read_scalar(md, s);
   int isolated = read_scalar(md + 1, s);
+  tp.max_inc = read_scalar(md + 2, s);
   SFEM_HIP(hipFreeAsync(md, s));
   SFEM_REQUIRE(!isolated, SFEM_EMESH, "a node belongs to no tetrahedron");
   SFEM_REQUIRE(tp.maxdeg <= kMaxDeg && 2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,

@@ -31,7 +31,7 @@ EXPORTS = [
     "sfem_set_bc_penalty", "sfem_set_nodal_load", "sfem_add_traction", "sfem_assemble",
     "sfem_get_sizes", "sfem_get_faces", "sfem_get_csr", "sfem_get_rhs", "sfem_spmv",
     "sfem_solve", "sfem_get_timings", "sfem_timer_start", "sfem_timer_stop",
-    "sfem_synchronize",
+    "sfem_synchronize", "sfem_set_schedule", "sfem_get_schedule", "sfem_autotune",
 ]
 
 
@@ -90,6 +90,9 @@ def lib() -> C.CDLL:
             "sfem_timer_start": (i32, [vp]),
             "sfem_timer_stop": (i32, [vp, C.POINTER(dbl)]),
             "sfem_synchronize": (i32, [vp]),
+            "sfem_set_schedule": (i32, [vp, i32, i32, i32]),
+            "sfem_get_schedule": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
+            "sfem_autotune": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(dbl)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -273,6 +276,21 @@ class Context:
         ms = C.c_double()
         self._check(self._L.sfem_timer_stop(self._h, C.byref(ms)))
         return ms.value
+
+    def set_schedule(self, variant: int, grid_cap: int = 4096, f32: bool = False):
+        self._check(self._L.sfem_set_schedule(self._h, ASM_F32_COPY if f32 else ASM_F64,
+                                              int(variant), int(grid_cap)))
+
+    def schedule(self, f32: bool = False):
+        v, g = C.c_int(), C.c_int()
+        self._check(self._L.sfem_get_schedule(self._h, ASM_F32_COPY if f32 else ASM_F64,
+                                              C.byref(v), C.byref(g)))
+        return v.value, g.value
+
+    def autotune(self, reps: int = 10):
+        a, b = C.c_double(), C.c_double()
+        self._check(self._L.sfem_autotune(self._h, int(reps), C.byref(a), C.byref(b)))
+        return {"f64": (self.schedule(False), a.value), "f32": (self.schedule(True), b.value)}
 
     def synchronize(self):
         self._check(self._L.sfem_synchronize(self._h))

@@ -48,21 +48,94 @@ def algorithmic_bytes(N, T, nf, nnz, nb, f32_copy=False, per_tet=False):
     return asm, spmv64, spmv32
 
 
+KERNEL_SOURCES = {
+    "cg_spmv_f64_c2": ("k_cg_spmv<double, double", "paper_2001_08849_amd/csrc/solve.hip"),
+    "assemble_c2": ("k_assemble<false>", "paper_2001_08849_amd/csrc/assemble.hip"),
+}
+
+
+def _sha(path):
+    import hashlib
+    return hashlib.sha256(open(os.path.join(ROOT, path), "rb").read()).hexdigest()
+
+
 def read_traffic(kernel_tag):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if
-    one exists for this kernel and its source has not changed since."""
-    path = os.path.join(PROFILE_DIR, f"{kernel_tag}_traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    profiles/traffic_<tag>.txt, if its kernel source is unchanged since."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{kernel_tag}.txt")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
-        import hashlib
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        text = open(path).read()
+        rec = json.loads(text[text.index("{"):text.rindex("}") + 1])
+        if _sha(rec["source"]) != rec["source_sha256"]:
             return None
         return float(rec["bytes_per_launch"])
     except Exception:
         return None
+
+
+def _counter_means(csv_path):
+    """Mean counter value per kernel name over its dispatches."""
+    import collections
+    import csv
+    per = collections.defaultdict(float)
+    name = {}
+    for r in csv.DictReader(open(csv_path)):
+        per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        name[r["Dispatch_Id"]] = r["Kernel_Name"]
+    acc = collections.defaultdict(list)
+    for d, v in per.items():
+        acc[name[d]].append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def summarize_profiles(prof_dir, command_note):
+    """Writes profiles/traffic_<tag>.txt from four rocprofv3 --pmc CSVs under
+    prof_dir (fetch/, write/ for the benchmark; cfetch/, cwrite/ for the
+    calibration copy) and profiles/kernels_c2.md from a --kernel-trace
+    --stats CSV (ktrace/)."""
+    import glob
+    f = lambda sub: glob.glob(os.path.join(prof_dir, sub, "*counter_collection.csv"))[0]
+    fetch, write = _counter_means(f("fetch")), _counter_means(f("write"))
+    cfetch, cwrite = _counter_means(f("cfetch")), _counter_means(f("cwrite"))
+    copy = [k for k in cfetch if "copyBuffer" in k][0]
+    true_bytes = float(1 << 30)
+    kf = true_bytes / (cfetch[copy][0] * 1024.0)   # FETCH_SIZE is in KiB
+    kw = true_bytes / (cwrite[copy][0] * 1024.0)
+    for tag, (pattern, src) in KERNEL_SOURCES.items():
+        kn = [k for k in fetch if pattern in k]
+        if not kn:
+            continue
+        fr, n = fetch[kn[0]]
+        wr, _ = write[[k for k in write if pattern in k][0]]
+        rec = {
+            "kernel": kn[0].split("(")[0], "dispatches": n,
+            "fetch_kib_raw": fr, "write_kib_raw": wr,
+            "copy_calibration": {"fetch_factor": kf, "write_factor": kw,
+                                 "copy": "1 GiB device-to-device (bench.py --copy-calibration)"},
+            "bytes_read": fr * 1024 * kf, "bytes_written": wr * 1024 * kw,
+            "bytes_per_launch": fr * 1024 * kf + wr * 1024 * kw,
+            "source": src, "source_sha256": _sha(src),
+        }
+        with open(os.path.join(PROFILE_DIR, f"traffic_{tag}.txt"), "w") as fh:
+            fh.write(f"# HBM traffic per launch of {rec['kernel']} on the 1.92M-tet cantilever\n")
+            fh.write(f"# commands: {command_note}\n")
+            fh.write("# FETCH_SIZE / WRITE_SIZE (KiB per dispatch, mean) scaled by what the same\n"
+                     "# counters read for a plain 1 GiB copy; stale once the source hash changes.\n")
+            fh.write(json.dumps(rec, indent=1) + "\n")
+    stats = glob.glob(os.path.join(prof_dir, "ktrace", "*kernel_stats.csv"))
+    if stats:
+        import csv
+        rows = list(csv.DictReader(open(stats[0])))
+        with open(os.path.join(PROFILE_DIR, "kernels_c2.md"), "w") as fh:
+            fh.write("# rocprofv3 kernel statistics, 1.92M-tet cantilever benchmark\n\n")
+            fh.write(f"Command: `{command_note}`\n\n")
+            fh.write("| kernel | calls | total ms | average us | % |\n|---|---|---|---|---|\n")
+            for r in rows[:25]:
+                nm = r["Name"].split("(")[0].replace("sfem::(anonymous namespace)::", "")
+                fh.write(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                         f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
 
 
 CPU_SNIPPET = r"""
@@ -133,11 +206,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=300000)
     ap.add_argument("--skip-solve", action="store_true", help="assembly only (profiling)")
+    ap.add_argument("--f32-ir", action="store_true", help="also time the FP32+FP64-IR solve")
+    ap.add_argument("--inner-rtol", type=float, default=1e-2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 CSVs under DIR")
+    ap.add_argument("--profile-command", default="", help="command line recorded in summaries")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.profile_command)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -163,18 +244,29 @@ def main():
     log(f"[bench] topology {ms_topo:.1f} ms: faces {s.n_faces} ({s.n_exterior} ext), "
         f"nnz {s.nnz}, blocks {s.n_blocks}")
 
-    ctx.assemble(f32_copy=False)
+    ctx.assemble(f32_copy=args.f32_ir)
     tuned = ctx.autotune(reps=10)
     log(f"[bench] autotuned row schedule (variant, grid cap) {tuned['f64'][0]}: "
         f"{tuned['f64'][1]:.1f} us per SpMV")
     u = np.empty(s.n_rows)
 
     def step(profile=False):
-        ctx.assemble(f32_copy=False)
+        ctx.assemble(f32_copy=args.f32_ir)
         ms_asm = ctx.timings()["ms_assemble"]
         if args.skip_solve:
             return ms_asm, None
         _, info = ctx.solve(rtol=1e-8, out=u, profile=profile)
+        if args.f32_ir:
+            _, info32 = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_IR,
+                                  inner_rtol=args.inner_rtol)
+            info["ir"] = info32
+            log(f"[bench]   FP32+FP64-IR: {info32['ms_solve']:.1f} ms, {info32['iters']} it, "
+                f"{info32['outer_steps']} outer, relres {info32['true_relres']:.2e}")
+            _, inforr = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_RR, profile=profile)
+            info["rr"] = inforr
+            log(f"[bench]   FP32-matrix CG + FP64 replacement: {inforr['ms_solve']:.1f} ms, "
+                f"{inforr['iters']} it, relres {inforr['true_relres']:.2e}, "
+                f"spmv {inforr['ms_spmv_avg'] * 1e3:.1f} us")
         return ms_asm, info
 
     for w in range(args.warmup):

@@ -60,7 +60,7 @@ enum {
 
 /* Solver choices (sfem_solve_opts). */
 enum { SFEM_PRECOND_JACOBI = 0, SFEM_PRECOND_LEARNED = 1 };
-enum { SFEM_MODE_F64 = 0, SFEM_MODE_F32_IR = 1 };
+enum { SFEM_MODE_F64 = 0, SFEM_MODE_F32_IR = 1, SFEM_MODE_F32_RR = 2 };
 
 /* ----------------------------------------------------------------------------
  * Context.  `device` is a HIP device ordinal; `hip_stream` is a hipStream_t
@@ -156,8 +156,14 @@ int sfem_spmv(sfem_ctx* ctx, const double* x, double* y, int ptr_kind);
  *                      check_every iterations and at every candidate stop,
  *                      with residual replacement.
  *   SFEM_MODE_F32_IR : iterative refinement: FP64 residual r = f - K u, an
- *                      FP32-matrix PCG solve of K d = r to inner_rtol (dot
- *                      products in FP64), u += d.  Needs SFEM_ASM_F32_COPY.
+ *                      FP32-matrix PCG solve of K d = r whose recursive
+ *                      residual falls by inner_rtol (dot products in FP64),
+ *                      u += d.  Needs SFEM_ASM_F32_COPY.
+ *   SFEM_MODE_F32_RR : one PCG run whose products use the FP32 matrix and
+ *                      whose vectors and dots are FP64; every check_every
+ *                      iterations the residual is replaced by the FP64
+ *                      residual f - K u (a refinement step that keeps the
+ *                      Krylov recurrences).  Needs SFEM_ASM_F32_COPY.
  * u: float64 [3 n_nodes] output (x0 = 0).  Returns SFEM_ENOCONV if rtol was
  * not reached within max_iter (u and info are still written).
  */
@@ -167,7 +173,7 @@ typedef struct {
   double rtol;        /* on the FP64 true relative residual */
   int max_iter;       /* cap on inner iterations (all outer steps) */
   int check_every;    /* true-residual period in iterations (0: 50) */
-  double inner_rtol;  /* F32_IR inner tolerance (0: 1e-3) */
+  double inner_rtol;  /* F32_IR inner tolerance (0: 1e-2) */
   int max_outer;      /* F32_IR outer-step cap (0: 30) */
   int profile;        /* nonzero: time every SpMV launch with HIP events */
 } sfem_solve_opts;

@@ -46,7 +46,7 @@ __device__ __forceinline__ void row3x2(const int (&I)[2], const bool (&valid)[2]
                                        const int32_t* __restrict__ bptr,
                                        const int32_t* __restrict__ bcol,
                                        const VT* __restrict__ val, const XF& x, double (&y)[2][3]) {
-  using AT = typename std::conditional<sizeof(VT) == 8, double, float>::type;
+  using AT = double;  // row sums in FP64 for every matrix / vector precision
   int rb[2], td[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
@@ -114,7 +114,7 @@ __device__ __forceinline__ void row3(int I, bool valid, int sub, const int32_t* 
   const int td = 3 * deg;
   const VT* v = val + 9 * int64_t(rb);
   const int32_t* cols = bcol + rb;
-  using AT = typename std::conditional<sizeof(VT) == 8, double, float>::type;
+  using AT = double;  // row sums in FP64 for every matrix / vector precision
   AT a0 = 0, a1 = 0, a2 = 0;
   for (int c = sub; c < td; c += LPR) {
     const int jj = c / 3;
@@ -486,7 +486,8 @@ void finalize(Ctx& c, FinalizeOp op, int nparts) {
 
 // ------------------------------------------------------------- host driver
 struct CgBuffers {
-  const void* val;
+  const void* val;       // matrix of the iteration (FP64 or FP32 values)
+  const void* val_true;  // FP64 matrix of the residual replacement
   const void* dinv;
   void *b, *x, *r, *z, *p0, *p1, *q;  // p0: search direction (p1 unused)
 };
@@ -546,8 +547,8 @@ void cg_replace(Ctx& c, const CgBuffers& B) {
   const int rg = row_grid(c.N, rs);
 #define L_(LPR, PAIR)                                                                          \
   k_cg_replace<VT, P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                     \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, (const P*)B.b, (const P*)B.x, \
-      (P*)B.r, (P*)B.z, (const P*)B.dinv, c.partials.get())
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val_true, (const P*)B.b,          \
+      (const P*)B.x, (P*)B.r, (P*)B.z, (const P*)B.dinv, c.partials.get())
   SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
@@ -572,13 +573,16 @@ __global__ void k_cg_clear(CgScalars* sc) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sc->converged = 0;
 }
 
-// One PCG solve of A x = b from x = 0, stopping when the true residual (the
-// replacement residual, computed in the solve's own precision) satisfies
-// ||r|| <= tol_abs, after max_iter iterations, or on stagnation near the
-// tolerance.  b is FP64 (scaled into P).  Returns the iterations done.
-template <typename VT, typename P>
+// One PCG solve of A x = b from x = 0.  With `replace` it stops when the
+// true residual (the replacement residual, computed in the solve's own
+// precision) satisfies ||r|| <= tol_abs, after max_iter iterations, or on
+// stagnation near the tolerance.  Without it (inner solves of the
+// refinement, whose accuracy the FP64 outer residual judges) it stops on the
+// recursive residual, which keeps falling below the working precision's
+// floor.  b is FP64 (scaled into P).  Returns the iterations done.
+template <typename VT, typename P, typename VTR = VT>
 int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double tol_abs,
-        int max_iter, int check_every, bool& met, bool& breakdown) {
+        int max_iter, int check_every, bool& met, bool& breakdown, bool replace = true) {
   const int64_t n = c.n_dof();
   hipStream_t s = c.stream;
   // B.b is the P-typed right-hand side the replacement uses; when it is b64
@@ -602,11 +606,17 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
   while (!met && done < max_iter && stale < 40) {
     const int chunk = std::min(check_every, max_iter - done);
     cg_iterations<VT, P>(c, B, chunk, parity);
-    cg_replace<VT, P>(c, B);
+    if (replace) cg_replace<VTR, P>(c, B);
     read_scalars(c);
     const int before = done;
     done = int(c.sc_host->aux[0]);
     collect_profile(c, chunk, before, done);
+    if (!replace) {
+      met = c.sc_host->converged == 1;
+      if (c.sc_host->converged == 2) breakdown = true;
+      if (met || breakdown || done == before) break;
+      continue;
+    }
     met = c.sc_host->rr_true <= tol2;
     if (c.sc_host->rr_true < best) {
       best = c.sc_host->rr_true;
@@ -745,6 +755,9 @@ static void ensure_work(Ctx& c, bool f32) {
 
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   const int64_t n = c.n_dof();
+  SFEM_REQUIRE(o.mode == SFEM_MODE_F64 || o.mode == SFEM_MODE_F32_IR ||
+                   o.mode == SFEM_MODE_F32_RR,
+               SFEM_EINVAL, "unknown solve mode");
   const bool f32 = o.mode == SFEM_MODE_F32_IR;
   ensure_work(c, f32);
   const int check_every = o.check_every > 0 ? o.check_every : 50;
@@ -763,26 +776,40 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   int status = SFEM_OK;
   if (fnorm == 0.0) {
     info.converged = 1;
-  } else if (!f32) {
-    CgBuffers B{c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(), c.z.get(),
-                c.p.get(), c.p2.get(), c.q.get()};
+  } else if (o.mode == SFEM_MODE_F64) {
+    CgBuffers B{c.val.get(), c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
+                c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
     bool met = false, brk = false;
     info.iters = pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
                                      check_every, met, brk);
     info.outer_steps = 1;
     info.true_relres = true_residual(c, c.x.get());
     info.converged = info.true_relres <= o.rtol;
+  } else if (o.mode == SFEM_MODE_F32_RR) {
+    SFEM_REQUIRE(c.have_f32, SFEM_ESTATE,
+                 "SFEM_MODE_F32_RR needs sfem_assemble(..., SFEM_ASM_F32_COPY)");
+    // one CG run: K32 products, FP64 vectors and dots; every check_every
+    // iterations the residual is replaced by the FP64 one, f - K64 x, which
+    // is the refinement step and the convergence test
+    CgBuffers B{c.val32.get(), c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
+                c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
+    bool met = false, brk = false;
+    info.iters = pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
+                                            check_every, met, brk);
+    info.outer_steps = info.iters / check_every + 1;
+    info.true_relres = true_residual(c, c.x.get());
+    info.converged = info.true_relres <= o.rtol;
   } else {
     SFEM_REQUIRE(c.have_f32, SFEM_ESTATE,
                  "SFEM_MODE_F32_IR needs sfem_assemble(..., SFEM_ASM_F32_COPY)");
-    const double inner = o.inner_rtol > 0 ? o.inner_rtol : 1e-3;
+    const double inner = o.inner_rtol > 0 ? o.inner_rtol : 1e-2;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 30;
     double* u = c.x.get();
     k_zero<<<div_up(n, 256), 256, 0, c.stream>>>(n, u);
     SFEM_HIP(hipGetLastError());
     // inner solve K32 d = r / scale in FP32; d accumulates in x32
-    CgBuffers B{c.val32.get(), c.dinv32.get(), c.b32.get(), c.x32.get(), c.r32.get(),
-                c.z32.get(), c.p32.get(), c.p32b.get(), c.q32.get()};
+    CgBuffers B{c.val32.get(), c.val32.get(), c.dinv32.get(), c.b32.get(), c.x32.get(),
+                c.r32.get(), c.z32.get(), c.p32.get(), c.p32b.get(), c.q32.get()};
     double relres = 1.0;
     int iters = 0, outer = 0;
     double* r64 = c.w.get();
@@ -795,8 +822,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
       const double scale = rnorm / std::sqrt(double(n));  // keeps FP32 values O(1)
       bool met = false, brk = false;
       const double tol = inner * std::sqrt(double(n));  // ||r / scale|| = sqrt(n)
-      iters += pcg<float, float>(c, B, r64, 1.0 / scale, tol, max_iter - iters, check_every, met,
-                                 brk);
+      iters += pcg<float, float>(c, B, r64, 1.0 / scale, tol, max_iter - iters,
+                                 std::max(check_every, 200), met, brk, /*replace=*/false);
       k_axpy_f32<<<div_up(n, 256), 256, 0, c.stream>>>(n, scale, c.x32.get(), u);
       SFEM_HIP(hipGetLastError());
       ++outer;

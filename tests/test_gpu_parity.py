@@ -333,3 +333,14 @@ def test_every_row_schedule_matches_oracle(small):
     print(f"{name}: worst SpMV error over schedules {worst:.2e}; autotuned f64 schedule "
           f"{v64}/{cap64} ({tuned['f64'][1]:.1f} us); solve error {eu:.2e}")
     assert worst <= 1e-13 and 0 <= v64 < 8 and eu <= 1e-8
+
+
+def test_c1_f32_matrix_with_f64_replacement(c1):
+    sfem = _sfem()
+    ctx = gpu_ctx(c1.p, f32=True)
+    u, info = ctx.solve(rtol=1e-8, mode=sfem.MODE_F32_RR)
+    ub = O.solve_banded(c1.Kb, c1.fb)
+    err = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+    print(f"c1: FP32-matrix CG + FP64 replacement iters {info['iters']} "
+          f"relres {info['true_relres']:.2e}; u error vs banded {err:.2e}")
+    assert info["converged"] and info["true_relres"] <= 1e-8 and err <= 1e-8

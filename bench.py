@@ -75,6 +75,11 @@ def read_traffic(kernel_tag):
         return None
 
 
+def _short(name):
+    name = name.replace("void ", "").replace("sfem::(anonymous namespace)::", "")
+    return name.split("(")[0]
+
+
 def _counter_means(csv_path):
     """Mean counter value per kernel name over its dispatches."""
     import collections
@@ -110,7 +115,7 @@ def summarize_profiles(prof_dir, command_note):
         fr, n = fetch[kn[0]]
         wr, _ = write[[k for k in write if pattern in k][0]]
         rec = {
-            "kernel": kn[0].split("(")[0], "dispatches": n,
+            "kernel": _short(kn[0]), "dispatches": n,
             "fetch_kib_raw": fr, "write_kib_raw": wr,
             "copy_calibration": {"fetch_factor": kf, "write_factor": kw,
                                  "copy": "1 GiB device-to-device (bench.py --copy-calibration)"},
@@ -133,7 +138,7 @@ def summarize_profiles(prof_dir, command_note):
             fh.write(f"Command: `{command_note}`\n\n")
             fh.write("| kernel | calls | total ms | average us | % |\n|---|---|---|---|---|\n")
             for r in rows[:25]:
-                nm = r["Name"].split("(")[0].replace("sfem::(anonymous namespace)::", "")
+                nm = _short(r["Name"])
                 fh.write(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                          f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
 

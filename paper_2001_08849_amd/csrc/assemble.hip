@@ -132,15 +132,16 @@ __device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
 //   C * max(lam + 2 mu) * max V_e / 2 * max |grad N|^2  =: 2^62 u.
 // Rounding each contribution to a multiple of u then costs at most C u / 2
 // per entry, about 1e-15 of that bound.
-__device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) {
-  atomicMax(p, (unsigned long long)__double_as_longlong(v));  // v >= 0: bits order as values
-}
+constexpr int kFixBlocks = 1024;
 
-__global__ void k_fix_bound(const double* __restrict__ xyz, const int32_t* __restrict__ tets,
-                            int64_t T, double lam0, double mu0, const double* __restrict__ lam_t,
-                            const double* __restrict__ mu_t,
-                            unsigned long long* __restrict__ maxes) {
-  double mF = 0, mV = 0, mG = 0;
+// Per-workgroup maxima of F and V G over the tets -> part[2 * block + {0,1}]
+// (a one-workgroup k_fix_unit reduces them).
+__global__ void __launch_bounds__(256)
+    k_fix_bound(const double* __restrict__ xyz, const int32_t* __restrict__ tets, int64_t T,
+                double lam0, double mu0, const double* __restrict__ lam_t,
+                const double* __restrict__ mu_t, double* __restrict__ part) {
+  __shared__ double smax[2][256 / kWave];
+  double mF = 0, mV = 0;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < T;
        t += int64_t(gridDim.x) * blockDim.x) {
     const int4 v = reinterpret_cast<const int4*>(tets)[t];
@@ -153,32 +154,50 @@ __global__ void k_fix_bound(const double* __restrict__ xyz, const int32_t* __res
     const double F = lam_t ? lam_t[t] + 2.0 * mu_t[t] : lam0 + 2.0 * mu0;
     mF = fmax(mF, F);
     mV = fmax(mV, vol * gg);
-    mG = 1.0;
   }
   mF = wave_max(mF);
   mV = wave_max(mV);
-  mG = wave_max(mG);
+  const int w = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    atomic_max_pos(maxes + 0, mF);
-    atomic_max_pos(maxes + 1, mV);
-    atomic_max_pos(maxes + 2, mG);
+    smax[0][w] = mF;
+    smax[1][w] = mV;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < int(blockDim.x) / kWave; ++k) {
+      mF = fmax(mF, smax[0][k]);
+      mV = fmax(mV, smax[1][k]);
+    }
+    part[2 * blockIdx.x] = mF;
+    part[2 * blockIdx.x + 1] = mV;
   }
 }
 
-// unit[0] = u, unit[1] = 1/u from the three maxima and C.
-__global__ void k_fix_unit(const unsigned long long* __restrict__ maxes, int C,
-                           double* __restrict__ unit) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double F = __longlong_as_double((long long)maxes[0]);
-  const double VG = __longlong_as_double((long long)maxes[1]);
+// unit[0] = u, unit[1] = 1/u from the maxima of the nparts partials and C.
+__global__ void __launch_bounds__(256)
+    k_fix_unit(const double* __restrict__ part, int nparts, int C, double* __restrict__ unit) {
+  double F = 0, VG = 0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    F = fmax(F, part[2 * b]);
+    VG = fmax(VG, part[2 * b + 1]);
+  }
+  F = wave_max(F);
+  VG = wave_max(VG);
+  __shared__ double s[2][4];
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s[0][threadIdx.x / kWave] = F;
+    s[1][threadIdx.x / kWave] = VG;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < int(blockDim.x) / kWave; ++k) {
+    F = fmax(F, s[0][k]);
+    VG = fmax(VG, s[1][k]);
+  }
   const double bound = double(C) * F * 0.5 * VG;
   const double u = bound * 0x1p-62;
   unit[0] = u;
   unit[1] = 1.0 / u;
-}
-
-__global__ void k_zero_u64(unsigned long long* p, int n) {
-  if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
 // Largest index i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
@@ -439,13 +458,13 @@ void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask)
   const Topology& tp = c.topo;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
   // fixed-point unit of this assembly (device side, no host round trip)
-  unsigned long long* maxes = reinterpret_cast<unsigned long long*>(c.fix.reserve(8));
-  double* unit = c.fix.get() + 4;
-  k_zero_u64<<<1, 64, 0, c.stream>>>(maxes, 3);
-  k_fix_bound<<<std::min<int64_t>(div_up(c.T, 256), 2048), 256, 0, c.stream>>>(
-      c.xyz.get(), c.tets.get(), c.T, c.lam0, c.mu0, c.per_tet ? c.lam_t.get() : nullptr,
-      c.per_tet ? c.mu_t.get() : nullptr, maxes);
-  k_fix_unit<<<1, 64, 0, c.stream>>>(maxes, tp.max_inc, unit);
+  double* part = c.fix.reserve(2 * kFixBlocks + 8);
+  double* unit = part + 2 * kFixBlocks;
+  const int nb = int(std::min<int64_t>(div_up(c.T, 256), kFixBlocks));
+  k_fix_bound<<<nb, 256, 0, c.stream>>>(c.xyz.get(), c.tets.get(), c.T, c.lam0, c.mu0,
+                                        c.per_tet ? c.lam_t.get() : nullptr,
+                                        c.per_tet ? c.mu_t.get() : nullptr, part);
+  k_fix_unit<<<1, 256, 0, c.stream>>>(part, nb, tp.max_inc, unit);
   SFEM_HIP(hipGetLastError());
   dim3 grid(tp.n_tiles), block(kAsmThreads);
   if (c.per_tet)

@@ -81,7 +81,7 @@ struct Ctx {
   DBuf<double> val;
   DBuf<float> val32;
   DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
-  DBuf<double> fix;              // assembly fixed-point maxima [0..3) and unit [4..6)
+  DBuf<double> fix;              // assembly fixed-point partial maxima, then the unit
   DBuf<float> dinv32;
 
   // solver work vectors

@@ -155,6 +155,12 @@ int sfem_spmv(sfem_ctx* ctx, const double* x, double* y, int ptr_kind);
  *   SFEM_MODE_F64    : Jacobi (or learned) PCG in FP64, true residual every
  *                      check_every iterations and at every candidate stop,
  *                      with residual replacement.
+ * precond: SFEM_PRECOND_JACOBI (z = D^-1 r) or SFEM_PRECOND_LEARNED (z = M r
+ * with the M of the last sfem_gnn_apply on this context; flexible CG with
+ * the Polak-Ribiere beta, in every mode).  M is symmetric but not forced
+ * positive definite: if r.M r <= 0 or the solve stops short of rtol, the
+ * solve continues with Jacobi PCG from the current u (info->fell_back = 1);
+ * the FP64 true residual remains the only stopping test.
  *   SFEM_MODE_F32_IR : iterative refinement: FP64 residual r = f - K u, an
  *                      FP32-matrix PCG solve of K d = r whose recursive
  *                      residual falls by inner_rtol (dot products in FP64),
@@ -219,6 +225,80 @@ int sfem_timer_stop(sfem_ctx* ctx, double* ms);
 
 /* Waits until all work queued on the context stream has finished. */
 int sfem_synchronize(sfem_ctx* ctx);
+
+/* ----------------------------------------------------------------------------
+ * Learned preconditioner (an extension: the paper solves directly).
+ *
+ * Graph: nodes = mesh nodes, edges = the 3x3 blocks (I, J) of K's pattern
+ * (self edges included).  With d = diag(K_bc) and A = D^-1/2 K_bc D^-1/2:
+ *   node features (8): A_II[0,1], A_II[0,2], A_II[1,2], log(d_3I+a / dbar)
+ *                      (a = 0..2; dbar = mean d over free DOFs), fixed(I), 1
+ *   edge features (12): A_IJ row-major, (p_J - p_I) / hbar (hbar = mean
+ *                      length of the off-diagonal edges)
+ * Network (width 64, 4 layers, ReLU):
+ *   h = relu(Wn x + bn), e = relu(We y + be)
+ *   per layer l: z = W_l [h_I; h_J; e_IJ] + b_l,  e += relu(z),
+ *                a_I = mean_J relu(z_IJ),  h += relu(U_l [h_I; a_I] + c_l)
+ *   R_IJ = Wo e_IJ (3x3),  S_IJ = (R_IJ + R_JI^T) / 2, zero in the rows and
+ *   columns of fixed DOFs;  M = D^-1/2 (I + S) D^-1/2.
+ * Loss over pairs (r, e) with K e = r:  mean (M r - e).K(M r - e) / e.K e.
+ * Parameters: one flat float32 vector, in this order, matrices row-major
+ * [fan_out][fan_in]: Wn[64][8] bn[64] We[64][12] be[64], then per layer
+ * W[64][192] b[64] U[64][128] c[64], then Wo[9][64]
+ * (sfem_gnn_num_params() floats).  Dense layers run in BF16 on the matrix
+ * cores with FP32 accumulation; the master copy and Adam state are FP32.
+ * A network lives on one device; every context it is used with must be on
+ * that device.  Re-assembling a context drops its M, features and pairs.
+ * Calls that take a context report errors through sfem_last_error(ctx)
+ * (sfem_gnn_train: the first context); the others through
+ * sfem_gnn_last_error.
+ */
+typedef struct sfem_gnn sfem_gnn;
+
+int64_t sfem_gnn_num_params(void);
+/* Glorot-uniform weights from `seed`, zero biases, zero decoder (so the
+ * untrained M equals Jacobi). */
+int sfem_gnn_create(sfem_gnn** out, int device, uint64_t seed);
+void sfem_gnn_destroy(sfem_gnn* g);
+const char* sfem_gnn_last_error(const sfem_gnn* g);
+/* Host float32 copies of the parameters (n must equal num_params).
+ * set_params also resets the Adam state. */
+int sfem_gnn_get_params(sfem_gnn* g, float* params, int64_t n);
+int sfem_gnn_set_params(sfem_gnn* g, const float* params, int64_t n);
+
+/* Training pairs of a context: r, e float32 [n_pairs][3 n_nodes] (ptr_kind),
+ * copied; r should be K_bc e.  Replaces earlier pairs. */
+int sfem_gnn_set_pairs(sfem_ctx* ctx, int64_t n_pairs, const float* r, const float* e,
+                       int ptr_kind);
+/* Pairs from the plain solver: n_rhs Jacobi-PCG solves K_bc x = b to 1e-10
+ * (b_0 = the load vector; b_k = K_bc D^-1/2 u_k for k > 0, u_k seeded
+ * uniform in [-1, 1) and zero on fixed DOFs), each giving up to
+ * snaps_per_rhs pairs e = x* - x_j, r = K_bc e for the iterates x_j at
+ * iterations its (j / snaps_per_rhs)^2 (x_0 = 0 included).  Replaces earlier
+ * pairs; *n_pairs gets the count kept.  Needs sfem_assemble. */
+int sfem_gnn_generate_pairs(sfem_ctx* ctx, int n_rhs, int snaps_per_rhs, uint64_t seed,
+                            int64_t* n_pairs);
+/* Loss of the pairs pair_ids[0..n_ids) (host, 1 <= n_ids <= 64) and, if grad
+ * is not NULL, its gradient (host float32 [num_params]).  Leaves the
+ * forward's M on the context. */
+int sfem_gnn_loss_grad(sfem_gnn* g, sfem_ctx* ctx, const int32_t* pair_ids, int n_ids,
+                       double* loss, float* grad);
+/* Adam training: step k uses context ctxs[k % n_ctx] and `batch` pair
+ * indices drawn uniformly (seeded); lr is the Adam step size (betas 0.9,
+ * 0.999, eps 1e-8).  losses (host, may be NULL) receives each step's
+ * minibatch loss. */
+int sfem_gnn_train(sfem_gnn* g, sfem_ctx* const* ctxs, int n_ctx, int steps, int batch,
+                   double lr, uint64_t seed, float* losses);
+/* Inference: computes M for the context (features + forward) and enables
+ * SFEM_PRECOND_LEARNED there.  ms (may be NULL): device time. */
+int sfem_gnn_apply(sfem_gnn* g, sfem_ctx* ctx, double* ms);
+
+/* The learned preconditioner of a context: correction S float32 [nnz] in the
+ * order of sfem_get_csr's values, and d^-1/2 float64 [3 n_nodes] (either
+ * pointer may be NULL). */
+int sfem_get_precond(sfem_ctx* ctx, float* correction, double* dinv_sqrt, int ptr_kind);
+/* z = M r (float64 [3 n_nodes]) with the learned preconditioner. */
+int sfem_precond_apply(sfem_ctx* ctx, const double* r, double* z, int ptr_kind);
 
 #ifdef __cplusplus
 }

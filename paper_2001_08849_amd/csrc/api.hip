@@ -1,13 +1,17 @@
 // extern "C" entry points of include/sfem.h.  Every call catches the
 // library's internal errors and turns them into an sfem_status plus a
 // message kept on the context.
-#include "ctx.h"
+#include "gnn.h"
 
 using sfem::Ctx;
 using sfem::Error;
 
 struct sfem_ctx {
   Ctx c;
+};
+
+struct sfem_gnn {
+  sfem::Gnn g;
 };
 
 namespace {
@@ -24,6 +28,22 @@ int guarded(sfem_ctx* h, F&& fn) {
     return e.code;
   } catch (const std::exception& e) {
     h->c.err = e.what();
+    return SFEM_EINVAL;
+  }
+}
+
+template <typename F>
+int gnn_guarded(sfem_gnn* h, F&& fn) {
+  if (!h) return SFEM_EINVAL;
+  h->g.err.clear();
+  try {
+    SFEM_HIP(hipSetDevice(h->g.device));
+    return fn(h->g);
+  } catch (const Error& e) {
+    h->g.err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    h->g.err = e.what();
     return SFEM_EINVAL;
   }
 }
@@ -95,6 +115,8 @@ __global__ void k_set_fixed(int64_t n, const int32_t* dof, const double* value, 
 }
 
 void reset_problem(Ctx& c) {
+  c.have_learned = false;
+  c.gnn.reset();
   c.have_material = false;
   c.per_tet = false;
   c.any_fixed = c.any_nonzero_bc = false;
@@ -334,6 +356,10 @@ int sfem_assemble(sfem_ctx* h, int flags) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
     SFEM_REQUIRE(c.have_material, SFEM_ESTATE, "set a material first");
+    // a new matrix invalidates the learned preconditioner, its features and
+    // the training pairs (r = K e) of the old one
+    c.have_learned = false;
+    c.gnn.reset();
     const int64_t nnz = 9 * c.topo.nb;
     c.val.reserve(nnz);
     const bool f32 = (flags & SFEM_ASM_F32_COPY) != 0;
@@ -452,8 +478,6 @@ int sfem_solve(sfem_ctx* h, const sfem_solve_opts* opts, double* u, int ptr_kind
     SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
     SFEM_REQUIRE(opts && u, SFEM_EINVAL, "null opts or u");
     SFEM_REQUIRE(opts->rtol > 0.0, SFEM_EINVAL, "rtol must be > 0");
-    SFEM_REQUIRE(opts->precond == SFEM_PRECOND_JACOBI, SFEM_EINVAL,
-                 "preconditioner not available in this build");
     sfem_solve_info tmp{};
     int st = sfem::solve(c, *opts, tmp);
     download(c, u, c.x.get(), c.n_dof(), ptr_kind);
@@ -521,6 +545,193 @@ int sfem_timer_stop(sfem_ctx* h, double* ms) {
 
 int sfem_synchronize(sfem_ctx* h) {
   return guarded(h, [&](Ctx& c) {
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+// ------------------------------------------------- learned preconditioner
+int64_t sfem_gnn_num_params(void) { return sfem::param_layout().total; }
+
+int sfem_gnn_create(sfem_gnn** out, int device, uint64_t seed) {
+  if (!out) return SFEM_EINVAL;
+  *out = nullptr;
+  sfem_gnn* h = new (std::nothrow) sfem_gnn;
+  if (!h) return SFEM_ENOMEM;
+  h->g.device = device;
+  const int st = gnn_guarded(h, [&](sfem::Gnn& g) {
+    int count = 0;
+    SFEM_HIP(hipGetDeviceCount(&count));
+    SFEM_REQUIRE(device >= 0 && device < count, SFEM_EINVAL, "bad device ordinal");
+    const int64_t n = sfem::param_layout().total;
+    g.params.reserve(n);
+    g.grad.reserve(n);
+    g.adam_m.reserve(n);
+    g.adam_v.reserve(n);
+    g.params_bf16.reserve(n);
+    sfem::gnn_init_params(g, seed);
+    return SFEM_OK;
+  });
+  if (st != SFEM_OK) {
+    sfem_gnn_destroy(h);
+    return st;
+  }
+  *out = h;
+  return SFEM_OK;
+}
+
+void sfem_gnn_destroy(sfem_gnn* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->g.device);
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+const char* sfem_gnn_last_error(const sfem_gnn* h) { return h ? h->g.err.c_str() : "null network"; }
+
+int sfem_gnn_get_params(sfem_gnn* h, float* params, int64_t n) {
+  return gnn_guarded(h, [&](sfem::Gnn& g) {
+    SFEM_REQUIRE(params && n == sfem::param_layout().total, SFEM_EINVAL,
+                 "params must hold sfem_gnn_num_params() floats");
+    SFEM_HIP(hipDeviceSynchronize());
+    SFEM_HIP(hipMemcpy(params, g.params.get(), sizeof(float) * n, hipMemcpyDeviceToHost));
+    return SFEM_OK;
+  });
+}
+
+int sfem_gnn_set_params(sfem_gnn* h, const float* params, int64_t n) {
+  return gnn_guarded(h, [&](sfem::Gnn& g) {
+    SFEM_REQUIRE(params && n == sfem::param_layout().total, SFEM_EINVAL,
+                 "params must hold sfem_gnn_num_params() floats");
+    SFEM_HIP(hipDeviceSynchronize());
+    const std::vector<float> zero(n, 0.f);
+    SFEM_HIP(hipMemcpy(g.params.get(), params, sizeof(float) * n, hipMemcpyHostToDevice));
+    SFEM_HIP(hipMemcpy(g.adam_m.get(), zero.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    SFEM_HIP(hipMemcpy(g.adam_v.get(), zero.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    g.adam_t = 0;
+    return SFEM_OK;
+  });
+}
+
+int sfem_gnn_set_pairs(sfem_ctx* h, int64_t n_pairs, const float* r, const float* e,
+                       int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(n_pairs >= 1 && r && e, SFEM_EINVAL, "need n_pairs >= 1 and non-null r, e");
+    SFEM_REQUIRE(ptr_kind == SFEM_PTR_HOST || ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL,
+                 "ptr_kind must be SFEM_PTR_HOST or SFEM_PTR_DEVICE");
+    sfem::gnn_set_pairs(c, n_pairs, r, e);
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_gnn_generate_pairs(sfem_ctx* h, int n_rhs, int snaps_per_rhs, uint64_t seed,
+                            int64_t* n_pairs) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    const int64_t k = sfem::gnn_generate_pairs(c, n_rhs, snaps_per_rhs, seed);
+    if (n_pairs) *n_pairs = k;
+    return SFEM_OK;
+  });
+}
+
+int sfem_gnn_loss_grad(sfem_gnn* gh, sfem_ctx* h, const int32_t* pair_ids, int n_ids,
+                       double* loss, float* grad) {
+  if (!gh) return SFEM_EINVAL;
+  return guarded(h, [&](Ctx& c) {
+    sfem::Gnn& g = gh->g;
+    SFEM_REQUIRE(g.device == c.device, SFEM_EINVAL, "network and context on different devices");
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    SFEM_REQUIRE(pair_ids && n_ids >= 1, SFEM_EINVAL, "need pair ids");
+    const double L = sfem::gnn_loss_grad(c, g, pair_ids, n_ids, grad != nullptr);
+    if (grad) {
+      SFEM_HIP(hipStreamSynchronize(c.stream));
+      SFEM_HIP(hipMemcpy(grad, g.grad.get(), sizeof(float) * sfem::param_layout().total,
+                         hipMemcpyDeviceToHost));
+    }
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    if (loss) *loss = L;
+    return SFEM_OK;
+  });
+}
+
+int sfem_gnn_train(sfem_gnn* gh, sfem_ctx* const* ctxs, int n_ctx, int steps, int batch,
+                   double lr, uint64_t seed, float* losses) {
+  if (!gh || !ctxs || n_ctx < 1) return SFEM_EINVAL;
+  for (int i = 0; i < n_ctx; ++i)
+    if (!ctxs[i]) return SFEM_EINVAL;
+  return guarded(ctxs[0], [&](Ctx&) {
+    sfem::Gnn& g = gh->g;
+    SFEM_REQUIRE(steps >= 0 && batch >= 1 && batch <= 64 && lr > 0.0, SFEM_EINVAL,
+                 "need steps >= 0, 1 <= batch <= 64, lr > 0");
+    for (int i = 0; i < n_ctx; ++i) {
+      Ctx& c = ctxs[i]->c;
+      SFEM_REQUIRE(c.device == g.device, SFEM_EINVAL, "network and context on different devices");
+      SFEM_REQUIRE(c.assembled && c.gnn && c.gnn->n_pairs > 0, SFEM_ESTATE,
+                   "every context needs sfem_assemble and training pairs");
+    }
+    uint64_t st = seed;
+    auto next = [&]() {  // splitmix64
+      st += 0x9e3779b97f4a7c15ull;
+      uint64_t z = st;
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+      return z ^ (z >> 31);
+    };
+    std::vector<int32_t> ids(batch);
+    for (int k = 0; k < steps; ++k) {
+      Ctx& c = ctxs[k % n_ctx]->c;
+      const uint64_t np = uint64_t(c.gnn->n_pairs);
+      for (int p = 0; p < batch; ++p) ids[p] = int32_t(next() % np);
+      const double L = sfem::gnn_loss_grad(c, g, ids.data(), batch, true);
+      sfem::gnn_adam(g, c.stream, lr, 0.9, 0.999, 1e-8);
+      // the next step may run on another context's stream
+      SFEM_HIP(hipStreamSynchronize(c.stream));
+      if (losses) losses[k] = float(L);
+    }
+    return SFEM_OK;
+  });
+}
+
+int sfem_gnn_apply(sfem_gnn* gh, sfem_ctx* h, double* ms) {
+  if (!gh) return SFEM_EINVAL;
+  return guarded(h, [&](Ctx& c) {
+    sfem::Gnn& g = gh->g;
+    SFEM_REQUIRE(g.device == c.device, SFEM_EINVAL, "network and context on different devices");
+    SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
+    SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+    sfem::gnn_forward(c, g, false);
+    SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+    SFEM_HIP(hipEventSynchronize(c.ev1));
+    float t = 0;
+    SFEM_HIP(hipEventElapsedTime(&t, c.ev0, c.ev1));
+    if (ms) *ms = t;
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_precond(sfem_ctx* h, float* correction, double* dinv_sqrt, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "call sfem_gnn_apply first");
+    download(c, correction, c.mval.get(), 9 * c.topo.nb, ptr_kind);
+    download(c, dinv_sqrt, c.msqrt.get(), c.n_dof(), ptr_kind);
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_precond_apply(sfem_ctx* h, const double* r, double* z, int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "call sfem_gnn_apply first");
+    SFEM_REQUIRE(r && z, SFEM_EINVAL, "null vector");
+    const int64_t n = c.n_dof();
+    sfem::DBuf<double> dr, dz;
+    dr.reserve(n);
+    dz.reserve(n);
+    upload(c, dr.get(), r, n, ptr_kind);
+    sfem::learned_apply(c, dr.get(), dz.get());
+    download(c, z, dz.get(), n, ptr_kind);
     SFEM_HIP(hipStreamSynchronize(c.stream));
     return SFEM_OK;
   });

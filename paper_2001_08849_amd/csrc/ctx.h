@@ -1,5 +1,7 @@
 // The library context: every device buffer of one mesh / problem.
 #pragma once
+#include <memory>
+
 #include "common.h"
 
 namespace sfem {
@@ -39,6 +41,8 @@ struct RowSched {
   int variant;
   int grid_cap;
 };
+
+struct GnnWork;
 
 struct CgScalars {
   double rz, rz_new, pq, alpha, beta, rr, rr_true, ff;
@@ -84,8 +88,16 @@ struct Ctx {
   DBuf<double> fix;              // assembly fixed-point partial maxima, then the unit
   DBuf<float> dinv32;
 
+  // learned preconditioner M = diag(msqrt) (I + S') diag(msqrt), S' in the
+  // scalar-CSR value layout of K
+  bool have_learned = false;
+  DBuf<float> mval;
+  DBuf<double> msqrt;
+  DBuf<float> msqrt32;
+  std::shared_ptr<GnnWork> gnn;  // features, activations and training pairs
+
   // solver work vectors
-  DBuf<double> x, r, z, p, p2, q, w;
+  DBuf<double> x, r, z, p, p2, q, w, xs;
   DBuf<float> x32, r32, z32, p32, p32b, q32, b32;
   DBuf<double> partials;
   DBuf<CgScalars> sc;

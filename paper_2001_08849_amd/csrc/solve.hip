@@ -15,7 +15,7 @@
 // finish (atomic ticket) reduces the partials in a fixed order, so results
 // are bit-reproducible.  Every `check_every` iterations the residual is
 // replaced by the true one, r = f - K x, whose norm the host reads.
-#include "ctx.h"
+#include "gnn.h"
 
 namespace sfem {
 
@@ -133,6 +133,14 @@ template <typename T>
 struct PlainX {
   const T* __restrict__ p;
   __device__ __forceinline__ T operator()(int64_t i) const { return p[i]; }
+};
+
+// Gathers s_i r_i (the Jacobi-scaled residual of the learned preconditioner).
+template <typename T>
+struct ScaledX {
+  const T* __restrict__ r;
+  const T* __restrict__ s;
+  __device__ __forceinline__ T operator()(int64_t i) const { return r[i] * s[i]; }
 };
 
 // Row loop shared by the row kernels.  Workgroups are dealt round-robin to
@@ -310,6 +318,47 @@ __global__ void __launch_bounds__(kVecThreads)
   store_partials<2>(v, partials);
 }
 
+// x += alpha p; r -= alpha q (the learned preconditioner applies z after).
+template <typename P>
+__global__ void __launch_bounds__(kVecThreads)
+    k_cg_xr(int64_t n, P* __restrict__ x, P* __restrict__ r, const P* __restrict__ p,
+            const P* __restrict__ q, const CgScalars* __restrict__ sc) {
+  if (sc->converged) return;
+  const P alpha = P(sc->alpha);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
+// Learned preconditioner z = M r = s (s r + S' (s r)), S' in the scalar-CSR
+// value layout of K (FP32), s = diag(K)^-1/2.  Partials (r.z_new), (r.r),
+// (r.z_old): the flexible (Polak-Ribiere) beta needs the previous z.
+// sc == nullptr: run unconditionally (start and residual replacement).
+template <typename P, int LPR, bool PAIR>
+__global__ void __launch_bounds__(kRowWaves * kWave)
+    k_mapply(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+             const float* __restrict__ mval, const P* __restrict__ s, const P* __restrict__ r,
+             P* __restrict__ z, const CgScalars* __restrict__ sc, double* __restrict__ partials) {
+  if (sc && sc->converged) return;
+  const ScaledX<P> xf{r, s};
+  double v[3] = {0.0, 0.0, 0.0};
+  row_apply<float, LPR, PAIR>(N, bptr, bcol, mval, xf, [&](int I, const double (&y)[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = 3 * int64_t(I) + a;
+      const double si = double(s[i]), ri = double(r[i]);
+      const P zi = P(si * (si * ri + y[a]));
+      v[0] += ri * double(zi);
+      v[1] += ri * ri;
+      v[2] += ri * double(z[i]);
+      z[i] = zi;
+    }
+  });
+  store_partials<3>(v, partials);
+}
+
 // Residual replacement: r = b - K x, z = dinv r; partials (r.r), (r.z).
 template <typename VT, typename P, int LPR, bool PAIR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
@@ -381,20 +430,27 @@ __global__ void __launch_bounds__(kVecThreads)
   store_partials<2>(v, partials);
 }
 
-enum FinalizeOp { kFinAlpha = 0, kFinBeta = 1, kFinReplace = 2, kFinResid = 3, kFinStart = 4 };
+enum FinalizeOp {
+  kFinAlpha = 0,
+  kFinBeta = 1,
+  kFinReplace = 2,
+  kFinResid = 3,
+  kFinStart = 4,
+  kFinBetaFlex = 5,   // learned M: (r.z_new, r.r, r.z_old)
+  kFinStartM = 6,     // learned M at the start: r.z
+  kFinReplaceM = 7    // learned M after a residual replacement: r.z
+};
 
 // One workgroup: adds the partials of the previous kernel in a fixed order
 // and updates the CG scalars.
 __global__ void __launch_bounds__(1024)
     k_finalize(int op, const double* __restrict__ partials, int nparts, CgScalars* __restrict__ sc) {
-  if ((op == kFinAlpha || op == kFinBeta) && sc->converged) return;
-  const int nv = op == kFinAlpha ? 1 : 2;
-  double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-    v[0] += partials[b * nv];
-    if (nv == 2) v[1] += partials[b * nv + 1];
-  }
-  block_sum<2>(v);
+  if ((op == kFinAlpha || op == kFinBeta || op == kFinBetaFlex) && sc->converged) return;
+  const int nv = op == kFinAlpha ? 1 : (op >= kFinBetaFlex ? 3 : 2);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+    for (int i = 0; i < nv; ++i) v[i] += partials[b * nv + i];
+  block_sum<3>(v);
   if (threadIdx.x != 0) return;
   switch (op) {
     case kFinAlpha:
@@ -425,6 +481,21 @@ __global__ void __launch_bounds__(1024)
       sc->rr_true = v[1];
       sc->beta = 0.0;
       sc->converged = 0;
+      break;
+    case kFinBetaFlex:
+      // r.M r must stay positive: otherwise M is not positive definite
+      // along r and the solve reports a breakdown (the host falls back)
+      sc->beta = (v[0] - v[2]) / sc->rz;
+      sc->rz = v[0];
+      sc->rr = v[1];
+      sc->aux[0] += 1.0;
+      if (v[1] <= sc->aux[1]) sc->converged = 1;
+      else if (!(v[0] > 0.0) || !isfinite(v[0]) || !isfinite(sc->beta)) sc->converged = 2;
+      break;
+    case kFinStartM:
+    case kFinReplaceM:
+      sc->rz = v[0];
+      if (v[1] > 0.0 && (!(v[0] > 0.0) || !isfinite(v[0]))) sc->converged = 2;
       break;
   }
 }
@@ -490,7 +561,24 @@ struct CgBuffers {
   const void* val_true;  // FP64 matrix of the residual replacement
   const void* dinv;
   void *b, *x, *r, *z, *p0, *p1, *q;  // p0: search direction (p1 unused)
+  const float* mval = nullptr;        // learned preconditioner S' (null: Jacobi)
+  const void* msq = nullptr;          // its diag(K)^-1/2, typed like the vectors
 };
+
+template <typename P>
+void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded) {
+  const RowSched rs = c.sched32;
+  const int rg = row_grid(c.N, rs);
+#define L_(LPR, PAIR)                                                                         \
+  k_mapply<P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                             \
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), B.mval, (const P*)B.msq, r, z,               \
+      guarded ? c.sc.get() : nullptr, c.partials.get())
+  SFEM_SCHED_SWITCH(rs.variant, L_)
+#undef L_
+  SFEM_HIP(hipGetLastError());
+}
+
+int mapply_parts(Ctx& c) { return row_grid(c.N, c.sched32); }
 
 // With c.profile set, every SpMV launch is bracketed by a pair of events;
 // their elapsed times are summed once the chunk has finished.
@@ -520,9 +608,15 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
 #undef L_
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k + 1], s));
     finalize(c, kFinAlpha, rg);
-    k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p, (const P*)B.q,
-                                              (const P*)B.dinv, c.sc.get(), c.partials.get());
-    finalize(c, kFinBeta, vg);
+    if (B.mval) {
+      k_cg_xr<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, p, (const P*)B.q, c.sc.get());
+      mapply<P>(c, B, (const P*)B.r, (P*)B.z, true);
+      finalize(c, kFinBetaFlex, mapply_parts(c));
+    } else {
+      k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p, (const P*)B.q,
+                                                (const P*)B.dinv, c.sc.get(), c.partials.get());
+      finalize(c, kFinBeta, vg);
+    }
   }
   SFEM_HIP(hipGetLastError());
 }
@@ -553,6 +647,10 @@ void cg_replace(Ctx& c, const CgBuffers& B) {
 #undef L_
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinReplace, rg);
+  if (B.mval) {
+    mapply<P>(c, B, (const P*)B.r, (P*)B.z, false);
+    finalize(c, kFinReplaceM, mapply_parts(c));
+  }
 }
 
 void read_scalars(Ctx& c) {
@@ -582,7 +680,8 @@ __global__ void k_cg_clear(CgScalars* sc) {
 // floor.  b is FP64 (scaled into P).  Returns the iterations done.
 template <typename VT, typename P, typename VTR = VT>
 int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double tol_abs,
-        int max_iter, int check_every, bool& met, bool& breakdown, bool replace = true) {
+        int max_iter, int check_every, bool& met, bool& breakdown, bool replace = true,
+        const std::function<void(int)>* hook = nullptr) {
   const int64_t n = c.n_dof();
   hipStream_t s = c.stream;
   // B.b is the P-typed right-hand side the replacement uses; when it is b64
@@ -594,12 +693,17 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
                                            c.partials.get());
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinStart, vg);
+  if (B.mval) {
+    mapply<P>(c, B, (const P*)B.r, (P*)B.z, false);
+    finalize(c, kFinStartM, mapply_parts(c));
+  }
   const double tol2 = tol_abs * tol_abs;
   k_cg_arm<<<1, 64, 0, s>>>(c.sc.get(), tol2);
   SFEM_HIP(hipGetLastError());
   read_scalars(c);
   met = c.sc_host->rr <= tol2;
-  breakdown = false;
+  breakdown = c.sc_host->converged == 2;
+  if (breakdown) return 0;
   int done = 0, parity = 0;
   double best = c.sc_host->rr;
   int stale = 0;  // checks without a new best, counted once near the tolerance
@@ -611,6 +715,7 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
     const int before = done;
     done = int(c.sc_host->aux[0]);
     collect_profile(c, chunk, before, done);
+    if (hook && done > before) (*hook)(done);
     if (!replace) {
       met = c.sc_host->converged == 1;
       if (c.sc_host->converged == 2) breakdown = true;
@@ -621,7 +726,9 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
     if (c.sc_host->rr_true < best) {
       best = c.sc_host->rr_true;
       stale = 0;
-    } else if (best <= 1e4 * tol2) {
+    } else if (best <= 1e4 * tol2 || B.mval) {
+      // Jacobi: stagnation counts only near the tolerance; the learned M
+      // (not guaranteed positive definite) gets the same budget anywhere
       ++stale;
     }
     if (c.sc_host->converged == 2) {
@@ -741,6 +848,7 @@ static void ensure_work(Ctx& c, bool f32) {
   c.p2.reserve(n);
   c.q.reserve(n);
   c.w.reserve(n);
+  c.xs.reserve(n);
   if (f32) {
     c.x32.reserve(n);
     c.r32.reserve(n);
@@ -750,7 +858,33 @@ static void ensure_work(Ctx& c, bool f32) {
     c.q32.reserve(n);
     c.b32.reserve(n);
   }
-  c.partials.reserve(2 * std::max(kRowGridMax, kVecGridMax) + 16);
+  c.partials.reserve(3 * std::max(kRowGridMax, kVecGridMax) + 16);
+}
+
+__global__ void k_axpy64(int64_t n, const double* __restrict__ d, double* __restrict__ u) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) u[i] += d[i];
+}
+
+// Jacobi fallback after a learned solve stopped short: from the current x,
+// solve K d = f - K x with Jacobi PCG and add d.  Returns the iterations.
+static int jacobi_fallback(Ctx& c, const CgBuffers& B, double tol_abs, int max_iter,
+                           int check_every, bool& met) {
+  const int64_t n = c.n_dof();
+  SFEM_HIP(hipMemcpyAsync(c.xs.get(), c.x.get(), sizeof(double) * n, hipMemcpyDeviceToDevice,
+                          c.stream));
+  resid64(c, c.xs.get(), c.w.get());
+  CgBuffers J = B;
+  J.val = c.val.get();
+  J.val_true = c.val.get();
+  J.mval = nullptr;
+  J.b = c.w.get();
+  bool brk = false;
+  const int its = pcg<double, double>(c, J, c.w.get(), 1.0, tol_abs, max_iter, check_every, met,
+                                      brk);
+  k_axpy64<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.xs.get(), c.x.get());
+  SFEM_HIP(hipGetLastError());
+  return its;
 }
 
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
@@ -758,6 +892,11 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   SFEM_REQUIRE(o.mode == SFEM_MODE_F64 || o.mode == SFEM_MODE_F32_IR ||
                    o.mode == SFEM_MODE_F32_RR,
                SFEM_EINVAL, "unknown solve mode");
+  SFEM_REQUIRE(o.precond == SFEM_PRECOND_JACOBI || o.precond == SFEM_PRECOND_LEARNED,
+               SFEM_EINVAL, "unknown preconditioner");
+  const bool learned = o.precond == SFEM_PRECOND_LEARNED;
+  SFEM_REQUIRE(!learned || c.have_learned, SFEM_ESTATE,
+               "SFEM_PRECOND_LEARNED needs sfem_gnn_apply on this context first");
   const bool f32 = o.mode == SFEM_MODE_F32_IR;
   ensure_work(c, f32);
   const int check_every = o.check_every > 0 ? o.check_every : 50;
@@ -776,27 +915,31 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   int status = SFEM_OK;
   if (fnorm == 0.0) {
     info.converged = 1;
-  } else if (o.mode == SFEM_MODE_F64) {
-    CgBuffers B{c.val.get(), c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
-                c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
-    bool met = false, brk = false;
-    info.iters = pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
-                                     check_every, met, brk);
-    info.outer_steps = 1;
-    info.true_relres = true_residual(c, c.x.get());
-    info.converged = info.true_relres <= o.rtol;
-  } else if (o.mode == SFEM_MODE_F32_RR) {
-    SFEM_REQUIRE(c.have_f32, SFEM_ESTATE,
-                 "SFEM_MODE_F32_RR needs sfem_assemble(..., SFEM_ASM_F32_COPY)");
-    // one CG run: K32 products, FP64 vectors and dots; every check_every
+  } else if (o.mode == SFEM_MODE_F64 || o.mode == SFEM_MODE_F32_RR) {
+    // F32_RR: K32 products, FP64 vectors and dots; every check_every
     // iterations the residual is replaced by the FP64 one, f - K64 x, which
     // is the refinement step and the convergence test
-    CgBuffers B{c.val32.get(), c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
+    const bool rr = o.mode == SFEM_MODE_F32_RR;
+    SFEM_REQUIRE(!rr || c.have_f32, SFEM_ESTATE,
+                 "SFEM_MODE_F32_RR needs sfem_assemble(..., SFEM_ASM_F32_COPY)");
+    CgBuffers B{rr ? (const void*)c.val32.get() : (const void*)c.val.get(),
+                c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
                 c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
+    if (learned) {
+      B.mval = c.mval.get();
+      B.msq = c.msqrt.get();
+    }
     bool met = false, brk = false;
-    info.iters = pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
-                                            check_every, met, brk);
-    info.outer_steps = info.iters / check_every + 1;
+    info.iters = rr ? pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm,
+                                                 max_iter, check_every, met, brk)
+                    : pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
+                                          check_every, met, brk);
+    if (learned && !met && info.iters < max_iter) {
+      info.fell_back = 1;
+      info.iters += jacobi_fallback(c, B, o.rtol * fnorm, max_iter - info.iters, check_every,
+                                    met);
+    }
+    info.outer_steps = rr ? info.iters / check_every + 1 : 1;
     info.true_relres = true_residual(c, c.x.get());
     info.converged = info.true_relres <= o.rtol;
   } else {
@@ -810,6 +953,7 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
     // inner solve K32 d = r / scale in FP32; d accumulates in x32
     CgBuffers B{c.val32.get(), c.val32.get(), c.dinv32.get(), c.b32.get(), c.x32.get(),
                 c.r32.get(), c.z32.get(), c.p32.get(), c.p32b.get(), c.q32.get()};
+    bool use_learned = learned;
     double relres = 1.0;
     int iters = 0, outer = 0;
     double* r64 = c.w.get();
@@ -822,14 +966,20 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
       const double scale = rnorm / std::sqrt(double(n));  // keeps FP32 values O(1)
       bool met = false, brk = false;
       const double tol = inner * std::sqrt(double(n));  // ||r / scale|| = sqrt(n)
+      B.mval = use_learned ? c.mval.get() : nullptr;
+      B.msq = c.msqrt32.get();
       iters += pcg<float, float>(c, B, r64, 1.0 / scale, tol, max_iter - iters,
                                  std::max(check_every, 200), met, brk, /*replace=*/false);
       k_axpy_f32<<<div_up(n, 256), 256, 0, c.stream>>>(n, scale, c.x32.get(), u);
       SFEM_HIP(hipGetLastError());
       ++outer;
       if (brk) {
-        status = SFEM_ENOCONV;
-        break;
+        if (!use_learned) {
+          status = SFEM_ENOCONV;
+          break;
+        }
+        use_learned = false;  // M not positive definite here: Jacobi from now on
+        info.fell_back = 1;
       }
     }
     info.iters = iters;
@@ -846,6 +996,25 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   info.ms_spmv_avg = c.prof_n ? c.prof_ms / c.prof_n : 0.0;
   if (!info.converged && status == SFEM_OK) status = SFEM_ENOCONV;
   return status;
+}
+
+int jacobi_run(Ctx& c, const double* b, double tol_abs, int every, int max_iter,
+               const std::function<void(int)>& hook) {
+  ensure_work(c, false);
+  c.profile = false;
+  CgBuffers B{c.val.get(), c.val.get(), c.dinv.get(), (void*)b, c.x.get(), c.r.get(),
+              c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
+  bool met = false, brk = false;
+  return pcg<double, double>(c, B, b, 1.0, tol_abs, max_iter, every, met, brk, true, &hook);
+}
+
+void learned_apply(Ctx& c, const double* r, double* z) {
+  SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");
+  ensure_work(c, false);
+  CgBuffers B{};
+  B.mval = c.mval.get();
+  B.msq = c.msqrt.get();
+  mapply<double>(c, B, r, z, false);
 }
 
 }  // namespace sfem

@@ -32,6 +32,10 @@ EXPORTS = [
     "sfem_get_sizes", "sfem_get_faces", "sfem_get_csr", "sfem_get_rhs", "sfem_spmv",
     "sfem_solve", "sfem_get_timings", "sfem_timer_start", "sfem_timer_stop",
     "sfem_synchronize", "sfem_set_schedule", "sfem_get_schedule", "sfem_autotune",
+    "sfem_gnn_num_params", "sfem_gnn_create", "sfem_gnn_destroy", "sfem_gnn_last_error",
+    "sfem_gnn_get_params", "sfem_gnn_set_params", "sfem_gnn_set_pairs",
+    "sfem_gnn_generate_pairs", "sfem_gnn_loss_grad", "sfem_gnn_train", "sfem_gnn_apply",
+    "sfem_get_precond", "sfem_precond_apply",
 ]
 
 
@@ -93,6 +97,19 @@ def lib() -> C.CDLL:
             "sfem_set_schedule": (i32, [vp, i32, i32, i32]),
             "sfem_get_schedule": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
             "sfem_autotune": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(dbl)]),
+            "sfem_gnn_num_params": (i64, []),
+            "sfem_gnn_create": (i32, [C.POINTER(vp), i32, C.c_uint64]),
+            "sfem_gnn_destroy": (None, [vp]),
+            "sfem_gnn_last_error": (C.c_char_p, [vp]),
+            "sfem_gnn_get_params": (i32, [vp, vp, i64]),
+            "sfem_gnn_set_params": (i32, [vp, vp, i64]),
+            "sfem_gnn_set_pairs": (i32, [vp, i64, vp, vp, i32]),
+            "sfem_gnn_generate_pairs": (i32, [vp, i32, i32, C.c_uint64, C.POINTER(i64)]),
+            "sfem_gnn_loss_grad": (i32, [vp, vp, vp, i32, C.POINTER(dbl), vp]),
+            "sfem_gnn_train": (i32, [vp, C.POINTER(vp), i32, i32, i32, dbl, C.c_uint64, vp]),
+            "sfem_gnn_apply": (i32, [vp, vp, C.POINTER(dbl)]),
+            "sfem_get_precond": (i32, [vp, vp, vp, i32]),
+            "sfem_precond_apply": (i32, [vp, vp, vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -112,7 +129,8 @@ def _arg(a, dtype):
         return None, PTR_HOST, None
     if _is_torch(a):
         import torch
-        want = {np.float64: torch.float64, np.int32: torch.int32}[dtype]
+        want = {np.float64: torch.float64, np.int32: torch.int32,
+                np.float32: torch.float32}[dtype]
         if a.dtype != want:
             raise TypeError(f"expected {want}, got {a.dtype}")
         if not a.is_contiguous():
@@ -299,6 +317,131 @@ class Context:
         a, b = C.c_double(), C.c_double()
         self._check(self._L.sfem_get_timings(self._h, C.byref(a), C.byref(b)))
         return {"ms_topology": a.value, "ms_assemble": b.value}
+
+
+    # ------------------------------------------------ learned preconditioner
+    def set_pairs(self, r, e):
+        """Training pairs: r, e float32 [n_pairs][3N] (r = K e)."""
+        pr, kr, a1 = _arg(r, np.float32)
+        pe, ke, a2 = _arg(e, np.float32)
+        n_pairs = (r.shape[0] if getattr(r, "ndim", 1) == 2 else 1)
+        if kr != ke:
+            raise ValueError("r and e must live on the same side")
+        self._check(self._L.sfem_gnn_set_pairs(self._h, int(n_pairs), pr, pe, kr))
+
+    def generate_pairs(self, n_rhs: int, snaps_per_rhs: int, seed: int = 0) -> int:
+        k = C.c_int64()
+        self._check(self._L.sfem_gnn_generate_pairs(self._h, int(n_rhs), int(snaps_per_rhs),
+                                                    int(seed), C.byref(k)))
+        return k.value
+
+    def precond(self):
+        """(S' float32 [nnz] in CSR value order, d^-1/2 float64 [3N])."""
+        sz = self.sizes()
+        S = np.empty(sz.nnz, dtype=np.float32)
+        s = np.empty(sz.n_rows, dtype=np.float64)
+        self._check(self._L.sfem_get_precond(self._h, S.ctypes.data_as(C.c_void_p),
+                                             s.ctypes.data_as(C.c_void_p), PTR_HOST))
+        return S, s
+
+    def precond_apply(self, r):
+        z = np.empty(self.sizes().n_rows, dtype=np.float64)
+        pr, kr, a = _arg(r, np.float64)
+        self._check(self._L.sfem_precond_apply(self._h, pr, z.ctypes.data_as(C.c_void_p), kr))
+        return z
+
+
+class Gnn:
+    """The learned preconditioner's network (sfem_gnn) on `device`."""
+
+    def __init__(self, device: int = 0, seed: int = 0):
+        L = lib()
+        h = C.c_void_p()
+        st = L.sfem_gnn_create(C.byref(h), device, int(seed))
+        if st != 0:
+            raise SfemError(st, "sfem_gnn_create failed")
+        self._h = h
+        self._L = L
+        self.n_params = int(L.sfem_gnn_num_params())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sfem_gnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ctx: Context | None = None):
+        if st != 0:
+            msg = (ctx._L.sfem_last_error(ctx._h) if ctx is not None
+                   else self._L.sfem_gnn_last_error(self._h)).decode()
+            raise SfemError(st, msg)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._L.sfem_gnn_get_params(self._h, out.ctypes.data_as(C.c_void_p),
+                                                self.n_params))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self._L.sfem_gnn_set_params(self._h, p.ctypes.data_as(C.c_void_p), p.size))
+
+    def loss_grad(self, ctx: Context, ids, grad: bool = True):
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        L = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if grad else None
+        st = self._L.sfem_gnn_loss_grad(self._h, ctx._h, ids.ctypes.data_as(C.c_void_p),
+                                        int(ids.size), C.byref(L),
+                                        g.ctypes.data_as(C.c_void_p) if grad else None)
+        self._check(st, ctx)
+        return (L.value, g) if grad else L.value
+
+    def train(self, ctxs, steps: int, batch: int = 32, lr: float = 1e-3, seed: int = 0):
+        arr = (C.c_void_p * len(ctxs))(*[c._h for c in ctxs])
+        losses = np.empty(max(steps, 1), dtype=np.float32)
+        st = self._L.sfem_gnn_train(self._h, arr, len(ctxs), int(steps), int(batch), float(lr),
+                                    int(seed), losses.ctypes.data_as(C.c_void_p))
+        self._check(st, ctxs[0])
+        return losses[:steps]
+
+    def apply(self, ctx: Context) -> float:
+        ms = C.c_double()
+        self._check(self._L.sfem_gnn_apply(self._h, ctx._h, C.byref(ms)), ctx)
+        return ms.value
+
+
+def unpack_params(flat):
+    """Splits the flat parameter vector into named arrays (the layout of
+    sfem_gnn_get_params)."""
+    flat = np.asarray(flat)
+    H, out, o = 64, {}, 0
+
+    def take(name, shape):
+        nonlocal o
+        n = int(np.prod(shape))
+        out[name] = flat[o:o + n].reshape(shape)
+        o += n
+
+    take("Wn", (H, 8)); take("bn", (H,)); take("We", (H, 12)); take("be", (H,))
+    for l in range(4):
+        take(f"W{l}", (H, 3 * H)); take(f"b{l}", (H,))
+        take(f"U{l}", (H, 2 * H)); take(f"c{l}", (H,))
+    take("Wo", (9, H))
+    assert o == flat.size
+    return out
+
+
+def pack_params(P) -> np.ndarray:
+    names = ["Wn", "bn", "We", "be"]
+    for l in range(4):
+        names += [f"W{l}", f"b{l}", f"U{l}", f"c{l}"]
+    names.append("Wo")
+    return np.concatenate([np.asarray(P[k], dtype=np.float32).ravel() for k in names])
 
 
 def setup_problem(ctx: Context, problem, f32_copy: bool = False, load_tris=None):

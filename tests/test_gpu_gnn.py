@@ -1,0 +1,255 @@
+"""GPU tests of the learned preconditioner: forward and gradient parity with
+the FP64 reference network, the solver integration (flexible PCG, Jacobi
+limit, fallback), determinism, and what training gains.
+
+Tolerances.  The dense layers take BF16 operands (unit roundoff u = 2^-9 ~
+2e-3) with FP32 accumulation; everything else is FP32/FP64.  A forward pass
+rounds every layer input once, so S' carries a few u of relative error
+(1.8e-3 measured): the bound is 5u = 1e-2.  A gradient passes through about
+twice as many rounded products plus FP32 loss panels (at most 1.6e-2
+per tensor measured): the bound is 25u = 5e-2 per tensor and 1e-2 on the
+whole vector, whose cosine with the reference must exceed 0.999.
+"""
+import numpy as np
+import pytest
+
+from oracle import fsfem as O
+from oracle import gnn_ref as G
+from paper_2001_08849_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+U_BF16 = 2.0 ** -9
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2001_08849_amd import sfem
+    return sfem
+
+
+def ref_system(p):
+    m = p.mesh
+    K = O.assemble(m.xyz, m.tets, p.E, p.nu)
+    f = O.traction_load(m.xyz, m.end_tris, p.traction)
+    Kb, fb = O.apply_dirichlet(K, f, p.fixed_dofs())
+    Kb = Kb.tocsr()
+    Kb.sort_indices()
+    return Kb, fb
+
+
+def blocks_to_csr(g, Kb, Sp):
+    """S' blocks [nb,3,3] -> values in the CSR order of Kb."""
+    out = np.zeros(Kb.nnz)
+    for k, (I, J) in enumerate(zip(g.row, g.bcol)):
+        for a in range(3):
+            lo, hi = Kb.indptr[3 * I + a], Kb.indptr[3 * I + a + 1]
+            cols = Kb.indices[lo:hi]
+            for c in range(3):
+                out[lo + np.searchsorted(cols, 3 * J + c)] = Sp[k, a, c]
+    return out
+
+
+def random_params(seed, scale_out=0.3):
+    P = G.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    P["Wo"] = rng.standard_normal(P["Wo"].shape) * scale_out
+    for k in P:
+        if k.startswith(("b", "c")):
+            P[k] = rng.standard_normal(P[k].shape) * 0.1
+    return P
+
+
+@pytest.fixture(scope="module")
+def small(S):
+    p = mg.learned_small(1, grid=(8, 3, 3))
+    ctx = S.Context(0)
+    S.setup_problem(ctx, p)
+    Kb, fb = ref_system(p)
+    g = G.build_graph(Kb, p.mesh.xyz, p.fixed_dofs())
+    return p, ctx, Kb, g
+
+
+def fp32_params(S, P):
+    """The reference parameters rounded to the network's FP32 master copy."""
+    flat = S.pack_params(P)
+    return flat, {k: v.astype(np.float64) for k, v in S.unpack_params(flat).items()}
+
+
+def test_forward_parity(S, small):
+    p, ctx, Kb, g = small
+    rp, ci, _ = ctx.csr()
+    assert np.array_equal(rp, Kb.indptr) and np.array_equal(ci, Kb.indices)
+    flat, P64 = fp32_params(S, random_params(3))
+    net = S.Gnn(0, seed=1)
+    net.set_params(flat)
+    net.apply(ctx)
+    S_gpu, s_gpu = ctx.precond()
+    Sp_ref, _ = G.forward(P64, g)
+    S_ref = blocks_to_csr(g, Kb, Sp_ref)
+    rel = np.linalg.norm(S_gpu - S_ref) / np.linalg.norm(S_ref)
+    print(f"S' relative Frobenius error {rel:.3e}")
+    assert rel < 5 * U_BF16
+    assert np.abs(S_gpu - S_ref).max() <= 10 * U_BF16 * np.abs(S_ref).max()
+    np.testing.assert_allclose(s_gpu, 1.0 / np.sqrt(Kb.diagonal()), rtol=1e-14)
+    # fixed DOFs: rows and columns of S' are exactly zero
+    fixed = np.zeros(Kb.shape[0], bool)
+    fixed[p.fixed_dofs()] = True
+    rows = np.repeat(np.arange(Kb.shape[0]), np.diff(Kb.indptr))
+    assert np.all(S_gpu[fixed[rows] | fixed[Kb.indices]] == 0.0)
+    # z = M r against the reference M
+    r = np.random.default_rng(0).standard_normal(Kb.shape[0])
+    z = ctx.precond_apply(r)
+    zr = G.apply_M(g, Sp_ref, r)
+    assert np.linalg.norm(z - zr) / np.linalg.norm(zr) < 5 * U_BF16
+
+
+def test_untrained_network_is_jacobi(S, small):
+    p, ctx, Kb, g = small
+    net = S.Gnn(0, seed=11)
+    net.apply(ctx)
+    S_gpu, _ = ctx.precond()
+    assert np.all(S_gpu == 0.0)
+    r = np.random.default_rng(1).standard_normal(Kb.shape[0])
+    np.testing.assert_allclose(ctx.precond_apply(r), r / Kb.diagonal(), rtol=1e-14)
+    # flexible PCG with M = D^-1 is Jacobi PCG
+    uj, ij = ctx.solve(rtol=1e-8)
+    ul, il = ctx.solve(rtol=1e-8, precond=S.PRECOND_LEARNED)
+    assert ij["converged"] and il["converged"] and not il["fell_back"]
+    assert abs(il["iters"] - ij["iters"]) <= max(2, 0.02 * ij["iters"])
+    assert np.linalg.norm(ul - uj) / np.linalg.norm(uj) < 1e-7
+
+
+def test_gradient_parity(S, small):
+    p, ctx, Kb, g = small
+    flat, P64 = fp32_params(S, random_params(4))
+    rng = np.random.default_rng(7)
+    n = Kb.shape[0]
+    E = rng.standard_normal((n, 8))
+    E[p.fixed_dofs()] = 0.0
+    R = Kb @ E
+    R32, E32 = np.ascontiguousarray(R.T, np.float32), np.ascontiguousarray(E.T, np.float32)
+    ctx.set_pairs(R32, E32)
+    net = S.Gnn(0, seed=1)
+    net.set_params(flat)
+    L_gpu, g_gpu = net.loss_grad(ctx, np.arange(8))
+    L_ref, g_ref = G.backward(P64, g, Kb, R32.T.astype(np.float64), E32.T.astype(np.float64))
+    assert abs(L_gpu - L_ref) / L_ref < 5 * U_BF16
+    gg = S.unpack_params(g_gpu)
+    worst = 0.0
+    for k, ref in g_ref.items():
+        nr = np.linalg.norm(ref)
+        if nr == 0.0:            # the last node update does not reach the output
+            assert np.all(gg[k] == 0.0), k
+            continue
+        rel = np.linalg.norm(gg[k] - ref) / nr
+        worst = max(worst, rel)
+        assert rel < 25 * U_BF16, (k, rel)
+    flat_ref = S.pack_params(g_ref).astype(np.float64)
+    tot = np.linalg.norm(g_gpu - flat_ref) / np.linalg.norm(flat_ref)
+    cos = g_gpu @ flat_ref / (np.linalg.norm(g_gpu) * np.linalg.norm(flat_ref))
+    print(f"gradient: worst tensor {worst:.3e}, total {tot:.3e}, cosine {cos:.6f}")
+    assert tot < 1e-2 and cos > 0.999
+    # loss without the gradient is the same number
+    assert net.loss_grad(ctx, np.arange(8), grad=False) == pytest.approx(L_gpu, rel=1e-6)
+
+
+def test_breakdown_falls_back_to_jacobi(S, small):
+    p, ctx, Kb, g = small
+    uj, ij = ctx.solve(rtol=1e-8)
+    net = S.Gnn(0, seed=1)
+    # NaN in the decoder: r.M r is not a number on the first iteration
+    flat = S.pack_params(random_params(5))
+    flat[-3] = np.nan
+    net.set_params(flat)
+    net.apply(ctx)
+    u, info = ctx.solve(rtol=1e-8, precond=S.PRECOND_LEARNED)
+    assert info["fell_back"] == 1 and info["converged"] == 1
+    assert np.linalg.norm(u - uj) / np.linalg.norm(uj) < 1e-7
+    # a strongly indefinite M (huge random decoder) also ends in a converged solve
+    net.set_params(S.pack_params(random_params(6, scale_out=50.0)))
+    net.apply(ctx)
+    u, info = ctx.solve(rtol=1e-8, precond=S.PRECOND_LEARNED)
+    assert info["converged"] == 1 and info["true_relres"] <= 1e-8
+
+
+def test_errors(S, small):
+    p, ctx, Kb, g = small
+    c2 = S.Context(0)
+    S.setup_problem(c2, p)
+    with pytest.raises(S.SfemError, match="ESTATE"):
+        c2.solve(rtol=1e-8, precond=S.PRECOND_LEARNED, raise_on_noconv=True)
+    with pytest.raises(S.SfemError, match="ESTATE"):
+        c2.precond()
+    net = S.Gnn(0, seed=1)
+    with pytest.raises(S.SfemError, match="ESTATE"):
+        net.loss_grad(c2, [0])          # no pairs yet
+    e = np.ones((1, Kb.shape[0]), np.float32)
+    c2.set_pairs((Kb @ e[0].astype(np.float64)).astype(np.float32)[None, :], e)
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        net.loss_grad(c2, [1])          # index out of range
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        net.loss_grad(c2, np.zeros(65, np.int32))
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        net.set_params(np.zeros(3, np.float32))
+
+
+def test_training_is_deterministic(S):
+    p = mg.learned_small(2, grid=(10, 3, 3))
+    ctx = S.Context(0)
+    S.setup_problem(ctx, p)
+    k = ctx.generate_pairs(3, 8, seed=3)
+    assert k >= 12
+    out = []
+    for _ in range(2):
+        net = S.Gnn(0, seed=9)
+        losses = net.train([ctx], steps=20, batch=16, lr=1e-3, seed=4)
+        out.append((losses, net.params()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_generated_pairs_are_consistent(S):
+    """r = K e for the stored pairs (checked through the loss of the untrained
+    network: with M = D^-1 the loss is an explicit function of (r, e))."""
+    p = mg.learned_small(3, grid=(6, 3, 3))
+    ctx = S.Context(0)
+    S.setup_problem(ctx, p)
+    k = ctx.generate_pairs(2, 6, seed=1)
+    assert 2 <= k <= 12
+    net = S.Gnn(0, seed=2)
+    L = net.loss_grad(ctx, np.arange(k), grad=False)
+    assert np.isfinite(L) and L > 0
+
+
+def test_training_gains_on_held_out_mesh(S):
+    """The headline property at test size: a network trained on three
+    blob-material cantilevers cuts the PCG iterations of a fourth, unseen one
+    (Jacobi: ~1,650 at 40x6x6; trained: ~650-750)."""
+    grid = (30, 5, 5)
+    ctxs = []
+    for mi in range(3):
+        c = S.Context(0)
+        S.setup_problem(c, mg.learned_small(mi, grid=grid))
+        assert c.generate_pairs(10, 20, seed=mi + 1) > 100
+        ctxs.append(c)
+    held = S.Context(0)
+    S.setup_problem(held, mg.learned_small(0, grid=grid, held_out=True))
+    net = S.Gnn(0, seed=5)
+    losses = net.train(ctxs, steps=800, batch=32, lr=1e-3, seed=1)
+    assert losses[-100:].mean() < losses[:20].mean()
+    net.apply(held)
+    uj, ij = held.solve(rtol=1e-8)
+    ul, il = held.solve(rtol=1e-8, precond=S.PRECOND_LEARNED)
+    print(f"held-out: Jacobi {ij['iters']} its {ij['ms_solve']:.1f} ms, "
+          f"learned {il['iters']} its {il['ms_solve']:.1f} ms")
+    assert il["converged"] and not il["fell_back"] and il["true_relres"] <= 1e-8
+    assert il["iters"] <= 0.7 * ij["iters"]
+    assert np.linalg.norm(ul - uj) / np.linalg.norm(uj) < 1e-6
+    # the mixed-precision modes accept the learned preconditioner too
+    c32 = S.Context(0)
+    S.setup_problem(c32, mg.learned_small(0, grid=grid, held_out=True), f32_copy=True)
+    net.apply(c32)
+    for mode in (S.MODE_F32_IR, S.MODE_F32_RR):
+        u, info = c32.solve(rtol=1e-8, mode=mode, precond=S.PRECOND_LEARNED)
+        assert info["converged"] and info["true_relres"] <= 1e-8, (mode, info)
+        assert np.linalg.norm(u - uj) / np.linalg.norm(uj) < 1e-6

@@ -203,16 +203,60 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
+def train_network(args, mg, sfem, np):
+    """Trains the learned preconditioner on blob-material cantilevers of
+    140x14x14 cells (164,640 tets each): pairs from Jacobi-PCG runs, Adam on
+    the device.  Returns the network and the training record."""
+    t0 = time.time()
+    ctxs, n_pairs = [], 0
+    for mi in range(args.train_meshes):
+        c = sfem.Context(0)
+        sfem.setup_problem(c, mg.learned_c4(mi))
+        n_pairs += c.generate_pairs(10, 64, seed=mi + 1)
+        ctxs.append(c)
+    t_pairs = time.time() - t0
+    log(f"[bench] training pairs: {n_pairs} from {len(ctxs)} meshes in {t_pairs:.1f}s")
+    net = sfem.Gnn(0, seed=5)
+    t1 = time.time()
+    n1 = int(0.6 * args.train_steps)
+    l1 = net.train(ctxs, steps=n1, batch=32, lr=1e-3, seed=1)
+    l2 = net.train(ctxs, steps=args.train_steps - n1, batch=32, lr=5e-4, seed=2)
+    losses = np.concatenate([l1, l2])
+    t_train = time.time() - t1
+    log(f"[bench] trained {args.train_steps} Adam steps in {t_train:.1f}s, minibatch loss "
+        f"{losses[:20].mean():.4f} -> {losses[-100:].mean():.4f}")
+    for c in ctxs:
+        c.close()
+    held = sfem.Context(0)
+    sfem.setup_problem(held, mg.learned_c4(0, held_out=True))
+    _, ij = held.solve(rtol=1e-8)
+    net.apply(held)
+    _, il = held.solve(rtol=1e-8, precond=sfem.PRECOND_LEARNED)
+    held.close()
+    log(f"[bench] held-out 164,640-tet blob mesh: Jacobi {ij['iters']} it {ij['ms_solve']:.1f} ms, "
+        f"learned {il['iters']} it {il['ms_solve']:.1f} ms (fell back {il['fell_back']})")
+    return {"net": net, "pairs": n_pairs, "train_meshes": args.train_meshes,
+            "steps": args.train_steps, "batch": 32, "pairs_s": t_pairs, "train_s": t_train,
+            "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-100:].mean()),
+            "heldout_c4": {"jacobi_iters": ij["iters"], "jacobi_ms": ij["ms_solve"],
+                           "learned_iters": il["iters"], "learned_ms": il["ms_solve"],
+                           "fell_back": il["fell_back"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=300000)
+    ap.add_argument("--cpu-sample", type=int, default=1000000)
     ap.add_argument("--skip-solve", action="store_true", help="assembly only (profiling)")
     ap.add_argument("--f32-ir", action="store_true", help="also time the FP32+FP64-IR solve")
     ap.add_argument("--inner-rtol", type=float, default=1e-2)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and the learned-preconditioner solve")
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--train-meshes", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -234,6 +278,8 @@ def main():
 
     from paper_2001_08849_amd import meshgen as mg
     from paper_2001_08849_amd import sfem
+
+    learned = None if args.no_learned else train_network(args, mg, sfem, np)
 
     t0 = time.time()
     prob = mg.cantilever_c2()
@@ -293,6 +339,19 @@ def main():
     total_ms = ctx.timer_stop()
     ctx.synchronize()
 
+    lsolves = []
+    if learned is not None and not args.skip_solve:
+        net = learned["net"]
+        for k in range(max(1, args.steps)):
+            ms_inf = net.apply(ctx)
+            _, info = ctx.solve(rtol=1e-8, out=u, precond=sfem.PRECOND_LEARNED, profile=True)
+            info["ms_inference"] = ms_inf
+            lsolves.append(info)
+            pinfo = ctx.precond_info()
+            log(f"[bench] learned {k}: inference {ms_inf:.1f} ms (theta {pinfo['theta']:.3f}), "
+                f"solve {info['ms_solve']:.1f} ms, {info['iters']} it, relres "
+                f"{info['true_relres']:.2e}, fell back {info['fell_back']}")
+
     asm_med = float(np.median(asm_ms))
     faces_per_s = s.n_faces / (asm_med * 1e-3)
     asm_bytes, spmv_bytes, _ = algorithmic_bytes(m.n_nodes, m.n_tets, s.n_faces, s.nnz,
@@ -322,10 +381,24 @@ def main():
         "topology_ms": ms_topo,
     }
     if solves:
-        out["solve_s"] = {"jacobi_f64": float(np.median([i["ms_solve"] for i in solves])) / 1e3,
-                          "learned_f32ir": None}
+        out["solve_s"] = {"jacobi_f64": float(np.median([i["ms_solve"] for i in solves])) / 1e3}
         out["solve_iters"] = {"jacobi_f64": solves[-1]["iters"]}
         out["solve_true_relres"] = {"jacobi_f64": solves[-1]["true_relres"]}
+        if lsolves:
+            ls = float(np.median([i["ms_solve"] for i in lsolves])) / 1e3
+            li = float(np.median([i["ms_inference"] for i in lsolves])) / 1e3
+            out["solve_s"]["learned"] = ls
+            out["solve_s"]["learned_incl_inference"] = ls + li
+            out["solve_iters"]["learned"] = lsolves[-1]["iters"]
+            out["solve_true_relres"]["learned"] = lsolves[-1]["true_relres"]
+            out["learned"] = {
+                "solver": "flexible PCG, K FP64, learned M (S' FP32, network BF16-MFMA), "
+                          "FP64 vectors and dots, true relres <= 1e-8",
+                "inference_s": li, "theta": ctx.precond_info()["theta"],
+                "fell_back": lsolves[-1]["fell_back"],
+                "speedup_vs_jacobi": out["solve_s"]["jacobi_f64"] / (ls + li),
+                "training": {k: v for k, v in learned.items() if k != "net"},
+            }
         spmv_ms = float(np.mean([i["ms_spmv_avg"] for i in solves]))
         ach = spmv_bytes / (spmv_ms * 1e-3) / 1e9
         out["roofline"] = {"kernel": "k_cg_spmv<double,double>", "bound": "hbm",

@@ -240,7 +240,11 @@ int sfem_synchronize(sfem_ctx* ctx);
  *   per layer l: z = W_l [h_I; h_J; e_IJ] + b_l,  e += relu(z),
  *                a_I = mean_J relu(z_IJ),  h += relu(U_l [h_I; a_I] + c_l)
  *   R_IJ = Wo e_IJ (3x3),  S_IJ = (R_IJ + R_JI^T) / 2, zero in the rows and
- *   columns of fixed DOFs;  M = D^-1/2 (I + S) D^-1/2.
+ *   columns of fixed DOFs;  M = D^-1/2 (I + theta S) D^-1/2 with
+ *   theta = min(1, 0.9 / (1.05 |lambda_min(S)|)) if lambda_min(S) < 0, else
+ *   1: I + theta S is then positive definite (lambda_min >= 0.1, allowing a
+ *   5% underestimate of |lambda_min| by the 40-step Lanczos run that
+ *   estimates it on the device).  Training uses the unscaled S.
  * Loss over pairs (r, e) with K e = r:  mean (M r - e).K(M r - e) / e.K e.
  * Parameters: one flat float32 vector, in this order, matrices row-major
  * [fan_out][fan_in]: Wn[64][8] bn[64] We[64][12] be[64], then per layer
@@ -289,13 +293,17 @@ int sfem_gnn_loss_grad(sfem_gnn* g, sfem_ctx* ctx, const int32_t* pair_ids, int 
  * minibatch loss. */
 int sfem_gnn_train(sfem_gnn* g, sfem_ctx* const* ctxs, int n_ctx, int steps, int batch,
                    double lr, uint64_t seed, float* losses);
-/* Inference: computes M for the context (features + forward) and enables
- * SFEM_PRECOND_LEARNED there.  ms (may be NULL): device time. */
+/* Inference: computes M for the context (features, forward, Lanczos and
+ * theta) and enables SFEM_PRECOND_LEARNED there.  ms (may be NULL): device
+ * time including the host round trips of the Lanczos run. */
 int sfem_gnn_apply(sfem_gnn* g, sfem_ctx* ctx, double* ms);
+/* theta and the Lanczos estimates of the extreme eigenvalues of S from the
+ * last sfem_gnn_apply (pointers may be NULL). */
+int sfem_get_precond_info(sfem_ctx* ctx, double* theta, double* lambda_min, double* lambda_max);
 
-/* The learned preconditioner of a context: correction S float32 [nnz] in the
- * order of sfem_get_csr's values, and d^-1/2 float64 [3 n_nodes] (either
- * pointer may be NULL). */
+/* The learned preconditioner of a context: the correction theta S (float32
+ * [nnz], in the order of sfem_get_csr's values, as the solver reads it) and
+ * d^-1/2 (float64 [3 n_nodes]); either pointer may be NULL. */
 int sfem_get_precond(sfem_ctx* ctx, float* correction, double* dinv_sqrt, int ptr_kind);
 /* z = M r (float64 [3 n_nodes]) with the learned preconditioner. */
 int sfem_precond_apply(sfem_ctx* ctx, const double* r, double* z, int ptr_kind);

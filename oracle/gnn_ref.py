@@ -17,9 +17,10 @@ Network (width H):
                    a_I = mean_J m_IJ,  t = Ul [h_I; a_I] + cl,  h <- h + relu(t)
   R_IJ = Wo e_IJ (3x3, row-major);  S_IJ = (R_IJ + R_JI^T) / 2
   S'_ij = S_ij, or 0 if DOF i or j is fixed
-  M = D^-1/2 (I + S') D^-1/2       (symmetric; positive definiteness is not
-                                    imposed: the solver judges it at run time
-                                    and falls back to Jacobi on breakdown)
+  M = D^-1/2 (I + theta S') D^-1/2, theta = min(1, 0.9 / (1.05 |lambda_min(S')|))
+      when lambda_min(S') < 0, else 1; so I + theta S' >= 0.1 I (positive
+      definite; the 1.05 leaves room for an estimate of lambda_min from
+      below in magnitude).  Training uses the unscaled S' (theta = 1).
 Loss over pairs (r_p, e_p) with K e_p = r_p:
   L = mean_p (M r_p - e_p)^T K (M r_p - e_p) / (e_p^T K e_p)
 """
@@ -146,8 +147,31 @@ def forward(P, g: Graph, layers: int = N_LAYERS):
     return Sp, c
 
 
+def correction_matrix(g: Graph, Sp):
+    """S' blocks as a scipy CSR matrix [3N, 3N]."""
+    import scipy.sparse as sp
+    n = 3 * g.N
+    rows = (3 * g.row[:, None, None] + np.arange(3)[None, :, None]).repeat(3, 2).ravel()
+    cols = (3 * g.bcol[:, None, None] + np.arange(3)[None, None, :]).repeat(3, 1).ravel()
+    return sp.csr_matrix((Sp.ravel(), (rows, cols)), shape=(n, n))
+
+
+def spd_theta(g: Graph, Sp):
+    """(theta, lambda_min(S')) with lambda_min computed exactly (dense for
+    small graphs, shift-free Lanczos to tight tolerance otherwise)."""
+    S = correction_matrix(g, Sp)
+    if S.shape[0] <= 4000:
+        lmin = float(np.linalg.eigvalsh(S.toarray())[0])
+    else:
+        import scipy.sparse.linalg as sla
+        lmin = float(sla.eigsh(S, k=1, which="SA", return_eigenvectors=False, tol=1e-10)[0])
+    theta = 1.0 if lmin >= 0.0 else min(1.0, 0.9 / (1.05 * -lmin))
+    return theta, lmin
+
+
 def apply_M(g: Graph, Sp, r):
-    """M r = D^-1/2 (I + S') D^-1/2 r for r [3N] or [3N, P]."""
+    """M r = D^-1/2 (I + S') D^-1/2 r for r [3N] or [3N, P] (pass theta S'
+    for the scaled inference preconditioner)."""
     s = 1.0 / np.sqrt(g.d)
     rh = (r.T * s).T
     y = rh.copy()

@@ -701,7 +701,7 @@ int sfem_gnn_apply(sfem_gnn* gh, sfem_ctx* h, double* ms) {
     SFEM_REQUIRE(g.device == c.device, SFEM_EINVAL, "network and context on different devices");
     SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
     SFEM_HIP(hipEventRecord(c.ev0, c.stream));
-    sfem::gnn_forward(c, g, false);
+    sfem::gnn_precondition(c, g);
     SFEM_HIP(hipEventRecord(c.ev1, c.stream));
     SFEM_HIP(hipEventSynchronize(c.ev1));
     float t = 0;
@@ -717,6 +717,16 @@ int sfem_get_precond(sfem_ctx* h, float* correction, double* dinv_sqrt, int ptr_
     download(c, correction, c.mval.get(), 9 * c.topo.nb, ptr_kind);
     download(c, dinv_sqrt, c.msqrt.get(), c.n_dof(), ptr_kind);
     SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_get_precond_info(sfem_ctx* h, double* theta, double* lambda_min, double* lambda_max) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "call sfem_gnn_apply first");
+    if (theta) *theta = c.m_theta;
+    if (lambda_min) *lambda_min = c.m_lmin;
+    if (lambda_max) *lambda_max = c.m_lmax;
     return SFEM_OK;
   });
 }

@@ -91,14 +91,15 @@ struct Ctx {
   // learned preconditioner M = diag(msqrt) (I + S') diag(msqrt), S' in the
   // scalar-CSR value layout of K
   bool have_learned = false;
+  double m_theta = 1.0, m_lmin = 0.0, m_lmax = 0.0;  // S' = theta S; Lanczos range of S
   DBuf<float> mval;
   DBuf<double> msqrt;
   DBuf<float> msqrt32;
   std::shared_ptr<GnnWork> gnn;  // features, activations and training pairs
 
   // solver work vectors
-  DBuf<double> x, r, z, p, p2, q, w, xs;
-  DBuf<float> x32, r32, z32, p32, p32b, q32, b32;
+  DBuf<double> x, r, z, p, p2, q, w, xs, rh;
+  DBuf<float> x32, r32, z32, p32, p32b, q32, b32, rh32;
   DBuf<double> partials;
   DBuf<CgScalars> sc;
   CgScalars* sc_host = nullptr;  // pinned mirror
@@ -132,6 +133,7 @@ void rhs_with_bc(Ctx& c);
 // spmv.hip
 void spmv_f64(Ctx& c, const double* val, const double* x, double* y, hipStream_t s);
 void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s);
+void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream_t s);
 // solve.hip
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info);
 double true_residual(Ctx& c, const double* u);

@@ -63,6 +63,11 @@ void gnn_features(Ctx& c);
 // Forward pass; keep = store every layer's activations (training).  Writes
 // S' into c.mval (scalar-CSR layout of K) and d^-1/2 into c.msqrt.
 void gnn_forward(Ctx& c, Gnn& g, bool keep);
+// Inference: forward, then S' = theta S with theta = min(1, 0.9 / (1.05
+// |lambda_min(S)|)) (lambda_min from Lanczos) so that I + S' is positive
+// definite; enables the learned preconditioner on the context.
+void gnn_precondition(Ctx& c, Gnn& g);
+constexpr int kLanczosSteps = 40;
 // Loss of the pairs `ids` (host indices) and, with grad, the gradient in
 // g.grad (same layout as the parameters).
 double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad);

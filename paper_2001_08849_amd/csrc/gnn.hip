@@ -701,6 +701,11 @@ __global__ void k_fill_f32(int64_t n, float v, float* __restrict__ out) {
   if (i < n) out[i] = v;
 }
 
+__global__ void k_fill_f64(int64_t n, double v, double* __restrict__ out) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
 // ------------------------------------------------------------------ pairs
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z += 0x9e3779b97f4a7c15ull;
@@ -748,6 +753,63 @@ __global__ void __launch_bounds__(256)
   if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+// Lanczos step: w -= alpha v + beta u, then (separately) u = v, v = w / |w|.
+__global__ void k_lanczos_w(int64_t n, double alpha, double beta, const double* __restrict__ v,
+                            const double* __restrict__ u, double* __restrict__ w) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] -= alpha * v[i] + beta * u[i];
+}
+
+__global__ void k_lanczos_next(int64_t n, double inv_beta, const double* __restrict__ w,
+                               double* __restrict__ v, double* __restrict__ u) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    u[i] = v[i];
+    v[i] = w[i] * inv_beta;
+  }
+}
+
+__global__ void k_scale_f64(int64_t n, double a, double* __restrict__ x) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= a;
+}
+
+__global__ void k_scale_f32(int64_t n, float a, float* __restrict__ x) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= a;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal (a, b)
+// (Sturm sequence; b[j] couples j-1 and j).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t j = 0; j < a.size(); ++j) {
+    const double off = j ? b[j] * b[j] : 0.0;
+    q = a[j] - x - (j ? off / q : 0.0);
+    if (q == 0.0) q = 1e-300;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// Smallest (k = 0) or largest (k = n-1) eigenvalue of the tridiagonal, by
+// bisection inside its Gershgorin interval.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k) {
+  double lo = 1e300, hi = -1e300;
+  for (size_t j = 0; j < a.size(); ++j) {
+    const double r = (j ? std::fabs(b[j]) : 0.0) + (j + 1 < a.size() ? std::fabs(b[j + 1]) : 0.0);
+    lo = std::min(lo, a[j] - r);
+    hi = std::max(hi, a[j] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(a, b, mid) > k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 int grid_for(int64_t items, int per_block, int cap) {
@@ -904,6 +966,49 @@ void gnn_forward(Ctx& c, Gnn& g, bool keep) {
       nb, w.erow.get(), tp.bptr.get(), tp.bcol.get(), w.etr.get(),
       c.any_fixed ? c.fixed.get() : nullptr, w.dS.get(), c.mval.get());
   SFEM_HIP(hipGetLastError());
+  c.have_learned = false;  // S is raw until gnn_precondition scales it
+}
+
+void gnn_precondition(Ctx& c, Gnn& g) {
+  gnn_forward(c, g, false);
+  const int64_t n = c.n_dof();
+  hipStream_t s = c.stream;
+  // Lanczos on the symmetric S from a fixed pseudo-random start
+  DBuf<double> v, u, w;
+  v.reserve(n);
+  u.reserve(n);
+  w.reserve(n);
+  k_random_load<<<div_up(n, 256), 256, 0, s>>>(n, 0x5eedull, 1.0, nullptr, v.get());
+  k_fill_f64<<<div_up(n, 256), 256, 0, s>>>(n, 0.0, u.get());
+  SFEM_HIP(hipGetLastError());
+  const double v0 = std::sqrt(dot(c, v.get(), v.get(), n));
+  k_scale_f64<<<div_up(n, 256), 256, 0, s>>>(n, 1.0 / v0, v.get());
+  std::vector<double> al, be{0.0};
+  for (int j = 0; j < kLanczosSteps; ++j) {
+    spmv_f32val(c, c.mval.get(), v.get(), w.get(), s);
+    const double a = dot(c, w.get(), v.get(), n);
+    k_lanczos_w<<<div_up(n, 256), 256, 0, s>>>(n, a, be.back(), v.get(), u.get(), w.get());
+    SFEM_HIP(hipGetLastError());
+    al.push_back(a);
+    const double b = std::sqrt(dot(c, w.get(), w.get(), n));
+    if (!(b > 1e-12 * std::fabs(a)) || !std::isfinite(b)) break;  // invariant subspace
+    be.push_back(b);
+    k_lanczos_next<<<div_up(n, 256), 256, 0, s>>>(n, 1.0 / b, w.get(), v.get(), u.get());
+  }
+  be.resize(al.size());
+  bool finite = true;
+  for (double a : al) finite = finite && std::isfinite(a);
+  c.m_lmin = finite ? tridiag_eig(al, be, 0) : NAN;
+  c.m_lmax = finite ? tridiag_eig(al, be, int(al.size()) - 1) : NAN;
+  double theta = 1.0;
+  if (finite && c.m_lmin < 0.0) theta = std::min(1.0, 0.9 / (1.05 * -c.m_lmin));
+  c.m_theta = theta;
+  if (theta < 1.0) {
+    k_scale_f32<<<div_up(9 * c.topo.nb, 256), 256, 0, s>>>(9 * c.topo.nb, float(theta),
+                                                            c.mval.get());
+    SFEM_HIP(hipGetLastError());
+  }
+  SFEM_HIP(hipStreamSynchronize(s));
   c.have_learned = true;
 }
 

@@ -318,38 +318,51 @@ __global__ void __launch_bounds__(kVecThreads)
   store_partials<2>(v, partials);
 }
 
-// x += alpha p; r -= alpha q (the learned preconditioner applies z after).
+// x += alpha p; r -= alpha q; rh = s r (the learned preconditioner applies
+// z after, gathering rh).
 template <typename P>
 __global__ void __launch_bounds__(kVecThreads)
     k_cg_xr(int64_t n, P* __restrict__ x, P* __restrict__ r, const P* __restrict__ p,
-            const P* __restrict__ q, const CgScalars* __restrict__ sc) {
+            const P* __restrict__ q, const P* __restrict__ s, P* __restrict__ rh,
+            const CgScalars* __restrict__ sc) {
   if (sc->converged) return;
   const P alpha = P(sc->alpha);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     x[i] += alpha * p[i];
-    r[i] -= alpha * q[i];
+    const P ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rh[i] = s[i] * ri;
   }
 }
 
-// Learned preconditioner z = M r = s (s r + S' (s r)), S' in the scalar-CSR
-// value layout of K (FP32), s = diag(K)^-1/2.  Partials (r.z_new), (r.r),
-// (r.z_old): the flexible (Polak-Ribiere) beta needs the previous z.
-// sc == nullptr: run unconditionally (start and residual replacement).
+// rh = s r (start and residual replacement).
+template <typename P>
+__global__ void k_rh(int64_t n, const P* __restrict__ s, const P* __restrict__ r,
+                     P* __restrict__ rh) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) rh[i] = s[i] * r[i];
+}
+
+// Learned preconditioner z = M r = s (rh + S' rh), rh = s r, S' in the
+// scalar-CSR value layout of K (FP32), s = diag(K)^-1/2.  Partials
+// (r.z_new), (r.r), (r.z_old): the flexible (Polak-Ribiere) beta needs the
+// previous z.  sc == nullptr: run unconditionally (start and replacement).
 template <typename P, int LPR, bool PAIR>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_mapply(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
              const float* __restrict__ mval, const P* __restrict__ s, const P* __restrict__ r,
-             P* __restrict__ z, const CgScalars* __restrict__ sc, double* __restrict__ partials) {
+             const P* __restrict__ rh, P* __restrict__ z, const CgScalars* __restrict__ sc,
+             double* __restrict__ partials) {
   if (sc && sc->converged) return;
-  const ScaledX<P> xf{r, s};
+  const PlainX<P> xf{rh};
   double v[3] = {0.0, 0.0, 0.0};
   row_apply<float, LPR, PAIR>(N, bptr, bcol, mval, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
-      const double si = double(s[i]), ri = double(r[i]);
-      const P zi = P(si * (si * ri + y[a]));
+      const double ri = double(r[i]);
+      const P zi = P(double(s[i]) * (double(rh[i]) + y[a]));
       v[0] += ri * double(zi);
       v[1] += ri * ri;
       v[2] += ri * double(z[i]);
@@ -563,16 +576,24 @@ struct CgBuffers {
   void *b, *x, *r, *z, *p0, *p1, *q;  // p0: search direction (p1 unused)
   const float* mval = nullptr;        // learned preconditioner S' (null: Jacobi)
   const void* msq = nullptr;          // its diag(K)^-1/2, typed like the vectors
+  void* rh = nullptr;                 // s r, typed like the vectors
 };
 
+// z = M r; with fresh_rh the scaled residual rh = s r is formed first (it
+// is otherwise maintained by k_cg_xr).
 template <typename P>
-void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded) {
+void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fresh_rh) {
   const RowSched rs = c.sched32;
   const int rg = row_grid(c.N, rs);
+  const int64_t n = c.n_dof();
+  if (fresh_rh) {
+    k_rh<P><<<div_up(n, 256), 256, 0, c.stream>>>(n, (const P*)B.msq, r, (P*)B.rh);
+    SFEM_HIP(hipGetLastError());
+  }
 #define L_(LPR, PAIR)                                                                         \
   k_mapply<P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                             \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), B.mval, (const P*)B.msq, r, z,               \
-      guarded ? c.sc.get() : nullptr, c.partials.get())
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), B.mval, (const P*)B.msq, r,                  \
+      (const P*)B.rh, z, guarded ? c.sc.get() : nullptr, c.partials.get())
   SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
@@ -609,8 +630,9 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k + 1], s));
     finalize(c, kFinAlpha, rg);
     if (B.mval) {
-      k_cg_xr<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, p, (const P*)B.q, c.sc.get());
-      mapply<P>(c, B, (const P*)B.r, (P*)B.z, true);
+      k_cg_xr<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, p, (const P*)B.q,
+                                            (const P*)B.msq, (P*)B.rh, c.sc.get());
+      mapply<P>(c, B, (const P*)B.r, (P*)B.z, true, false);
       finalize(c, kFinBetaFlex, mapply_parts(c));
     } else {
       k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p, (const P*)B.q,
@@ -648,7 +670,7 @@ void cg_replace(Ctx& c, const CgBuffers& B) {
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinReplace, rg);
   if (B.mval) {
-    mapply<P>(c, B, (const P*)B.r, (P*)B.z, false);
+    mapply<P>(c, B, (const P*)B.r, (P*)B.z, false, true);
     finalize(c, kFinReplaceM, mapply_parts(c));
   }
 }
@@ -694,7 +716,7 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinStart, vg);
   if (B.mval) {
-    mapply<P>(c, B, (const P*)B.r, (P*)B.z, false);
+    mapply<P>(c, B, (const P*)B.r, (P*)B.z, false, true);
     finalize(c, kFinStartM, mapply_parts(c));
   }
   const double tol2 = tol_abs * tol_abs;
@@ -762,6 +784,17 @@ void spmv_f32_sched(Ctx& c, const RowSched& rs, const float* val, const float* x
   const int rg = row_grid(c.N, rs);
 #define L_(LPR, PAIR)                                                      \
   k_spmv<float, float, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(        \
+      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
+  SFEM_SCHED_SWITCH(rs.variant, L_)
+#undef L_
+  SFEM_HIP(hipGetLastError());
+}
+
+void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream_t s) {
+  const RowSched rs = c.sched32;
+  const int rg = row_grid(c.N, rs);
+#define L_(LPR, PAIR)                                                      \
+  k_spmv<float, double, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(       \
       c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
   SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
@@ -849,7 +882,9 @@ static void ensure_work(Ctx& c, bool f32) {
   c.q.reserve(n);
   c.w.reserve(n);
   c.xs.reserve(n);
+  c.rh.reserve(n);
   if (f32) {
+    c.rh32.reserve(n);
     c.x32.reserve(n);
     c.r32.reserve(n);
     c.z32.reserve(n);
@@ -928,6 +963,7 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
     if (learned) {
       B.mval = c.mval.get();
       B.msq = c.msqrt.get();
+      B.rh = c.rh.get();
     }
     bool met = false, brk = false;
     info.iters = rr ? pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm,
@@ -968,6 +1004,7 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
       const double tol = inner * std::sqrt(double(n));  // ||r / scale|| = sqrt(n)
       B.mval = use_learned ? c.mval.get() : nullptr;
       B.msq = c.msqrt32.get();
+      B.rh = c.rh32.get();
       iters += pcg<float, float>(c, B, r64, 1.0 / scale, tol, max_iter - iters,
                                  std::max(check_every, 200), met, brk, /*replace=*/false);
       k_axpy_f32<<<div_up(n, 256), 256, 0, c.stream>>>(n, scale, c.x32.get(), u);
@@ -1014,7 +1051,8 @@ void learned_apply(Ctx& c, const double* r, double* z) {
   CgBuffers B{};
   B.mval = c.mval.get();
   B.msq = c.msqrt.get();
-  mapply<double>(c, B, r, z, false);
+  B.rh = c.rh.get();
+  mapply<double>(c, B, r, z, false, true);
 }
 
 }  // namespace sfem

@@ -35,7 +35,7 @@ EXPORTS = [
     "sfem_gnn_num_params", "sfem_gnn_create", "sfem_gnn_destroy", "sfem_gnn_last_error",
     "sfem_gnn_get_params", "sfem_gnn_set_params", "sfem_gnn_set_pairs",
     "sfem_gnn_generate_pairs", "sfem_gnn_loss_grad", "sfem_gnn_train", "sfem_gnn_apply",
-    "sfem_get_precond", "sfem_precond_apply",
+    "sfem_get_precond", "sfem_precond_apply", "sfem_get_precond_info",
 ]
 
 
@@ -110,6 +110,7 @@ def lib() -> C.CDLL:
             "sfem_gnn_apply": (i32, [vp, vp, C.POINTER(dbl)]),
             "sfem_get_precond": (i32, [vp, vp, vp, i32]),
             "sfem_precond_apply": (i32, [vp, vp, vp, i32]),
+            "sfem_get_precond_info": (i32, [vp] + [C.POINTER(dbl)] * 3),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -343,6 +344,12 @@ class Context:
         self._check(self._L.sfem_get_precond(self._h, S.ctypes.data_as(C.c_void_p),
                                              s.ctypes.data_as(C.c_void_p), PTR_HOST))
         return S, s
+
+    def precond_info(self):
+        """{'theta', 'lambda_min', 'lambda_max'} of the last Gnn.apply."""
+        t, a, b = C.c_double(), C.c_double(), C.c_double()
+        self._check(self._L.sfem_get_precond_info(self._h, C.byref(t), C.byref(a), C.byref(b)))
+        return {"theta": t.value, "lambda_min": a.value, "lambda_max": b.value}
 
     def precond_apply(self, r):
         z = np.empty(self.sizes().n_rows, dtype=np.float64)

@@ -138,3 +138,22 @@ def test_graph_transpose_and_features(tiny):
     # Jacobi-scaled diagonal blocks have unit diagonals
     dk = g.y[g.row == g.bcol][:, [0, 4, 8]]
     np.testing.assert_allclose(dk, 1.0, rtol=1e-14)
+
+
+def test_spd_theta_makes_M_positive_definite(tiny):
+    g, K, R, E = tiny
+    for seed, so in ((1, 0.05), (2, 3.0), (3, 30.0)):
+        P = random_params(seed, scale_out=so)
+        Sp, _ = G.forward(P, g)
+        theta, lmin = G.spd_theta(g, Sp)
+        S = G.correction_matrix(g, Sp).toarray()
+        ev = np.linalg.eigvalsh(S)
+        assert lmin == pytest.approx(ev[0], rel=1e-10, abs=1e-12)
+        if lmin >= -0.9 / 1.05:
+            assert theta == 1.0
+        else:
+            assert theta == pytest.approx(0.9 / (1.05 * -lmin))
+        lam = np.linalg.eigvalsh(np.eye(S.shape[0]) + theta * S)
+        assert lam[0] >= 0.1 - 1e-12
+    # the strongest output needs the scaling
+    assert theta < 1.0

@@ -76,21 +76,31 @@ def fp32_params(S, P):
     return flat, {k: v.astype(np.float64) for k, v in S.unpack_params(flat).items()}
 
 
-def test_forward_parity(S, small):
+@pytest.mark.parametrize("seed,scale_out", [(3, 0.3), (8, 3.0)])
+def test_forward_parity(S, small, seed, scale_out):
     p, ctx, Kb, g = small
     rp, ci, _ = ctx.csr()
     assert np.array_equal(rp, Kb.indptr) and np.array_equal(ci, Kb.indices)
-    flat, P64 = fp32_params(S, random_params(3))
+    flat, P64 = fp32_params(S, random_params(seed, scale_out))
     net = S.Gnn(0, seed=1)
     net.set_params(flat)
     net.apply(ctx)
     S_gpu, s_gpu = ctx.precond()
+    info = ctx.precond_info()
     Sp_ref, _ = G.forward(P64, g)
+    theta_ref, lmin_ref = G.spd_theta(g, Sp_ref)
     S_ref = blocks_to_csr(g, Kb, Sp_ref)
-    rel = np.linalg.norm(S_gpu - S_ref) / np.linalg.norm(S_ref)
-    print(f"S' relative Frobenius error {rel:.3e}")
+    raw = S_gpu.astype(np.float64) / info["theta"]
+    rel = np.linalg.norm(raw - S_ref) / np.linalg.norm(S_ref)
+    print(f"S relative Frobenius error {rel:.3e}; lambda_min {info['lambda_min']:.5f} "
+          f"(exact {lmin_ref:.5f}), theta {info['theta']:.5f} (exact {theta_ref:.5f})")
     assert rel < 5 * U_BF16
-    assert np.abs(S_gpu - S_ref).max() <= 10 * U_BF16 * np.abs(S_ref).max()
+    assert np.abs(raw - S_ref).max() <= 10 * U_BF16 * np.abs(S_ref).max()
+    # the Lanczos estimate of lambda_min(S) and theta follow the exact ones
+    assert info["lambda_min"] == pytest.approx(lmin_ref, rel=10 * U_BF16)
+    assert info["theta"] == pytest.approx(theta_ref, rel=10 * U_BF16)
+    if scale_out > 1:
+        assert info["theta"] < 1.0
     np.testing.assert_allclose(s_gpu, 1.0 / np.sqrt(Kb.diagonal()), rtol=1e-14)
     # fixed DOFs: rows and columns of S' are exactly zero
     fixed = np.zeros(Kb.shape[0], bool)
@@ -100,7 +110,7 @@ def test_forward_parity(S, small):
     # z = M r against the reference M
     r = np.random.default_rng(0).standard_normal(Kb.shape[0])
     z = ctx.precond_apply(r)
-    zr = G.apply_M(g, Sp_ref, r)
+    zr = G.apply_M(g, theta_ref * Sp_ref, r)
     assert np.linalg.norm(z - zr) / np.linalg.norm(zr) < 5 * U_BF16
 
 

@@ -308,6 +308,77 @@ int sfem_get_precond(sfem_ctx* ctx, float* correction, double* dinv_sqrt, int pt
 /* z = M r (float64 [3 n_nodes]) with the learned preconditioner. */
 int sfem_precond_apply(sfem_ctx* ctx, const double* r, double* z, int ptr_kind);
 
+/* ----------------------------------------------------------------------------
+ * Batched solves: many meshes, up to four load cases each, in one solve
+ * (an extension; the paper solves one mesh).  The meshes are concatenated
+ * into one block-diagonal system built by the single-mesh pipeline; the four
+ * load cases of a mesh share K and are multiplied together.  Every (mesh,
+ * load case) pair is its own CG system with its own scalars, Jacobi
+ * preconditioner and FP64 true-residual stopping test (every check_every
+ * iterations, with residual replacement); a system that meets rtol, breaks
+ * down (p.K p <= 0) or stagnates for 40 checks stops iterating while the
+ * others continue.  With use_graph, one check period (check_every
+ * iterations + the residual check) is captured in a hipGraph once and
+ * replayed.  Inputs are host arrays, copied; errors through
+ * sfem_batch_last_error.
+ */
+typedef struct sfem_batch sfem_batch;
+
+int sfem_batch_create(sfem_batch** out, int device);
+void sfem_batch_destroy(sfem_batch* b);
+const char* sfem_batch_last_error(const sfem_batch* b);
+/* Adds a mesh (0-based local node ids): xyz float64 [n_nodes][3], tets int32
+ * [n_tets][4], homogeneous E, nu, and the local DOFs fixed to zero.
+ * *mesh_index (may be NULL) gets its index. */
+int sfem_batch_add_mesh(sfem_batch* b, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                        const int32_t* tets, double E, double nu, int64_t n_fixed,
+                        const int32_t* fixed_dofs, int* mesh_index);
+/* Uniform traction t (force per area) on triangles (local node ids, int32
+ * [n_tri][3]) of a mesh, for load case rhs in [0, 4).  Load cases without
+ * any traction are zero and count as solved. */
+int sfem_batch_add_traction(sfem_batch* b, int mesh, int rhs, int64_t n_tri,
+                            const int32_t* tri, const double t[3]);
+/* Topology, assembly, loads and BCs of all meshes (flags: SFEM_ASM_F64 or
+ * SFEM_ASM_F32_COPY, needed by SFEM_MODE_F32_RR). */
+int sfem_batch_build(sfem_batch* b, int flags);
+int sfem_batch_sizes(sfem_batch* b, int* n_meshes, int64_t* n_nodes, int64_t* n_tets,
+                     int64_t* n_faces, int64_t* nnz);
+/* Autotuner.  Meshes fall into size buckets by node count: 0 (< 8192),
+ * 1 (< 32768), 2 (larger).  For each non-empty bucket every (lanes per node
+ * row in {8, 16, 32}) x (node rows per workgroup in {16, 64, 256}) schedule
+ * of the 4-right-hand-side product is timed over `reps` launches (0: 5) of
+ * that bucket alone; the fastest is kept and cached for the process under
+ * the bucket's shape (bucket, log2 of its node rows, mean block degree).
+ * With use_cache, a cached shape is reused without timing.  precision:
+ * SFEM_ASM_F64 or SFEM_ASM_F32_COPY.  *us: the tuned product's time. */
+int sfem_batch_autotune(sfem_batch* b, int reps, int use_cache, int precision, double* us);
+int sfem_batch_get_schedule(sfem_batch* b, int bucket, int* lanes_per_row, int* rows_per_wg,
+                            int* n_meshes, int* from_cache);
+
+typedef struct {
+  int mode;           /* SFEM_MODE_F64 or SFEM_MODE_F32_RR (FP32 products, FP64 rest) */
+  double rtol;        /* per system, on the FP64 true relative residual */
+  int max_iter;       /* cap on iterations (0: 100000) */
+  int check_every;    /* iterations per check period (0: 50) */
+  int use_graph;      /* nonzero: replay a captured hipGraph per period */
+} sfem_batch_opts;
+
+typedef struct {
+  double ms_solve;    /* device time of the whole batched solve */
+  int periods;        /* check periods run */
+  int all_converged;
+  int max_iters;      /* most iterations of any system */
+  double worst_relres;
+} sfem_batch_info;
+
+/* Solves all systems; SFEM_ENOCONV if any did not converge. */
+int sfem_batch_solve(sfem_batch* b, const sfem_batch_opts* opts, sfem_batch_info* info);
+/* Displacements of (mesh, load case): float64 [3 n_nodes(mesh)]. */
+int sfem_batch_get_solution(sfem_batch* b, int mesh, int rhs, double* u, int ptr_kind);
+/* Per system s = 4 mesh + rhs (host arrays of 4 n_meshes, NULL to skip). */
+int sfem_batch_get_system_info(sfem_batch* b, int32_t* iters, int32_t* converged,
+                               double* relres, int32_t* breakdown);
+
 #ifdef __cplusplus
 }
 #endif

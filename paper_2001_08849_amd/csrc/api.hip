@@ -1,18 +1,10 @@
 // extern "C" entry points of include/sfem.h.  Every call catches the
 // library's internal errors and turns them into an sfem_status plus a
 // message kept on the context.
-#include "gnn.h"
+#include "handles.h"
 
 using sfem::Ctx;
 using sfem::Error;
-
-struct sfem_ctx {
-  Ctx c;
-};
-
-struct sfem_gnn {
-  sfem::Gnn g;
-};
 
 namespace {
 
@@ -204,8 +196,6 @@ int sfem_set_mesh(sfem_ctx* h, int64_t n_nodes, const double* xyz, int64_t n_tet
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(n_nodes > 0 && n_tets > 0 && xyz && tets, SFEM_EINVAL, "empty or null mesh");
     SFEM_REQUIRE(n_nodes < (int64_t(1) << 21), SFEM_EINVAL, "n_nodes must be < 2^21");
-    SFEM_REQUIRE(double(n_nodes) * double(n_nodes) * 4.0 * double(n_tets) < 9.2e18, SFEM_EINVAL,
-                 "n_nodes^2 * 4 n_tets must be < 2^63");
     c.topo.valid = false;
     c.N = n_nodes;
     c.T = n_tets;

@@ -1,0 +1,913 @@
+// Many meshes and load cases in one solve.
+//
+// The meshes are concatenated into one mesh with disjoint node ranges, so
+// the single-mesh pipeline (face adjacency, pattern, assembly, loads, BCs)
+// builds all of them in one pass and K is block diagonal.  Up to four load
+// cases per mesh share K: vectors are stored [3N][4] (the four right-hand
+// sides of a DOF side by side) and one product reads K once for all four.
+//
+// CG runs one independent system per (mesh, load case): workgroups own runs
+// of node rows inside one mesh and write per-workgroup partial sums per load
+// case; a one-thread-per-system kernel adds the partials of its mesh in a
+// fixed order (bit-reproducible) and updates that system's scalars.  A
+// system leaves the iteration once its FP64 true residual, recomputed every
+// `check_every` iterations, meets the tolerance (or stagnates, or breaks
+// down).  The iterations of a check period are captured once in a hipGraph
+// and replayed until every system has finished.
+//
+// Autotuner: meshes fall into size buckets; for each bucket the lanes per
+// node row and the node rows per workgroup are timed over a candidate set
+// (the bucket's own product launch) and the choice is cached per bucket
+// shape for the rest of the process.
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "handles.h"
+
+namespace sfem {
+
+namespace {
+
+constexpr int kNR = 4;             // right-hand sides per product
+constexpr int kBThreads = 256;
+constexpr int kNumBuckets = 3;     // mesh sizes: < 8192, < 32768, >= 32768 nodes
+constexpr int kNumLpr = 3;
+constexpr int kLprs[kNumLpr] = {8, 16, 32};
+constexpr int kNumRw = 3;
+constexpr int kRws[kNumRw] = {16, 64, 256};
+
+struct BScal {
+  double rz, pq, alpha, beta, rr, rr_true, ff, tol2, best;
+  int active, iters, breakdown, stale;
+};
+
+enum BOp { kBStart = 0, kBAlpha = 1, kBBeta = 2, kBReplace = 3 };
+
+template <int LPR>
+__device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Block sum of 8 doubles; thread j < 8 stores sum j at out[j].
+__device__ __forceinline__ void block_store8(double (&v)[8], double* out) {
+  __shared__ double sm[kBThreads / 64][8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = wave_sum(v[j]);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sm[wid][j] = v[j];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double s = 0.0;
+    for (int q = 0; q < kBThreads / 64; ++q) s += sm[q][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// True when every system of the workgroup's mesh has finished (then the
+// workgroup has nothing to do; a block-uniform test).
+__device__ __forceinline__ bool mesh_done(const BScal* __restrict__ sc, int m) {
+  if (!sc) return false;
+  const BScal* s = sc + m * kNR;
+  return !(s[0].active | s[1].active | s[2].active | s[3].active);
+}
+
+// Product of K with a [3N][4] panel over the node rows [wr[w].x, wr[w].y)
+// of workgroup w = wbase + blockIdx.x.
+//   EPI 0: Y = K X, partials (x.y) per load case.
+//   EPI 1: residual replacement Y = F - K X, Z = dinv Y, partials (y.y),
+//          (y.z) per load case.
+// Partials: part[w][k][2].
+template <typename VT, int LPR, int EPI>
+__global__ void __launch_bounds__(kBThreads)
+    k_bspmm(int wbase, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+            const BScal* __restrict__ sc, const int32_t* __restrict__ bptr,
+            const int32_t* __restrict__ bcol, const VT* __restrict__ val,
+            const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ Y,
+            double* __restrict__ Z, const double* __restrict__ dinv, double* __restrict__ part) {
+  constexpr int G = kBThreads / LPR;
+  const int w = wbase + blockIdx.x;
+  if (mesh_done(sc, wmesh[w])) return;
+  const int2 rr = wr[w];
+  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int I0 = rr.x; I0 < rr.y; I0 += G) {
+    const int I = I0 + g;
+    const bool valid = I < rr.y;
+    int rb = 0, deg = 0;
+    if (valid) {
+      rb = bptr[I];
+      deg = bptr[I + 1] - rb;
+    }
+    const int td = 3 * deg;
+    const VT* v = val + 9 * int64_t(rb);
+    double acc[3][kNR];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
+    for (int c = sub; c < td; c += LPR) {
+      const int jj = c / 3;
+      const int64_t col = 3 * int64_t(bcol[rb + jj]) + (c - 3 * jj);
+      const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
+      const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
+      const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
+      const double a3[3] = {double(v[c]), double(v[td + c]), double(v[2 * td + c])};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < kNR; ++k) acc[a][k] += a3[a] * x4[k];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
+    if (valid && sub == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = 3 * int64_t(I) + a;
+#pragma unroll
+        for (int k = 0; k < kNR; ++k) {
+          const int64_t e = i * kNR + k;
+          if constexpr (EPI == 0) {
+            Y[e] = acc[a][k];
+            pv[2 * k] += X[e] * acc[a][k];
+          } else {
+            const double r = F[e] - acc[a][k];
+            const double z = dinv[i] * r;
+            Y[e] = r;
+            Z[e] = z;
+            pv[2 * k] += r * r;
+            pv[2 * k + 1] += r * z;
+          }
+        }
+      }
+    }
+  }
+  block_store8(pv, part + int64_t(w) * 8);
+}
+
+// p = z + beta p on active systems.
+__global__ void __launch_bounds__(kBThreads)
+    k_bp(const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+         const BScal* __restrict__ sc, const double* __restrict__ Z, double* __restrict__ P) {
+  const int w = blockIdx.x;
+  if (mesh_done(sc, wmesh[w])) return;
+  const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
+  const BScal* s = sc + wmesh[w] * kNR;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
+    const BScal& q = s[e % kNR];
+    if (q.active) P[e] = Z[e] + q.beta * P[e];
+  }
+}
+
+// x += alpha p; r -= alpha q; z = dinv r on active systems; partials (r.z),
+// (r.r) per load case.
+__global__ void __launch_bounds__(kBThreads)
+    k_bupdate(const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+              const BScal* __restrict__ sc, const double* __restrict__ dinv,
+              double* __restrict__ X, double* __restrict__ R, double* __restrict__ Z,
+              const double* __restrict__ P, const double* __restrict__ Q,
+              double* __restrict__ part) {
+  const int w = blockIdx.x;
+  if (mesh_done(sc, wmesh[w])) return;
+  const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
+  const BScal* s = sc + wmesh[w] * kNR;
+  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
+    const int k = int(e % kNR);
+    const BScal& q = s[k];
+    if (!q.active) continue;
+    const double r = R[e] - q.alpha * Q[e];
+    const double z = dinv[e / kNR] * r;
+    X[e] += q.alpha * P[e];
+    R[e] = r;
+    Z[e] = z;
+    pv[2 * k] += r * z;
+    pv[2 * k + 1] += r * r;
+  }
+  block_store8(pv, part + int64_t(w) * 8);
+}
+
+// Start from x = 0: r = f, z = dinv f, p = 0; partials (r.z), (r.r).
+__global__ void __launch_bounds__(kBThreads)
+    k_bstart(const int2* __restrict__ wr, const double* __restrict__ dinv,
+             const double* __restrict__ F, double* __restrict__ X, double* __restrict__ R,
+             double* __restrict__ Z, double* __restrict__ P, double* __restrict__ part) {
+  const int w = blockIdx.x;
+  const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
+  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
+    const int k = int(e % kNR);
+    const double f = F[e];
+    const double z = dinv[e / kNR] * f;
+    X[e] = 0.0;
+    R[e] = f;
+    Z[e] = z;
+    P[e] = 0.0;
+    pv[2 * k] += f * z;
+    pv[2 * k + 1] += f * f;
+  }
+  block_store8(pv, part + int64_t(w) * 8);
+}
+
+// One workgroup per mesh: sums the partials of the mesh's workgroups
+// [mw[m].x, mw[m].y) (thread t takes workgroups t, t + 256, ... in order,
+// then a fixed-shape tree) and updates the scalars of its 4 systems.
+// Finished systems are final and left untouched.
+__global__ void __launch_bounds__(kBThreads)
+    k_bfinal(int op, const int2* __restrict__ mw, const double* __restrict__ part,
+             BScal* __restrict__ sc, double rtol2, int max_stale) {
+  const int m = blockIdx.x;
+  BScal* sys = sc + m * kNR;
+  if (op != kBStart && mesh_done(sc, m)) return;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int w = mw[m].x + threadIdx.x; w < mw[m].y; w += kBThreads)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] += part[int64_t(w) * 8 + j];
+  __shared__ double tot[8];
+  block_store8(v, tot);
+  __syncthreads();
+  if (threadIdx.x >= kNR) return;
+  const int k = threadIdx.x;
+  const double v0 = tot[2 * k], v1 = tot[2 * k + 1];
+  BScal& c = sys[k];
+  switch (op) {
+    case kBStart:  // v0 = f.dinv f, v1 = f.f
+      c.rz = v0;
+      c.rr = v1;
+      c.rr_true = v1;
+      c.ff = v1;
+      c.tol2 = rtol2 * v1;
+      c.best = v1;
+      c.beta = 0.0;
+      c.alpha = 0.0;
+      c.pq = 0.0;
+      c.iters = 0;
+      c.breakdown = 0;
+      c.stale = 0;
+      c.active = (v1 > 0.0 && v1 > c.tol2) ? 1 : 0;
+      break;
+    case kBAlpha:  // v0 = p.K p
+      if (!c.active) return;
+      c.pq = v0;
+      c.alpha = c.rz / v0;
+      if (!(v0 > 0.0) || !isfinite(c.alpha)) {
+        c.alpha = 0.0;
+        c.active = 0;
+        c.breakdown = 1;
+      }
+      break;
+    case kBBeta:  // v0 = r.z, v1 = r.r
+      if (!c.active) return;
+      c.beta = c.rz > 0.0 ? v0 / c.rz : 0.0;
+      if (!isfinite(c.beta)) c.beta = 0.0;
+      c.rz = v0;
+      c.rr = v1;
+      c.iters += 1;
+      break;
+    case kBReplace:  // replaced residual: v0 = r.r, v1 = r.z
+      if (!c.active) return;
+      c.rr_true = v0;
+      c.rr = v0;
+      c.rz = v1;
+      if (v0 <= c.tol2) {
+        c.active = 0;
+      } else if (v0 < c.best) {
+        c.best = v0;
+        c.stale = 0;
+      } else if (c.best <= 1e4 * c.tol2 && ++c.stale >= max_stale) {
+        // stagnation counts only near the tolerance: CG residual norms may
+        // rise far above their start before they fall
+        c.active = 0;
+      }
+      break;
+  }
+}
+
+// Column k of a [3N][4] panel (rows [i0, i0 + n)) into a contiguous vector.
+__global__ void k_bcolumn(int64_t n, const double* __restrict__ X, int k, double* __restrict__ out) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = X[i * kNR + k];
+}
+
+__global__ void k_bset_column(int64_t n, const double* __restrict__ f, int k,
+                              double* __restrict__ F) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) F[i * kNR + k] = f[i];
+}
+
+__global__ void k_bzero(int64_t n, double* __restrict__ x) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// Autotuner cache: (bucket, log2 of the bucket's node rows, mean block
+// degree) -> (lanes per row, rows per workgroup).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;
+
+int bucket_of(int64_t nodes) { return nodes < 8192 ? 0 : (nodes < 32768 ? 1 : 2); }
+
+}  // namespace
+
+// ------------------------------------------------------------- host state
+struct BatchState {
+  int n_meshes = 0;
+  std::vector<int64_t> node0;        // [n_meshes + 1] first node of each mesh
+  std::vector<int> bucket;           // per mesh
+  int lpr[kNumBuckets] = {16, 16, 16};
+  int rw[kNumBuckets] = {64, 64, 64};
+  bool from_cache[kNumBuckets] = {false, false, false};
+  // workgroup table, bucket-major (a mesh's workgroups are contiguous)
+  std::vector<int2> h_wr;            // node rows [x, y) per workgroup
+  std::vector<int32_t> h_wmesh;      // mesh per workgroup
+  std::vector<int2> h_mw;            // workgroups [x, y) per mesh
+  int bw0[kNumBuckets + 1] = {0, 0, 0, 0};
+  DBuf<int2> wr, mw;
+  DBuf<int32_t> wmesh;
+  DBuf<double> F, X, R, Z, P, Q, part;
+  DBuf<BScal> sc;
+  BScal* sc_host = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_key[2] = {-1, -1};       // (mode, check_every) of the captured period
+  ~BatchState() {
+    drop_graph();
+    if (sc_host) (void)hipHostFree(sc_host);
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_key[0] = graph_key[1] = -1;
+  }
+  int n_wg() const { return bw0[kNumBuckets]; }
+};
+
+namespace {
+
+void build_table(Ctx& c, BatchState& b) {
+  b.h_wr.clear();
+  b.h_wmesh.clear();
+  b.h_mw.assign(b.n_meshes, int2{0, 0});
+  int w = 0;
+  for (int bk = 0; bk < kNumBuckets; ++bk) {
+    b.bw0[bk] = w;
+    for (int m = 0; m < b.n_meshes; ++m) {
+      if (b.bucket[m] != bk) continue;
+      const int first = w;
+      for (int64_t r = b.node0[m]; r < b.node0[m + 1]; r += b.rw[bk]) {
+        const int64_t r1 = std::min<int64_t>(r + b.rw[bk], b.node0[m + 1]);
+        b.h_wr.push_back(int2{int(r), int(r1)});
+        b.h_wmesh.push_back(m);
+        ++w;
+      }
+      b.h_mw[m] = int2{first, w};
+    }
+  }
+  b.bw0[kNumBuckets] = w;
+  b.wr.reserve(std::max(1, w));
+  b.wmesh.reserve(std::max(1, w));
+  b.mw.reserve(std::max(1, b.n_meshes));
+  b.part.reserve(size_t(std::max(1, w)) * 8);
+  SFEM_HIP(hipMemcpyAsync(b.wr.get(), b.h_wr.data(), sizeof(int2) * w, hipMemcpyHostToDevice,
+                          c.stream));
+  SFEM_HIP(hipMemcpyAsync(b.wmesh.get(), b.h_wmesh.data(), sizeof(int32_t) * w,
+                          hipMemcpyHostToDevice, c.stream));
+  SFEM_HIP(hipMemcpyAsync(b.mw.get(), b.h_mw.data(), sizeof(int2) * b.n_meshes,
+                          hipMemcpyHostToDevice, c.stream));
+  SFEM_HIP(hipStreamSynchronize(c.stream));
+  b.drop_graph();
+}
+
+// One product of K (FP64 or FP32 values) with a panel, bucket by bucket,
+// each with its own lanes-per-row; only_bucket >= 0 restricts to one.
+template <int EPI>
+void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, double* Y,
+           double* Z, int only_bucket = -1, bool use_sc = true) {
+  for (int bk = 0; bk < kNumBuckets; ++bk) {
+    if (only_bucket >= 0 && bk != only_bucket) continue;
+    const int nw = b.bw0[bk + 1] - b.bw0[bk];
+    if (nw == 0) continue;
+#define L_(VT, VAL, LPR)                                                                   \
+  k_bspmm<VT, LPR, EPI><<<nw, kBThreads, 0, c.stream>>>(                                  \
+      b.bw0[bk], b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(), \
+      c.topo.bcol.get(), VAL, X, F, Y, Z, c.dinv.get(), b.part.get())
+    if (f32) {
+      switch (b.lpr[bk]) {
+        case 8: L_(float, c.val32.get(), 8); break;
+        case 16: L_(float, c.val32.get(), 16); break;
+        default: L_(float, c.val32.get(), 32); break;
+      }
+    } else {
+      switch (b.lpr[bk]) {
+        case 8: L_(double, c.val.get(), 8); break;
+        case 16: L_(double, c.val.get(), 16); break;
+        default: L_(double, c.val.get(), 32); break;
+      }
+    }
+#undef L_
+    SFEM_HIP(hipGetLastError());
+  }
+}
+
+void bfinal(Ctx& c, BatchState& b, BOp op, double rtol2, int max_stale) {
+  k_bfinal<<<b.n_meshes, kBThreads, 0, c.stream>>>(int(op), b.mw.get(), b.part.get(), b.sc.get(),
+                                                   rtol2, max_stale);
+  SFEM_HIP(hipGetLastError());
+}
+
+// One check period: `iters` CG iterations, then the FP64 residual
+// replacement and the convergence test (kernel launches only: capturable).
+void period(Ctx& c, BatchState& b, bool f32, int iters, double rtol2, int max_stale) {
+  const int W = b.n_wg();
+  for (int k = 0; k < iters; ++k) {
+    k_bp<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), b.wmesh.get(), b.sc.get(), b.Z.get(),
+                                        b.P.get());
+    bspmm<0>(c, b, f32, b.P.get(), nullptr, b.Q.get(), nullptr);
+    bfinal(c, b, kBAlpha, rtol2, max_stale);
+    k_bupdate<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), b.wmesh.get(), b.sc.get(),
+                                             c.dinv.get(), b.X.get(), b.R.get(), b.Z.get(),
+                                             b.P.get(), b.Q.get(), b.part.get());
+    bfinal(c, b, kBBeta, rtol2, max_stale);
+  }
+  bspmm<1>(c, b, false, b.X.get(), b.F.get(), b.R.get(), b.Z.get());
+  bfinal(c, b, kBReplace, rtol2, max_stale);
+  SFEM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host driver
+void batch_prepare(Ctx& c, BatchState& b) {
+  const int64_t n = c.n_dof();
+  b.bucket.resize(b.n_meshes);
+  for (int m = 0; m < b.n_meshes; ++m) {
+    b.bucket[m] = bucket_of(b.node0[m + 1] - b.node0[m]);
+  }
+  for (auto* v : {&b.F, &b.X, &b.R, &b.Z, &b.P, &b.Q}) v->reserve(size_t(n) * kNR);
+  b.sc.reserve(size_t(b.n_meshes) * kNR);
+  if (!b.sc_host)
+    SFEM_HIP(hipHostMalloc((void**)&b.sc_host, sizeof(BScal) * b.n_meshes * kNR,
+                           hipHostMallocDefault));
+  k_bzero<<<div_up(n * kNR, 256), 256, 0, c.stream>>>(n * kNR, b.F.get());
+  SFEM_HIP(hipGetLastError());
+  build_table(c, b);
+}
+
+// Right-hand side k from the context's current f_bc.
+void batch_set_column(Ctx& c, BatchState& b, int k) {
+  const int64_t n = c.n_dof();
+  k_bset_column<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.f_bc.get(), k, b.F.get());
+  SFEM_HIP(hipGetLastError());
+}
+
+static std::tuple<int, int, int> tune_key(Ctx& c, BatchState& b, int bk) {
+  int64_t rows = 0, blocks = 0;
+  std::vector<int32_t> bp;
+  for (int m = 0; m < b.n_meshes; ++m)
+    if (b.bucket[m] == bk) rows += b.node0[m + 1] - b.node0[m];
+  // mean block degree of the bucket from the host copy of the row pointers
+  for (int m = 0; m < b.n_meshes; ++m) {
+    if (b.bucket[m] != bk) continue;
+    int32_t lohi[2];
+    SFEM_HIP(hipMemcpy(&lohi[0], c.topo.bptr.get() + b.node0[m], sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+    SFEM_HIP(hipMemcpy(&lohi[1], c.topo.bptr.get() + b.node0[m + 1], sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+    blocks += lohi[1] - lohi[0];
+  }
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= rows) ++lg;
+  const int deg = rows ? int((blocks + rows / 2) / rows) : 0;
+  return {bk, lg, deg};
+}
+
+// Times every (lanes per row, rows per workgroup) candidate for each
+// non-empty bucket unless the bucket's shape is cached (use_cache).
+// Returns the tuned product time in microseconds (all buckets).
+double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32) {
+  if (reps <= 0) reps = 5;
+  SFEM_HIP(hipStreamSynchronize(c.stream));
+  for (int bk = 0; bk < kNumBuckets; ++bk) {
+    bool any = false;
+    for (int m = 0; m < b.n_meshes; ++m) any = any || b.bucket[m] == bk;
+    if (!any) continue;
+    const auto key = tune_key(c, b, bk);
+    if (use_cache) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        b.lpr[bk] = it->second.first;
+        b.rw[bk] = it->second.second;
+        b.from_cache[bk] = true;
+        continue;
+      }
+    }
+    double best = 1e30;
+    int bl = b.lpr[bk], br = b.rw[bk];
+    for (int li = 0; li < kNumLpr; ++li)
+      for (int ri = 0; ri < kNumRw; ++ri) {
+        b.lpr[bk] = kLprs[li];
+        b.rw[bk] = kRws[ri];
+        build_table(c, b);
+        bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, false);  // warm
+        SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+        for (int r = 0; r < reps; ++r)
+          bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, false);
+        SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+        SFEM_HIP(hipEventSynchronize(c.ev1));
+        float ms = 0;
+        SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        if (ms < best) {
+          best = ms;
+          bl = kLprs[li];
+          br = kRws[ri];
+        }
+      }
+    b.lpr[bk] = bl;
+    b.rw[bk] = br;
+    b.from_cache[bk] = false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {bl, br};
+  }
+  build_table(c, b);
+  // time the tuned product over all buckets
+  bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, -1, false);
+  SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+  for (int r = 0; r < reps; ++r)
+    bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, -1, false);
+  SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+  SFEM_HIP(hipEventSynchronize(c.ev1));
+  float ms = 0;
+  SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  return 1e3 * ms / reps;
+}
+
+// Solves every (mesh, load case) system.  Returns the number of check
+// periods run; the per-system scalars are left in b.sc_host.
+int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int check_every,
+                bool use_graph, double* ms_out) {
+  SFEM_REQUIRE(!f32 || c.have_f32, SFEM_ESTATE, "the FP32 mode needs an FP32 copy of K");
+  const int W = b.n_wg();
+  const double rtol2 = rtol * rtol;
+  const int max_stale = 40;
+  const int n_sys = b.n_meshes * kNR;
+  SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+  k_bstart<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), c.dinv.get(), b.F.get(), b.X.get(),
+                                          b.R.get(), b.Z.get(), b.P.get(), b.part.get());
+  SFEM_HIP(hipGetLastError());
+  bfinal(c, b, kBStart, rtol2, max_stale);
+  if (use_graph && (b.graph_key[0] != int(f32) || b.graph_key[1] != check_every)) {
+    b.drop_graph();
+    SFEM_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      period(c, b, f32, check_every, rtol2, max_stale);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(c.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SFEM_HIP(hipStreamEndCapture(c.stream, &b.graph));
+    SFEM_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    b.graph_key[0] = int(f32);
+    b.graph_key[1] = check_every;
+  }
+  int periods = 0;
+  for (int done = 0; done < max_iter; done += check_every) {
+    if (use_graph) SFEM_HIP(hipGraphLaunch(b.exec, c.stream));
+    else period(c, b, f32, check_every, rtol2, max_stale);
+    ++periods;
+    SFEM_HIP(hipMemcpyAsync(b.sc_host, b.sc.get(), sizeof(BScal) * n_sys,
+                            hipMemcpyDeviceToHost, c.stream));
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    bool any = false;
+    for (int s = 0; s < n_sys; ++s) any = any || b.sc_host[s].active;
+    if (!any) break;
+  }
+  SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+  SFEM_HIP(hipEventSynchronize(c.ev1));
+  float ms = 0;
+  SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  if (ms_out) *ms_out = ms;
+  return periods;
+}
+
+void batch_column(Ctx& c, BatchState& b, int m, int k, double* out_dev) {
+  const int64_t i0 = 3 * b.node0[m], n = 3 * (b.node0[m + 1] - b.node0[m]);
+  k_bcolumn<<<div_up(n, 256), 256, 0, c.stream>>>(n, b.X.get() + i0 * kNR, k, out_dev);
+  SFEM_HIP(hipGetLastError());
+}
+
+void batch_system(const BatchState& b, int s, int* iters, int* converged, double* relres,
+                  int* breakdown) {
+  const BScal& q = b.sc_host[s];
+  *iters = q.iters;
+  *converged = q.rr_true <= q.tol2 ? 1 : 0;
+  *relres = q.ff > 0 ? std::sqrt(q.rr_true / q.ff) : 0.0;
+  *breakdown = q.breakdown;
+}
+
+int batch_bucket_info(const BatchState& b, int bk, int* lanes, int* rows, int* cached) {
+  *lanes = b.lpr[bk];
+  *rows = b.rw[bk];
+  *cached = b.from_cache[bk] ? 1 : 0;
+  int n = 0;
+  for (int m = 0; m < b.n_meshes; ++m) n += b.bucket[m] == bk;
+  return n;
+}
+
+}  // namespace sfem
+
+// ================================================================ C ABI
+struct sfem_batch {
+  sfem_ctx* ctx = nullptr;
+  int device = 0;
+  std::string err;
+  struct Mesh {
+    std::vector<double> xyz;
+    std::vector<int32_t> tets;
+    double E, nu;
+    std::vector<int32_t> fixed;
+  };
+  struct Trac {
+    int mesh, rhs;
+    std::vector<int32_t> tri;
+    double t[3];
+  };
+  std::vector<Mesh> meshes;
+  std::vector<Trac> trac;
+  bool built = false;
+  std::unique_ptr<sfem::BatchState> st = std::make_unique<sfem::BatchState>();
+};
+
+namespace {
+
+template <typename F>
+int bguarded(sfem_batch* h, F&& fn) {
+  if (!h) return SFEM_EINVAL;
+  h->err.clear();
+  try {
+    SFEM_HIP(hipSetDevice(h->device));
+    return fn(*h);
+  } catch (const sfem::Error& e) {
+    h->err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return SFEM_EINVAL;
+  }
+}
+
+int check(sfem_batch& h, int st) {
+  if (st != SFEM_OK) throw sfem::Error{st, std::string("batch build: ") + sfem_last_error(h.ctx)};
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfem_batch_create(sfem_batch** out, int device) {
+  if (!out) return SFEM_EINVAL;
+  *out = nullptr;
+  sfem_batch* h = new (std::nothrow) sfem_batch;
+  if (!h) return SFEM_ENOMEM;
+  h->device = device;
+  const int st = sfem_create(&h->ctx, device, nullptr);
+  if (st != SFEM_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return SFEM_OK;
+}
+
+void sfem_batch_destroy(sfem_batch* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  if (h->ctx) (void)hipStreamSynchronize(h->ctx->c.stream);
+  h->st.reset();  // graph and device buffers before the context's stream
+  sfem_destroy(h->ctx);
+  delete h;
+}
+
+const char* sfem_batch_last_error(const sfem_batch* h) { return h ? h->err.c_str() : "null batch"; }
+
+int sfem_batch_add_mesh(sfem_batch* h, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                        const int32_t* tets, double E, double nu, int64_t n_fixed,
+                        const int32_t* fixed_dofs, int* mesh_index) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(!b.built, SFEM_ESTATE, "the batch is already built");
+    SFEM_REQUIRE(n_nodes > 0 && n_tets > 0 && xyz && tets, SFEM_EINVAL, "empty mesh");
+    SFEM_REQUIRE(n_fixed >= 0 && (fixed_dofs || n_fixed == 0), SFEM_EINVAL, "bad fixed DOFs");
+    SFEM_REQUIRE(E > 0.0 && nu > -1.0 && nu < 0.5, SFEM_EINVAL, "need E > 0, -1 < nu < 0.5");
+    int64_t total = 0;
+    for (const auto& m : b.meshes) total += int64_t(m.xyz.size() / 3);
+    SFEM_REQUIRE(total + n_nodes < (int64_t(1) << 30), SFEM_EINVAL, "batch too large");
+    sfem_batch::Mesh m;
+    m.xyz.assign(xyz, xyz + 3 * n_nodes);
+    m.tets.assign(tets, tets + 4 * n_tets);
+    for (int32_t v : m.tets)
+      SFEM_REQUIRE(v >= 0 && v < n_nodes, SFEM_EINVAL, "tet node index out of range");
+    m.fixed.assign(fixed_dofs, fixed_dofs + n_fixed);
+    for (int32_t d : m.fixed)
+      SFEM_REQUIRE(d >= 0 && d < 3 * n_nodes, SFEM_EINVAL, "fixed DOF out of range");
+    m.E = E;
+    m.nu = nu;
+    b.meshes.push_back(std::move(m));
+    if (mesh_index) *mesh_index = int(b.meshes.size()) - 1;
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_add_traction(sfem_batch* h, int mesh, int rhs, int64_t n_tri, const int32_t* tri,
+                            const double t[3]) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(!b.built, SFEM_ESTATE, "the batch is already built");
+    SFEM_REQUIRE(mesh >= 0 && mesh < int(b.meshes.size()), SFEM_EINVAL, "bad mesh index");
+    SFEM_REQUIRE(rhs >= 0 && rhs < 4, SFEM_EINVAL, "rhs must be in [0, 4)");
+    SFEM_REQUIRE(n_tri >= 0 && t && (tri || n_tri == 0), SFEM_EINVAL, "bad traction");
+    const int64_t nn = int64_t(b.meshes[mesh].xyz.size() / 3);
+    sfem_batch::Trac tr{mesh, rhs, std::vector<int32_t>(tri, tri + 3 * n_tri), {t[0], t[1], t[2]}};
+    for (int32_t v : tr.tri) SFEM_REQUIRE(v >= 0 && v < nn, SFEM_EINVAL, "triangle node out of range");
+    b.trac.push_back(std::move(tr));
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_build(sfem_batch* h, int flags) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(!b.built, SFEM_ESTATE, "the batch is already built");
+    SFEM_REQUIRE(!b.meshes.empty(), SFEM_ESTATE, "add meshes first");
+    std::vector<double> xyz, E, nu;
+    std::vector<int32_t> tets, fixed;
+    std::vector<int64_t> node0{0};
+    for (const auto& m : b.meshes) {
+      const int64_t off = node0.back();
+      xyz.insert(xyz.end(), m.xyz.begin(), m.xyz.end());
+      for (int32_t v : m.tets) tets.push_back(int32_t(v + off));
+      E.insert(E.end(), m.tets.size() / 4, m.E);
+      nu.insert(nu.end(), m.tets.size() / 4, m.nu);
+      for (int32_t d : m.fixed) fixed.push_back(int32_t(d + 3 * off));
+      node0.push_back(off + int64_t(m.xyz.size() / 3));
+    }
+    sfem_ctx* ch = b.ctx;
+    check(b, sfem_set_mesh(ch, node0.back(), xyz.data(), int64_t(tets.size() / 4), tets.data(),
+                           SFEM_PTR_HOST));
+    check(b, sfem_set_material_per_tet(ch, E.data(), nu.data(), SFEM_PTR_HOST));
+    if (!fixed.empty())
+      check(b, sfem_set_dirichlet(ch, int64_t(fixed.size()), fixed.data(), nullptr, SFEM_PTR_HOST));
+    check(b, sfem_assemble(ch, flags));
+    sfem::Ctx& c = ch->c;
+    sfem::BatchState& s = *b.st;
+    s.n_meshes = int(b.meshes.size());
+    s.node0 = node0;
+    sfem::batch_prepare(c, s);
+    // load cases: f_user := tractions of case k, f_bc := BCs applied, column k
+    const int64_t n = c.n_dof();
+    for (int k = 0; k < 4; ++k) {
+      SFEM_HIP(hipMemsetAsync(c.f_user.get(), 0, sizeof(double) * n, c.stream));
+      bool any = false;
+      for (const auto& tr : b.trac) {
+        if (tr.rhs != k || tr.tri.empty()) continue;
+        const int64_t off = node0[tr.mesh];
+        std::vector<int32_t> g(tr.tri.size());
+        for (size_t i = 0; i < g.size(); ++i) g[i] = int32_t(tr.tri[i] + off);
+        sfem::DBuf<int32_t> dt;
+        dt.reserve(g.size());
+        SFEM_HIP(hipMemcpyAsync(dt.get(), g.data(), sizeof(int32_t) * g.size(),
+                                hipMemcpyHostToDevice, c.stream));
+        sfem::traction_load(c, int64_t(g.size() / 3), dt.get(), tr.t);
+        SFEM_HIP(hipStreamSynchronize(c.stream));
+        any = true;
+      }
+      if (!any) continue;
+      sfem::rhs_with_bc(c);
+      sfem::batch_set_column(c, s, k);
+    }
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    b.built = true;
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_sizes(sfem_batch* h, int* n_meshes, int64_t* n_nodes, int64_t* n_tets,
+                     int64_t* n_faces, int64_t* nnz) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    const sfem::Ctx& c = b.ctx->c;
+    if (n_meshes) *n_meshes = b.st->n_meshes;
+    if (n_nodes) *n_nodes = c.N;
+    if (n_tets) *n_tets = c.T;
+    if (n_faces) *n_faces = c.topo.nf;
+    if (nnz) *nnz = 9 * c.topo.nb;
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_autotune(sfem_batch* h, int reps, int use_cache, int precision, double* us) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    const bool f32 = precision == SFEM_ASM_F32_COPY;
+    SFEM_REQUIRE(!f32 || b.ctx->c.have_f32, SFEM_ESTATE, "no FP32 copy of K");
+    const double t = sfem::batch_autotune(b.ctx->c, *b.st, reps, use_cache != 0, f32);
+    if (us) *us = t;
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_get_schedule(sfem_batch* h, int bucket, int* lanes_per_row, int* rows_per_wg,
+                            int* n_meshes, int* from_cache) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    SFEM_REQUIRE(bucket >= 0 && bucket < 3, SFEM_EINVAL, "bucket must be in [0, 3)");
+    int l = 0, r = 0, fc = 0;
+    const int n = sfem::batch_bucket_info(*b.st, bucket, &l, &r, &fc);
+    if (lanes_per_row) *lanes_per_row = l;
+    if (rows_per_wg) *rows_per_wg = r;
+    if (n_meshes) *n_meshes = n;
+    if (from_cache) *from_cache = fc;
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_solve(sfem_batch* h, const sfem_batch_opts* o, sfem_batch_info* info) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    SFEM_REQUIRE(o && o->rtol > 0.0, SFEM_EINVAL, "need opts with rtol > 0");
+    SFEM_REQUIRE(o->mode == SFEM_MODE_F64 || o->mode == SFEM_MODE_F32_RR, SFEM_EINVAL,
+                 "batch modes: SFEM_MODE_F64 or SFEM_MODE_F32_RR");
+    const int every = o->check_every > 0 ? o->check_every : 50;
+    const int max_iter = o->max_iter > 0 ? o->max_iter : 100000;
+    double ms = 0;
+    const int periods = sfem::batch_solve(b.ctx->c, *b.st, o->mode == SFEM_MODE_F32_RR, o->rtol,
+                                          max_iter, every, o->use_graph != 0, &ms);
+    int all = 1, worst_it = 0;
+    double worst = 0.0;
+    for (int s = 0; s < b.st->n_meshes * 4; ++s) {
+      int it, conv, brk;
+      double rr;
+      sfem::batch_system(*b.st, s, &it, &conv, &rr, &brk);
+      all = all && conv;
+      worst = std::max(worst, rr);
+      worst_it = std::max(worst_it, it);
+    }
+    if (info) {
+      info->ms_solve = ms;
+      info->periods = periods;
+      info->all_converged = all;
+      info->max_iters = worst_it;
+      info->worst_relres = worst;
+    }
+    return all ? SFEM_OK : SFEM_ENOCONV;
+  });
+}
+
+int sfem_batch_get_solution(sfem_batch* h, int mesh, int rhs, double* u, int ptr_kind) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    SFEM_REQUIRE(mesh >= 0 && mesh < b.st->n_meshes && rhs >= 0 && rhs < 4 && u, SFEM_EINVAL,
+                 "bad mesh / rhs / output");
+    SFEM_REQUIRE(ptr_kind == SFEM_PTR_HOST || ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL,
+                 "bad ptr_kind");
+    sfem::Ctx& c = b.ctx->c;
+    const int64_t n = 3 * (b.st->node0[mesh + 1] - b.st->node0[mesh]);
+    if (ptr_kind == SFEM_PTR_DEVICE) {
+      sfem::batch_column(c, *b.st, mesh, rhs, u);
+    } else {
+      sfem::DBuf<double> tmp;
+      tmp.reserve(n);
+      sfem::batch_column(c, *b.st, mesh, rhs, tmp.get());
+      SFEM_HIP(hipMemcpyAsync(u, tmp.get(), sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    }
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_get_system_info(sfem_batch* h, int32_t* iters, int32_t* converged, double* relres,
+                               int32_t* breakdown) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    for (int s = 0; s < b.st->n_meshes * 4; ++s) {
+      int it, conv, brk;
+      double rr;
+      sfem::batch_system(*b.st, s, &it, &conv, &rr, &brk);
+      if (iters) iters[s] = it;
+      if (converged) converged[s] = conv;
+      if (relres) relres[s] = rr;
+      if (breakdown) breakdown[s] = brk;
+    }
+    return SFEM_OK;
+  });
+}
+
+}  // extern "C"

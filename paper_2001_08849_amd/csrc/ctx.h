@@ -24,6 +24,7 @@ struct Topology {
   int maxdeg = 0;                // most blocks in one node row
   int max_inc = 0;               // most incident faces of one node
   int n_tiles = 0;
+  int64_t key_w = 0;             // face-key base: largest tet vertex-id spread + 1
   DBuf<int32_t> face;            // [nf][kFaceStride]
   DBuf<int32_t> inc_ptr;         // [N+2] (bucket N collects exterior padding)
   DBuf<int32_t> inc;             // face ids per node, ascending

@@ -25,7 +25,27 @@ __device__ __forceinline__ void sort3(int& a, int& b, int& c) {
 
 // Face of tet t opposite its local vertex lf: bucket = smallest node, value
 // encodes (middle, largest) node and the (tet, local face) payload.
-__global__ void k_face_entries(const int32_t* __restrict__ tets, int64_t T, int64_t N,
+// Largest vertex-id spread (max - min) of a tet: per-block maxima.
+__global__ void k_tet_spread(const int32_t* __restrict__ tets, int64_t T,
+                             int32_t* __restrict__ part) {
+  int m = 0;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < T;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int4 v = reinterpret_cast<const int4*>(tets)[t];
+    const int lo = min(min(v.x, v.y), min(v.z, v.w)), hi = max(max(v.x, v.y), max(v.z, v.w));
+    m = max(m, hi - lo);
+  }
+  m = wave_max(m);
+  __shared__ int sm[4];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
+}
+
+// Face entries bucketed by their smallest vertex a; the value packs the
+// other two vertices relative to a (b - a, c - a < W, W = largest tet
+// vertex-id spread + 1) above the entry index 4t + lf.
+__global__ void k_face_entries(const int32_t* __restrict__ tets, int64_t T, uint64_t W,
                                int32_t* __restrict__ bucket, uint64_t* __restrict__ vals) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= T) return;
@@ -37,7 +57,8 @@ __global__ void k_face_entries(const int32_t* __restrict__ tets, int64_t T, int6
     int a = v[(lf + 1) & 3], b = v[(lf + 2) & 3], c = v[(lf + 3) & 3];
     sort3(a, b, c);
     bucket[4 * t + lf] = a;
-    vals[4 * t + lf] = (uint64_t(b) * uint64_t(N) + uint64_t(c)) * T4 + uint64_t(4 * t + lf);
+    vals[4 * t + lf] =
+        (uint64_t(b - a) * W + uint64_t(c - a)) * T4 + uint64_t(4 * t + lf);
   }
 }
 
@@ -65,7 +86,7 @@ __global__ void k_face_count(const int32_t* __restrict__ ptr, const uint64_t* __
 
 __global__ void k_face_write(const int32_t* __restrict__ ptr, const uint64_t* __restrict__ v,
                              const int32_t* __restrict__ fptr, const int32_t* __restrict__ tets,
-                             int64_t N, uint64_t T4, int32_t* __restrict__ face,
+                             int64_t N, uint64_t W, uint64_t T4, int32_t* __restrict__ face,
                              unsigned long long* __restrict__ n_ext) {
   int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (a >= N) return;
@@ -88,8 +109,8 @@ __global__ void k_face_write(const int32_t* __restrict__ ptr, const uint64_t* __
     }
     int* row = face + int64_t(f) * kFaceStride;
     row[0] = int(a);
-    row[1] = int(key / uint64_t(N));
-    row[2] = int(key % uint64_t(N));
+    row[1] = int(a + int64_t(key / W));
+    row[2] = int(a + int64_t(key % W));
     row[3] = o1;
     row[4] = o2;
     row[5] = t1;
@@ -320,7 +341,32 @@ void build_topology(Ctx& c) {
   SFEM_HIP(hipMallocAsync((void**)&fs, sizeof(uint64_t) * n4, s));
   SFEM_HIP(hipMallocAsync((void**)&fptr, sizeof(int32_t) * (N + 1), s));
   SFEM_HIP(hipMallocAsync((void**)&fcnt, sizeof(int32_t) * (N + 1), s));
-  k_face_entries<<<div_up(T, B), B, 0, s>>>(c.tets.get(), T, N, fb, fv);
+  // key base: the largest vertex-id spread of a tet (small for banded
+  // numberings; a batch of meshes never has a tet spanning two meshes)
+  {
+    const int G = int(std::min<int64_t>(1024, div_up(T, B)));
+    int32_t* part = nullptr;
+    SFEM_HIP(hipMallocAsync((void**)&part, sizeof(int32_t) * G, s));
+    k_tet_spread<<<G, B, 0, s>>>(c.tets.get(), T, part);
+    SFEM_HIP(hipGetLastError());
+    std::vector<int32_t> hp(G);
+    SFEM_HIP(hipMemcpyAsync(hp.data(), part, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    SFEM_HIP(hipStreamSynchronize(s));
+    SFEM_HIP(hipFreeAsync(part, s));
+    tp.key_w = 1 + *std::max_element(hp.begin(), hp.end());
+  }
+  const uint64_t W = uint64_t(tp.key_w);
+  if (double(W) * double(W) * 4.0 * double(T) >= 9.2e18) {
+    (void)hipFreeAsync(err, s);
+    (void)hipFreeAsync(fb, s);
+    (void)hipFreeAsync(fv, s);
+    (void)hipFreeAsync(fs, s);
+    (void)hipFreeAsync(fptr, s);
+    (void)hipFreeAsync(fcnt, s);
+    throw Error{SFEM_EINVAL, "face keys overflow: (largest tet vertex-id spread + 1)^2 * 4 n_tets "
+                             "must be < 2^63 (renumber the nodes)"};
+  }
+  k_face_entries<<<div_up(T, B), B, 0, s>>>(c.tets.get(), T, W, fb, fv);
   SFEM_HIP(hipGetLastError());
   bucket_sort_u64(fb, fv, n4, int(N), fptr, fs, s);
   k_face_count<<<div_up(N, B), B, 0, s>>>(fptr, fs, N, uint64_t(n4), fcnt, err);
@@ -346,8 +392,8 @@ void build_topology(Ctx& c) {
   unsigned long long* next = nullptr;
   SFEM_HIP(hipMallocAsync((void**)&next, sizeof(unsigned long long), s));
   SFEM_HIP(hipMemsetAsync(next, 0, sizeof(unsigned long long), s));
-  k_face_write<<<div_up(N, B), B, 0, s>>>(fptr, fs, face_ofs, c.tets.get(), N, uint64_t(n4),
-                                          tp.face.get(), next);
+  k_face_write<<<div_up(N, B), B, 0, s>>>(fptr, fs, face_ofs, c.tets.get(), N, W,
+                                          uint64_t(n4), tp.face.get(), next);
   SFEM_HIP(hipGetLastError());
   tp.ne = int64_t(read_scalar(next, s));
   SFEM_HIP(hipFreeAsync(fb, s));

@@ -36,6 +36,10 @@ EXPORTS = [
     "sfem_gnn_get_params", "sfem_gnn_set_params", "sfem_gnn_set_pairs",
     "sfem_gnn_generate_pairs", "sfem_gnn_loss_grad", "sfem_gnn_train", "sfem_gnn_apply",
     "sfem_get_precond", "sfem_precond_apply", "sfem_get_precond_info",
+    "sfem_batch_create", "sfem_batch_destroy", "sfem_batch_last_error", "sfem_batch_add_mesh",
+    "sfem_batch_add_traction", "sfem_batch_build", "sfem_batch_sizes", "sfem_batch_autotune",
+    "sfem_batch_get_schedule", "sfem_batch_solve", "sfem_batch_get_solution",
+    "sfem_batch_get_system_info",
 ]
 
 
@@ -49,6 +53,19 @@ class SolveOpts(C.Structure):
     _fields_ = [("precond", C.c_int), ("mode", C.c_int), ("rtol", C.c_double),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("inner_rtol", C.c_double),
                 ("max_outer", C.c_int), ("profile", C.c_int)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("mode", C.c_int), ("rtol", C.c_double), ("max_iter", C.c_int),
+                ("check_every", C.c_int), ("use_graph", C.c_int)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("ms_solve", C.c_double), ("periods", C.c_int), ("all_converged", C.c_int),
+                ("max_iters", C.c_int), ("worst_relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveInfo(C.Structure):
@@ -111,6 +128,19 @@ def lib() -> C.CDLL:
             "sfem_get_precond": (i32, [vp, vp, vp, i32]),
             "sfem_precond_apply": (i32, [vp, vp, vp, i32]),
             "sfem_get_precond_info": (i32, [vp] + [C.POINTER(dbl)] * 3),
+            "sfem_batch_create": (i32, [C.POINTER(vp), i32]),
+            "sfem_batch_destroy": (None, [vp]),
+            "sfem_batch_last_error": (C.c_char_p, [vp]),
+            "sfem_batch_add_mesh": (i32, [vp, i64, vp, i64, vp, dbl, dbl, i64, vp,
+                                          C.POINTER(i32)]),
+            "sfem_batch_add_traction": (i32, [vp, i32, i32, i64, vp, C.POINTER(dbl)]),
+            "sfem_batch_build": (i32, [vp, i32]),
+            "sfem_batch_sizes": (i32, [vp, C.POINTER(i32)] + [C.POINTER(i64)] * 4),
+            "sfem_batch_autotune": (i32, [vp, i32, i32, i32, C.POINTER(dbl)]),
+            "sfem_batch_get_schedule": (i32, [vp, i32] + [C.POINTER(i32)] * 4),
+            "sfem_batch_solve": (i32, [vp, C.POINTER(BatchOpts), C.POINTER(BatchInfo)]),
+            "sfem_batch_get_solution": (i32, [vp, i32, i32, vp, i32]),
+            "sfem_batch_get_system_info": (i32, [vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -420,6 +450,113 @@ class Gnn:
         ms = C.c_double()
         self._check(self._L.sfem_gnn_apply(self._h, ctx._h, C.byref(ms)), ctx)
         return ms.value
+
+
+class Batch:
+    """Many meshes x up to 4 load cases solved together (sfem_batch)."""
+
+    def __init__(self, device: int = 0):
+        L = lib()
+        h = C.c_void_p()
+        st = L.sfem_batch_create(C.byref(h), device)
+        if st != 0:
+            raise SfemError(st, "sfem_batch_create failed")
+        self._h, self._L = h, L
+        self.n_meshes = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sfem_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SfemError(st, self._L.sfem_batch_last_error(self._h).decode())
+        return st
+
+    def add_mesh(self, xyz, tets, E, nu, fixed_dofs) -> int:
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        fx = np.ascontiguousarray(fixed_dofs, dtype=np.int32)
+        idx = C.c_int()
+        self._check(self._L.sfem_batch_add_mesh(
+            self._h, xyz.shape[0], xyz.ctypes.data_as(C.c_void_p), tets.shape[0],
+            tets.ctypes.data_as(C.c_void_p), float(E), float(nu), fx.size,
+            fx.ctypes.data_as(C.c_void_p), C.byref(idx)))
+        self.n_meshes += 1
+        return idx.value
+
+    def add_traction(self, mesh: int, rhs: int, tris, t):
+        tris = np.ascontiguousarray(tris, dtype=np.int32)
+        tv = (C.c_double * 3)(*[float(v) for v in np.asarray(t).reshape(-1)[:3]])
+        self._check(self._L.sfem_batch_add_traction(self._h, int(mesh), int(rhs), tris.shape[0],
+                                                    tris.ctypes.data_as(C.c_void_p), tv))
+
+    def build(self, f32_copy: bool = False):
+        self._check(self._L.sfem_batch_build(self._h, ASM_F32_COPY if f32_copy else ASM_F64))
+
+    def sizes(self):
+        m = C.c_int()
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self._L.sfem_batch_sizes(self._h, C.byref(m), C.byref(a), C.byref(b),
+                                             C.byref(c), C.byref(d)))
+        return {"meshes": m.value, "nodes": a.value, "tets": b.value, "faces": c.value,
+                "nnz": d.value}
+
+    def autotune(self, reps: int = 5, use_cache: bool = True, f32: bool = False) -> float:
+        us = C.c_double()
+        self._check(self._L.sfem_batch_autotune(self._h, int(reps), int(use_cache),
+                                                ASM_F32_COPY if f32 else ASM_F64, C.byref(us)))
+        return us.value
+
+    def schedule(self, bucket: int):
+        v = [C.c_int() for _ in range(4)]
+        self._check(self._L.sfem_batch_get_schedule(self._h, int(bucket), *[C.byref(x) for x in v]))
+        return {"lanes_per_row": v[0].value, "rows_per_wg": v[1].value, "meshes": v[2].value,
+                "from_cache": v[3].value}
+
+    def solve(self, rtol: float = 1e-8, mode: int = MODE_F64, max_iter: int = 0,
+              check_every: int = 0, use_graph: bool = True, raise_on_noconv: bool = False):
+        o = BatchOpts(mode, rtol, max_iter, check_every, int(use_graph))
+        info = BatchInfo()
+        st = self._L.sfem_batch_solve(self._h, C.byref(o), C.byref(info))
+        if st != 0 and (st != -5 or raise_on_noconv):
+            self._check(st)
+        return info.as_dict()
+
+    def solution(self, mesh: int, rhs: int, n_nodes: int) -> np.ndarray:
+        out = np.empty(3 * n_nodes, dtype=np.float64)
+        self._check(self._L.sfem_batch_get_solution(self._h, int(mesh), int(rhs),
+                                                    out.ctypes.data_as(C.c_void_p), PTR_HOST))
+        return out
+
+    def system_info(self):
+        n = 4 * self.n_meshes
+        it, cv, bk = (np.empty(n, np.int32) for _ in range(3))
+        rr = np.empty(n, np.float64)
+        self._check(self._L.sfem_batch_get_system_info(
+            self._h, it.ctypes.data_as(C.c_void_p), cv.ctypes.data_as(C.c_void_p),
+            rr.ctypes.data_as(C.c_void_p), bk.ctypes.data_as(C.c_void_p)))
+        return {"iters": it, "converged": cv, "relres": rr, "breakdown": bk}
+
+
+def batch_from_items(items, f32_copy: bool = False, device: int = 0) -> Batch:
+    """A built Batch from meshgen.BatchItem's (clamp at x = 0, the four end
+    tractions as load cases 0..3)."""
+    b = Batch(device)
+    for it in items:
+        m = it.mesh
+        idx = b.add_mesh(m.xyz, m.tets, it.E, it.nu, m.clamp_dofs())
+        for k in range(it.tractions.shape[0]):
+            b.add_traction(idx, k, m.end_tris, it.tractions[k])
+    b.build(f32_copy=f32_copy)
+    return b
 
 
 def unpack_params(flat):

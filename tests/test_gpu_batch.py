@@ -1,0 +1,163 @@
+"""GPU tests of the batched solve: every (mesh, load case) system against
+the FP64 oracle, hipGraph replay against eager launches, the FP32-product
+mode, the per-bucket autotuner and its cache, and the full 64-mesh batch
+(all 256 systems to 1e-8 true residual, sampled meshes against the oracle).
+"""
+import numpy as np
+import pytest
+
+from oracle import fsfem as O
+from paper_2001_08849_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2001_08849_amd import sfem
+    return sfem
+
+
+def oracle_solutions(item):
+    """u for each of the item's load cases: FP64 oracle, banded Cholesky."""
+    m = item.mesh
+    K = O.assemble(m.xyz, m.tets, item.E, item.nu)
+    out = []
+    for t in item.tractions:
+        f = O.traction_load(m.xyz, m.end_tris, t)
+        Kb, fb = O.apply_dirichlet(K, f, m.clamp_dofs())
+        out.append(O.solve_banded(Kb, fb))
+    return out
+
+
+@pytest.fixture(scope="module")
+def small_items():
+    # uneven sizes across all three buckets' lower end; meshes of 2..4 cells
+    # across so the oracle's banded solve stays quick
+    return mg.batch_c3(n_meshes=6, seed=5, nx_range=(4, 30), nyz_range=(2, 4))
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_batch_matches_oracle_per_system(S, small_items):
+    b = S.batch_from_items(small_items)
+    sz = b.sizes()
+    assert sz["meshes"] == len(small_items)
+    assert sz["tets"] == sum(it.mesh.n_tets for it in small_items)
+    info = b.solve(rtol=1e-10, use_graph=True)
+    assert info["all_converged"] == 1, info
+    si = b.system_info()
+    assert np.all(si["converged"] == 1) and np.all(si["relres"] <= 1e-10)
+    worst = 0.0
+    for mi, it in enumerate(small_items):
+        refs = oracle_solutions(it)
+        for k, ref in enumerate(refs):
+            u = b.solution(mi, k, it.mesh.n_nodes)
+            worst = max(worst, rel(u, ref))
+    print(f"batch of {len(small_items)} meshes x 4 load cases: worst u error {worst:.2e}, "
+          f"max iters {info['max_iters']}")
+    assert worst < 1e-8
+
+
+def test_graph_replay_equals_eager_launches(S, small_items):
+    b = S.batch_from_items(small_items)
+    b.solve(rtol=1e-10, use_graph=False)
+    eager = [b.solution(m, k, it.mesh.n_nodes) for m, it in enumerate(small_items) for k in range(4)]
+    it_e = b.system_info()["iters"].copy()
+    for _ in range(3):  # replays of the same captured graph, with eager work between
+        b.solve(rtol=1e-10, use_graph=True)
+        graph = [b.solution(m, k, it.mesh.n_nodes) for m, it in enumerate(small_items)
+                 for k in range(4)]
+        assert all(np.array_equal(x, y) for x, y in zip(eager, graph))
+        assert np.array_equal(b.system_info()["iters"], it_e)
+
+
+def test_fp32_products_with_fp64_replacement(S, small_items):
+    b = S.batch_from_items(small_items, f32_copy=True)
+    info = b.solve(rtol=1e-8, mode=S.MODE_F32_RR)
+    assert info["all_converged"] == 1 and info["worst_relres"] <= 1e-8
+    it = small_items[0]
+    refs = oracle_solutions(it)
+    for k in range(4):
+        assert rel(b.solution(0, k, it.mesh.n_nodes), refs[k]) < 1e-6
+
+
+def test_autotuner_buckets_and_cache(S):
+    items = mg.batch_c3(n_meshes=5, seed=11, nx_range=(20, 60), nyz_range=(4, 14))
+    b = S.batch_from_items(items)
+    b.solve(rtol=1e-9)
+    before = [b.solution(m, k, it.mesh.n_nodes) for m, it in enumerate(items) for k in range(4)]
+    us = b.autotune(reps=3, use_cache=False)
+    assert us > 0
+    sched = [b.schedule(k) for k in range(3)]
+    assert sum(s["meshes"] for s in sched) == len(items)
+    for s in sched:
+        if s["meshes"]:
+            assert s["lanes_per_row"] in (8, 16, 32) and s["rows_per_wg"] in (16, 64, 256)
+            assert s["from_cache"] == 0
+    b.solve(rtol=1e-9)
+    after = [b.solution(m, k, it.mesh.n_nodes) for m, it in enumerate(items) for k in range(4)]
+    assert max(rel(x, y) for x, y in zip(after, before)) < 1e-7
+    # the same shapes in a new batch come from the cache, with the same choice
+    b2 = S.batch_from_items(items)
+    b2.autotune(reps=3, use_cache=True)
+    for k in range(3):
+        s2 = b2.schedule(k)
+        if s2["meshes"]:
+            assert s2["from_cache"] == 1
+            assert (s2["lanes_per_row"], s2["rows_per_wg"]) == \
+                (sched[k]["lanes_per_row"], sched[k]["rows_per_wg"])
+
+
+def test_zero_load_case_and_errors(S):
+    it = mg.batch_c3(n_meshes=1, seed=7, nx_range=(4, 6), nyz_range=(2, 3))[0]
+    b = S.Batch(0)
+    with pytest.raises(S.SfemError, match="ESTATE"):
+        b.solve()
+    m = b.add_mesh(it.mesh.xyz, it.mesh.tets, it.E, it.nu, it.mesh.clamp_dofs())
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        b.add_traction(1, 0, it.mesh.end_tris, it.tractions[0])
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        b.add_traction(m, 4, it.mesh.end_tris, it.tractions[0])
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        b.add_mesh(it.mesh.xyz, it.mesh.tets + 10**6, it.E, it.nu, [])
+    b.add_traction(m, 2, it.mesh.end_tris, it.tractions[2])      # only load case 2
+    b.build()
+    with pytest.raises(S.SfemError, match="ESTATE"):
+        b.build()
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        b.solve(mode=S.MODE_F32_IR)
+    with pytest.raises(S.SfemError, match="ESTATE"):
+        b.solve(mode=S.MODE_F32_RR)                                # no FP32 copy
+    info = b.solve(rtol=1e-10)
+    si = b.system_info()
+    assert info["all_converged"] == 1
+    assert list(si["iters"][[0, 1, 3]]) == [0, 0, 0] and si["iters"][2] > 0
+    assert np.all(b.solution(m, 0, it.mesh.n_nodes) == 0.0)
+    ref = oracle_solutions(it)[2]
+    assert rel(b.solution(m, 2, it.mesh.n_nodes), ref) < 1e-8
+
+
+def test_full_c3_batch(S):
+    """64 meshes of 1.9k-288k tets x 4 load cases in one batched solve: every
+    system reaches 1e-8, and sampled small meshes match the oracle."""
+    items = mg.batch_c3()
+    b = S.batch_from_items(items)
+    sz = b.sizes()
+    print(f"c3: {sz['meshes']} meshes, {sz['tets']} tets, {sz['faces']} faces, nnz {sz['nnz']}")
+    us = b.autotune(reps=3)
+    info = b.solve(rtol=1e-8, use_graph=True)
+    print(f"c3: tuned 4-rhs product {us:.0f} us; solve {info['ms_solve']:.0f} ms, "
+          f"{info['periods']} periods, max iters {info['max_iters']}, worst relres "
+          f"{info['worst_relres']:.2e}; schedules {[b.schedule(k) for k in range(3)]}")
+    assert info["all_converged"] == 1 and info["worst_relres"] <= 1e-8
+    si = b.system_info()
+    assert np.all(si["relres"] <= 1e-8) and not np.any(si["breakdown"])
+    sizes = np.array([it.mesh.n_tets for it in items])
+    for mi in np.argsort(sizes)[:2]:
+        refs = oracle_solutions(items[mi])
+        for k in range(4):
+            err = rel(b.solution(int(mi), k, items[mi].mesh.n_nodes), refs[k])
+            assert err < 1e-7, (mi, k, err)

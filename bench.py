@@ -298,7 +298,7 @@ def main():
     ctx.assemble(f32_copy=args.f32_ir)
     tuned = ctx.autotune(reps=10)
     log(f"[bench] autotuned row schedule (variant, grid cap) {tuned['f64'][0]}: "
-        f"{tuned['f64'][1]:.1f} us per SpMV")
+        f"{tuned['f64'][1]:.1f} us per PCG iteration")
     u = np.empty(s.n_rows)
 
     def step(profile=False):
@@ -376,7 +376,7 @@ def main():
             "solver": "Jacobi PCG FP64, x0=0, true relres <= 1e-8",
         },
         "row_schedule": {"variant": tuned["f64"][0][0], "grid_cap": tuned["f64"][0][1],
-                         "autotuned_spmv_us": tuned["f64"][1]},
+                         "autotuned_us_per_pcg_iteration": tuned["f64"][1]},
         "assembly_ms": asm_med,
         "topology_ms": ms_topo,
     }

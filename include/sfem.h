@@ -202,20 +202,32 @@ int sfem_solve(sfem_ctx* ctx, const sfem_solve_opts* opts, double* u, int ptr_ki
  * most recent numeric assembly (HIP events on the context stream). */
 int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
 
-/* Row-kernel schedules (SpMV, residual and CG product kernels): `variant`
- * in [0, 8) picks the lanes per node row {8,16,32,64} (variant % 4) and one
- * or two rows per lane group per step (variant / 4); `grid_cap` caps the
- * workgroups launched.  precision: SFEM_ASM_F64 or SFEM_ASM_F32_COPY (the
- * schedule of the FP32 matrix).  All schedules compute the same products up
- * to floating-point summation order. */
+/* Row-kernel schedules (SpMV, residual, CG product and learned-M kernels):
+ * `variant` in [0, SFEM_NUM_SCHEDULES) picks lanes per node row and a loop
+ * shape:
+ *   0-3   8/16/32/64 lanes, one row per lane group and step;
+ *   4-7   8/16/32/64 lanes, two rows per step (loads of both in flight);
+ *   8-9   16/32 lanes, one row, column loop unrolled by 3;
+ *   10-12 16/32/64 lanes, unrolled, nontemporal matrix-value loads;
+ *   13    32 lanes, two rows, nontemporal matrix-value loads;
+ *   14-16 4/8/16 lanes, packed layout: a copy of the values made once per
+ *         assembly in which each node row is a [9][deg rounded up to 4]
+ *         array, read 4 blocks per lane with 16-byte loads.
+ * `grid_cap` caps the workgroups launched.  precision: SFEM_ASM_F64 or
+ * SFEM_ASM_F32_COPY (the schedule of FP32 matrices, also used by the learned
+ * M).  All schedules compute the same products up to floating-point
+ * summation order. */
+enum { SFEM_NUM_SCHEDULES = 17 };
 int sfem_set_schedule(sfem_ctx* ctx, int precision, int variant, int grid_cap);
 int sfem_get_schedule(sfem_ctx* ctx, int precision, int* variant, int* grid_cap);
 
 /* Autotuner: times every schedule (variant x grid cap in {1024, 2048, 4096,
- * 8192}) on the context's assembled matrix, `reps` launches each (0: 10),
- * with HIP events, and keeps the fastest for FP64 and, if an FP32 copy
- * exists, for FP32.  Returns the best microseconds per SpMV (pointers may
- * be NULL).  Needs sfem_assemble. */
+ * 8192}) on the context's assembled matrix and keeps the fastest.  FP64:
+ * `reps` (0: 10) Jacobi-PCG iterations from b = 1 per candidate, i.e. the
+ * product inside the CG loop; *best_us_f64 is the time per iteration.  FP32
+ * copy (if any): `reps` isolated products; *best_us_f32 per product.
+ * Pointers may be NULL.  Needs sfem_assemble; leaves the solver's work
+ * vectors overwritten. */
 int sfem_autotune(sfem_ctx* ctx, int reps, double* best_us_f64, double* best_us_f32);
 
 /* Wall-clock device timer on the context stream: start records an event,

@@ -108,6 +108,7 @@ __global__ void k_set_fixed(int64_t n, const int32_t* dof, const double* value, 
 
 void reset_problem(Ctx& c) {
   c.have_learned = false;
+  c.nb4 = 0;
   c.gnn.reset();
   c.have_material = false;
   c.per_tet = false;
@@ -350,6 +351,7 @@ int sfem_assemble(sfem_ctx* h, int flags) {
     // the training pairs (r = K e) of the old one
     c.have_learned = false;
     c.gnn.reset();
+    c.packed64 = c.packed32 = false;
     const int64_t nnz = 9 * c.topo.nb;
     c.val.reserve(nnz);
     const bool f32 = (flags & SFEM_ASM_F32_COPY) != 0;

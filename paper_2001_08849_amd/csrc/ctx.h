@@ -37,7 +37,7 @@ struct Topology {
 
 // Row-kernel schedule: variant index (lanes per row, rows per group step)
 // and a cap on the grid size.
-constexpr int kNumSched = 8;
+constexpr int kNumSched = 17;
 struct RowSched {
   int variant;
   int grid_cap;
@@ -85,6 +85,15 @@ struct Ctx {
   bool have_f32 = false;
   DBuf<double> val;
   DBuf<float> val32;
+  // Packed layout of the block pattern (for the packed row schedules and
+  // the learned M): node row I holds a [9][d4] array (component q = 3a + c
+  // major, blocks minor; d4 = deg rounded up to 4, zero padding) at
+  // 9 * ptr4[I]; col4 lists its block columns padded with I.
+  DBuf<int32_t> ptr4, col4;
+  int64_t nb4 = 0;
+  DBuf<double> valp;             // K_bc packed (valid while packed64)
+  DBuf<float> valp32;            // FP32 copy packed (valid while packed32)
+  bool packed64 = false, packed32 = false;
   DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
   DBuf<double> fix;              // assembly fixed-point partial maxima, then the unit
   DBuf<float> dinv32;
@@ -94,6 +103,7 @@ struct Ctx {
   bool have_learned = false;
   double m_theta = 1.0, m_lmin = 0.0, m_lmax = 0.0;  // S' = theta S; Lanczos range of S
   DBuf<float> mval;
+  DBuf<float> mvalp;             // the same values in the packed layout
   DBuf<double> msqrt;
   DBuf<float> msqrt32;
   std::shared_ptr<GnnWork> gnn;  // features, activations and training pairs
@@ -135,6 +145,9 @@ void rhs_with_bc(Ctx& c);
 void spmv_f64(Ctx& c, const double* val, const double* x, double* y, hipStream_t s);
 void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s);
 void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream_t s);
+// Packed layout: pattern tables (once per mesh) and a value repack.
+void pack_pattern(Ctx& c);
+void pack_values_f32(Ctx& c, const float* csr, float* packed);
 // solve.hip
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info);
 double true_residual(Ctx& c, const double* u);

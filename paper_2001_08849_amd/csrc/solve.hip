@@ -41,7 +41,15 @@ __device__ __forceinline__ double group_sum(double v) {
 // result is used, so each lane keeps many independent loads in flight.
 constexpr int kUnroll = 3;
 
-template <typename VT, int LPR, class XF>
+// Matrix-value load; NT: nontemporal (the value stream is read once per
+// product and should not evict the gathered x from L2).
+template <bool NT, typename T>
+__device__ __forceinline__ T ldv(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <typename VT, int LPR, bool NT, class XF>
 __device__ __forceinline__ void row3x2(const int (&I)[2], const bool (&valid)[2], int sub,
                                        const int32_t* __restrict__ bptr,
                                        const int32_t* __restrict__ bcol,
@@ -82,9 +90,9 @@ __device__ __forceinline__ void row3x2(const int (&I)[2], const bool (&valid)[2]
         const int c = c0 + u * LPR + sub;
         const VT* v = val + 9 * int64_t(rb[r]) + c;
         xv[r][u] = on[r][u] ? AT(x(int64_t(col[r][u]))) : AT(0);
-        v0[r][u] = on[r][u] ? AT(v[0]) : AT(0);
-        v1[r][u] = on[r][u] ? AT(v[td[r]]) : AT(0);
-        v2[r][u] = on[r][u] ? AT(v[2 * td[r]]) : AT(0);
+        v0[r][u] = on[r][u] ? AT(ldv<NT>(v)) : AT(0);
+        v1[r][u] = on[r][u] ? AT(ldv<NT>(v + td[r])) : AT(0);
+        v2[r][u] = on[r][u] ? AT(ldv<NT>(v + 2 * td[r])) : AT(0);
       }
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -101,7 +109,7 @@ __device__ __forceinline__ void row3x2(const int (&I)[2], const bool (&valid)[2]
     for (int a = 0; a < 3; ++a) y[r][a] = group_sum<LPR>(double(acc[r][a]));
 }
 
-template <typename VT, int LPR, class XF>
+template <typename VT, int LPR, bool NT, class XF>
 __device__ __forceinline__ void row3(int I, bool valid, int sub, const int32_t* __restrict__ bptr,
                                      const int32_t* __restrict__ bcol,
                                      const VT* __restrict__ val, const XF& x, double& y0,
@@ -120,13 +128,60 @@ __device__ __forceinline__ void row3(int I, bool valid, int sub, const int32_t* 
     const int jj = c / 3;
     const int b = c - 3 * jj;
     const AT xv = AT(x(3 * int64_t(cols[jj]) + b));
-    a0 += AT(v[c]) * xv;
-    a1 += AT(v[td + c]) * xv;
-    a2 += AT(v[2 * td + c]) * xv;
+    a0 += AT(ldv<NT>(v + c)) * xv;
+    a1 += AT(ldv<NT>(v + td + c)) * xv;
+    a2 += AT(ldv<NT>(v + 2 * td + c)) * xv;
   }
   y0 = group_sum<LPR>(double(a0));
   y1 = group_sum<LPR>(double(a1));
   y2 = group_sum<LPR>(double(a2));
+}
+
+// One row per group, column loop unrolled by kUnroll with every load of a
+// step issued before any is used (more loads in flight per lane than row3).
+template <typename VT, int LPR, bool NT, class XF>
+__device__ __forceinline__ void row3u(int I, bool valid, int sub, const int32_t* __restrict__ bptr,
+                                      const int32_t* __restrict__ bcol,
+                                      const VT* __restrict__ val, const XF& x, double& y0,
+                                      double& y1, double& y2) {
+  int rb = 0, deg = 0;
+  if (valid) {
+    rb = bptr[I];
+    deg = bptr[I + 1] - rb;
+  }
+  const int td = 3 * deg;
+  const VT* v = val + 9 * int64_t(rb);
+  const int32_t* cols = bcol + rb;
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int c0 = 0; c0 < td; c0 += kUnroll * LPR) {
+    int col[kUnroll];
+    bool on[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int c = c0 + u * LPR + sub;
+      on[u] = c < td;
+      const int jj = c / 3;
+      col[u] = on[u] ? 3 * cols[jj] + (c - 3 * jj) : 0;
+    }
+    double xv[kUnroll], v0[kUnroll], v1[kUnroll], v2[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int c = c0 + u * LPR + sub;
+      xv[u] = on[u] ? double(x(int64_t(col[u]))) : 0.0;
+      v0[u] = on[u] ? double(ldv<NT>(v + c)) : 0.0;
+      v1[u] = on[u] ? double(ldv<NT>(v + td + c)) : 0.0;
+      v2[u] = on[u] ? double(ldv<NT>(v + 2 * td + c)) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      a0 += v0[u] * xv[u];
+      a1 += v1[u] * xv[u];
+      a2 += v2[u] * xv[u];
+    }
+  }
+  y0 = group_sum<LPR>(a0);
+  y1 = group_sum<LPR>(a1);
+  y2 = group_sum<LPR>(a2);
 }
 
 template <typename T>
@@ -195,25 +250,93 @@ __device__ __forceinline__ void for_rows2(int64_t N, Body2&& body2) {
   }
 }
 
-// Row schedule: LPR lanes per node row; PAIR: two rows per group per step
-// (more loads in flight, more registers).  epi(I, y) runs for each valid row
-// in the group's first lane.
-template <typename VT, int LPR, bool PAIR, class XF, class Epi>
+// Four consecutive values of a packed row (16-byte aligned).
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float* p, double (&v)[4]) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = a.z;
+  v[3] = a.w;
+}
+
+// The three sums of node row I in the packed layout (ptr4 / col4 / values
+// [9][d4] per row): a lane takes 4 blocks per step with one int4 column
+// load and nine 4-wide value loads (36 entries; the CSR-order layout needs
+// 60 loads for as many).
+template <typename VT, int LPR, class XF>
+__device__ __forceinline__ void row3p(int I, bool valid, int sub, const int32_t* __restrict__ ptr4,
+                                      const int32_t* __restrict__ col4,
+                                      const VT* __restrict__ valp, const XF& x, double& y0,
+                                      double& y1, double& y2) {
+  int r4 = 0, d4 = 0;
+  if (valid) {
+    r4 = ptr4[I];
+    d4 = ptr4[I + 1] - r4;
+  }
+  const VT* w = valp + 9 * int64_t(r4);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
+    const int4 J = *reinterpret_cast<const int4*>(col4 + r4 + jb);
+    double m[9][4];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) load4(w + q * d4 + jb, m[q]);
+    const int Js[4] = {J.x, J.y, J.z, J.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t j3 = 3 * int64_t(Js[t]);
+      const double x0 = double(x(j3)), x1 = double(x(j3 + 1)), x2 = double(x(j3 + 2));
+      a0 += m[0][t] * x0 + m[1][t] * x1 + m[2][t] * x2;
+      a1 += m[3][t] * x0 + m[4][t] * x1 + m[5][t] * x2;
+      a2 += m[6][t] * x0 + m[7][t] * x1 + m[8][t] * x2;
+    }
+  }
+  y0 = group_sum<LPR>(a0);
+  y1 = group_sum<LPR>(a1);
+  y2 = group_sum<LPR>(a2);
+}
+
+// Row schedule: LPR lanes per node row; MODE bit 0: two rows per group
+// per step, bit 1: one row with the unrolled column loop, bit 2:
+// nontemporal matrix-value loads, bit 3: the packed layout (bptr, bcol, val
+// are then ptr4, col4 and the packed values).  epi(I, y) runs for each
+// valid row in the group's first lane.
+template <typename VT, int LPR, int MODE, class XF, class Epi>
 __device__ __forceinline__ void row_apply(int64_t N, const int32_t* __restrict__ bptr,
                                           const int32_t* __restrict__ bcol,
                                           const VT* __restrict__ val, const XF& xf, Epi&& epi) {
-  if constexpr (PAIR) {
+  constexpr bool NT = (MODE & 4) != 0;
+  if constexpr ((MODE & 8) != 0) {
+    for_rows<LPR>(N, [&](int I, bool valid, int sub) {
+      double y[3];
+      row3p<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+      if (valid && sub == 0) epi(I, y);
+    });
+  } else if constexpr ((MODE & 1) != 0) {
     for_rows2<LPR>(N, [&](const int (&I)[2], const bool (&valid)[2], int sub) {
       double yy[2][3];
-      row3x2<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, yy);
+      row3x2<VT, LPR, NT>(I, valid, sub, bptr, bcol, val, xf, yy);
 #pragma unroll
       for (int r = 0; r < 2; ++r)
         if (valid[r] && sub == 0) epi(I[r], yy[r]);
     });
+  } else if constexpr ((MODE & 2) != 0) {
+    for_rows<LPR>(N, [&](int I, bool valid, int sub) {
+      double y[3];
+      row3u<VT, LPR, NT>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+      if (valid && sub == 0) epi(I, y);
+    });
   } else {
     for_rows<LPR>(N, [&](int I, bool valid, int sub) {
       double y[3];
-      row3<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+      row3<VT, LPR, NT>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
       if (valid && sub == 0) epi(I, y);
     });
   }
@@ -250,12 +373,12 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double* partials
     for (int i = 0; i < NV; ++i) partials[blockIdx.x * NV + i] = v[i];
 }
 
-template <typename VT, typename XT, int LPR, bool PAIR>
+template <typename VT, typename XT, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
            const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y) {
   const PlainX<XT> xf{x};
-  row_apply<VT, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&yy)[3]) {
+  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&yy)[3]) {
     y[3 * int64_t(I) + 0] = XT(yy[0]);
     y[3 * int64_t(I) + 1] = XT(yy[1]);
     y[3 * int64_t(I) + 2] = XT(yy[2]);
@@ -275,7 +398,7 @@ __global__ void __launch_bounds__(kVecThreads)
 }
 
 // q = K p, partial (p.q).
-template <typename VT, typename P, int LPR, bool PAIR>
+template <typename VT, typename P, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
               const VT* __restrict__ val, const P* __restrict__ p, P* __restrict__ q,
@@ -283,7 +406,7 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
   if (sc->converged) return;
   const PlainX<P> xf{p};
   double v[1] = {0.0};
-  row_apply<VT, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
+  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -344,20 +467,26 @@ __global__ void k_rh(int64_t n, const P* __restrict__ s, const P* __restrict__ r
   if (i < n) rh[i] = s[i] * r[i];
 }
 
-// Learned preconditioner z = M r = s (rh + S' rh), rh = s r, S' in the
-// scalar-CSR value layout of K (FP32), s = diag(K)^-1/2.  Partials
+// Learned preconditioner z = M r = s (rh + S' rh), rh = s r, s =
+// diag(K)^-1/2, with S' (FP32) in the packed layout: node row I holds a
+// [9][d4] array (component q = 3a + c major, blocks minor, d4 = deg rounded
+// up to 4) at 9 ptr4[I], block columns col4 padded with I and zero values.
+// A lane takes 4 blocks per step: one int4 column load and nine float4 value
+// loads for 36 entries (the row kernels' layout needs 60 loads).  Partials
 // (r.z_new), (r.r), (r.z_old): the flexible (Polak-Ribiere) beta needs the
 // previous z.  sc == nullptr: run unconditionally (start and replacement).
-template <typename P, int LPR, bool PAIR>
+constexpr int kMLanes = 8;  // lanes per node row: 32 blocks per step
+
+template <typename P>
 __global__ void __launch_bounds__(kRowWaves * kWave)
-    k_mapply(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-             const float* __restrict__ mval, const P* __restrict__ s, const P* __restrict__ r,
+    k_mapply(int64_t N, const int32_t* __restrict__ ptr4, const int32_t* __restrict__ col4,
+             const float* __restrict__ mvalp, const P* __restrict__ s, const P* __restrict__ r,
              const P* __restrict__ rh, P* __restrict__ z, const CgScalars* __restrict__ sc,
              double* __restrict__ partials) {
   if (sc && sc->converged) return;
   const PlainX<P> xf{rh};
   double v[3] = {0.0, 0.0, 0.0};
-  row_apply<float, LPR, PAIR>(N, bptr, bcol, mval, xf, [&](int I, const double (&y)[3]) {
+  row_apply<float, kMLanes, 8>(N, ptr4, col4, mvalp, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -373,7 +502,7 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
 }
 
 // Residual replacement: r = b - K x, z = dinv r; partials (r.r), (r.z).
-template <typename VT, typename P, int LPR, bool PAIR>
+template <typename VT, typename P, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_replace(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                  const VT* __restrict__ val, const P* __restrict__ b, const P* __restrict__ x,
@@ -381,7 +510,7 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
                  double* __restrict__ partials) {
   const PlainX<P> xf{x};
   double v[2] = {0.0, 0.0};
-  row_apply<VT, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
+  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -397,7 +526,7 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
 }
 
 // FP64 residual of the outer problem: r = f - K u; partials ||r||^2, ||f||^2.
-template <int LPR, bool PAIR>
+template <int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_resid64(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
               const double* __restrict__ val, const double* __restrict__ f,
@@ -405,7 +534,7 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
               double* __restrict__ partials) {
   const PlainX<double> xf{u};
   double v[2] = {0.0, 0.0};
-  row_apply<double, LPR, PAIR>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
+  row_apply<double, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -528,35 +657,108 @@ __global__ void k_zero(int64_t n, double* __restrict__ u) {
 constexpr int kRowGridMax = 4096;
 constexpr int kVecGridMax = 2048;
 
-// Row-kernel schedules: lanes per row and one/two rows per group step.
+// Row-kernel schedules: lanes per row and the MODE bits of row_apply.
 struct SchedShape {
   int lpr;
-  bool pair;
+  int mode;
 };
-constexpr SchedShape kSched[kNumSched] = {{8, false},  {16, false}, {32, false}, {64, false},
-                                          {8, true},   {16, true},  {32, true},  {64, true}};
+constexpr SchedShape kSched[kNumSched] = {
+    {8, 0},  {16, 0}, {32, 0}, {64, 0},   // one row per step
+    {8, 1},  {16, 1}, {32, 1}, {64, 1},   // two rows per step
+    {16, 2}, {32, 2},                     // one row, unrolled columns
+    {16, 6}, {32, 6}, {64, 6},            // unrolled, nontemporal values
+    {32, 5},                              // two rows, nontemporal values
+    {4, 8},  {8, 8},  {16, 8}};           // packed layout, 4 blocks per lane
 
 int row_grid(int64_t N, const RowSched& rs) {
   const SchedShape sh = kSched[rs.variant];
-  const int64_t rows_per_block = int64_t(kRowWaves) * (kWave / sh.lpr) * (sh.pair ? 2 : 1);
+  const int64_t rows_per_block = int64_t(kRowWaves) * (kWave / sh.lpr) * ((sh.mode & 1) ? 2 : 1);
   int g = div_up(N, rows_per_block);
   const int cap = std::min(rs.grid_cap, kRowGridMax);
   g = g < cap ? g : cap;
   return div_up(g, kXcds) * kXcds;  // for_rows needs a multiple of kXcds
 }
 
-// Launch KERNEL<prefix..., LPR, PAIR> for the schedule's variant.
+// Launch KERNEL<prefix..., LPR, MODE> for the schedule's variant.
 #define SFEM_SCHED_SWITCH(variant, LAUNCH) \
   switch (variant) {                        \
-    case 0: LAUNCH(8, false); break;        \
-    case 1: LAUNCH(16, false); break;       \
-    case 2: LAUNCH(32, false); break;       \
-    case 3: LAUNCH(64, false); break;       \
-    case 4: LAUNCH(8, true); break;         \
-    case 5: LAUNCH(16, true); break;        \
-    case 6: LAUNCH(32, true); break;        \
-    default: LAUNCH(64, true); break;       \
+    case 0: LAUNCH(8, 0); break;            \
+    case 1: LAUNCH(16, 0); break;           \
+    case 2: LAUNCH(32, 0); break;           \
+    case 3: LAUNCH(64, 0); break;           \
+    case 4: LAUNCH(8, 1); break;            \
+    case 5: LAUNCH(16, 1); break;           \
+    case 6: LAUNCH(32, 1); break;           \
+    case 7: LAUNCH(64, 1); break;           \
+    case 8: LAUNCH(16, 2); break;           \
+    case 9: LAUNCH(32, 2); break;           \
+    case 10: LAUNCH(16, 6); break;          \
+    case 11: LAUNCH(32, 6); break;          \
+    case 12: LAUNCH(64, 6); break;          \
+    case 13: LAUNCH(32, 5); break;          \
+    case 14: LAUNCH(4, 8); break;           \
+    case 15: LAUNCH(8, 8); break;           \
+    default: LAUNCH(16, 8); break;          \
   }
+
+// Pattern tables of the packed layout (once per mesh).
+__global__ void k_deg4(int64_t N, const int32_t* __restrict__ bptr, int32_t* __restrict__ d4) {
+  int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I < N) d4[I] = (bptr[I + 1] - bptr[I] + 3) & ~3;
+}
+
+__global__ void k_col4(int64_t N, const int32_t* __restrict__ bptr,
+                       const int32_t* __restrict__ bcol, const int32_t* __restrict__ p4,
+                       int32_t* __restrict__ c4) {
+  int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb, r4 = p4[I], d4 = p4[I + 1] - r4;
+  for (int j = 0; j < d4; ++j) c4[r4 + j] = j < deg ? bcol[rb + j] : int(I);
+}
+
+// CSR-order values -> packed layout; one wave per node row.
+template <typename T>
+__global__ void k_pack(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ p4,
+                       const T* __restrict__ csr, T* __restrict__ packed) {
+  const int lane = threadIdx.x & 63;
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 64;
+  if (I >= N) return;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb, r4 = p4[I], d4 = p4[I + 1] - r4;
+  const T* src = csr + 9 * int64_t(rb);
+  T* dst = packed + 9 * int64_t(r4);
+  for (int k = lane; k < 9 * d4; k += 64) {
+    const int q = k / d4, j = k - q * d4;
+    const int a = q / 3, c = q - 3 * a;
+    dst[k] = j < deg ? src[a * 3 * deg + 3 * j + c] : T(0);
+  }
+}
+
+// The arrays a schedule reads: the CSR-order layout or the packed one.
+template <typename VT>
+struct Lay {
+  const int32_t* ptr;
+  const int32_t* col;
+  const VT* val;
+};
+
+void ensure_packed64(Ctx& c);
+void ensure_packed32(Ctx& c);
+
+template <typename VT>
+Lay<VT> lay(Ctx& c, const RowSched& rs, const VT* csr_val) {
+  if (!(kSched[rs.variant].mode & 8)) return {c.topo.bptr.get(), c.topo.bcol.get(), csr_val};
+  const void* pv = nullptr;
+  if ((const void*)csr_val == (const void*)c.val.get()) {
+    ensure_packed64(c);
+    pv = c.valp.get();
+  } else if ((const void*)csr_val == (const void*)c.val32.get()) {
+    ensure_packed32(c);
+    pv = c.valp32.get();
+  } else {
+    throw Error{SFEM_EINVAL, "packed schedule for a matrix without a packed copy"};
+  }
+  return {c.ptr4.get(), c.col4.get(), static_cast<const VT*>(pv)};
+}
 
 int vec_grid(int64_t n) {
   int g = div_up(n, kVecThreads);
@@ -574,32 +776,35 @@ struct CgBuffers {
   const void* val_true;  // FP64 matrix of the residual replacement
   const void* dinv;
   void *b, *x, *r, *z, *p0, *p1, *q;  // p0: search direction (p1 unused)
-  const float* mval = nullptr;        // learned preconditioner S' (null: Jacobi)
+  const float* mval = nullptr;        // learned S', packed (null: Jacobi)
+  const int32_t* mptr4 = nullptr;
+  const int32_t* mcol4 = nullptr;
   const void* msq = nullptr;          // its diag(K)^-1/2, typed like the vectors
   void* rh = nullptr;                 // s r, typed like the vectors
 };
+
+int mapply_parts(Ctx& c) {
+  const RowSched rs{0, kRowGridMax};
+  const int64_t rows_per_block = int64_t(kRowWaves) * (kWave / kMLanes);
+  int g = div_up(c.N, rows_per_block);
+  g = g < rs.grid_cap ? g : rs.grid_cap;
+  return div_up(g, kXcds) * kXcds;  // for_rows needs a multiple of kXcds
+}
 
 // z = M r; with fresh_rh the scaled residual rh = s r is formed first (it
 // is otherwise maintained by k_cg_xr).
 template <typename P>
 void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fresh_rh) {
-  const RowSched rs = c.sched32;
-  const int rg = row_grid(c.N, rs);
   const int64_t n = c.n_dof();
   if (fresh_rh) {
     k_rh<P><<<div_up(n, 256), 256, 0, c.stream>>>(n, (const P*)B.msq, r, (P*)B.rh);
     SFEM_HIP(hipGetLastError());
   }
-#define L_(LPR, PAIR)                                                                         \
-  k_mapply<P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                             \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), B.mval, (const P*)B.msq, r,                  \
-      (const P*)B.rh, z, guarded ? c.sc.get() : nullptr, c.partials.get())
-  SFEM_SCHED_SWITCH(rs.variant, L_)
-#undef L_
+  k_mapply<P><<<mapply_parts(c), kRowWaves * kWave, 0, c.stream>>>(
+      c.N, B.mptr4, B.mcol4, B.mval, (const P*)B.msq, r, (const P*)B.rh, z,
+      guarded ? c.sc.get() : nullptr, c.partials.get());
   SFEM_HIP(hipGetLastError());
 }
-
-int mapply_parts(Ctx& c) { return row_grid(c.N, c.sched32); }
 
 // With c.profile set, every SpMV launch is bracketed by a pair of events;
 // their elapsed times are summed once the chunk has finished.
@@ -618,13 +823,14 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
     }
   (void)parity;
   P* p = (P*)B.p0;
+  const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val);
   for (int k = 0; k < iters; ++k) {
     k_cg_p<P><<<vg, kVecThreads, 0, s>>>(n, (const P*)B.z, p, c.sc.get());
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k], s));
-#define L_(LPR, PAIR)                                                                          \
-  k_cg_spmv<VT, P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(                                 \
-      N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val, p, (P*)B.q, c.sc.get(),        \
-      c.partials.get())
+#define L_(LPR, MODE)                                                                          \
+  k_cg_spmv<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(N, LY.ptr, LY.col, LY.val, p,     \
+                                                                (P*)B.q, c.sc.get(),           \
+                                                                c.partials.get())
     SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k + 1], s));
@@ -661,10 +867,11 @@ template <typename VT, typename P>
 void cg_replace(Ctx& c, const CgBuffers& B) {
   const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
   const int rg = row_grid(c.N, rs);
-#define L_(LPR, PAIR)                                                                          \
-  k_cg_replace<VT, P, LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                     \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), (const VT*)B.val_true, (const P*)B.b,          \
-      (const P*)B.x, (P*)B.r, (P*)B.z, (const P*)B.dinv, c.partials.get())
+  const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val_true);
+#define L_(LPR, MODE)                                                                          \
+  k_cg_replace<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, c.stream>>>(                     \
+      c.N, LY.ptr, LY.col, LY.val, (const P*)B.b, (const P*)B.x, (P*)B.r, (P*)B.z,            \
+      (const P*)B.dinv, c.partials.get())
   SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
@@ -771,9 +978,10 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
 void spmv_f64_sched(Ctx& c, const RowSched& rs, const double* val, const double* x, double* y,
                     hipStream_t s) {
   const int rg = row_grid(c.N, rs);
-#define L_(LPR, PAIR)                                                        \
-  k_spmv<double, double, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(        \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
+  const Lay<double> LY = lay<double>(c, rs, val);
+#define L_(LPR, MODE)                                                        \
+  k_spmv<double, double, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(        \
+      c.N, LY.ptr, LY.col, LY.val, x, y)
   SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
@@ -782,22 +990,21 @@ void spmv_f64_sched(Ctx& c, const RowSched& rs, const double* val, const double*
 void spmv_f32_sched(Ctx& c, const RowSched& rs, const float* val, const float* x, float* y,
                     hipStream_t s) {
   const int rg = row_grid(c.N, rs);
-#define L_(LPR, PAIR)                                                      \
-  k_spmv<float, float, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(        \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
+  const Lay<float> LY = lay<float>(c, rs, val);
+#define L_(LPR, MODE)                                                      \
+  k_spmv<float, float, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(        \
+      c.N, LY.ptr, LY.col, LY.val, x, y)
   SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
 }
 
 void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream_t s) {
-  const RowSched rs = c.sched32;
+  // any FP32 matrix in the CSR-order layout (no packed copy): a fixed schedule
+  const RowSched rs{2, 4096};
   const int rg = row_grid(c.N, rs);
-#define L_(LPR, PAIR)                                                      \
-  k_spmv<float, double, LPR, PAIR><<<rg, kRowWaves * kWave, 0, s>>>(       \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), val, x, y)
-  SFEM_SCHED_SWITCH(rs.variant, L_)
-#undef L_
+  k_spmv<float, double, 32, 0><<<rg, kRowWaves * kWave, 0, s>>>(c.N, c.topo.bptr.get(),
+                                                                 c.topo.bcol.get(), val, x, y);
   SFEM_HIP(hipGetLastError());
 }
 
@@ -811,33 +1018,63 @@ void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s)
 
 // Times every row schedule (variant x grid cap) on this context's matrix
 // with HIP events and keeps the fastest for FP64 and, if present, FP32.
+static void ensure_work(Ctx& c, bool f32);
+
+__global__ void k_ones(int64_t n, double* __restrict__ u) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) u[i] = 1.0;
+}
+
+// Times every row schedule (variant x grid cap) and keeps the fastest.
+// FP64: `reps` Jacobi-PCG iterations on the context's matrix from a fixed
+// start (b = 1), i.e. the product inside the loop where the vector kernels
+// share the caches (an isolated product favours other schedules); the time
+// per iteration is reported.  FP32 (if present): `reps` isolated products.
 void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
   const int64_t n = c.n_dof();
-  c.x.reserve(n);
-  c.q.reserve(n);
+  ensure_work(c, false);
   c.x32.reserve(n);
   c.q32.reserve(n);
   k_zero<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.x.get());
+  k_ones<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.w.get());
   SFEM_HIP(hipGetLastError());
+  const bool prof = c.profile;
+  c.profile = false;
   const int caps[] = {1024, 2048, 4096, 8192};
+  const RowSched keep64 = c.sched64;
   for (int prec = 0; prec < (c.have_f32 ? 2 : 1); ++prec) {
     double best = 1e30;
-    RowSched pick = prec ? c.sched32 : c.sched64;
+    RowSched pick = prec ? c.sched32 : keep64;
     for (int v = 0; v < kNumSched; ++v)
       for (int cap : caps) {
         const RowSched rs{v, cap};
-        auto run = [&] {
-          if (prec == 0) spmv_f64_sched(c, rs, c.val.get(), c.x.get(), c.q.get(), c.stream);
-          else spmv_f32_sched(c, rs, c.val32.get(), c.x32.get(), c.q32.get(), c.stream);
-        };
-        run();  // warm
-        SFEM_HIP(hipEventRecord(c.ev0, c.stream));
-        for (int r = 0; r < reps; ++r) run();
-        SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+        double us = 0.0;
+        if (prec == 0) {
+          c.sched64 = rs;
+          CgBuffers B{c.val.get(), c.val.get(), c.dinv.get(), c.w.get(), c.x.get(), c.r.get(),
+                      c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
+          const int vg = vec_grid(n);
+          k_cg_start<double><<<vg, kVecThreads, 0, c.stream>>>(
+              n, c.w.get(), 1.0, nullptr, c.x.get(), c.r.get(), c.z.get(), c.p.get(), c.p2.get(),
+              c.dinv.get(), c.partials.get());
+          finalize(c, kFinStart, vg);
+          k_cg_arm<<<1, 64, 0, c.stream>>>(c.sc.get(), 0.0);
+          int parity = 0;
+          cg_iterations<double, double>(c, B, 2, parity);  // warm
+          SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+          cg_iterations<double, double>(c, B, reps, parity);
+          SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+        } else {
+          spmv_f32_sched(c, rs, c.val32.get(), c.x32.get(), c.q32.get(), c.stream);  // warm
+          SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+          for (int r = 0; r < reps; ++r)
+            spmv_f32_sched(c, rs, c.val32.get(), c.x32.get(), c.q32.get(), c.stream);
+          SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+        }
         SFEM_HIP(hipEventSynchronize(c.ev1));
         float ms = 0;
         SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-        const double us = 1e3 * ms / reps;
+        us = 1e3 * ms / reps;
         if (us < best) {
           best = us;
           pick = rs;
@@ -851,14 +1088,15 @@ void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
       if (best_us32) *best_us32 = best;
     }
   }
+  c.profile = prof;
 }
 
 void resid64(Ctx& c, const double* u, double* r) {
   const int rg = row_grid(c.N, c.sched64);
-#define L_(LPR, PAIR)                                                                 \
-  k_resid64<LPR, PAIR><<<rg, kRowWaves * kWave, 0, c.stream>>>(                       \
-      c.N, c.topo.bptr.get(), c.topo.bcol.get(), c.val.get(), c.f_bc.get(), u, r, \
-      c.partials.get())
+  const Lay<double> LY = lay<double>(c, c.sched64, c.val.get());
+#define L_(LPR, MODE)                                                                 \
+  k_resid64<LPR, MODE><<<rg, kRowWaves * kWave, 0, c.stream>>>(                       \
+      c.N, LY.ptr, LY.col, LY.val, c.f_bc.get(), u, r, c.partials.get())
   SFEM_SCHED_SWITCH(c.sched64.variant, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
@@ -961,7 +1199,9 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
                 c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
                 c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
     if (learned) {
-      B.mval = c.mval.get();
+      B.mval = c.mvalp.get();
+      B.mptr4 = c.ptr4.get();
+      B.mcol4 = c.col4.get();
       B.msq = c.msqrt.get();
       B.rh = c.rh.get();
     }
@@ -1002,7 +1242,9 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
       const double scale = rnorm / std::sqrt(double(n));  // keeps FP32 values O(1)
       bool met = false, brk = false;
       const double tol = inner * std::sqrt(double(n));  // ||r / scale|| = sqrt(n)
-      B.mval = use_learned ? c.mval.get() : nullptr;
+      B.mval = use_learned ? c.mvalp.get() : nullptr;
+      B.mptr4 = c.ptr4.get();
+      B.mcol4 = c.col4.get();
       B.msq = c.msqrt32.get();
       B.rh = c.rh32.get();
       iters += pcg<float, float>(c, B, r64, 1.0 / scale, tol, max_iter - iters,
@@ -1045,11 +1287,63 @@ int jacobi_run(Ctx& c, const double* b, double tol_abs, int every, int max_iter,
   return pcg<double, double>(c, B, b, 1.0, tol_abs, max_iter, every, met, brk, true, &hook);
 }
 
+void pack_pattern(Ctx& c) {
+  if (c.nb4 > 0) return;
+  const int64_t N = c.N;
+  hipStream_t s = c.stream;
+  c.ptr4.reserve(N + 1);
+  DBuf<int32_t> d4;
+  d4.reserve(N);
+  k_deg4<<<div_up(N, 256), 256, 0, s>>>(N, c.topo.bptr.get(), d4.get());
+  SFEM_HIP(hipGetLastError());
+  exclusive_scan_i32(d4.get(), c.ptr4.get(), N, s);
+  int32_t nb4 = 0;
+  SFEM_HIP(hipMemcpyAsync(&nb4, c.ptr4.get() + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SFEM_HIP(hipStreamSynchronize(s));
+  c.col4.reserve(nb4);
+  k_col4<<<div_up(N, 256), 256, 0, s>>>(N, c.topo.bptr.get(), c.topo.bcol.get(), c.ptr4.get(),
+                                         c.col4.get());
+  SFEM_HIP(hipGetLastError());
+  c.nb4 = nb4;
+}
+
+void pack_values_f32(Ctx& c, const float* csr, float* packed) {
+  pack_pattern(c);
+  k_pack<float><<<div_up(c.N * 64, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(),
+                                                              c.ptr4.get(), csr, packed);
+  SFEM_HIP(hipGetLastError());
+}
+
+namespace {
+void ensure_packed64(Ctx& c) {
+  if (c.packed64) return;
+  pack_pattern(c);
+  c.valp.reserve(9 * c.nb4);
+  k_pack<double><<<div_up(c.N * 64, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(),
+                                                               c.ptr4.get(), c.val.get(),
+                                                               c.valp.get());
+  SFEM_HIP(hipGetLastError());
+  c.packed64 = true;
+}
+
+void ensure_packed32(Ctx& c) {
+  if (c.packed32) return;
+  SFEM_REQUIRE(c.have_f32, SFEM_ESTATE, "no FP32 copy of K to pack");
+  c.valp32.reserve(9 * c.nb4 > 0 ? 9 * c.nb4 : 1);
+  pack_pattern(c);
+  c.valp32.reserve(9 * c.nb4);
+  pack_values_f32(c, c.val32.get(), c.valp32.get());
+  c.packed32 = true;
+}
+}  // namespace
+
 void learned_apply(Ctx& c, const double* r, double* z) {
   SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");
   ensure_work(c, false);
   CgBuffers B{};
-  B.mval = c.mval.get();
+  B.mval = c.mvalp.get();
+  B.mptr4 = c.ptr4.get();
+  B.mcol4 = c.col4.get();
   B.msq = c.msqrt.get();
   B.rh = c.rh.get();
   mapply<double>(c, B, r, z, false, true);

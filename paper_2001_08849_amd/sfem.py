@@ -21,6 +21,7 @@ K_UNCONSTRAINED, K_WITH_BC = 0, 1
 ASM_F64, ASM_F32_COPY = 0, 1
 PRECOND_JACOBI, PRECOND_LEARNED = 0, 1
 MODE_F64, MODE_F32_IR, MODE_F32_RR = 0, 1, 2
+NUM_SCHEDULES = 17
 
 STATUS = {0: "SFEM_OK", -1: "SFEM_EINVAL", -2: "SFEM_EMESH", -3: "SFEM_ENOMEM",
           -4: "SFEM_EHIP", -5: "SFEM_ENOCONV", -6: "SFEM_ESTATE"}

@@ -312,15 +312,15 @@ def test_assembly_bit_reproducible():
 
 
 def test_every_row_schedule_matches_oracle(small):
-    """All 8 row schedules (lanes per row x rows per step) and grid caps give
-    the oracle's K x; the autotuner picks a valid one."""
+    """Every row schedule (lanes per row x loop shape x value loads) and grid
+    cap gives the oracle's K x; the autotuner picks a valid one."""
     name, cs = small
     sfem = _sfem()
     ctx = gpu_ctx(cs.p, f32=True)
     x = np.random.default_rng(11).standard_normal(cs.K.shape[0])
     yr = cs.Kb @ x
     worst = 0.0
-    for v in range(8):
+    for v in range(sfem.NUM_SCHEDULES):
         for cap in (8, 1024, 4096):
             ctx.set_schedule(v, cap)
             y = ctx.spmv(x)
@@ -332,7 +332,7 @@ def test_every_row_schedule_matches_oracle(small):
     eu = np.linalg.norm(u - ud) / np.linalg.norm(ud)
     print(f"{name}: worst SpMV error over schedules {worst:.2e}; autotuned f64 schedule "
           f"{v64}/{cap64} ({tuned['f64'][1]:.1f} us); solve error {eu:.2e}")
-    assert worst <= 1e-13 and 0 <= v64 < 8 and eu <= 1e-8
+    assert worst <= 1e-13 and 0 <= v64 < sfem.NUM_SCHEDULES and eu <= 1e-8
 
 
 def test_c1_f32_matrix_with_f64_replacement(c1):

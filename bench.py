@@ -48,9 +48,18 @@ def algorithmic_bytes(N, T, nf, nnz, nb, f32_copy=False, per_tet=False):
     return asm, spmv64, spmv32
 
 
+def mapply_bytes(N, nnz, nb):
+    """Learned M apply z = s (rh + S' rh): FP32 S' once, block columns, row
+    offsets, the gathered rh, then r, s, rh, z_old read and z written per
+    DOF (FP64 vectors)."""
+    n = 3 * N
+    return 4 * nnz + 4 * nb + 4 * (N + 1) + 8 * n + 5 * 8 * n
+
+
 KERNEL_SOURCES = {
     "cg_spmv_f64_c2": ("k_cg_spmv<double, double", "paper_2001_08849_amd/csrc/solve.hip"),
     "assemble_c2": ("k_assemble<false>", "paper_2001_08849_amd/csrc/assemble.hip"),
+    "mapply_c2": ("k_mapply<double>", "paper_2001_08849_amd/csrc/solve.hip"),
 }
 
 
@@ -81,17 +90,26 @@ def _short(name):
 
 
 def _counter_means(csv_path):
-    """Mean counter value per kernel name over its dispatches."""
+    """Mean counter value per kernel name over its dispatches at the grid it
+    was launched with most often (the solver's launches; the autotuner also
+    tries other grid caps)."""
     import collections
     import csv
     per = collections.defaultdict(float)
-    name = {}
+    name, grid = {}, {}
     for r in csv.DictReader(open(csv_path)):
         per[r["Dispatch_Id"]] += float(r["Counter_Value"])
         name[r["Dispatch_Id"]] = r["Kernel_Name"]
+        grid[r["Dispatch_Id"]] = int(r.get("Grid_Size", 0) or 0)
+    count = collections.Counter((name[d], grid[d]) for d in per)
+    mode = {}
+    for (nm, g), k in count.items():
+        if nm not in mode or k > count[(nm, mode[nm])]:
+            mode[nm] = g
     acc = collections.defaultdict(list)
     for d, v in per.items():
-        acc[name[d]].append(v)
+        if grid[d] == mode[name[d]]:
+            acc[name[d]].append(v)
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
@@ -109,11 +127,13 @@ def summarize_profiles(prof_dir, command_note):
     kf = true_bytes / (cfetch[copy][0] * 1024.0)   # FETCH_SIZE is in KiB
     kw = true_bytes / (cwrite[copy][0] * 1024.0)
     for tag, (pattern, src) in KERNEL_SOURCES.items():
-        kn = [k for k in fetch if pattern in k]
+        # the schedule variant launched most often at full size (the one the
+        # solver ran, not the autotuner's candidates)
+        kn = sorted((k for k in fetch if pattern in k), key=lambda k: -fetch[k][1])
         if not kn:
             continue
         fr, n = fetch[kn[0]]
-        wr, _ = write[[k for k in write if pattern in k][0]]
+        wr, _ = write[kn[0]]
         rec = {
             "kernel": _short(kn[0]), "dispatches": n,
             "fetch_kib_raw": fr, "write_kib_raw": wr,
@@ -130,7 +150,7 @@ def summarize_profiles(prof_dir, command_note):
                      "# counters read for a plain 1 GiB copy; stale once the source hash changes.\n")
             fh.write(json.dumps(rec, indent=1) + "\n")
     stats = glob.glob(os.path.join(prof_dir, "ktrace", "*kernel_stats.csv"))
-    if stats:
+    if stats and not os.environ.get("SFEM_KEEP_KERNEL_TABLE"):
         import csv
         rows = list(csv.DictReader(open(stats[0])))
         with open(os.path.join(PROFILE_DIR, "kernels_c2.md"), "w") as fh:
@@ -207,6 +227,11 @@ def train_network(args, mg, sfem, np):
     """Trains the learned preconditioner on blob-material cantilevers of
     140x14x14 cells (164,640 tets each): pairs from Jacobi-PCG runs, Adam on
     the device.  Returns the network and the training record."""
+    if args.train_steps <= 0:
+        # untrained network (M = Jacobi exactly): exercises the learned
+        # solve's kernels at full size without the training meshes
+        log("[bench] --train-steps 0: untrained network, no pairs or training")
+        return {"net": sfem.Gnn(0, seed=5), "pairs": 0, "train_meshes": 0, "steps": 0}
     t0 = time.time()
     ctxs, n_pairs = [], 0
     for mi in range(args.train_meshes):
@@ -391,6 +416,15 @@ def main():
             out["solve_s"]["learned_incl_inference"] = ls + li
             out["solve_iters"]["learned"] = lsolves[-1]["iters"]
             out["solve_true_relres"]["learned"] = lsolves[-1]["true_relres"]
+            mms = float(np.mean([i["ms_mapply_avg"] for i in lsolves]))
+            mb = mapply_bytes(m.n_nodes, s.nnz, s.n_blocks)
+            ach_m = mb / (mms * 1e-3) / 1e9 if mms > 0 else None
+            out["roofline_mapply"] = {
+                "kernel": "k_mapply<double>", "bound": "hbm", "achieved": ach_m,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach_m / HBM_PEAK_GBS if ach_m else None,
+                "traffic": read_traffic("mapply_c2"), "bytes_per_launch": mb,
+                "us_per_launch": mms * 1e3}
             out["learned"] = {
                 "solver": "flexible PCG, K FP64, learned M (S' FP32, network BF16-MFMA), "
                           "FP64 vectors and dots, true relres <= 1e-8",
@@ -401,7 +435,8 @@ def main():
             }
         spmv_ms = float(np.mean([i["ms_spmv_avg"] for i in solves]))
         ach = spmv_bytes / (spmv_ms * 1e-3) / 1e9
-        out["roofline"] = {"kernel": "k_cg_spmv<double,double>", "bound": "hbm",
+        out["roofline"] = {"kernel": f"k_cg_spmv<double,double> (row schedule "
+                                     f"{tuned['f64'][0][0]})", "bound": "hbm",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS,
                            "traffic": read_traffic("cg_spmv_f64_c2"),

@@ -193,6 +193,8 @@ typedef struct {
   double ms_solve;    /* device time of the solve (HIP events) */
   double ms_spmv_avg; /* mean device time of one CG SpMV launch (profile) */
   int n_spmv;         /* SpMV launches timed (profile) */
+  double ms_mapply_avg; /* mean device time of one learned-M launch (profile) */
+  int n_mapply;       /* learned-M launches timed (profile) */
 } sfem_solve_info;
 
 int sfem_solve(sfem_ctx* ctx, const sfem_solve_opts* opts, double* u, int ptr_kind,

@@ -124,8 +124,8 @@ struct Ctx {
   hipEvent_t tev0 = nullptr, tev1 = nullptr;  // sfem_timer_*
   std::vector<hipEvent_t> prof_ev;             // per-launch SpMV timing
   bool profile = false;
-  double prof_ms = 0;
-  int prof_n = 0;
+  double prof_ms = 0, prof_mms = 0;  // summed SpMV / learned-M launch times
+  int prof_n = 0, prof_mn = 0;
   double ms_topology = 0, ms_assemble = 0;
 
   int64_t n_dof() const { return 3 * N; }

@@ -816,7 +816,7 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   const int rg = row_grid(N, rs);
   const int vg = vec_grid(n);
   if (c.profile)
-    while (int(c.prof_ev.size()) < 2 * iters) {
+    while (int(c.prof_ev.size()) < 4 * iters) {
       hipEvent_t e;
       SFEM_HIP(hipEventCreate(&e));
       c.prof_ev.push_back(e);
@@ -826,19 +826,21 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val);
   for (int k = 0; k < iters; ++k) {
     k_cg_p<P><<<vg, kVecThreads, 0, s>>>(n, (const P*)B.z, p, c.sc.get());
-    if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k], s));
+    if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k], s));
 #define L_(LPR, MODE)                                                                          \
   k_cg_spmv<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(N, LY.ptr, LY.col, LY.val, p,     \
                                                                 (P*)B.q, c.sc.get(),           \
                                                                 c.partials.get())
     SFEM_SCHED_SWITCH(rs.variant, L_)
 #undef L_
-    if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[2 * k + 1], s));
+    if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k + 1], s));
     finalize(c, kFinAlpha, rg);
     if (B.mval) {
       k_cg_xr<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, p, (const P*)B.q,
                                             (const P*)B.msq, (P*)B.rh, c.sc.get());
+      if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k + 2], s));
       mapply<P>(c, B, (const P*)B.r, (P*)B.z, true, false);
+      if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k + 3], s));
       finalize(c, kFinBetaFlex, mapply_parts(c));
     } else {
       k_cg_update<P><<<vg, kVecThreads, 0, s>>>(n, (P*)B.x, (P*)B.r, (P*)B.z, p, (const P*)B.q,
@@ -849,17 +851,23 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   SFEM_HIP(hipGetLastError());
 }
 
-// Adds the SpMV launches of the last chunk that did work (a launch that
-// returned at once because the solve had converged is not counted).
-void collect_profile(Ctx& c, int iters, int done_before, int done_after) {
+// Adds the SpMV (and learned M) launches of the last chunk that did work (a
+// launch that returned at once because the solve had converged is not
+// counted).
+void collect_profile(Ctx& c, int iters, int done_before, int done_after, bool learned) {
   if (!c.profile) return;
   SFEM_HIP(hipStreamSynchronize(c.stream));
   const int worked = std::min(iters, done_after - done_before);
   for (int k = 0; k < worked; ++k) {
     float ms = 0;
-    SFEM_HIP(hipEventElapsedTime(&ms, c.prof_ev[2 * k], c.prof_ev[2 * k + 1]));
+    SFEM_HIP(hipEventElapsedTime(&ms, c.prof_ev[4 * k], c.prof_ev[4 * k + 1]));
     c.prof_ms += ms;
     c.prof_n += 1;
+    if (learned) {
+      SFEM_HIP(hipEventElapsedTime(&ms, c.prof_ev[4 * k + 2], c.prof_ev[4 * k + 3]));
+      c.prof_mms += ms;
+      c.prof_mn += 1;
+    }
   }
 }
 
@@ -943,7 +951,7 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
     read_scalars(c);
     const int before = done;
     done = int(c.sc_host->aux[0]);
-    collect_profile(c, chunk, before, done);
+    collect_profile(c, chunk, before, done, B.mval != nullptr);
     if (hook && done > before) (*hook)(done);
     if (!replace) {
       met = c.sc_host->converged == 1;
@@ -1177,6 +1185,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   c.profile = o.profile != 0;
   c.prof_ms = 0;
   c.prof_n = 0;
+  c.prof_mms = 0;
+  c.prof_mn = 0;
   SFEM_HIP(hipEventRecord(c.ev0, c.stream));
 
   // ||f||: the residual of u = 0
@@ -1273,6 +1283,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   info.ms_solve = ms;
   info.n_spmv = c.prof_n;
   info.ms_spmv_avg = c.prof_n ? c.prof_ms / c.prof_n : 0.0;
+  info.n_mapply = c.prof_mn;
+  info.ms_mapply_avg = c.prof_mn ? c.prof_mms / c.prof_mn : 0.0;
   if (!info.converged && status == SFEM_OK) status = SFEM_ENOCONV;
   return status;
 }

@@ -72,7 +72,8 @@ class BatchInfo(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer_steps", C.c_int), ("fell_back", C.c_int),
                 ("converged", C.c_int), ("true_relres", C.c_double), ("ms_solve", C.c_double),
-                ("ms_spmv_avg", C.c_double), ("n_spmv", C.c_int)]
+                ("ms_spmv_avg", C.c_double), ("n_spmv", C.c_int),
+                ("ms_mapply_avg", C.c_double), ("n_mapply", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

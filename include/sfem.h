@@ -316,8 +316,9 @@ int sfem_gnn_apply(sfem_gnn* g, sfem_ctx* ctx, double* ms);
 int sfem_get_precond_info(sfem_ctx* ctx, double* theta, double* lambda_min, double* lambda_max);
 
 /* The learned preconditioner of a context: the correction theta S (float32
- * [nnz], in the order of sfem_get_csr's values, as the solver reads it) and
- * d^-1/2 (float64 [3 n_nodes]); either pointer may be NULL. */
+ * [nnz], in the order of sfem_get_csr's values; the solver applies these
+ * values rounded to BF16) and d^-1/2 (float64 [3 n_nodes]); either pointer
+ * may be NULL. */
 int sfem_get_precond(sfem_ctx* ctx, float* correction, double* dinv_sqrt, int ptr_kind);
 /* z = M r (float64 [3 n_nodes]) with the learned preconditioner. */
 int sfem_precond_apply(sfem_ctx* ctx, const double* r, double* z, int ptr_kind);

@@ -103,7 +103,7 @@ struct Ctx {
   bool have_learned = false;
   double m_theta = 1.0, m_lmin = 0.0, m_lmax = 0.0;  // S' = theta S; Lanczos range of S
   DBuf<float> mval;
-  DBuf<float> mvalp;             // the same values in the packed layout
+  DBuf<__bf16> mvalp;            // the same values, BF16, in the packed layout
   DBuf<double> msqrt;
   DBuf<float> msqrt32;
   std::shared_ptr<GnnWork> gnn;  // features, activations and training pairs
@@ -148,6 +148,7 @@ void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream
 // Packed layout: pattern tables (once per mesh) and a value repack.
 void pack_pattern(Ctx& c);
 void pack_values_f32(Ctx& c, const float* csr, float* packed);
+void pack_values_bf16(Ctx& c, const float* csr, __bf16* packed);
 // solve.hip
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info);
 double true_residual(Ctx& c, const double* u);

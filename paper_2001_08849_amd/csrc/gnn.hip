@@ -1011,7 +1011,7 @@ void gnn_precondition(Ctx& c, Gnn& g) {
   // packed copy for the solver's M apply
   pack_pattern(c);
   c.mvalp.reserve(9 * c.nb4);
-  pack_values_f32(c, c.mval.get(), c.mvalp.get());
+  pack_values_bf16(c, c.mval.get(), c.mvalp.get());
   SFEM_HIP(hipStreamSynchronize(s));
   c.have_learned = true;
 }

@@ -259,6 +259,14 @@ __device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
   v[2] = b.x;
   v[3] = b.y;
 }
+__device__ __forceinline__ void load4(const __bf16* p, double (&v)[4]) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const bf16x4 a = *reinterpret_cast<const bf16x4*>(p);
+  v[0] = float(a[0]);
+  v[1] = float(a[1]);
+  v[2] = float(a[2]);
+  v[3] = float(a[3]);
+}
 __device__ __forceinline__ void load4(const float* p, double (&v)[4]) {
   const float4 a = *reinterpret_cast<const float4*>(p);
   v[0] = a.x;
@@ -468,7 +476,7 @@ __global__ void k_rh(int64_t n, const P* __restrict__ s, const P* __restrict__ r
 }
 
 // Learned preconditioner z = M r = s (rh + S' rh), rh = s r, s =
-// diag(K)^-1/2, with S' (FP32) in the packed layout: node row I holds a
+// diag(K)^-1/2, with S' (BF16) in the packed layout: node row I holds a
 // [9][d4] array (component q = 3a + c major, blocks minor, d4 = deg rounded
 // up to 4) at 9 ptr4[I], block columns col4 padded with I and zero values.
 // A lane takes 4 blocks per step: one int4 column load and nine float4 value
@@ -480,13 +488,13 @@ constexpr int kMLanes = 8;  // lanes per node row: 32 blocks per step
 template <typename P>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_mapply(int64_t N, const int32_t* __restrict__ ptr4, const int32_t* __restrict__ col4,
-             const float* __restrict__ mvalp, const P* __restrict__ s, const P* __restrict__ r,
+             const __bf16* __restrict__ mvalp, const P* __restrict__ s, const P* __restrict__ r,
              const P* __restrict__ rh, P* __restrict__ z, const CgScalars* __restrict__ sc,
              double* __restrict__ partials) {
   if (sc && sc->converged) return;
   const PlainX<P> xf{rh};
   double v[3] = {0.0, 0.0, 0.0};
-  row_apply<float, kMLanes, 8>(N, ptr4, col4, mvalp, xf, [&](int I, const double (&y)[3]) {
+  row_apply<__bf16, kMLanes, 8>(N, ptr4, col4, mvalp, xf, [&](int I, const double (&y)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -776,7 +784,7 @@ struct CgBuffers {
   const void* val_true;  // FP64 matrix of the residual replacement
   const void* dinv;
   void *b, *x, *r, *z, *p0, *p1, *q;  // p0: search direction (p1 unused)
-  const float* mval = nullptr;        // learned S', packed (null: Jacobi)
+  const __bf16* mval = nullptr;       // learned S', packed BF16 (null: Jacobi)
   const int32_t* mptr4 = nullptr;
   const int32_t* mcol4 = nullptr;
   const void* msq = nullptr;          // its diag(K)^-1/2, typed like the vectors
@@ -1317,6 +1325,30 @@ void pack_pattern(Ctx& c) {
                                          c.col4.get());
   SFEM_HIP(hipGetLastError());
   c.nb4 = nb4;
+}
+
+// CSR-order FP32 values -> packed BF16 (round to nearest even).
+__global__ void k_pack_bf16(int64_t N, const int32_t* __restrict__ bptr,
+                            const int32_t* __restrict__ p4, const float* __restrict__ csr,
+                            __bf16* __restrict__ packed) {
+  const int lane = threadIdx.x & 63;
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 64;
+  if (I >= N) return;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb, r4 = p4[I], d4 = p4[I + 1] - r4;
+  const float* src = csr + 9 * int64_t(rb);
+  __bf16* dst = packed + 9 * int64_t(r4);
+  for (int k = lane; k < 9 * d4; k += 64) {
+    const int q = k / d4, j = k - q * d4;
+    const int a = q / 3, c = q - 3 * a;
+    dst[k] = __bf16(j < deg ? src[a * 3 * deg + 3 * j + c] : 0.f);
+  }
+}
+
+void pack_values_bf16(Ctx& c, const float* csr, __bf16* packed) {
+  pack_pattern(c);
+  k_pack_bf16<<<div_up(c.N * 64, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(),
+                                                            c.ptr4.get(), csr, packed);
+  SFEM_HIP(hipGetLastError());
 }
 
 void pack_values_f32(Ctx& c, const float* csr, float* packed) {

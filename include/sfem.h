@@ -165,11 +165,16 @@ int sfem_spmv(sfem_ctx* ctx, const double* x, double* y, int ptr_kind);
  *                      FP32-matrix PCG solve of K d = r whose recursive
  *                      residual falls by inner_rtol (dot products in FP64),
  *                      u += d.  Needs SFEM_ASM_F32_COPY.
- *   SFEM_MODE_F32_RR : one PCG run whose products use the FP32 matrix and
- *                      whose vectors and dots are FP64; every check_every
- *                      iterations the residual is replaced by the FP64
- *                      residual f - K u (a refinement step that keeps the
- *                      Krylov recurrences).  Needs SFEM_ASM_F32_COPY.
+ *   SFEM_MODE_F32_RR : PCG with FP64 vectors and dots and FP32-matrix
+ *                      products, the residual replaced every check_every
+ *                      iterations by the FP64 residual f - K u, until the
+ *                      FP64 true relative residual reaches f32_until (0:
+ *                      1e-3) or stagnates; then FP64 PCG on the correction
+ *                      K d = f - K u from the current u.  K u is a small
+ *                      difference of large entries (K annihilates rigid
+ *                      motions, u is smooth), so an FP32 product's error is
+ *                      large relative to ||f||: FP32 products only pay at
+ *                      loose accuracy.  Needs SFEM_ASM_F32_COPY.
  * u: float64 [3 n_nodes] output (x0 = 0).  Returns SFEM_ENOCONV if rtol was
  * not reached within max_iter (u and info are still written).
  */
@@ -182,6 +187,7 @@ typedef struct {
   double inner_rtol;  /* F32_IR inner tolerance (0: 1e-2) */
   int max_outer;      /* F32_IR outer-step cap (0: 30) */
   int profile;        /* nonzero: time every SpMV launch with HIP events */
+  double f32_until;   /* F32_RR: FP32 products down to this relres (0: 1e-3) */
 } sfem_solve_opts;
 
 typedef struct {

@@ -929,6 +929,7 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
         const std::function<void(int)>* hook = nullptr) {
   const int64_t n = c.n_dof();
   hipStream_t s = c.stream;
+  const double tol2 = tol_abs * tol_abs;
   // B.b is the P-typed right-hand side the replacement uses; when it is b64
   // itself (FP64 solve) there is nothing to convert
   P* bconv = (static_cast<const void*>(B.b) == static_cast<const void*>(b64)) ? nullptr : (P*)B.b;
@@ -942,7 +943,6 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
     mapply<P>(c, B, (const P*)B.r, (P*)B.z, false, true);
     finalize(c, kFinStartM, mapply_parts(c));
   }
-  const double tol2 = tol_abs * tol_abs;
   k_cg_arm<<<1, 64, 0, s>>>(c.sc.get(), tol2);
   SFEM_HIP(hipGetLastError());
   read_scalars(c);
@@ -1155,6 +1155,25 @@ __global__ void k_axpy64(int64_t n, const double* __restrict__ d, double* __rest
   if (i < n) u[i] += d[i];
 }
 
+// From the current x: solve K d = f - K x by FP64 PCG with B's
+// preconditioner and add d (the restart of SFEM_MODE_F32_RR).
+static int refine64(Ctx& c, const CgBuffers& B, double tol_abs, int max_iter, int check_every,
+                    bool& met, bool& brk) {
+  const int64_t n = c.n_dof();
+  SFEM_HIP(hipMemcpyAsync(c.xs.get(), c.x.get(), sizeof(double) * n, hipMemcpyDeviceToDevice,
+                          c.stream));
+  resid64(c, c.xs.get(), c.w.get());
+  CgBuffers J = B;
+  J.val = c.val.get();
+  J.val_true = c.val.get();
+  J.b = c.w.get();
+  const int its = pcg<double, double>(c, J, c.w.get(), 1.0, tol_abs, max_iter, check_every, met,
+                                      brk);
+  k_axpy64<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.xs.get(), c.x.get());
+  SFEM_HIP(hipGetLastError());
+  return its;
+}
+
 // Jacobi fallback after a learned solve stopped short: from the current x,
 // solve K d = f - K x with Jacobi PCG and add d.  Returns the iterations.
 static int jacobi_fallback(Ctx& c, const CgBuffers& B, double tol_abs, int max_iter,
@@ -1224,10 +1243,26 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
       B.rh = c.rh.get();
     }
     bool met = false, brk = false;
-    info.iters = rr ? pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm,
-                                                 max_iter, check_every, met, brk)
-                    : pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
-                                          check_every, met, brk);
+    if (rr) {
+      // FP32 products while the FP64 true residual is above the switch
+      // level, then FP64 products, continuing the same recurrence
+      const double sw = std::max(o.rtol, o.f32_until > 0 ? o.f32_until : 1e-3);
+      info.iters = pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, sw * fnorm, max_iter,
+                                              check_every, met, brk);
+      // then FP64 products, restarted on the correction K d = f - K u from
+      // the current u (search directions built with FP32 products are not
+      // conjugate for the FP64 matrix, so continuing the recurrence stalls)
+      if (!brk && info.iters < max_iter && sw > o.rtol) {
+        B.val = c.val.get();
+        bool met2 = false;
+        info.iters += refine64(c, B, o.rtol * fnorm, max_iter - info.iters, check_every, met2,
+                               brk);
+        met = met2;
+      }
+    } else {
+      info.iters = pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
+                                       check_every, met, brk);
+    }
     if (learned && !met && info.iters < max_iter) {
       info.fell_back = 1;
       info.iters += jacobi_fallback(c, B, o.rtol * fnorm, max_iter - info.iters, check_every,

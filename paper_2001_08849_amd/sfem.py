@@ -53,7 +53,7 @@ class SfemError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("precond", C.c_int), ("mode", C.c_int), ("rtol", C.c_double),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int), ("profile", C.c_int)]
+                ("max_outer", C.c_int), ("profile", C.c_int), ("f32_until", C.c_double)]
 
 
 class BatchOpts(C.Structure):
@@ -308,9 +308,9 @@ class Context:
     def solve(self, rtol: float = 1e-8, mode: int = MODE_F64, precond: int = PRECOND_JACOBI,
               max_iter: int = 0, check_every: int = 0, inner_rtol: float = 0.0,
               max_outer: int = 0, out=None, raise_on_noconv: bool = False,
-              profile: bool = False):
+              profile: bool = False, f32_until: float = 0.0):
         opts = SolveOpts(precond, mode, rtol, max_iter, check_every, inner_rtol, max_outer,
-                         int(profile))
+                         int(profile), f32_until)
         info = SolveInfo()
         if out is None:
             out = np.empty(self.sizes().n_rows, dtype=np.float64)

@@ -324,6 +324,38 @@ def assemble_rows(xyz, tets, E, nu, nodes, faces=None):
 
 
 # --------------------------------------------------------------- plain FEM-T4
+def face_strain_stress(xyz, tets, E, nu, u, faces=None):
+    """Post-processing (Sec. 3.4): the smoothed strain of every smoothing
+    domain, eps_k = B_k d_k (the B of Eq. 4 built from the smoothed
+    gradients of Eq. 7 and the displacements d_k of the domain's support
+    nodes), and its stress sigma_k = c_k eps_k with the domain's c of Eq. 9
+    (volume-weighted Lame constants, as in the stiffness).  Voigt order xx,
+    yy, zz, yz, xz, xy with engineering shear strains.  Rows in face-table
+    order.  Returns (eps [N_f, 6], sigma [N_f, 6])."""
+    if faces is None:
+        faces = extract_faces(tets)
+    tab = faces["table"]
+    T = tets.shape[0]
+    vol = tet_volume(xyz[tets])
+    lam_t, mu_t = lame(_per_tet(E, T), _per_tet(nu, T))
+    U = np.asarray(u, dtype=np.float64).reshape(-1, 3)
+    eps = np.zeros((tab.shape[0], 6))
+    sig = np.zeros((tab.shape[0], 6))
+    ext = tab[:, 4] < 0
+    for mask in (ext, ~ext):
+        blk = tab[mask]
+        if not blk.shape[0]:
+            continue
+        bbar, _ = smoothed_gradients(xyz, blk)
+        lam, mu = face_material(blk, vol, lam_t, mu_t)
+        nodes = blk[:, [0, 1, 2, 5]] if blk[0, 4] < 0 else blk[:, [0, 1, 2, 5, 6]]
+        d = U[nodes].reshape(blk.shape[0], -1)
+        e = np.einsum("fij,fj->fi", B_matrix(bbar), d)
+        eps[mask] = e
+        sig[mask] = np.einsum("fij,fj->fi", D_matrix(lam, mu), e)
+    return eps, sig
+
+
 def fem_t4_assemble(xyz, tets, E, nu) -> sp.csr_matrix:
     """Conventional FEM with linear tets: K = sum_e V_e B_e^T c B_e, the
     comparison method of Sec. 4.1 (used only by the ordering test)."""

@@ -344,3 +344,46 @@ def test_table4_ordering_and_band():
         w_fs, w_t4 = u[3 * s + 2].mean(), ut[3 * s + 2].mean()
         assert abs(w_t4) < abs(w_fs) < abs(t10)
     assert abs(w_fs / gold[-1, 2] - 1) < 0.10
+
+
+def test_face_strain_patch_and_rigid_motions():
+    """Smoothed strains: a linear displacement field u = A x + c gives the
+    exact constant strain sym(A) (Voigt, engineering shear) on every
+    smoothing domain, interior and exterior, and its stress is the
+    isotropic c applied to it with the domain's own material; a rigid
+    motion (translation + infinitesimal rotation) gives zero strain."""
+    m = mg.box_mesh(4, 3, 2, 2.0, 1.5, 1.0, jitter=0.2, seed=5)
+    rng = np.random.default_rng(8)
+    E = 10.0 ** rng.uniform(9, 11, size=m.n_tets)
+    nu = rng.uniform(0.2, 0.45, size=m.n_tets)
+    A = rng.standard_normal((3, 3))
+    c = rng.standard_normal(3)
+    u = (m.xyz @ A.T + c).reshape(-1)
+    eps, sig = O.face_strain_stress(m.xyz, m.tets, E, nu, u)
+    Sym = 0.5 * (A + A.T)
+    want = np.array([Sym[0, 0], Sym[1, 1], Sym[2, 2], 2 * Sym[1, 2], 2 * Sym[0, 2], 2 * Sym[0, 1]])
+    np.testing.assert_allclose(eps, np.broadcast_to(want, eps.shape), rtol=0, atol=1e-12)
+    # stress: tr(eps) lambda + 2 mu eps on the diagonal, mu gamma off it, with
+    # lambda, mu recovered from the stress of a pure dilatation
+    ones = (m.xyz @ np.eye(3).T).reshape(-1)          # eps = (1, 1, 1, 0, 0, 0)
+    _, sd = O.face_strain_stress(m.xyz, m.tets, E, nu, ones)
+    three_lam_2mu = sd[:, 0]                           # 3 lambda + 2 mu
+    np.testing.assert_allclose(sd[:, 0], sd[:, 1], rtol=1e-12)
+    assert np.abs(sd[:, 3:]).max() <= 1e-12 * np.abs(sd).max()
+    shear = np.zeros((3, 3)); shear[0, 1] = shear[1, 0] = 0.5   # gamma_xy = 1
+    _, ss = O.face_strain_stress(m.xyz, m.tets, E, nu, (m.xyz @ shear.T).reshape(-1))
+    mu_f = ss[:, 5]
+    lam_f = (three_lam_2mu - 2 * mu_f) / 3.0
+    tr = want[:3].sum()
+    np.testing.assert_allclose(sig[:, 0], lam_f * tr + 2 * mu_f * want[0], rtol=1e-10)
+    np.testing.assert_allclose(sig[:, 4], mu_f * want[4], rtol=1e-10)
+    # the recovered constants lie between the smallest and largest tet values
+    lam_t, mu_t = O.lame(E, nu)
+    assert mu_f.min() >= mu_t.min() * (1 - 1e-12) and mu_f.max() <= mu_t.max() * (1 + 1e-12)
+    # rigid motion
+    W = rng.standard_normal((3, 3)) * 1e-3
+    W = W - W.T
+    ur = (m.xyz @ W.T + c).reshape(-1)
+    er, sr = O.face_strain_stress(m.xyz, m.tets, E, nu, ur)
+    # roundoff only: |u| ~ 1 over cells of ~0.5 gives strains ~1e-15
+    assert np.abs(er).max() < 1e-13 and np.abs(sr).max() < 1e-13 * E.max()

@@ -364,6 +364,18 @@ def main():
     total_ms = ctx.timer_stop()
     ctx.synchronize()
 
+    stress = None
+    if not args.skip_solve:
+        # post-processing: smoothed strain and stress of every smoothing domain
+        times = [ctx.face_stress(u)[2] for _ in range(3)]
+        sb = 32 * s.n_faces + 48 * m.n_nodes + 96 * s.n_faces
+        ms_s = float(np.median(times))
+        stress = {"kernel": "k_face_stress<false>", "ms": ms_s, "faces": s.n_faces,
+                  "faces_per_s": s.n_faces / (ms_s * 1e-3), "bytes": sb,
+                  "achieved_GBs": sb / (ms_s * 1e-3) / 1e9,
+                  "frac": sb / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench] stress recovery: {ms_s:.3f} ms for {s.n_faces} faces")
+
     lsolves = []
     if learned is not None and not args.skip_solve:
         net = learned["net"]
@@ -446,6 +458,8 @@ def main():
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_a / HBM_PEAK_GBS,
                                 "traffic": read_traffic("assemble_c2"),
                                 "bytes_per_launch": asm_bytes, "us_per_launch": asm_med * 1e3}
+    if stress:
+        out["stress_recovery"] = stress
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, 1 thread) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -206,6 +206,18 @@ typedef struct {
 int sfem_solve(sfem_ctx* ctx, const sfem_solve_opts* opts, double* u, int ptr_kind,
                sfem_solve_info* info);
 
+/* Post-processing (Sec. 3.4): smoothed strain and stress of every smoothing
+ * domain for displacements u (float64 [3 n_nodes]).  strain = B_k d_k (the B
+ * of Eq. 4 with the smoothed gradients of Eq. 7 and the displacements of
+ * the domain's support nodes), stress = c_k strain (the domain's isotropic
+ * c of Eq. 9, volume-weighted Lame constants as in the stiffness); each
+ * float64 [n_faces][6] in the order of sfem_get_faces, Voigt xx, yy, zz,
+ * yz, xz, xy with engineering shear strains.  Either output may be NULL.
+ * Needs a mesh and a material (not an assembly).  ms (may be NULL): device
+ * time of the kernel. */
+int sfem_face_stress(sfem_ctx* ctx, const double* u, double* strain, double* stress,
+                     int ptr_kind, double* ms);
+
 /* Device time in milliseconds of the most recent topology build and the
  * most recent numeric assembly (HIP events on the context stream). */
 int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);

@@ -479,6 +479,43 @@ int sfem_solve(sfem_ctx* h, const sfem_solve_opts* opts, double* u, int ptr_kind
   });
 }
 
+int sfem_face_stress(sfem_ctx* h, const double* u, double* strain, double* stress,
+                     int ptr_kind, double* ms) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
+    SFEM_REQUIRE(c.have_material, SFEM_ESTATE, "set a material first");
+    SFEM_REQUIRE(u, SFEM_EINVAL, "null displacement vector");
+    const int64_t n = c.n_dof(), m = 6 * c.topo.nf;
+    sfem::DBuf<double> du, de, ds;
+    const double* ud = u;
+    double *ed = strain, *sd = stress;
+    if (ptr_kind == SFEM_PTR_HOST) {
+      du.reserve(n);
+      upload(c, du.get(), u, n, ptr_kind);
+      ud = du.get();
+      ed = strain ? de.reserve(m) : nullptr;
+      sd = stress ? ds.reserve(m) : nullptr;
+    } else {
+      SFEM_REQUIRE(ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL, "bad ptr_kind");
+    }
+    SFEM_HIP(hipEventRecord(c.tev0, c.stream));
+    sfem::face_stress(c, ud, ed, sd);
+    SFEM_HIP(hipEventRecord(c.tev1, c.stream));
+    SFEM_HIP(hipEventSynchronize(c.tev1));
+    if (ms) {
+      float t = 0;
+      SFEM_HIP(hipEventElapsedTime(&t, c.tev0, c.tev1));
+      *ms = t;
+    }
+    if (ptr_kind == SFEM_PTR_HOST) {
+      download(c, strain, ed, m, ptr_kind);
+      download(c, stress, sd, m, ptr_kind);
+    }
+    SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
 int sfem_get_timings(sfem_ctx* h, double* ms_topology, double* ms_assemble) {
   return guarded(h, [&](Ctx& c) {
     if (ms_topology) *ms_topology = c.ms_topology;

@@ -540,6 +540,71 @@ void face_table_public(Ctx& c, int32_t* out) {
   SFEM_HIP(hipGetLastError());
 }
 
+namespace {
+
+// Post-processing: smoothed strain eps_k = B_k d_k and stress
+// sigma_k = c_k eps_k of every smoothing domain (Voigt xx, yy, zz, yz, xz,
+// xy; engineering shear), with the domain's b, V_k and Lame constants as in
+// the stiffness.  One thread per face.
+template <bool HET>
+__global__ void __launch_bounds__(256)
+    k_face_stress(int64_t nf, const int32_t* __restrict__ face, const double* __restrict__ xyz,
+                  double lam0, double mu0, const double* __restrict__ lam_t,
+                  const double* __restrict__ mu_t, const double* __restrict__ u,
+                  double* __restrict__ eps, double* __restrict__ sig) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int sup[5];
+  Vec3 b[5];
+  double Vk, lam, mu;
+  const int n = face_geometry<HET>(face + f * kFaceStride, xyz, lam0, mu0, lam_t, mu_t, sup, b,
+                                   Vk, lam, mu);
+  // displacement gradient G[a][c] = sum_I u_I[a] b_I[c]
+  double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int I = 0; I < n; ++I) {
+    const double* uI = u + 3 * int64_t(sup[I]);
+    const double ua[3] = {uI[0], uI[1], uI[2]};
+    const double bc[3] = {b[I].x, b[I].y, b[I].z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G[a][c] += ua[a] * bc[c];
+  }
+  const double e[6] = {G[0][0], G[1][1], G[2][2], G[1][2] + G[2][1], G[0][2] + G[2][0],
+                       G[0][1] + G[1][0]};
+  const double tr = e[0] + e[1] + e[2];
+  // 16-byte stores (a face's 6 values start at a multiple of 48 bytes)
+  if (eps) {
+    double2* o = reinterpret_cast<double2*>(eps + 6 * f);
+    o[0] = make_double2(e[0], e[1]);
+    o[1] = make_double2(e[2], e[3]);
+    o[2] = make_double2(e[4], e[5]);
+  }
+  if (sig) {
+    double2* o = reinterpret_cast<double2*>(sig + 6 * f);
+    o[0] = make_double2(lam * tr + 2.0 * mu * e[0], lam * tr + 2.0 * mu * e[1]);
+    o[1] = make_double2(lam * tr + 2.0 * mu * e[2], mu * e[3]);
+    o[2] = make_double2(mu * e[4], mu * e[5]);
+  }
+}
+
+}  // namespace
+
+void face_stress(Ctx& c, const double* u, double* eps, double* sig) {
+  const int64_t nf = c.topo.nf;
+  if (nf == 0) return;
+  const int B = 256;
+  if (c.per_tet)
+    k_face_stress<true><<<div_up(nf, B), B, 0, c.stream>>>(nf, c.topo.face.get(), c.xyz.get(),
+                                                           0.0, 0.0, c.lam_t.get(), c.mu_t.get(),
+                                                           u, eps, sig);
+  else
+    k_face_stress<false><<<div_up(nf, B), B, 0, c.stream>>>(nf, c.topo.face.get(), c.xyz.get(),
+                                                            c.lam0, c.mu0, nullptr, nullptr, u,
+                                                            eps, sig);
+  SFEM_HIP(hipGetLastError());
+}
+
 void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t[3]) {
   if (n_tri <= 0) return;
   hipStream_t s = c.stream;

@@ -137,6 +137,7 @@ void build_topology(Ctx& c);
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 void bc_mask_values(Ctx& c);
 void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t[3]);
+void face_stress(Ctx& c, const double* u, double* eps, double* sig);
 void scalar_csr_pattern(Ctx& c, int32_t* row_ptr, int32_t* col_idx);
 void face_table_public(Ctx& c, int32_t* out);
 void extract_dinv(Ctx& c);

@@ -36,7 +36,7 @@ EXPORTS = [
     "sfem_gnn_num_params", "sfem_gnn_create", "sfem_gnn_destroy", "sfem_gnn_last_error",
     "sfem_gnn_get_params", "sfem_gnn_set_params", "sfem_gnn_set_pairs",
     "sfem_gnn_generate_pairs", "sfem_gnn_loss_grad", "sfem_gnn_train", "sfem_gnn_apply",
-    "sfem_get_precond", "sfem_precond_apply", "sfem_get_precond_info",
+    "sfem_get_precond", "sfem_precond_apply", "sfem_get_precond_info", "sfem_face_stress",
     "sfem_batch_create", "sfem_batch_destroy", "sfem_batch_last_error", "sfem_batch_add_mesh",
     "sfem_batch_add_traction", "sfem_batch_build", "sfem_batch_sizes", "sfem_batch_autotune",
     "sfem_batch_get_schedule", "sfem_batch_solve", "sfem_batch_get_solution",
@@ -130,6 +130,7 @@ def lib() -> C.CDLL:
             "sfem_get_precond": (i32, [vp, vp, vp, i32]),
             "sfem_precond_apply": (i32, [vp, vp, vp, i32]),
             "sfem_get_precond_info": (i32, [vp] + [C.POINTER(dbl)] * 3),
+            "sfem_face_stress": (i32, [vp, vp, vp, vp, i32, C.POINTER(dbl)]),
             "sfem_batch_create": (i32, [C.POINTER(vp), i32]),
             "sfem_batch_destroy": (None, [vp]),
             "sfem_batch_last_error": (C.c_char_p, [vp]),
@@ -319,6 +320,21 @@ class Context:
         if st != 0 and (st != -5 or raise_on_noconv):
             self._check(st)
         return out, info.as_dict()
+
+    def face_stress(self, u):
+        """(strain, stress) float64 [n_faces][6] of every smoothing domain and
+        the kernel's device ms."""
+        nf = self.sizes().n_faces
+        eps = np.empty((nf, 6), dtype=np.float64)
+        sig = np.empty((nf, 6), dtype=np.float64)
+        pu, ku, a = _arg(u, np.float64)
+        if ku != PTR_HOST:
+            raise ValueError("face_stress takes a host u")
+        ms = C.c_double()
+        self._check(self._L.sfem_face_stress(self._h, pu, eps.ctypes.data_as(C.c_void_p),
+                                             sig.ctypes.data_as(C.c_void_p), PTR_HOST,
+                                             C.byref(ms)))
+        return eps, sig, ms.value
 
     def timer_start(self):
         self._check(self._L.sfem_timer_start(self._h))

@@ -247,7 +247,20 @@ __global__ void __launch_bounds__(kAsmThreads)
   }
   __syncthreads();
 
-  for (int e = e0 + tid; e < e1; e += kAsmThreads) {
+  // Items are stored row by row; neighbouring lanes would add into the same
+  // row's blocks (same LDS words and banks).  Visit them with a stride
+  // coprime to their count instead, so a wave's lanes spread over the
+  // tile's rows.  The fixed-point sums do not depend on the order.
+  const int n_items = e1 - e0;
+  int stride = 1;
+  if (n_items > 1)
+    for (const int cand : {61, 59, 53, 47, 43, 41, 37, 31})
+      if (n_items % cand != 0) {
+        stride = cand;
+        break;
+      }
+  for (int k = tid; k < n_items; k += kAsmThreads) {
+    const int e = e0 + int((int64_t(k) * stride) % n_items);
     const int li = upper_index(sinc, nn, e - e0);
     const int I = n0 + li;
     const int rb = sptr[li];

@@ -49,11 +49,11 @@ def algorithmic_bytes(N, T, nf, nnz, nb, f32_copy=False, per_tet=False):
 
 
 def mapply_bytes(N, nnz, nb):
-    """Learned M apply z = s (rh + S' rh): FP32 S' once, block columns, row
-    offsets, the gathered rh, then r, s, rh, z_old read and z written per
+    """Learned M apply z = s (rh + S' rh): the BF16 values of S' once, block
+    columns, row offsets, then rh, r, s and z_old read and z written once per
     DOF (FP64 vectors)."""
     n = 3 * N
-    return 4 * nnz + 4 * nb + 4 * (N + 1) + 8 * n + 5 * 8 * n
+    return 2 * nnz + 4 * nb + 4 * (N + 1) + 5 * 8 * n
 
 
 KERNEL_SOURCES = {
@@ -84,7 +84,29 @@ def read_traffic(kernel_tag):
         return None
 
 
+def _demangle_nested(name):
+    """Kernel name and builtin template arguments of an Itanium-mangled
+    nested name (_ZN<len><id>...I<types>E...). The profiler leaves names
+    with __bf16 parameters (DF16b) mangled."""
+    import re
+    i, ids = 3, []
+    while i < len(name) and name[i].isdigit():
+        n = re.match(r"\d+", name[i:]).group(0)
+        i += len(n)
+        ids.append(name[i:i + int(n)])
+        i += int(n)
+    base = ids[-1] if ids else name
+    if i < len(name) and name[i] == "I":
+        j = name.find("E", i)
+        types = {"d": "double", "f": "float", "i": "int", "b": "bool"}
+        args = [types.get(c, c) for c in name[i + 1:j]]
+        base += "<" + ", ".join(args) + ">"
+    return base
+
+
 def _short(name):
+    if name.startswith("_ZN"):
+        return _demangle_nested(name)
     name = name.replace("void ", "").replace("sfem::(anonymous namespace)::", "")
     return name.split("(")[0]
 
@@ -129,7 +151,7 @@ def summarize_profiles(prof_dir, command_note):
     for tag, (pattern, src) in KERNEL_SOURCES.items():
         # the schedule variant launched most often at full size (the one the
         # solver ran, not the autotuner's candidates)
-        kn = sorted((k for k in fetch if pattern in k), key=lambda k: -fetch[k][1])
+        kn = sorted((k for k in fetch if pattern in _short(k)), key=lambda k: -fetch[k][1])
         if not kn:
             continue
         fr, n = fetch[kn[0]]
@@ -149,15 +171,23 @@ def summarize_profiles(prof_dir, command_note):
             fh.write("# FETCH_SIZE / WRITE_SIZE (KiB per dispatch, mean) scaled by what the same\n"
                      "# counters read for a plain 1 GiB copy; stale once the source hash changes.\n")
             fh.write(json.dumps(rec, indent=1) + "\n")
-    stats = glob.glob(os.path.join(prof_dir, "ktrace", "*kernel_stats.csv"))
-    if stats and not os.environ.get("SFEM_KEEP_KERNEL_TABLE"):
+    tables = [("ktrace", "kernels_c2.md",
+               "rocprofv3 kernel statistics, 1.92M-tet cantilever benchmark (untrained "
+               "network: every launch at full size)"),
+              ("ktrace_train", "kernels_training_c4.md",
+               "rocprofv3 kernel statistics, benchmark with training (pairs and BF16-MFMA "
+               "training on the 164,640-tet meshes, then the 1.92M-tet runs)")]
+    for sub, fname, title in tables:
+        stats = glob.glob(os.path.join(prof_dir, sub, "*kernel_stats.csv"))
+        if not stats:
+            continue
         import csv
         rows = list(csv.DictReader(open(stats[0])))
-        with open(os.path.join(PROFILE_DIR, "kernels_c2.md"), "w") as fh:
-            fh.write("# rocprofv3 kernel statistics, 1.92M-tet cantilever benchmark\n\n")
+        with open(os.path.join(PROFILE_DIR, fname), "w") as fh:
+            fh.write(f"# {title}\n\n")
             fh.write(f"Command: `{command_note}`\n\n")
             fh.write("| kernel | calls | total ms | average us | % |\n|---|---|---|---|---|\n")
-            for r in rows[:25]:
+            for r in rows[:30]:
                 nm = _short(r["Name"])
                 fh.write(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                          f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
@@ -287,6 +317,8 @@ def main():
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR")
     ap.add_argument("--profile-command", default="", help="command line recorded in summaries")
+    ap.add_argument("--schedule", default="", metavar="VARIANT,GRID_CAP",
+                    help="pin the FP64 row schedule instead of autotuning it")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -321,9 +353,17 @@ def main():
         f"nnz {s.nnz}, blocks {s.n_blocks}")
 
     ctx.assemble(f32_copy=args.f32_ir)
-    tuned = ctx.autotune(reps=10)
-    log(f"[bench] autotuned row schedule (variant, grid cap) {tuned['f64'][0]}: "
-        f"{tuned['f64'][1]:.1f} us per PCG iteration")
+    if args.schedule:
+        # pinned (counter runs: the profiler serialises kernels, which would
+        # distort the autotuner's timings and change its choice)
+        v, cap = (int(x) for x in args.schedule.split(","))
+        ctx.set_schedule(v, cap)
+        tuned = {"f64": ((v, cap), None)}
+        log(f"[bench] row schedule pinned to (variant, grid cap) {(v, cap)}")
+    else:
+        tuned = ctx.autotune(reps=10)
+        log(f"[bench] autotuned row schedule (variant, grid cap) {tuned['f64'][0]}: "
+            f"{tuned['f64'][1]:.1f} us per PCG iteration")
     u = np.empty(s.n_rows)
 
     def step(profile=False):
@@ -438,7 +478,7 @@ def main():
                 "traffic": read_traffic("mapply_c2"), "bytes_per_launch": mb,
                 "us_per_launch": mms * 1e3}
             out["learned"] = {
-                "solver": "flexible PCG, K FP64, learned M (S' FP32, network BF16-MFMA), "
+                "solver": "flexible PCG, K FP64, learned M (S' BF16 in the padded node-row layout, network BF16-MFMA), "
                           "FP64 vectors and dots, true relres <= 1e-8",
                 "inference_s": li, "theta": ctx.precond_info()["theta"],
                 "fell_back": lsolves[-1]["fell_back"],

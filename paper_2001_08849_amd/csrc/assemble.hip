@@ -93,7 +93,8 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
   double V2;
   tet_grads(A, B, C, E, g2, V2);
   const double W = V1 + V2;
-  const double w1 = V1 / W, w2 = V2 / W;
+  const double iW = 1.0 / W;
+  const double w1 = V1 * iW, w2 = V2 * iW;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     b[i] = {w1 * g1[i].x + w2 * g2[i].x, w1 * g1[i].y + w2 * g2[i].y, w1 * g1[i].z + w2 * g2[i].z};
@@ -122,82 +123,59 @@ __device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
 }
 
 // ---------------------------------------------------------- fixed-point unit
-// The tile accumulates in 64-bit integers (LDS integer atomics are about
-// twice as fast as FP64 ones on this chip, and integer sums do not depend
-// on the order of the additions, so the matrix is bit-reproducible).  A
-// contribution V_k [lam b_p b_q^T + mu b_q b_p^T + mu (b_p.b_q) I] is at most
-// (lam + 2 mu) V_k |b_p| |b_q| in magnitude; b_p is a convex combination of
-// tet gradients and V_k <= max V_e / 2, so every partial sum of the <= C
-// contributions an entry receives is below
-//   C * max(lam + 2 mu) * max V_e / 2 * max |grad N|^2  =: 2^62 u.
-// Rounding each contribution to a multiple of u then costs at most C u / 2
-// per entry, about 1e-15 of that bound.
-constexpr int kFixBlocks = 1024;
+// A tile accumulates in 64-bit integers (LDS integer atomics are about twice
+// as fast as FP64 ones on this chip, and integer sums do not depend on the
+// order of the additions, so the matrix is bit-reproducible).
+//
+// Bound of one contribution.  An entry of V_k [lam b_p b_q^T + mu b_q b_p^T
+// + mu (b_p.b_q) I] is at most (|lam| + 2 mu)_k V_k |b_p| |b_q|.  The
+// domain's constants are convex combinations of its tets' ones, and with
+// b = (V_1 g_1 + V_2 g_2) / (V_1 + V_2), V_k = (V_1 + V_2) / 4 and
+// G_i = max_a |grad N_a^i|^2, Cauchy-Schwarz gives
+//   V_k |b_p| |b_q| <= (V_1 G_1 + V_2 G_2) / 4 <= max(V_1 G_1, V_2 G_2) / 2.
+// The face record keeps max(V_i G_i) (rounded up to FP32) in its spare word;
+// a row's unit u is the power of two with every contribution of its items
+// below 2^50 u, so the rounding is relative to the row's own magnitude
+// whatever the material contrast across the mesh.  A contribution (in units of u) is accumulated onto the shift
+// 1.5 * 2^52 by FMAs: every intermediate lies in [2^52, 2^53), where the FP64
+// spacing is 1, so each FMA rounds to an integer and the low mantissa bits
+// hold the contribution's integer value (its two or three terms are rounded
+// once each: error <= 1.5 u).  The partial sums of the <= max_inc (< 2^12)
+// contributions an entry receives stay below 2^62 u; rounding costs at most
+// 1.5 max_inc u per entry, about 2^-49 max_inc of the row's largest
+// contribution.
 
-// Per-workgroup maxima of F and V G over the tets -> part[2 * block + {0,1}]
-// (a one-workgroup k_fix_unit reduces them).
+// max(V_1 G_1, V_2 G_2) of every face, into the spare word of its record.
 __global__ void __launch_bounds__(256)
-    k_fix_bound(const double* __restrict__ xyz, const int32_t* __restrict__ tets, int64_t T,
-                double lam0, double mu0, const double* __restrict__ lam_t,
-                const double* __restrict__ mu_t, double* __restrict__ part) {
-  __shared__ double smax[2][256 / kWave];
-  double mF = 0, mV = 0;
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < T;
-       t += int64_t(gridDim.x) * blockDim.x) {
-    const int4 v = reinterpret_cast<const int4*>(tets)[t];
+    k_face_bound(const double* __restrict__ xyz, int64_t nf, int32_t* __restrict__ face) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int32_t* row = face + f * kFaceStride;
+  const int4 r0 = *reinterpret_cast<const int4*>(row);
+  const int e = row[4];
+  const Vec3 A = load3(xyz, r0.x), B = load3(xyz, r0.y), C = load3(xyz, r0.z);
+  double vg = 0.0;
+  for (int t = 0; t < 2; ++t) {
+    const int o = t == 0 ? r0.w : e;
+    if (o < 0) break;
     Vec3 g[4];
     double vol;
-    tet_grads(load3(xyz, v.x), load3(xyz, v.y), load3(xyz, v.z), load3(xyz, v.w), g, vol);
-    double gg = 0;
+    tet_grads(A, B, C, load3(xyz, o), g, vol);
+    double gg = 0.0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) gg = fmax(gg, dot(g[a], g[a]));
-    const double F = lam_t ? lam_t[t] + 2.0 * mu_t[t] : lam0 + 2.0 * mu0;
-    mF = fmax(mF, F);
-    mV = fmax(mV, vol * gg);
+    vg = fmax(vg, vol * gg);
   }
-  mF = wave_max(mF);
-  mV = wave_max(mV);
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    smax[0][w] = mF;
-    smax[1][w] = mV;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < int(blockDim.x) / kWave; ++k) {
-      mF = fmax(mF, smax[0][k]);
-      mV = fmax(mV, smax[1][k]);
-    }
-    part[2 * blockIdx.x] = mF;
-    part[2 * blockIdx.x + 1] = mV;
-  }
+  float v32 = float(vg);
+  if (double(v32) < vg) v32 = nextafterf(v32, INFINITY);
+  row[7] = __float_as_int(v32);
 }
 
-// unit[0] = u, unit[1] = 1/u from the maxima of the nparts partials and C.
-__global__ void __launch_bounds__(256)
-    k_fix_unit(const double* __restrict__ part, int nparts, int C, double* __restrict__ unit) {
-  double F = 0, VG = 0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-    F = fmax(F, part[2 * b]);
-    VG = fmax(VG, part[2 * b + 1]);
-  }
-  F = wave_max(F);
-  VG = wave_max(VG);
-  __shared__ double s[2][4];
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    s[0][threadIdx.x / kWave] = F;
-    s[1][threadIdx.x / kWave] = VG;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int k = 1; k < int(blockDim.x) / kWave; ++k) {
-    F = fmax(F, s[0][k]);
-    VG = fmax(VG, s[1][k]);
-  }
-  const double bound = double(C) * F * 0.5 * VG;
-  const double u = bound * 0x1p-62;
-  unit[0] = u;
-  unit[1] = 1.0 / u;
+constexpr double kShift = 0x1.8p52;
+
+// Integer value of t - kShift for t in [2^52, 2^53) (two's complement).
+__device__ __forceinline__ unsigned long long unshift(double t) {
+  return static_cast<unsigned long long>(__double_as_longlong(t)) - 0x4338000000000000ull;
 }
 
 // Largest index i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
@@ -216,18 +194,18 @@ __device__ __forceinline__ int upper_index(const int32_t* a, int n, int v) {
 // are evaluated in registers and the row's 4 or 5 blocks K_{I,J} are added
 // into the LDS copy of the rows with the column slots from the slot map.
 template <bool HET>
-__global__ void __launch_bounds__(kAsmThreads)
+__global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(6)))
     k_assemble(const double* __restrict__ xyz, const int32_t* __restrict__ face,
                const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
                const uint32_t* __restrict__ slot, const int32_t* __restrict__ bptr,
                const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
                double lam0, double mu0, const double* __restrict__ lam_t,
-               const double* __restrict__ mu_t, const double* __restrict__ unit,
-               const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
-               float* __restrict__ val32) {
+               const double* __restrict__ mu_t, const uint8_t* __restrict__ fixed,
+               double penalty, double* __restrict__ val, float* __restrict__ val32) {
   __shared__ unsigned long long sval[kTileBlocks * 9];  // fixed point, units of u
   __shared__ int32_t sptr[kTileBlocks + 1];  // block offsets of the tile's rows
   __shared__ int32_t sinc[kTileBlocks + 1];  // incidence offsets of the tile's rows
+  __shared__ int16_t sexp[kTileBlocks];     // per row: its unit is 2^(sexp - 50)
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -240,18 +218,30 @@ __global__ void __launch_bounds__(kAsmThreads)
   const int e0 = inc_ptr[n0], e1 = inc_ptr[n1];
 
   for (int i = tid; i < 9 * nblk; i += kAsmThreads) sval[i] = 0ull;
-  const double u = unit[0], inv_u = unit[1];
   for (int i = tid; i <= nn; i += kAsmThreads) {
     sptr[i] = bptr[n0 + i] - b0;
     sinc[i] = inc_ptr[n0 + i] - e0;
   }
+  const int n_items = e1 - e0;
+  __syncthreads();
+  // each row's unit, from the largest contribution bound of its items
+  for (int li = wid; li < nn; li += nwaves) {
+    double bmax = 0.0;
+    for (int k = sinc[li] + lane; k < sinc[li + 1]; k += kWave) {
+      const int4 r1 =
+          *reinterpret_cast<const int4*>(face + int64_t(inc[e0 + k]) * kFaceStride + 4);
+      double F = fabs(lam0) + 2.0 * mu0;
+      if (HET) {
+        F = fabs(lam_t[r1.y]) + 2.0 * mu_t[r1.y];
+        if (r1.z >= 0) F = fmax(F, fabs(lam_t[r1.z]) + 2.0 * mu_t[r1.z]);
+      }
+      bmax = fmax(bmax, F * double(__int_as_float(r1.w)));
+    }
+    bmax = wave_max(bmax);
+    if (lane == 0) sexp[li] = int16_t(bmax > 0.0 ? ilogb(0.5 * bmax) + 1 : 0);  // 0.5 bmax < 2^sexp
+  }
   __syncthreads();
 
-  // Items are stored row by row; neighbouring lanes would add into the same
-  // row's blocks (same LDS words and banks).  Visit them with a stride
-  // coprime to their count instead, so a wave's lanes spread over the
-  // tile's rows.  The fixed-point sums do not depend on the order.
-  const int n_items = e1 - e0;
   int stride = 1;
   if (n_items > 1)
     for (const int cand : {61, 59, 53, 47, 43, 41, 37, 31})
@@ -259,8 +249,13 @@ __global__ void __launch_bounds__(kAsmThreads)
         stride = cand;
         break;
       }
+  // item k is (k * stride) mod n_items, advanced incrementally
+  const int step = n_items > 0 ? int((int64_t(kAsmThreads) * stride) % n_items) : 0;
+  int pos = n_items > 0 ? int((int64_t(tid) * stride) % n_items) : 0;
   for (int k = tid; k < n_items; k += kAsmThreads) {
-    const int e = e0 + int((int64_t(k) * stride) % n_items);
+    const int e = e0 + pos;
+    pos += step;
+    if (pos >= n_items) pos -= n_items;
     const int li = upper_index(sinc, nn, e - e0);
     const int I = n0 + li;
     const int rb = sptr[li];
@@ -271,26 +266,29 @@ __global__ void __launch_bounds__(kAsmThreads)
     double Vk, lam, mu;
     const int n = face_geometry<HET>(face + int64_t(inc[e]) * kFaceStride, xyz, lam0, mu0, lam_t,
                                      mu_t, sup, b, Vk, lam, mu);
-    const double lV = lam * Vk * inv_u, mV = mu * Vk * inv_u;  // in units of u
+    const double inv_u = ldexp(1.0, 50 - sexp[li]);
+    const double lV = lam * Vk * inv_u, mV = mu * Vk * inv_u;  // in units of the row's u
     Vec3 bp = b[0];
 #pragma unroll
     for (int p = 1; p < 5; ++p)
       if (sup[p] == I) bp = b[p];
-    const double bpa[3] = {bp.x, bp.y, bp.z};
+    const double lbp[3] = {lV * bp.x, lV * bp.y, lV * bp.z};
+    const double mbp[3] = {mV * bp.x, mV * bp.y, mV * bp.z};
     unsigned long long* rowv = sval + 9 * rb;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       if (q >= n) continue;
       const int jj = int((code >> (6 * q)) & 63u);
       const double bqa[3] = {b[q].x, b[q].y, b[q].z};
-      const double d = mV * (bpa[0] * bqa[0] + bpa[1] * bqa[1] + bpa[2] * bqa[2]);
+      // mu V_k (b_p . b_q) on the block's diagonal, already shifted
+      const double dS = fma(mV, bp.x * bqa[0] + bp.y * bqa[1] + bp.z * bqa[2], kShift);
       unsigned long long* dst = rowv + 3 * jj;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double v = lV * bpa[a] * bqa[c] + mV * bpa[c] * bqa[a] + (a == c ? d : 0.0);
-          atomicAdd(dst + a * 3 * deg + c, (unsigned long long)__double2ll_rn(v));
+          const double t = fma(lbp[a], bqa[c], fma(mbp[c], bqa[a], a == c ? dS : kShift));
+          atomicAdd(dst + a * 3 * deg + c, unshift(t));
         }
       }
     }
@@ -305,6 +303,7 @@ __global__ void __launch_bounds__(kAsmThreads)
     const int three_deg = 3 * deg;
     const float inv3d = 1.0f / float(three_deg);
     const int64_t gbase = 9 * (int64_t(b0) + rb);
+    const double u = ldexp(1.0, sexp[li] - 50);
     for (int k = lane; k < 9 * deg; k += kWave) {
       double v = double((long long)sval[9 * rb + k]) * u;
       if (fixed) {
@@ -467,29 +466,26 @@ __global__ void k_traction_gather(int64_t N, const int32_t* __restrict__ ptr,
 
 }  // namespace
 
+void face_bounds(Ctx& c) {
+  k_face_bound<<<div_up(c.topo.nf, 256), 256, 0, c.stream>>>(c.xyz.get(), c.topo.nf,
+                                                             c.topo.face.get());
+  SFEM_HIP(hipGetLastError());
+}
+
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask) {
   const Topology& tp = c.topo;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
-  // fixed-point unit of this assembly (device side, no host round trip)
-  double* part = c.fix.reserve(2 * kFixBlocks + 8);
-  double* unit = part + 2 * kFixBlocks;
-  const int nb = int(std::min<int64_t>(div_up(c.T, 256), kFixBlocks));
-  k_fix_bound<<<nb, 256, 0, c.stream>>>(c.xyz.get(), c.tets.get(), c.T, c.lam0, c.mu0,
-                                        c.per_tet ? c.lam_t.get() : nullptr,
-                                        c.per_tet ? c.mu_t.get() : nullptr, part);
-  k_fix_unit<<<1, 256, 0, c.stream>>>(part, nb, tp.max_inc, unit);
-  SFEM_HIP(hipGetLastError());
   dim3 grid(tp.n_tiles), block(kAsmThreads);
   if (c.per_tet)
     k_assemble<true><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), unit,
-        fixed, c.penalty, val_out, val32_out);
+        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), fixed,
+        c.penalty, val_out, val32_out);
   else
     k_assemble<false><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, unit, fixed,
-        c.penalty, val_out, val32_out);
+        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, fixed, c.penalty,
+        val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

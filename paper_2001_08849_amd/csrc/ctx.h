@@ -12,8 +12,9 @@ constexpr int kTileBlocks = 640;
 // Largest node degree (3x3 blocks in a row) the slot map can encode.
 constexpr int kMaxDeg = 64;
 
-// Face record in HBM: support nodes (a, b, c, o1, o2) then tets (t1, t2),
-// padded to 32 bytes.  o2 = t2 = -1 for an exterior face.
+// Face record in HBM: support nodes (a, b, c, o1, o2), tets (t1, t2), and
+// the face's assembly bound max(V_i G_i) as FP32 bits (32 bytes).  o2 = t2 =
+// -1 for an exterior face.
 constexpr int kFaceStride = 8;
 
 struct Topology {
@@ -95,7 +96,6 @@ struct Ctx {
   DBuf<float> valp32;            // FP32 copy packed (valid while packed32)
   bool packed64 = false, packed32 = false;
   DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
-  DBuf<double> fix;              // assembly fixed-point partial maxima, then the unit
   DBuf<float> dinv32;
 
   // learned preconditioner M = diag(msqrt) (I + S') diag(msqrt), S' in the
@@ -133,6 +133,7 @@ struct Ctx {
 
 // topology.hip
 void build_topology(Ctx& c);
+void face_bounds(Ctx& c);  // fills the face records' assembly bound
 // assemble.hip
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 void bc_mask_values(Ctx& c);

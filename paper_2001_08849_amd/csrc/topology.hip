@@ -453,6 +453,8 @@ void build_topology(Ctx& c) {
   SFEM_REQUIRE(!isolated, SFEM_EMESH, "a node belongs to no tetrahedron");
   SFEM_REQUIRE(tp.maxdeg <= kMaxDeg && 2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,
                "a node has more than 64 neighbours (" + std::to_string(tp.maxdeg) + ")");
+  SFEM_REQUIRE(tp.max_inc < 4096, SFEM_EMESH,
+               "a node lies on more than 4095 faces (" + std::to_string(tp.max_inc) + ")");
   tp.slot.reserve(tp.n_inc);
   k_slot_map<<<div_up(N * kWave, B), B, 0, s>>>(tp.inc_ptr.get(), tp.inc.get(), tp.face.get(),
                                                 tp.bptr.get(), tp.bcol.get(), N, tp.slot.get());
@@ -463,6 +465,7 @@ void build_topology(Ctx& c) {
   tp.tile_first.reserve(tp.n_tiles + 1);
   k_tiles<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), N, C, tp.tile_first.get(), tp.n_tiles);
   SFEM_HIP(hipGetLastError());
+  face_bounds(c);
   SFEM_HIP(hipFreeAsync(err, s));
   SFEM_HIP(hipStreamSynchronize(s));
   tp.valid = true;

@@ -101,7 +101,9 @@ def test_forward_parity(S, small, seed, scale_out):
     assert info["theta"] == pytest.approx(theta_ref, rel=10 * U_BF16)
     if scale_out > 1:
         assert info["theta"] < 1.0
-    np.testing.assert_allclose(s_gpu, 1.0 / np.sqrt(Kb.diagonal()), rtol=1e-14)
+    # s = diag(K)^-1/2 from the GPU's K, whose entries match the oracle to the
+    # assembly's row-relative bar (1e-12; diag(K) is its row's largest entry)
+    np.testing.assert_allclose(s_gpu, 1.0 / np.sqrt(Kb.diagonal()), rtol=1e-12)
     # fixed DOFs: rows and columns of S' are exactly zero
     fixed = np.zeros(Kb.shape[0], bool)
     fixed[p.fixed_dofs()] = True
@@ -121,7 +123,9 @@ def test_untrained_network_is_jacobi(S, small):
     S_gpu, _ = ctx.precond()
     assert np.all(S_gpu == 0.0)
     r = np.random.default_rng(1).standard_normal(Kb.shape[0])
-    np.testing.assert_allclose(ctx.precond_apply(r), r / Kb.diagonal(), rtol=1e-14)
+    # D^-1 of the GPU's K: its diagonal matches the oracle to the assembly's
+    # row-relative bar (1e-12)
+    np.testing.assert_allclose(ctx.precond_apply(r), r / Kb.diagonal(), rtol=1e-12)
     # flexible PCG with M = D^-1 is Jacobi PCG
     uj, ij = ctx.solve(rtol=1e-8)
     ul, il = ctx.solve(rtol=1e-8, precond=S.PRECOND_LEARNED)

@@ -79,9 +79,12 @@ int sfem_set_stream(sfem_ctx* ctx, void* hip_stream);
  * Copies both arrays, checks every index is in [0, n_nodes), and builds the
  * topology on the device: the face table (Alg. 1, by device sort of face
  * keys), the node-to-face incidence and the CSR pattern.  Errors:
- * SFEM_EINVAL (bad index / sizes; n_nodes must be < 2^21 and
- * n_nodes^2 * 4 n_tets < 2^63), SFEM_EMESH (a face in more than two tets,
- * or a tet of zero volume).  Resets material, BCs and loads.
+ * SFEM_EINVAL (bad index / sizes; n_nodes must be < 2^29, the matrix's
+ * 9 x (3x3 blocks) < 2^31, and (largest vertex-id spread of a tet + 1)^2 *
+ * 4 n_tets < 2^63: renumber arbitrary numberings with sfem_rcm_permutation),
+ * SFEM_EMESH (a face in more than two tets, a tet of zero volume, a node in
+ * no tet, a node with more than 64 neighbours).  Resets material, BCs and
+ * loads.
  */
 int sfem_set_mesh(sfem_ctx* ctx, int64_t n_nodes, const double* xyz,
                   int64_t n_tets, const int32_t* tets, int ptr_kind);
@@ -411,6 +414,53 @@ int sfem_batch_get_solution(sfem_batch* b, int mesh, int rhs, double* u, int ptr
 /* Per system s = 4 mesh + rhs (host arrays of 4 n_meshes, NULL to skip). */
 int sfem_batch_get_system_info(sfem_batch* b, int32_t* iters, int32_t* converged,
                                double* relres, int32_t* breakdown);
+
+/* ----------------------------------------------------------------------------
+ * Mesh files and node renumbering (the step before the path).
+ *
+ * TetGen output (Sec. 3.2 reads the Node / Element / Face matrices from
+ * TetGen's .node, .ele and .face files).  sfem_tetgen_read parses
+ * <stem>.node and <stem>.ele, and <stem>.face when present, on the host:
+ * '#' comments, point attributes and markers are skipped, the first point's
+ * index (0 or 1) is the base of all node references, and every reference is
+ * range-checked.  Only 4-node tets are accepted.  *out is always set (free
+ * it with sfem_tetgen_free, also after an error: sfem_tetgen_last_error
+ * holds the message).  Errors: SFEM_EINVAL (missing file, malformed line,
+ * index out of range, not 4-node tets), SFEM_ENOMEM.
+ */
+typedef struct sfem_tetgen sfem_tetgen;
+int sfem_tetgen_read(sfem_tetgen** out, const char* stem);
+const char* sfem_tetgen_last_error(const sfem_tetgen* m);
+/* n_faces = -1 when there is no .face file; has_markers: the .face file has
+ * a boundary-marker column. */
+int sfem_tetgen_sizes(const sfem_tetgen* m, int64_t* n_nodes, int64_t* n_tets, int64_t* n_faces,
+                      int* has_markers, int* index_base);
+/* Host copies, 0-based: xyz float64 [n_nodes][3], tets int32 [n_tets][4],
+ * faces int32 [n_faces][3], markers int32 [n_faces]; any may be NULL. */
+int sfem_tetgen_get(const sfem_tetgen* m, double* xyz, int32_t* tets, int32_t* faces,
+                    int32_t* markers);
+void sfem_tetgen_free(sfem_tetgen* m);
+
+/* Reverse Cuthill-McKee numbering of the nodes, computed on ctx's device
+ * and stream (ctx's own mesh and problem are not touched).  Graph: nodes
+ * sharing a tet.  Start of each connected component: George & Liu's
+ * pseudo-peripheral node, beginning from the least (degree, id) node still
+ * to be numbered.  Cuthill & McKee: each node numbers its unnumbered
+ * neighbours by increasing (degree, id); components follow one another;
+ * the order is then reversed.  The result depends only on the mesh.
+ * perm int32 [n_nodes] gets perm[new] = old.  tets: int32 [n_tets][4]
+ * (ptr_kind), perm: perm_ptr_kind; ms (may be NULL) gets the device time.
+ * Errors: SFEM_EINVAL (sizes, index out of range). */
+int sfem_rcm_permutation(sfem_ctx* ctx, int64_t n_nodes, int64_t n_tets, const int32_t* tets,
+                         int ptr_kind, int32_t* perm, int perm_ptr_kind, double* ms);
+
+/* Applies perm[new] = old on the device: xyz_out[new] = xyz[perm[new]] and
+ * tets_out = old -> new ids of tets.  All arrays of one ptr_kind; xyz /
+ * xyz_out or tets / tets_out may be NULL.  Errors: SFEM_EINVAL (perm is not
+ * a permutation of 0..n_nodes-1, sizes, indices). */
+int sfem_permute_mesh(sfem_ctx* ctx, int64_t n_nodes, int64_t n_tets, const int32_t* perm,
+                      const double* xyz, const int32_t* tets, double* xyz_out,
+                      int32_t* tets_out, int ptr_kind);
 
 #ifdef __cplusplus
 }

@@ -196,7 +196,7 @@ int sfem_set_mesh(sfem_ctx* h, int64_t n_nodes, const double* xyz, int64_t n_tet
                   const int32_t* tets, int ptr_kind) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(n_nodes > 0 && n_tets > 0 && xyz && tets, SFEM_EINVAL, "empty or null mesh");
-    SFEM_REQUIRE(n_nodes < (int64_t(1) << 21), SFEM_EINVAL, "n_nodes must be < 2^21");
+    SFEM_REQUIRE(n_nodes < (int64_t(1) << 29), SFEM_EINVAL, "n_nodes must be < 2^29");
     c.topo.valid = false;
     c.N = n_nodes;
     c.T = n_tets;
@@ -476,6 +476,86 @@ int sfem_solve(sfem_ctx* h, const sfem_solve_opts* opts, double* u, int ptr_kind
     SFEM_HIP(hipStreamSynchronize(c.stream));
     if (info) *info = tmp;
     return st;
+  });
+}
+
+int sfem_rcm_permutation(sfem_ctx* h, int64_t n_nodes, int64_t n_tets, const int32_t* tets,
+                         int ptr_kind, int32_t* perm, int perm_ptr_kind, double* ms) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(n_nodes > 0 && n_tets > 0 && tets && perm, SFEM_EINVAL, "empty or null mesh");
+    SFEM_REQUIRE(n_nodes < (int64_t(1) << 29) && n_tets < (int64_t(1) << 29), SFEM_EINVAL,
+                 "mesh too large");
+    SFEM_REQUIRE(perm_ptr_kind == SFEM_PTR_HOST || perm_ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL,
+                 "bad ptr_kind");
+    sfem::DBuf<int32_t> dt, dp;
+    const int32_t* td = tets;
+    if (ptr_kind == SFEM_PTR_HOST) {
+      upload(c, dt.reserve(4 * n_tets), tets, 4 * n_tets, ptr_kind);
+      td = dt.get();
+    } else {
+      SFEM_REQUIRE(ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL, "bad ptr_kind");
+    }
+    SFEM_REQUIRE(indices_ok(c, td, 4 * n_tets, n_nodes), SFEM_EINVAL,
+                 "tet node index out of range");
+    int32_t* pd = perm_ptr_kind == SFEM_PTR_DEVICE ? perm : dp.reserve(n_nodes);
+    SFEM_HIP(hipEventRecord(c.tev0, c.stream));
+    sfem::rcm_order(c.stream, n_nodes, n_tets, td, pd);
+    SFEM_HIP(hipEventRecord(c.tev1, c.stream));
+    SFEM_HIP(hipEventSynchronize(c.tev1));
+    if (ms) {
+      float t = 0;
+      SFEM_HIP(hipEventElapsedTime(&t, c.tev0, c.tev1));
+      *ms = t;
+    }
+    if (perm_ptr_kind == SFEM_PTR_HOST) download(c, perm, pd, n_nodes, SFEM_PTR_HOST);
+    return SFEM_OK;
+  });
+}
+
+int sfem_permute_mesh(sfem_ctx* h, int64_t n_nodes, int64_t n_tets, const int32_t* perm,
+                      const double* xyz, const int32_t* tets, double* xyz_out, int32_t* tets_out,
+                      int ptr_kind) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(n_nodes > 0 && n_tets >= 0 && perm, SFEM_EINVAL, "empty or null input");
+    SFEM_REQUIRE((xyz == nullptr) == (xyz_out == nullptr) &&
+                     (tets == nullptr) == (tets_out == nullptr),
+                 SFEM_EINVAL, "give both an input and an output array, or neither");
+    SFEM_REQUIRE(ptr_kind == SFEM_PTR_HOST || ptr_kind == SFEM_PTR_DEVICE, SFEM_EINVAL,
+                 "bad ptr_kind");
+    const bool host = ptr_kind == SFEM_PTR_HOST;
+    sfem::DBuf<int32_t> dp, dt, dto;
+    sfem::DBuf<double> dx, dxo;
+    const int32_t* pd = perm;
+    const double* xd = xyz;
+    const int32_t* td = tets;
+    double* xo = xyz_out;
+    int32_t* to = tets_out;
+    if (host) {
+      upload(c, dp.reserve(n_nodes), perm, n_nodes, ptr_kind);
+      pd = dp.get();
+      if (xyz) {
+        upload(c, dx.reserve(3 * n_nodes), xyz, 3 * n_nodes, ptr_kind);
+        xd = dx.get();
+        xo = dxo.reserve(3 * n_nodes);
+      }
+      if (tets && n_tets > 0) {
+        upload(c, dt.reserve(4 * n_tets), tets, 4 * n_tets, ptr_kind);
+        td = dt.get();
+        to = dto.reserve(4 * n_tets);
+      }
+    }
+    SFEM_REQUIRE(sfem::is_permutation(c.stream, n_nodes, pd), SFEM_EINVAL,
+                 "perm is not a permutation of 0..n_nodes-1");
+    if (tets && n_tets > 0)
+      SFEM_REQUIRE(indices_ok(c, td, 4 * n_tets, n_nodes), SFEM_EINVAL,
+                   "tet node index out of range");
+    sfem::permute_mesh(c.stream, n_nodes, n_tets, pd, xd, n_tets > 0 ? td : nullptr, xo,
+                       n_tets > 0 ? to : nullptr);
+    if (host) {
+      if (xyz) download(c, xyz_out, xo, 3 * n_nodes, ptr_kind);
+      if (tets && n_tets > 0) download(c, tets_out, to, 4 * n_tets, ptr_kind);
+    }
+    return SFEM_OK;
   });
 }
 

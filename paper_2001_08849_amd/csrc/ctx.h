@@ -134,6 +134,11 @@ struct Ctx {
 // topology.hip
 void build_topology(Ctx& c);
 void face_bounds(Ctx& c);  // fills the face records' assembly bound
+// Reverse Cuthill-McKee: perm[new] = old (device arrays, synchronous).
+void rcm_order(hipStream_t s, int64_t N, int64_t T, const int32_t* tets, int32_t* perm);
+bool is_permutation(hipStream_t s, int64_t N, const int32_t* perm);
+void permute_mesh(hipStream_t s, int64_t N, int64_t T, const int32_t* perm, const double* xyz,
+                  const int32_t* tets, double* xyz_out, int32_t* tets_out);
 // assemble.hip
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 void bc_mask_values(Ctx& c);

@@ -40,7 +40,9 @@ EXPORTS = [
     "sfem_batch_create", "sfem_batch_destroy", "sfem_batch_last_error", "sfem_batch_add_mesh",
     "sfem_batch_add_traction", "sfem_batch_build", "sfem_batch_sizes", "sfem_batch_autotune",
     "sfem_batch_get_schedule", "sfem_batch_solve", "sfem_batch_get_solution",
-    "sfem_batch_get_system_info",
+    "sfem_batch_get_system_info", "sfem_tetgen_read", "sfem_tetgen_last_error",
+    "sfem_tetgen_sizes", "sfem_tetgen_get", "sfem_tetgen_free", "sfem_rcm_permutation",
+    "sfem_permute_mesh",
 ]
 
 
@@ -144,6 +146,13 @@ def lib() -> C.CDLL:
             "sfem_batch_solve": (i32, [vp, C.POINTER(BatchOpts), C.POINTER(BatchInfo)]),
             "sfem_batch_get_solution": (i32, [vp, i32, i32, vp, i32]),
             "sfem_batch_get_system_info": (i32, [vp, vp, vp, vp, vp]),
+            "sfem_tetgen_read": (i32, [C.POINTER(vp), C.c_char_p]),
+            "sfem_tetgen_last_error": (C.c_char_p, [vp]),
+            "sfem_tetgen_sizes": (i32, [vp] + [C.POINTER(i64)] * 3 + [C.POINTER(i32)] * 2),
+            "sfem_tetgen_get": (i32, [vp, vp, vp, vp, vp]),
+            "sfem_tetgen_free": (None, [vp]),
+            "sfem_rcm_permutation": (i32, [vp, i64, i64, vp, i32, vp, i32, C.POINTER(dbl)]),
+            "sfem_permute_mesh": (i32, [vp, i64, i64, vp, vp, vp, vp, vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -335,6 +344,31 @@ class Context:
                                              sig.ctypes.data_as(C.c_void_p), PTR_HOST,
                                              C.byref(ms)))
         return eps, sig, ms.value
+
+    def rcm_permutation(self, n_nodes: int, tets):
+        """(perm, device ms): reverse Cuthill-McKee numbering of a mesh's nodes,
+        perm[new] = old.  tets: int32 [n_tets, 4], host array or device
+        tensor (then perm is returned on the host all the same)."""
+        pt, kt, a = _arg(tets, np.int32)
+        n_tets = (a.numel() if _is_torch(a) else a.size) // 4
+        perm = np.empty(int(n_nodes), np.int32)
+        ms = C.c_double()
+        self._check(self._L.sfem_rcm_permutation(self._h, int(n_nodes), int(n_tets), pt, kt,
+                                                 perm.ctypes.data_as(C.c_void_p), PTR_HOST,
+                                                 C.byref(ms)))
+        return perm, ms.value
+
+    def permute_mesh(self, perm, xyz, tets):
+        """Renumbered (xyz, tets) for perm[new] = old (host arrays)."""
+        pp, _, p_ = _arg(perm, np.int32)
+        px, _, x_ = _arg(xyz, np.float64)
+        pt, _, t_ = _arg(tets, np.int32)
+        xo = np.empty_like(x_).reshape(-1, 3)
+        to = np.empty_like(t_).reshape(-1, 4)
+        self._check(self._L.sfem_permute_mesh(self._h, p_.size, t_.size // 4, pp, px, pt,
+                                              xo.ctypes.data_as(C.c_void_p),
+                                              to.ctypes.data_as(C.c_void_p), PTR_HOST))
+        return xo, to
 
     def timer_start(self):
         self._check(self._L.sfem_timer_start(self._h))
@@ -562,6 +596,35 @@ class Batch:
             self._h, it.ctypes.data_as(C.c_void_p), cv.ctypes.data_as(C.c_void_p),
             rr.ctypes.data_as(C.c_void_p), bk.ctypes.data_as(C.c_void_p)))
         return {"iters": it, "converged": cv, "relres": rr, "breakdown": bk}
+
+
+def read_tetgen(stem: str):
+    """(xyz [N,3], tets [T,4], faces [F,3] or None, markers [F] or None),
+    0-based, from TetGen's <stem>.node / .ele / .face (parsed by the
+    library on the host)."""
+    L = lib()
+    h = C.c_void_p()
+    st = L.sfem_tetgen_read(C.byref(h), str(stem).encode())
+    try:
+        if st != 0:
+            raise SfemError(st, (L.sfem_tetgen_last_error(h) or b"").decode())
+        n, t, f = C.c_int64(), C.c_int64(), C.c_int64()
+        hm, base = C.c_int(), C.c_int()
+        st = L.sfem_tetgen_sizes(h, C.byref(n), C.byref(t), C.byref(f), C.byref(hm),
+                                 C.byref(base))
+        if st != 0:
+            raise SfemError(st, "sizes")
+        xyz = np.empty((n.value, 3), np.float64)
+        tets = np.empty((t.value, 4), np.int32)
+        faces = np.empty((max(f.value, 0), 3), np.int32) if f.value >= 0 else None
+        marks = np.empty(f.value, np.int32) if (f.value >= 0 and hm.value) else None
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        st = L.sfem_tetgen_get(h, ptr(xyz), ptr(tets), ptr(faces), ptr(marks))
+        if st != 0:
+            raise SfemError(st, "get")
+        return xyz, tets, faces, marks
+    finally:
+        L.sfem_tetgen_free(h)
 
 
 def batch_from_items(items, f32_copy: bool = False, device: int = 0) -> Batch:

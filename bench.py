@@ -298,6 +298,52 @@ def train_network(args, mg, sfem, np):
                            "fell_back": il["fell_back"]}}
 
 
+def renumbering_leg(prob, sfem, np, sched):
+    """Node numbering and the CG product: the 1.92M-tet cantilever with its
+    node ids shuffled (an unstructured generator's arbitrary numbering), then
+    renumbered by the library's reverse Cuthill-McKee; the same row schedule
+    times 300 Jacobi-PCG iterations on the generator's, the shuffled and the
+    RCM numbering."""
+    m = prob.mesh
+    N = m.n_nodes
+    sh = np.random.default_rng(12).permutation(N)
+    inv = np.empty_like(sh)
+    inv[sh] = np.arange(N)
+    xyz_s, tets_s = m.xyz[sh], inv[m.tets].astype(np.int32)      # synthetic input
+    ctx = sfem.Context(0)
+    ctx.rcm_permutation(N, tets_s)                                # warm-up
+    perm, ms_rcm = ctx.rcm_permutation(N, tets_s)
+    xyz_r, tets_r = ctx.permute_mesh(perm, xyz_s, tets_s)
+    old_of = {"generator": np.arange(N), "shuffled": sh, "rcm": sh[perm]}
+    meshes = {"generator": (m.xyz, m.tets), "shuffled": (xyz_s, tets_s), "rcm": (xyz_r, tets_r)}
+    clamp = np.flatnonzero(m.xyz[:, 0] == 0.0)
+    res = {"rcm_ms": ms_rcm, "bandwidth": {}, "topology_ms": {}, "assembly_ms": {},
+           "us_per_cg_iteration": {}, "cg_spmv_us": {}}
+    for name, (x, t) in meshes.items():
+        new_of_old = np.empty(N, np.int64)
+        new_of_old[old_of[name]] = np.arange(N)
+        c = sfem.Context(0)
+        c.set_mesh(x, t)
+        c.set_material(prob.E, prob.nu)
+        c.set_dirichlet(np.sort((3 * new_of_old[clamp][:, None] + np.arange(3)).ravel()))
+        c.add_traction(new_of_old[m.end_tris], np.asarray(prob.traction, float))
+        c.assemble()
+        c.assemble()
+        c.set_schedule(*sched)
+        c.solve(rtol=1e-8, max_iter=50)
+        _, info = c.solve(rtol=1e-8, max_iter=300, profile=True)
+        tt = np.asarray(t, np.int64)
+        res["bandwidth"][name] = int((tt.max(axis=1) - tt.min(axis=1)).max())
+        res["topology_ms"][name] = c.timings()["ms_topology"]
+        res["assembly_ms"][name] = c.timings()["ms_assemble"]
+        res["us_per_cg_iteration"][name] = info["ms_solve"] / max(info["iters"], 1) * 1e3
+        res["cg_spmv_us"][name] = info["ms_spmv_avg"] * 1e3
+        log(f"[bench] numbering {name}: bandwidth {res['bandwidth'][name]}, assembly "
+            f"{res['assembly_ms'][name]:.3f} ms, CG product {res['cg_spmv_us'][name]:.1f} us, "
+            f"iteration {res['us_per_cg_iteration'][name]:.1f} us")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +354,8 @@ def main():
     ap.add_argument("--skip-solve", action="store_true", help="assembly only (profiling)")
     ap.add_argument("--f32-ir", action="store_true", help="also time the FP32+FP64-IR solve")
     ap.add_argument("--inner-rtol", type=float, default=1e-2)
+    ap.add_argument("--no-renumbering", action="store_true",
+                    help="skip the shuffled / RCM numbering comparison")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and the learned-preconditioner solve")
     ap.add_argument("--train-steps", type=int, default=2000)
@@ -500,6 +548,8 @@ def main():
                                 "bytes_per_launch": asm_bytes, "us_per_launch": asm_med * 1e3}
     if stress:
         out["stress_recovery"] = stress
+    if not args.no_renumbering and not args.skip_solve:
+        out["renumbering"] = renumbering_leg(prob, sfem, np, tuned["f64"][0])
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, 1 thread) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -89,6 +89,22 @@ int sfem_set_stream(sfem_ctx* ctx, void* hip_stream);
 int sfem_set_mesh(sfem_ctx* ctx, int64_t n_nodes, const double* xyz,
                   int64_t n_tets, const int32_t* tets, int ptr_kind);
 
+/* Smoothing domains of the assembly.  SFEM_DOMAIN_FACE (default): the
+ * paper's face-based domains (FS-FEM, Sec. 2.1).  SFEM_DOMAIN_EDGE: the
+ * edge-based member of the S-FEM family (ES-FEM), built the same way: the
+ * domain of edge (a, b) is, in every tet around the edge, the two sub-tets
+ * (a, b, face centroid, tet centroid) of the faces through the edge (a
+ * sixth of the tet); V_k = sum V_e / 6; b_I = sum (V_e / 6) grad N_I^e /
+ * V_k (the boundary integral of n N_I over the domain); the support is
+ * every node of those tets; K_k = V_k B^T c B with volume-weighted c.
+ * Limits of the edge domains: at most 12 tets around an edge and 64 block
+ * columns per node row (SFEM_EMESH otherwise).  Takes effect at the next
+ * sfem_set_mesh; called after a mesh was set, it rebuilds the topology and,
+ * as sfem_set_mesh does, resets material, BCs and loads.  Stress recovery
+ * (sfem_face_stress) is for face domains only (SFEM_ESTATE otherwise). */
+enum { SFEM_DOMAIN_FACE = 0, SFEM_DOMAIN_EDGE = 1 };
+int sfem_set_smoothing_domain(sfem_ctx* ctx, int domain);
+
 /* Homogeneous isotropic material (the c of Eq. 9): E > 0, -1 < nu < 0.5. */
 int sfem_set_material(sfem_ctx* ctx, double E, double nu);
 

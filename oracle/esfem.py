@@ -147,3 +147,49 @@ def assemble(xyz, tets, E, nu) -> sp.csr_matrix:
     K.sum_duplicates()
     K.sort_indices()
     return K
+
+
+def assemble_rows(xyz, tets, E, nu, nodes):
+    """Rows 3I..3I+2 of the global ES-FEM matrix for the given nodes, each
+    as (sorted scalar columns, values [3, ncols]), from only the edges whose
+    support holds I (the edges of the tets holding I)."""
+    xyz = np.asarray(xyz, float)
+    tets = np.asarray(tets, np.int64)
+    T = len(tets)
+    Et = np.full(T, float(E)) if np.ndim(E) == 0 else np.asarray(E, float)
+    nut = np.full(T, float(nu)) if np.ndim(nu) == 0 else np.asarray(nu, float)
+    lam_t, mu_t = lame(Et, nut)
+    Ek, ptr, etets = edge_table(tets)
+    key = Ek[:, 0] * len(xyz) + Ek[:, 1]
+    out = {}
+    for I in nodes:
+        star = np.flatnonzero((tets == I).any(axis=1))
+        cand = set()
+        for t in star:
+            v = tets[t]
+            for i, j in _EDGES:
+                a, b = min(v[i], v[j]), max(v[i], v[j])
+                cand.add(int(np.searchsorted(key, a * len(xyz) + b)))
+        acc = {}
+        for k in sorted(cand):
+            tt = etets[ptr[k]:ptr[k + 1]]
+            sub_edges = (Ek[k:k + 1], np.array([0, len(tt)]), tt)
+            sup, bb, Vk = smoothed_gradients(xyz, tets, sub_edges)
+            tv = tet_volume(xyz[tets[tt]])
+            w = tv / 6.0
+            lam = np.dot(w, lam_t[tt]) / w.sum()
+            mu = np.dot(w, mu_t[tt]) / w.sum()
+            B = B_matrix(bb[0])
+            K = Vk[0] * B.T @ D_matrix(lam, mu) @ B
+            S = sup[0]
+            p = int(np.flatnonzero(S == I)[0])
+            for q, J in enumerate(S):
+                blk = K[3 * p:3 * p + 3, 3 * q:3 * q + 3]
+                acc[int(J)] = acc.get(int(J), 0.0) + blk
+        cols = sorted(acc)
+        vals = np.zeros((3, 3 * len(cols)))
+        for i, J in enumerate(cols):
+            vals[:, 3 * i:3 * i + 3] = acc[J]
+        sc = (3 * np.array(cols)[:, None] + np.arange(3)).ravel()
+        out[int(I)] = (sc, vals)
+    return out

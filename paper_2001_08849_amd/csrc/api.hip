@@ -225,6 +225,26 @@ int sfem_set_mesh(sfem_ctx* h, int64_t n_nodes, const double* xyz, int64_t n_tet
   });
 }
 
+int sfem_set_smoothing_domain(sfem_ctx* h, int domain) {
+  return guarded(h, [&](Ctx& c) {
+    SFEM_REQUIRE(domain == SFEM_DOMAIN_FACE || domain == SFEM_DOMAIN_EDGE, SFEM_EINVAL,
+                 "domain must be SFEM_DOMAIN_FACE or SFEM_DOMAIN_EDGE");
+    if (domain == c.domain) return SFEM_OK;
+    c.domain = domain;
+    if (c.N > 0 && c.T > 0) {
+      c.topo.valid = false;
+      reset_problem(c);
+      try {
+        sfem::build_topology(c);
+      } catch (...) {
+        c.N = c.T = 0;
+        throw;
+      }
+    }
+    return SFEM_OK;
+  });
+}
+
 int sfem_set_material(sfem_ctx* h, double E, double nu) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
@@ -564,6 +584,8 @@ int sfem_face_stress(sfem_ctx* h, const double* u, double* strain, double* stres
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
     SFEM_REQUIRE(c.have_material, SFEM_ESTATE, "set a material first");
+    SFEM_REQUIRE(c.domain == SFEM_DOMAIN_FACE, SFEM_ESTATE,
+                 "stress recovery is implemented for face smoothing domains");
     SFEM_REQUIRE(u, SFEM_EINVAL, "null displacement vector");
     const int64_t n = c.n_dof(), m = 6 * c.topo.nf;
     sfem::DBuf<double> du, de, ds;

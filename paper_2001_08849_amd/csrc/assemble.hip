@@ -19,40 +19,13 @@
 // are streamed to HBM once, coalesced, with the essential BCs applied on the
 // way out.
 #include "ctx.h"
+#include "geom.h"
 
 namespace sfem {
 
 namespace {
 
 constexpr int kAsmThreads = 512;
-
-struct Vec3 {
-  double x, y, z;
-};
-__device__ __forceinline__ Vec3 sub(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ Vec3 cross(Vec3 a, Vec3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
-__device__ __forceinline__ double dot(Vec3 a, Vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ Vec3 load3(const double* __restrict__ xyz, int n) {
-  const double* p = xyz + 3 * int64_t(n);
-  return {p[0], p[1], p[2]};
-}
-
-// Gradients of the barycentric shape functions of tet (P0, P1, P2, P3) and
-// its volume (Eq. 10, orientation-free).
-__device__ __forceinline__ void tet_grads(Vec3 P0, Vec3 P1, Vec3 P2, Vec3 P3, Vec3 g[4],
-                                          double& vol) {
-  Vec3 e1 = sub(P1, P0), e2 = sub(P2, P0), e3 = sub(P3, P0);
-  Vec3 c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
-  double det = dot(e1, c23);
-  double inv = 1.0 / det;
-  g[1] = {c23.x * inv, c23.y * inv, c23.z * inv};
-  g[2] = {c31.x * inv, c31.y * inv, c31.z * inv};
-  g[3] = {c12.x * inv, c12.y * inv, c12.z * inv};
-  g[0] = {-(g[1].x + g[2].x + g[3].x), -(g[1].y + g[2].y + g[3].y), -(g[1].z + g[2].z + g[3].z)};
-  vol = fabs(det) * (1.0 / 6.0);
-}
 
 // Smoothed gradients b[0..n-1] of the face's support nodes (A, B, C, D[, E]),
 // V_k, and the domain's Lame constants.
@@ -169,24 +142,6 @@ __global__ void __launch_bounds__(256)
   float v32 = float(vg);
   if (double(v32) < vg) v32 = nextafterf(v32, INFINITY);
   row[7] = __float_as_int(v32);
-}
-
-constexpr double kShift = 0x1.8p52;
-
-// Integer value of t - kShift for t in [2^52, 2^53) (two's complement).
-__device__ __forceinline__ unsigned long long unshift(double t) {
-  return static_cast<unsigned long long>(__double_as_longlong(t)) - 0x4338000000000000ull;
-}
-
-// Largest index i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
-__device__ __forceinline__ int upper_index(const int32_t* a, int n, int v) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (a[mid] <= v) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
 }
 
 // One workgroup per tile of node rows.  Work item = incidence entry e of a
@@ -473,6 +428,10 @@ void face_bounds(Ctx& c) {
 }
 
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask) {
+  if (c.domain == SFEM_DOMAIN_EDGE) {
+    assemble_edge_values(c, val_out, val32_out, apply_mask);
+    return;
+  }
   const Topology& tp = c.topo;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
   dim3 grid(tp.n_tiles), block(kAsmThreads);

@@ -36,6 +36,25 @@ struct Topology {
   bool valid = false;
 };
 
+// Edge-based smoothing domains (ES-FEM): one domain per mesh edge, made of
+// a sixth of every tet around the edge; its support is all nodes of those
+// tets.
+constexpr int kEdgeSup = 16;   // support nodes of an edge domain, at most
+constexpr int kEdgeTets = 12;  // tets around one edge, at most
+constexpr int kEdgeRec = 4 + 3 * kEdgeSup;  // V_k, lam, mu, bound, b[kEdgeSup][3]
+
+struct EdgeTopo {
+  int64_t ne = 0;                // edges
+  int64_t n_inc = 0;             // (node, edge) incidences: sum of support sizes
+  int max_inc = 0;               // most edge domains holding one node
+  DBuf<int32_t> etab;            // [ne][4]: a < b, first entry, tet count
+  DBuf<uint64_t> ent;            // tet entries (b << 32 | tet), grouped by edge
+  DBuf<int32_t> esup;            // [ne][kEdgeSup] support nodes ascending, -1 padded
+  DBuf<int32_t> inc_ptr, inc;    // node -> edges whose support holds it (ascending)
+  DBuf<uint8_t> slot;            // [n_inc][kEdgeSup] block slot of each support node
+  DBuf<double> rec;              // [ne][kEdgeRec], per assembly
+};
+
 // Row-kernel schedule: variant index (lanes per row, rows per group step)
 // and a cap on the grid size.
 constexpr int kNumSched = 17;
@@ -65,6 +84,8 @@ struct Ctx {
   DBuf<double> xyz;
   DBuf<int32_t> tets;
   Topology topo;
+  int domain = SFEM_DOMAIN_FACE;  // smoothing domains of the assembly
+  EdgeTopo et;                    // SFEM_DOMAIN_EDGE only
 
   // material
   bool have_material = false;
@@ -139,6 +160,13 @@ void rcm_order(hipStream_t s, int64_t N, int64_t T, const int32_t* tets, int32_t
 bool is_permutation(hipStream_t s, int64_t N, const int32_t* perm);
 void permute_mesh(hipStream_t s, int64_t N, int64_t T, const int32_t* perm, const double* xyz,
                   const int32_t* tets, double* xyz_out, int32_t* tets_out);
+// Block pattern + assembly tiles of smoothing domains (rows of STRIDE ints,
+// PER support nodes or -1 each); returns the most domains holding a node.
+template <int STRIDE, int PER>
+int build_pattern(Ctx& c, const int32_t* inc_ptr, const int32_t* inc, const int32_t* rows);
+// esfem.hip: edge topology (replaces the face pattern) and edge assembly
+void build_edge_topology(Ctx& c);
+void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 // assemble.hip
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 void bc_mask_values(Ctx& c);

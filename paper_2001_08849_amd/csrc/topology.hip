@@ -138,17 +138,18 @@ __global__ void k_inc_entries(const int32_t* __restrict__ face, int64_t nf, int6
 }
 
 // Block pattern of node rows, one wave per node: candidate neighbours are the
-// support nodes of the node's incident faces; duplicates are dropped.
+// support nodes of the node's incident smoothing domains (rows of STRIDE
+// ints, the first PER of them support nodes or -1); duplicates are dropped.
 // Pass 0 counts distinct neighbours, pass 1 writes them in ascending order.
 // Candidate lists up to kPatLds are staged in LDS with duplicates marked -1;
 // longer ones (far beyond any T4 mesh of sane quality) are read from HBM.
 constexpr int kPatWaves = 4;
 constexpr int kPatLds = 1024;  // <= 16 candidates per lane
 
-template <int PASS>
+template <int PASS, int STRIDE, int PER>
 __global__ void __launch_bounds__(kPatWaves * kWave)
     k_pattern(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
-              const int32_t* __restrict__ face, int64_t N, int32_t* __restrict__ deg,
+              const int32_t* __restrict__ rows, int64_t N, int32_t* __restrict__ deg,
               const int32_t* __restrict__ bptr, int32_t* __restrict__ bcol) {
   __shared__ int32_t cand[kPatWaves][kPatLds];
   const int lane = threadIdx.x & (kWave - 1);
@@ -157,12 +158,13 @@ __global__ void __launch_bounds__(kPatWaves * kWave)
   int b = 0, m = 0;
   if (I < N) {
     b = inc_ptr[I];
-    m = 5 * (inc_ptr[I + 1] - b);
+    m = PER * (inc_ptr[I + 1] - b);
   }
   const bool staged = m <= kPatLds;
   int32_t* s = cand[wid];
+  // candidate i: support node i % PER of the (i / PER)-th incident domain
   auto cand_at = [&](int i) -> int32_t {
-    return face[int64_t(inc[b + i / 5]) * kFaceStride + i % 5];
+    return rows[int64_t(inc[b + i / PER]) * STRIDE + i % PER];
   };
   if (staged)
     for (int i = lane; i < m; i += kWave) s[i] = cand_at(i);
@@ -316,6 +318,61 @@ T read_scalar(const T* dev, hipStream_t s) {
 
 }  // namespace
 
+// Block pattern (bptr, bcol, nb, maxdeg) of the smoothing domains given by
+// a node -> domain incidence and the domains' support rows, then the
+// assembly tiles.  Returns the most domains holding one node.
+template <int STRIDE, int PER>
+int build_pattern(Ctx& c, const int32_t* inc_ptr, const int32_t* inc, const int32_t* rows) {
+  hipStream_t s = c.stream;
+  Topology& tp = c.topo;
+  const int64_t N = c.N;
+  const int B = 256;
+  int32_t* deg = nullptr;
+  SFEM_HIP(hipMallocAsync((void**)&deg, sizeof(int32_t) * (N + 1), s));
+  tp.bptr.reserve(N + 1);
+  const int pg = div_up(N, kPatWaves);
+  k_pattern<0, STRIDE, PER><<<pg, kPatWaves * kWave, 0, s>>>(inc_ptr, inc, rows, N, deg, nullptr,
+                                                               nullptr);
+  SFEM_HIP(hipGetLastError());
+  exclusive_scan_i32(deg, tp.bptr.get(), N, s);
+  tp.nb = read_scalar(tp.bptr.get() + N, s);
+  SFEM_REQUIRE(tp.nb >= N, SFEM_EMESH, "a node belongs to no tetrahedron");
+  SFEM_REQUIRE(9 * tp.nb < (int64_t(1) << 31), SFEM_EINVAL,
+               "matrix too large for int32 CSR indices");
+  tp.bcol.reserve(tp.nb);
+  k_pattern<1, STRIDE, PER><<<pg, kPatWaves * kWave, 0, s>>>(inc_ptr, inc, rows, N, nullptr,
+                                                               tp.bptr.get(), tp.bcol.get());
+  SFEM_HIP(hipGetLastError());
+  SFEM_HIP(hipFreeAsync(deg, s));
+
+  int* md = nullptr;
+  SFEM_HIP(hipMallocAsync((void**)&md, 3 * sizeof(int), s));
+  SFEM_HIP(hipMemsetAsync(md, 0, 3 * sizeof(int), s));
+  k_maxdeg<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), inc_ptr, N, md);
+  SFEM_HIP(hipGetLastError());
+  tp.maxdeg = read_scalar(md, s);
+  const int isolated = read_scalar(md + 1, s);
+  const int max_inc = read_scalar(md + 2, s);
+  SFEM_HIP(hipFreeAsync(md, s));
+  SFEM_REQUIRE(!isolated, SFEM_EMESH, "a node belongs to no tetrahedron");
+  SFEM_REQUIRE(tp.maxdeg <= kMaxDeg && 2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,
+               "a node has more than 64 neighbours (" + std::to_string(tp.maxdeg) + ")");
+  SFEM_REQUIRE(max_inc < 4096, SFEM_EMESH,
+               "a node lies in more than 4095 smoothing domains (" + std::to_string(max_inc) +
+                   ")");
+
+  const int C = kTileBlocks - tp.maxdeg;
+  const int last = read_scalar(tp.bptr.get() + (N - 1), s);
+  tp.n_tiles = last / C + 1;
+  tp.tile_first.reserve(tp.n_tiles + 1);
+  k_tiles<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), N, C, tp.tile_first.get(), tp.n_tiles);
+  SFEM_HIP(hipGetLastError());
+  return max_inc;
+}
+
+template int build_pattern<kEdgeSup, kEdgeSup>(Ctx&, const int32_t*, const int32_t*,
+                                              const int32_t*);
+
 void build_topology(Ctx& c) {
   hipStream_t s = c.stream;
   Topology& tp = c.topo;
@@ -421,53 +478,16 @@ void build_topology(Ctx& c) {
   SFEM_HIP(hipFreeAsync(iv, s));
   tp.n_inc = read_scalar(tp.inc_ptr.get() + N, s);
 
-  // 3. block pattern
-  int32_t* deg = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&deg, sizeof(int32_t) * (N + 1), s));
-  tp.bptr.reserve(N + 1);
-  const int pg = div_up(N, kPatWaves);
-  k_pattern<0><<<pg, kPatWaves * kWave, 0, s>>>(tp.inc_ptr.get(), tp.inc.get(), tp.face.get(), N,
-                                                 deg, nullptr, nullptr);
-  SFEM_HIP(hipGetLastError());
-  exclusive_scan_i32(deg, tp.bptr.get(), N, s);
-  tp.nb = read_scalar(tp.bptr.get() + N, s);
-  SFEM_REQUIRE(tp.nb >= N, SFEM_EMESH, "a node belongs to no tetrahedron");
-  SFEM_REQUIRE(9 * tp.nb < (int64_t(1) << 31), SFEM_EINVAL,
-               "matrix too large for int32 CSR indices");
-  tp.bcol.reserve(tp.nb);
-  k_pattern<1><<<pg, kPatWaves * kWave, 0, s>>>(tp.inc_ptr.get(), tp.inc.get(), tp.face.get(), N,
-                                                 nullptr, tp.bptr.get(), tp.bcol.get());
-  SFEM_HIP(hipGetLastError());
-  SFEM_HIP(hipFreeAsync(deg, s));
-
-  // 4. assembly tiles
-  int* md = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&md, 3 * sizeof(int), s));
-  SFEM_HIP(hipMemsetAsync(md, 0, 3 * sizeof(int), s));
-  k_maxdeg<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), tp.inc_ptr.get(), N, md);
-  SFEM_HIP(hipGetLastError());
-  tp.maxdeg = read_scalar(md, s);
-  int isolated = read_scalar(md + 1, s);
-  tp.max_inc = read_scalar(md + 2, s);
-  SFEM_HIP(hipFreeAsync(md, s));
-  SFEM_REQUIRE(!isolated, SFEM_EMESH, "a node belongs to no tetrahedron");
-  SFEM_REQUIRE(tp.maxdeg <= kMaxDeg && 2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,
-               "a node has more than 64 neighbours (" + std::to_string(tp.maxdeg) + ")");
-  SFEM_REQUIRE(tp.max_inc < 4096, SFEM_EMESH,
-               "a node lies on more than 4095 faces (" + std::to_string(tp.max_inc) + ")");
+  // 3.-4. block pattern of the face domains, assembly tiles
+  tp.max_inc = build_pattern<kFaceStride, 5>(c, tp.inc_ptr.get(), tp.inc.get(), tp.face.get());
   tp.slot.reserve(tp.n_inc);
   k_slot_map<<<div_up(N * kWave, B), B, 0, s>>>(tp.inc_ptr.get(), tp.inc.get(), tp.face.get(),
                                                 tp.bptr.get(), tp.bcol.get(), N, tp.slot.get());
   SFEM_HIP(hipGetLastError());
-  const int C = kTileBlocks - tp.maxdeg;
-  int last = read_scalar(tp.bptr.get() + (N - 1), s);
-  tp.n_tiles = last / C + 1;
-  tp.tile_first.reserve(tp.n_tiles + 1);
-  k_tiles<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), N, C, tp.tile_first.get(), tp.n_tiles);
-  SFEM_HIP(hipGetLastError());
   face_bounds(c);
   SFEM_HIP(hipFreeAsync(err, s));
   SFEM_HIP(hipStreamSynchronize(s));
+  if (c.domain == SFEM_DOMAIN_EDGE) build_edge_topology(c);
   tp.valid = true;
 }
 

@@ -22,6 +22,7 @@ ASM_F64, ASM_F32_COPY = 0, 1
 PRECOND_JACOBI, PRECOND_LEARNED = 0, 1
 MODE_F64, MODE_F32_IR, MODE_F32_RR = 0, 1, 2
 NUM_SCHEDULES = 17
+DOMAIN_FACE, DOMAIN_EDGE = 0, 1
 
 STATUS = {0: "SFEM_OK", -1: "SFEM_EINVAL", -2: "SFEM_EMESH", -3: "SFEM_ENOMEM",
           -4: "SFEM_EHIP", -5: "SFEM_ENOCONV", -6: "SFEM_ESTATE"}
@@ -42,7 +43,7 @@ EXPORTS = [
     "sfem_batch_get_schedule", "sfem_batch_solve", "sfem_batch_get_solution",
     "sfem_batch_get_system_info", "sfem_tetgen_read", "sfem_tetgen_last_error",
     "sfem_tetgen_sizes", "sfem_tetgen_get", "sfem_tetgen_free", "sfem_rcm_permutation",
-    "sfem_permute_mesh",
+    "sfem_permute_mesh", "sfem_set_smoothing_domain",
 ]
 
 
@@ -153,6 +154,7 @@ def lib() -> C.CDLL:
             "sfem_tetgen_free": (None, [vp]),
             "sfem_rcm_permutation": (i32, [vp, i64, i64, vp, i32, vp, i32, C.POINTER(dbl)]),
             "sfem_permute_mesh": (i32, [vp, i64, i64, vp, vp, vp, vp, vp, i32]),
+            "sfem_set_smoothing_domain": (i32, [vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -344,6 +346,10 @@ class Context:
                                              sig.ctypes.data_as(C.c_void_p), PTR_HOST,
                                              C.byref(ms)))
         return eps, sig, ms.value
+
+    def set_smoothing_domain(self, domain: int):
+        """DOMAIN_FACE (the paper's FS-FEM, default) or DOMAIN_EDGE (ES-FEM)."""
+        self._check(self._L.sfem_set_smoothing_domain(self._h, int(domain)))
 
     def rcm_permutation(self, n_nodes: int, tets):
         """(perm, device ms): reverse Cuthill-McKee numbering of a mesh's nodes,

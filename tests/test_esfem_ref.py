@@ -103,3 +103,16 @@ def test_softer_than_fem_t4():
         tips[name] = np.abs(u[2::3]).max()
     print(tips)
     assert tips["es"] > tips["fem"]
+
+
+def test_rows_equal_full_assembly():
+    m = mg.box_mesh(4, 3, 3, 2.0, 1.5, 1.5, jitter=0.15, seed=2)
+    rng = np.random.default_rng(1)
+    E = 10.0 ** rng.uniform(9, 11, m.n_tets)
+    K = ES.assemble(m.xyz, m.tets, E, 0.3)
+    for I, (cols, vals) in ES.assemble_rows(m.xyz, m.tets, E, 0.3, [0, 17, 40]).items():
+        for a in range(3):
+            r = 3 * I + a
+            sl = slice(K.indptr[r], K.indptr[r + 1])
+            assert np.array_equal(K.indices[sl], cols)
+            assert np.abs(K.data[sl] - vals[a]).max() <= 1e-14 * np.abs(vals[a]).max()

@@ -85,6 +85,18 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
 }
 
 // Position of node J among the ascending block columns cols[0..deg).
+// Largest face bound max(V_i G_i) among the faces incident to each node.
+__global__ void k_row_bound(int64_t N, const int32_t* __restrict__ inc_ptr,
+                            const int32_t* __restrict__ inc, const int32_t* __restrict__ face,
+                            float* __restrict__ row_vg) {
+  const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  float m = 0.0f;
+  for (int e = inc_ptr[I]; e < inc_ptr[I + 1]; ++e)
+    m = fmaxf(m, __int_as_float(face[int64_t(inc[e]) * kFaceStride + 7]));
+  row_vg[I] = m;
+}
+
 __device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
   int lo = 0, hi = deg - 1;
   while (lo < hi) {
@@ -154,9 +166,10 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
                const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
                const uint32_t* __restrict__ slot, const int32_t* __restrict__ bptr,
                const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
-               double lam0, double mu0, const double* __restrict__ lam_t,
-               const double* __restrict__ mu_t, const uint8_t* __restrict__ fixed,
-               double penalty, double* __restrict__ val, float* __restrict__ val32) {
+               const float* __restrict__ row_vg, double lam0, double mu0,
+               const double* __restrict__ lam_t, const double* __restrict__ mu_t,
+               const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
+               float* __restrict__ val32) {
   __shared__ unsigned long long sval[kTileBlocks * 9];  // fixed point, units of u
   __shared__ int32_t sptr[kTileBlocks + 1];  // block offsets of the tile's rows
   __shared__ int32_t sinc[kTileBlocks + 1];  // incidence offsets of the tile's rows
@@ -179,8 +192,15 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
   }
   const int n_items = e1 - e0;
   __syncthreads();
-  // each row's unit, from the largest contribution bound of its items
-  for (int li = wid; li < nn; li += nwaves) {
+  // each row's unit, from the largest contribution bound of its items (one
+  // material: the row's precomputed largest face bound)
+  if (!HET) {
+    for (int li = tid; li < nn; li += kAsmThreads) {
+      const double bmax = (fabs(lam0) + 2.0 * mu0) * double(row_vg[n0 + li]);
+      sexp[li] = int16_t(bmax > 0.0 ? ilogb(0.5 * bmax) + 1 : 0);  // 0.5 bmax < 2^sexp
+    }
+  }
+  for (int li = wid; HET && li < nn; li += nwaves) {
     double bmax = 0.0;
     for (int k = sinc[li] + lane; k < sinc[li + 1]; k += kWave) {
       const int4 r1 =
@@ -422,8 +442,11 @@ __global__ void k_traction_gather(int64_t N, const int32_t* __restrict__ ptr,
 }  // namespace
 
 void face_bounds(Ctx& c) {
-  k_face_bound<<<div_up(c.topo.nf, 256), 256, 0, c.stream>>>(c.xyz.get(), c.topo.nf,
-                                                             c.topo.face.get());
+  Topology& tp = c.topo;
+  k_face_bound<<<div_up(tp.nf, 256), 256, 0, c.stream>>>(c.xyz.get(), tp.nf, tp.face.get());
+  tp.row_vg.reserve(tp.N);
+  k_row_bound<<<div_up(tp.N, 256), 256, 0, c.stream>>>(tp.N, tp.inc_ptr.get(), tp.inc.get(),
+                                                      tp.face.get(), tp.row_vg.get());
   SFEM_HIP(hipGetLastError());
 }
 
@@ -438,13 +461,13 @@ void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask)
   if (c.per_tet)
     k_assemble<true><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, c.lam_t.get(), c.mu_t.get(), fixed,
-        c.penalty, val_out, val32_out);
+        tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, c.lam_t.get(),
+        c.mu_t.get(), fixed, c.penalty, val_out, val32_out);
   else
     k_assemble<false><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), c.lam0, c.mu0, nullptr, nullptr, fixed, c.penalty,
-        val_out, val32_out);
+        tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, nullptr, nullptr,
+        fixed, c.penalty, val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

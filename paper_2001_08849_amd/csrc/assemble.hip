@@ -85,6 +85,14 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
 }
 
 // Position of node J among the ascending block columns cols[0..deg).
+// Exponent e of a row's unit 2^(e - 50): 0.5 bmax < 2^e (half the largest
+// face bound bounds every contribution), clamped so that 2^(50 - e) stays a
+// normal double (a larger e only coarsens the unit of absurdly small rows).
+__device__ __forceinline__ int16_t row_exponent(double bmax) {
+  const int e = bmax > 0.0 ? ilogb(0.5 * bmax) + 1 : 0;
+  return int16_t(e < -973 ? -973 : e);
+}
+
 // Largest face bound max(V_i G_i) among the faces incident to each node.
 __global__ void k_row_bound(int64_t N, const int32_t* __restrict__ inc_ptr,
                             const int32_t* __restrict__ inc, const int32_t* __restrict__ face,
@@ -197,7 +205,7 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
   if (!HET) {
     for (int li = tid; li < nn; li += kAsmThreads) {
       const double bmax = (fabs(lam0) + 2.0 * mu0) * double(row_vg[n0 + li]);
-      sexp[li] = int16_t(bmax > 0.0 ? ilogb(0.5 * bmax) + 1 : 0);  // 0.5 bmax < 2^sexp
+      sexp[li] = row_exponent(bmax);
     }
   }
   for (int li = wid; HET && li < nn; li += nwaves) {
@@ -213,7 +221,7 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
       bmax = fmax(bmax, F * double(__int_as_float(r1.w)));
     }
     bmax = wave_max(bmax);
-    if (lane == 0) sexp[li] = int16_t(bmax > 0.0 ? ilogb(0.5 * bmax) + 1 : 0);  // 0.5 bmax < 2^sexp
+    if (lane == 0) sexp[li] = row_exponent(bmax);
   }
   __syncthreads();
 
@@ -241,7 +249,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     double Vk, lam, mu;
     const int n = face_geometry<HET>(face + int64_t(inc[e]) * kFaceStride, xyz, lam0, mu0, lam_t,
                                      mu_t, sup, b, Vk, lam, mu);
-    const double inv_u = ldexp(1.0, 50 - sexp[li]);
+    // 2^(50 - sexp) built from its exponent bits (sexp is clamped to keep it normal)
+    const double inv_u = __longlong_as_double((long long)(1023 + 50 - sexp[li]) << 52);
     const double lV = lam * Vk * inv_u, mV = mu * Vk * inv_u;  // in units of the row's u
     Vec3 bp = b[0];
 #pragma unroll

@@ -110,17 +110,27 @@ __global__ void __launch_bounds__(kBThreads)
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
-    for (int c = sub; c < td; c += LPR) {
-      const int jj = c / 3;
-      const int64_t col = 3 * int64_t(bcol[rb + jj]) + (c - 3 * jj);
-      const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
-      const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
-      const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
-      const double a3[3] = {double(v[c]), double(v[td + c]), double(v[2 * td + c])};
+    // two columns per step (the second masked past the row), so each lane
+    // keeps twice the loads in flight
+    for (int c0 = sub; c0 < td; c0 += 2 * LPR) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int h = 0; h < 2; ++h) {
+        const int c = c0 + h * LPR;
+        const bool in = c < td;
+        const int cc = in ? c : c0;
+        const int jj = cc / 3;
+        const int64_t col = 3 * int64_t(bcol[rb + jj]) + (cc - 3 * jj);
+        const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
+        const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
+        const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
+        const double m = in ? 1.0 : 0.0;
+        const double a3[3] = {m * double(v[cc]), m * double(v[td + cc]),
+                              m * double(v[2 * td + cc])};
 #pragma unroll
-        for (int k = 0; k < kNR; ++k) acc[a][k] += a3[a] * x4[k];
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int k = 0; k < kNR; ++k) acc[a][k] += a3[a] * x4[k];
+      }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a)

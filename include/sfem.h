@@ -396,16 +396,24 @@ int sfem_batch_build(sfem_batch* b, int flags);
 int sfem_batch_sizes(sfem_batch* b, int* n_meshes, int64_t* n_nodes, int64_t* n_tets,
                      int64_t* n_faces, int64_t* nnz);
 /* Autotuner.  Meshes fall into size buckets by node count: 0 (< 8192),
- * 1 (< 32768), 2 (larger).  For each non-empty bucket every (lanes per node
- * row in {8, 16, 32}) x (node rows per workgroup in {16, 64, 256}) schedule
- * of the 4-right-hand-side product is timed over `reps` launches (0: 5) of
- * that bucket alone; the fastest is kept and cached for the process under
+ * 1 (< 32768), 2 (larger).  For each non-empty bucket every schedule of the
+ * 4-right-hand-side product is timed over `reps` launches (0: 5) of that
+ * bucket alone: (lanes per node row in {8, 16, 32} on the CSR-order values,
+ * or in {4, 8} on the packed layout, FP64 only) x (node rows per workgroup
+ * in {16, 64, 256}).  The fastest is kept and cached for the process under
  * the bucket's shape (bucket, log2 of its node rows, mean block degree).
  * With use_cache, a cached shape is reused without timing.  precision:
- * SFEM_ASM_F64 or SFEM_ASM_F32_COPY.  *us: the tuned product's time. */
+ * SFEM_ASM_F64 or SFEM_ASM_F32_COPY (CSR-order candidates only; an FP32
+ * product under a packed schedule uses 16 lanes on the CSR order).
+ * *us: the tuned product's time.  get_schedule reports a bucket's choice;
+ * *packed = 1 for the packed layout. */
 int sfem_batch_autotune(sfem_batch* b, int reps, int use_cache, int precision, double* us);
 int sfem_batch_get_schedule(sfem_batch* b, int bucket, int* lanes_per_row, int* rows_per_wg,
-                            int* n_meshes, int* from_cache);
+                            int* n_meshes, int* from_cache, int* packed);
+/* Sets a bucket's schedule by hand (one of the tuner's candidates; tests and
+ * tools).  Errors: SFEM_EINVAL (not a candidate), SFEM_ESTATE (not built). */
+int sfem_batch_set_schedule(sfem_batch* b, int bucket, int lanes_per_row, int rows_per_wg,
+                            int packed);
 
 typedef struct {
   int mode;           /* SFEM_MODE_F64 or SFEM_MODE_F32_RR (FP32 products, FP64 rest) */

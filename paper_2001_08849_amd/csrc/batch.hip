@@ -34,6 +34,8 @@ constexpr int kBThreads = 256;
 constexpr int kNumBuckets = 3;     // mesh sizes: < 8192, < 32768, >= 32768 nodes
 constexpr int kNumLpr = 3;
 constexpr int kLprs[kNumLpr] = {8, 16, 32};
+constexpr int kNumPLpr = 2;                  // packed layout (FP64 values)
+constexpr int kPLprs[kNumPLpr] = {4, 8};
 constexpr int kNumRw = 3;
 constexpr int kRws[kNumRw] = {16, 64, 256};
 
@@ -130,6 +132,100 @@ __global__ void __launch_bounds__(kBThreads)
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int k = 0; k < kNR; ++k) acc[a][k] += a3[a] * x4[k];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
+    if (valid && sub == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = 3 * int64_t(I) + a;
+#pragma unroll
+        for (int k = 0; k < kNR; ++k) {
+          const int64_t e = i * kNR + k;
+          if constexpr (EPI == 0) {
+            Y[e] = acc[a][k];
+            pv[2 * k] += X[e] * acc[a][k];
+          } else {
+            const double r = F[e] - acc[a][k];
+            const double z = dinv[i] * r;
+            Y[e] = r;
+            Z[e] = z;
+            pv[2 * k] += r * r;
+            pv[2 * k + 1] += r * z;
+          }
+        }
+      }
+    }
+  }
+  block_store8(pv, part + int64_t(w) * 8);
+}
+
+// The same product on the packed layout of the single-system row kernels
+// (node row I: a [9][d4] array at 9 ptr4[I], d4 = degree rounded up to 4,
+// block columns col4 padded with I and zero values).  A lane takes 4 blocks
+// per step: one int4 of columns, 18 double2 value loads and, per block, the
+// 12 panel entries of its node (6 double2 loads) for 144 FMAs.
+template <int LPR, int EPI>
+__global__ void __launch_bounds__(kBThreads)
+    k_bspmm_p(int wbase, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+              const BScal* __restrict__ sc, const int32_t* __restrict__ ptr4,
+              const int32_t* __restrict__ col4, const double* __restrict__ valp,
+              const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ Y,
+              double* __restrict__ Z, const double* __restrict__ dinv, double* __restrict__ part) {
+  constexpr int G = kBThreads / LPR;
+  const int w = wbase + blockIdx.x;
+  if (mesh_done(sc, wmesh[w])) return;
+  const int2 rr = wr[w];
+  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int I0 = rr.x; I0 < rr.y; I0 += G) {
+    const int I = I0 + g;
+    const bool valid = I < rr.y;
+    int r4 = 0, d4 = 0;
+    if (valid) {
+      r4 = ptr4[I];
+      d4 = ptr4[I + 1] - r4;
+    }
+    const double* wv = valp + 9 * int64_t(r4);
+    double acc[3][kNR];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
+    for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
+      const int4 J = *reinterpret_cast<const int4*>(col4 + r4 + jb);
+      double m[9][4];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const double2 lo = *reinterpret_cast<const double2*>(wv + q * d4 + jb);
+        const double2 hi = *reinterpret_cast<const double2*>(wv + q * d4 + jb + 2);
+        m[q][0] = lo.x;
+        m[q][1] = lo.y;
+        m[q][2] = hi.x;
+        m[q][3] = hi.y;
+      }
+      const int Js[4] = {J.x, J.y, J.z, J.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double2* xp = reinterpret_cast<const double2*>(X + 12 * int64_t(Js[t]));
+        double x[3][kNR];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          const double2 a = xp[2 * cc], b = xp[2 * cc + 1];
+          x[cc][0] = a.x;
+          x[cc][1] = a.y;
+          x[cc][2] = b.x;
+          x[cc][3] = b.y;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+            for (int k = 0; k < kNR; ++k) acc[a][k] += m[3 * a + cc][t] * x[cc][k];
       }
     }
 #pragma unroll
@@ -332,6 +428,7 @@ struct BatchState {
   std::vector<int> bucket;           // per mesh
   int lpr[kNumBuckets] = {16, 16, 16};
   int rw[kNumBuckets] = {64, 64, 64};
+  bool packed[kNumBuckets] = {false, false, false};  // FP64 products on the packed layout
   bool from_cache[kNumBuckets] = {false, false, false};
   // workgroup table, bucket-major (a mesh's workgroups are contiguous)
   std::vector<int2> h_wr;            // node rows [x, y) per workgroup
@@ -409,7 +506,17 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
   k_bspmm<VT, LPR, EPI><<<nw, kBThreads, 0, c.stream>>>(                                  \
       b.bw0[bk], b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(), \
       c.topo.bcol.get(), VAL, X, F, Y, Z, c.dinv.get(), b.part.get())
-    if (f32) {
+#define P_(LPR)                                                                              \
+  k_bspmm_p<LPR, EPI><<<nw, kBThreads, 0, c.stream>>>(                                      \
+      b.bw0[bk], b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.ptr4.get(),     \
+      c.col4.get(), c.valp.get(), X, F, Y, Z, c.dinv.get(), b.part.get())
+    if (f32 && b.packed[bk]) {
+      L_(float, c.val32.get(), 16);  // FP32 values keep the CSR order
+    } else if (b.packed[bk]) {
+      SFEM_REQUIRE(c.packed64, SFEM_ESTATE, "packed copy of K missing");
+      if (b.lpr[bk] == 4) P_(4);
+      else P_(8);
+    } else if (f32) {
       switch (b.lpr[bk]) {
         case 8: L_(float, c.val32.get(), 8); break;
         case 16: L_(float, c.val32.get(), 16); break;
@@ -423,6 +530,7 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
       }
     }
 #undef L_
+#undef P_
     SFEM_HIP(hipGetLastError());
   }
 }
@@ -504,6 +612,7 @@ static std::tuple<int, int, int> tune_key(Ctx& c, BatchState& b, int bk) {
 // Returns the tuned product time in microseconds (all buckets).
 double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32) {
   if (reps <= 0) reps = 5;
+  pack_values64(c);  // the packed candidates read it
   SFEM_HIP(hipStreamSynchronize(c.stream));
   for (int bk = 0; bk < kNumBuckets; ++bk) {
     bool any = false;
@@ -514,7 +623,8 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune_cache.find(key);
       if (it != g_tune_cache.end()) {
-        b.lpr[bk] = it->second.first;
+        b.packed[bk] = it->second.first < 0;   // packed schedules are cached negated
+        b.lpr[bk] = std::abs(it->second.first);
         b.rw[bk] = it->second.second;
         b.from_cache[bk] = true;
         continue;
@@ -522,9 +632,13 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
     }
     double best = 1e30;
     int bl = b.lpr[bk], br = b.rw[bk];
-    for (int li = 0; li < kNumLpr; ++li)
+    bool bp = b.packed[bk];
+    const int n_cand = kNumLpr + (f32 ? 0 : kNumPLpr);
+    for (int li = 0; li < n_cand; ++li)
       for (int ri = 0; ri < kNumRw; ++ri) {
-        b.lpr[bk] = kLprs[li];
+        const bool pk = li >= kNumLpr;
+        b.packed[bk] = pk;
+        b.lpr[bk] = pk ? kPLprs[li - kNumLpr] : kLprs[li];
         b.rw[bk] = kRws[ri];
         build_table(c, b);
         bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, false);  // warm
@@ -537,15 +651,17 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
         SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
         if (ms < best) {
           best = ms;
-          bl = kLprs[li];
+          bl = b.lpr[bk];
           br = kRws[ri];
+          bp = pk;
         }
       }
     b.lpr[bk] = bl;
     b.rw[bk] = br;
+    b.packed[bk] = bp;
     b.from_cache[bk] = false;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {bl, br};
+    g_tune_cache[key] = {bp ? -bl : bl, br};
   }
   build_table(c, b);
   // time the tuned product over all buckets
@@ -569,6 +685,7 @@ int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int 
   const double rtol2 = rtol * rtol;
   const int max_stale = 40;
   const int n_sys = b.n_meshes * kNR;
+  if (b.packed[0] || b.packed[1] || b.packed[2]) pack_values64(c);  // before any capture
   SFEM_HIP(hipEventRecord(c.ev0, c.stream));
   k_bstart<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), c.dinv.get(), b.F.get(), b.X.get(),
                                           b.R.get(), b.Z.get(), b.P.get(), b.part.get());
@@ -625,7 +742,21 @@ void batch_system(const BatchState& b, int s, int* iters, int* converged, double
   *breakdown = q.breakdown;
 }
 
-int batch_bucket_info(const BatchState& b, int bk, int* lanes, int* rows, int* cached) {
+void batch_rebuild_table(Ctx& c, BatchState& b) {
+  build_table(c, b);
+  if (b.packed[0] || b.packed[1] || b.packed[2]) pack_values64(c);
+}
+
+void batch_set_schedule(BatchState& b, int bk, int lanes, int rows, bool packed) {
+  b.lpr[bk] = lanes;
+  b.rw[bk] = rows;
+  b.packed[bk] = packed;
+  b.from_cache[bk] = false;
+}
+
+int batch_bucket_info(const BatchState& b, int bk, int* lanes, int* rows, int* cached,
+                      int* packed) {
+  *packed = b.packed[bk] ? 1 : 0;
   *lanes = b.lpr[bk];
   *rows = b.rw[bk];
   *cached = b.from_cache[bk] ? 1 : 0;
@@ -834,13 +965,29 @@ int sfem_batch_autotune(sfem_batch* h, int reps, int use_cache, int precision, d
   });
 }
 
-int sfem_batch_get_schedule(sfem_batch* h, int bucket, int* lanes_per_row, int* rows_per_wg,
-                            int* n_meshes, int* from_cache) {
+int sfem_batch_set_schedule(sfem_batch* h, int bucket, int lanes_per_row, int rows_per_wg,
+                            int packed) {
   return bguarded(h, [&](sfem_batch& b) {
     SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
     SFEM_REQUIRE(bucket >= 0 && bucket < 3, SFEM_EINVAL, "bucket must be in [0, 3)");
-    int l = 0, r = 0, fc = 0;
-    const int n = sfem::batch_bucket_info(*b.st, bucket, &l, &r, &fc);
+    const bool ok_l = packed ? (lanes_per_row == 4 || lanes_per_row == 8)
+                             : (lanes_per_row == 8 || lanes_per_row == 16 || lanes_per_row == 32);
+    SFEM_REQUIRE(ok_l && (rows_per_wg == 16 || rows_per_wg == 64 || rows_per_wg == 256),
+                 SFEM_EINVAL, "not one of the tuner's schedules");
+    sfem::batch_set_schedule(*b.st, bucket, lanes_per_row, rows_per_wg, packed != 0);
+    sfem::batch_rebuild_table(b.ctx->c, *b.st);
+    return SFEM_OK;
+  });
+}
+
+int sfem_batch_get_schedule(sfem_batch* h, int bucket, int* lanes_per_row, int* rows_per_wg,
+                            int* n_meshes, int* from_cache, int* packed) {
+  return bguarded(h, [&](sfem_batch& b) {
+    SFEM_REQUIRE(b.built, SFEM_ESTATE, "build the batch first");
+    SFEM_REQUIRE(bucket >= 0 && bucket < 3, SFEM_EINVAL, "bucket must be in [0, 3)");
+    int l = 0, r = 0, fc = 0, pk = 0;
+    const int n = sfem::batch_bucket_info(*b.st, bucket, &l, &r, &fc, &pk);
+    if (packed) *packed = pk;
     if (lanes_per_row) *lanes_per_row = l;
     if (rows_per_wg) *rows_per_wg = r;
     if (n_meshes) *n_meshes = n;

@@ -183,6 +183,7 @@ void spmv_f32(Ctx& c, const float* val, const float* x, float* y, hipStream_t s)
 void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream_t s);
 // Packed layout: pattern tables (once per mesh) and a value repack.
 void pack_pattern(Ctx& c);
+void pack_values64(Ctx& c);  // packed copy of the FP64 K (once per assembly)
 void pack_values_f32(Ctx& c, const float* csr, float* packed);
 void pack_values_bf16(Ctx& c, const float* csr, __bf16* packed);
 // solve.hip

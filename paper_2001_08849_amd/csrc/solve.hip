@@ -1416,6 +1416,9 @@ void ensure_packed32(Ctx& c) {
 }
 }  // namespace
 
+void pack_values64(Ctx& c) { ensure_packed64(c); }
+
+
 void learned_apply(Ctx& c, const double* r, double* z) {
   SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");
   ensure_work(c, false);

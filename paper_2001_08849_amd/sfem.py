@@ -43,7 +43,7 @@ EXPORTS = [
     "sfem_batch_get_schedule", "sfem_batch_solve", "sfem_batch_get_solution",
     "sfem_batch_get_system_info", "sfem_tetgen_read", "sfem_tetgen_last_error",
     "sfem_tetgen_sizes", "sfem_tetgen_get", "sfem_tetgen_free", "sfem_rcm_permutation",
-    "sfem_permute_mesh", "sfem_set_smoothing_domain",
+    "sfem_permute_mesh", "sfem_set_smoothing_domain", "sfem_batch_set_schedule",
 ]
 
 
@@ -143,7 +143,8 @@ def lib() -> C.CDLL:
             "sfem_batch_build": (i32, [vp, i32]),
             "sfem_batch_sizes": (i32, [vp, C.POINTER(i32)] + [C.POINTER(i64)] * 4),
             "sfem_batch_autotune": (i32, [vp, i32, i32, i32, C.POINTER(dbl)]),
-            "sfem_batch_get_schedule": (i32, [vp, i32] + [C.POINTER(i32)] * 4),
+            "sfem_batch_get_schedule": (i32, [vp, i32] + [C.POINTER(i32)] * 5),
+            "sfem_batch_set_schedule": (i32, [vp, i32, i32, i32, i32]),
             "sfem_batch_solve": (i32, [vp, C.POINTER(BatchOpts), C.POINTER(BatchInfo)]),
             "sfem_batch_get_solution": (i32, [vp, i32, i32, vp, i32]),
             "sfem_batch_get_system_info": (i32, [vp, vp, vp, vp, vp]),
@@ -573,11 +574,15 @@ class Batch:
                                                 ASM_F32_COPY if f32 else ASM_F64, C.byref(us)))
         return us.value
 
+    def set_schedule(self, bucket: int, lanes_per_row: int, rows_per_wg: int, packed: bool):
+        self._check(self._L.sfem_batch_set_schedule(self._h, int(bucket), int(lanes_per_row),
+                                                    int(rows_per_wg), int(bool(packed))))
+
     def schedule(self, bucket: int):
-        v = [C.c_int() for _ in range(4)]
+        v = [C.c_int() for _ in range(5)]
         self._check(self._L.sfem_batch_get_schedule(self._h, int(bucket), *[C.byref(x) for x in v]))
         return {"lanes_per_row": v[0].value, "rows_per_wg": v[1].value, "meshes": v[2].value,
-                "from_cache": v[3].value}
+                "from_cache": v[3].value, "packed": v[4].value}
 
     def solve(self, rtol: float = 1e-8, mode: int = MODE_F64, max_iter: int = 0,
               check_every: int = 0, use_graph: bool = True, raise_on_noconv: bool = False):

@@ -61,6 +61,24 @@ def test_batch_matches_oracle_per_system(S, small_items):
     assert worst < 1e-8
 
 
+def test_every_product_schedule_matches_oracle(S, small_items):
+    """Both product kernels (CSR-order values, 8/16/32 lanes; packed layout,
+    4/8 lanes) on every bucket solve every system to the oracle."""
+    refs = [oracle_solutions(it) for it in small_items]
+    for packed, lanes in [(False, 8), (False, 32), (True, 4), (True, 8)]:
+        b = S.batch_from_items(small_items)
+        for bk in range(3):
+            b.set_schedule(bk, lanes, 64, packed)
+        info = b.solve(rtol=1e-10, use_graph=True)
+        worst = max(rel(b.solution(m, k, it.mesh.n_nodes), refs[m][k])
+                    for m, it in enumerate(small_items) for k in range(4))
+        print(f"batch product {'packed' if packed else 'CSR'} {lanes} lanes: worst u error "
+              f"{worst:.2e}")
+        assert info["all_converged"] == 1 and worst < 1e-8
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        b.set_schedule(0, 16, 64, True)
+
+
 def test_graph_replay_equals_eager_launches(S, small_items):
     b = S.batch_from_items(small_items)
     b.solve(rtol=1e-10, use_graph=False)
@@ -95,7 +113,8 @@ def test_autotuner_buckets_and_cache(S):
     assert sum(s["meshes"] for s in sched) == len(items)
     for s in sched:
         if s["meshes"]:
-            assert s["lanes_per_row"] in (8, 16, 32) and s["rows_per_wg"] in (16, 64, 256)
+            lanes = (4, 8) if s["packed"] else (8, 16, 32)
+            assert s["lanes_per_row"] in lanes and s["rows_per_wg"] in (16, 64, 256)
             assert s["from_cache"] == 0
     b.solve(rtol=1e-9)
     after = [b.solution(m, k, it.mesh.n_nodes) for m, it in enumerate(items) for k in range(4)]
@@ -107,8 +126,8 @@ def test_autotuner_buckets_and_cache(S):
         s2 = b2.schedule(k)
         if s2["meshes"]:
             assert s2["from_cache"] == 1
-            assert (s2["lanes_per_row"], s2["rows_per_wg"]) == \
-                (sched[k]["lanes_per_row"], sched[k]["rows_per_wg"])
+            assert (s2["lanes_per_row"], s2["rows_per_wg"], s2["packed"]) == \
+                (sched[k]["lanes_per_row"], sched[k]["rows_per_wg"], sched[k]["packed"])
 
 
 def test_zero_load_case_and_errors(S):

@@ -109,3 +109,42 @@ def test_switching_domains_and_errors(S):
         c.set_smoothing_domain(7)
     c.set_smoothing_domain(S.DOMAIN_FACE)
     assert c.sizes().nnz == nnz_face
+
+
+def test_learned_preconditioner_on_edge_domains(S):
+    """The network runs on any block pattern: on the ES-FEM matrix its
+    correction S (random weights) matches the FP64 reference network to the
+    BF16 bound, and the learned flexible PCG solves to the dense answer."""
+    from oracle import gnn_ref as G
+    p = mg.learned_small(2, grid=(8, 3, 3))
+    m = p.mesh
+    c = es_ctx(S, p)
+    K = ES.assemble(m.xyz, m.tets, p.E, p.nu)
+    f = O.traction_load(m.xyz, m.end_tris, np.asarray(p.traction, float))
+    Kb, fb = O.apply_dirichlet(K, f, p.fixed_dofs())
+    Kb = Kb.tocsr()
+    Kb.sort_indices()
+    P = G.init_params(4)
+    rng = np.random.default_rng(5)
+    P["Wo"] = rng.standard_normal(P["Wo"].shape) * 0.3
+    flat = S.pack_params(P)
+    P64 = {k: v.astype(np.float64) for k, v in S.unpack_params(flat).items()}
+    net = S.Gnn(0, seed=1)
+    net.set_params(flat)
+    net.apply(c)
+    S_gpu, _ = c.precond()
+    theta = c.precond_info()["theta"]
+    g = G.build_graph(Kb, m.xyz, p.fixed_dofs())
+    Sp, _ = G.forward(P64, g)
+    ref = np.zeros(Kb.nnz)
+    for k, (I, J) in enumerate(zip(g.row, g.bcol)):
+        for a in range(3):
+            lo, hi = Kb.indptr[3 * I + a], Kb.indptr[3 * I + a + 1]
+            ref[lo + np.searchsorted(Kb.indices[lo:hi], 3 * J + np.arange(3))] = Sp[k, a]
+    err = np.linalg.norm(S_gpu / theta - ref) / np.linalg.norm(ref)
+    u, info = c.solve(rtol=1e-10, precond=S.PRECOND_LEARNED)
+    ud = O.solve_dense(Kb, fb)
+    eu = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+    print(f"ES-FEM learned M: S error {err:.2e} (theta {theta:.3f}); flexible PCG "
+          f"{info['iters']} iterations, u error {eu:.2e}")
+    assert err < 5 * 2.0 ** -9 and info["converged"] and eu < 1e-8

@@ -606,6 +606,17 @@ def main():
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_a / HBM_PEAK_GBS,
                                 "traffic": read_traffic("assemble_c2"),
                                 "bytes_per_launch": asm_bytes, "us_per_launch": asm_med * 1e3}
+    # the kernel's real limiter: one 64-bit LDS atomic per (row, face, entry)
+    # contribution, 144 per exterior and 225 per interior face (the COO length
+    # of Eq. 12); peaks: 16 per clock per CU without bank conflicts (128 B/clk
+    # of LDS), 5.1 per clock per CU measured for random addresses
+    n_atom = 144 * s.n_exterior + 225 * (s.n_faces - s.n_exterior)
+    rate = n_atom / (asm_med * 1e-3)
+    clk = 256 * 2.4e9
+    out["roofline_assembly"]["lds_atomics"] = {
+        "per_launch": n_atom, "achieved_per_s": rate,
+        "peak_conflict_free_per_s": 16 * clk, "frac_conflict_free": rate / (16 * clk),
+        "peak_random_measured_per_s": 5.1 * clk, "frac_random_measured": rate / (5.1 * clk)}
     if stress:
         out["stress_recovery"] = stress
     if not args.no_batch and not args.skip_solve:

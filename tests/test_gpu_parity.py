@@ -344,3 +344,35 @@ def test_c1_f32_matrix_with_f64_replacement(c1):
     print(f"c1: FP32-matrix CG + FP64 replacement iters {info['iters']} "
           f"relres {info['true_relres']:.2e}; u error vs banded {err:.2e}")
     assert info["converged"] and info["true_relres"] <= 1e-8 and err <= 1e-8
+
+
+def test_mesh_beyond_two_million_nodes():
+    """A 2.26M-node, 13.3M-tet cantilever (past the 2^21 nodes a 21-bit face
+    key would allow): face counts equal the structured closed forms
+    (N_e = 4(nx ny + ny nz + nz nx), N_i = (24 nx ny nz - N_e) / 2), sampled
+    rows match the oracle, and Jacobi PCG reaches 1e-8."""
+    sfem = _sfem()
+    nx, ny, nz = 221, 100, 100
+    p = mg.cantilever_scaled(nx, ny, nz, jitter=0.1, seed=5, L=(44.2, 20.0, 20.0))
+    m = p.mesh
+    assert m.n_nodes > 2 ** 21
+    ctx = gpu_ctx(p)
+    s = ctx.sizes()
+    ne = 4 * (nx * ny + ny * nz + nz * nx)
+    assert (s.n_faces, s.n_exterior) == (ne + (24 * nx * ny * nz - ne) // 2, ne)
+    rp, ci, va = ctx.csr(sfem.K_UNCONSTRAINED)
+    rng = np.random.default_rng(1)
+    picks = [0, m.n_nodes - 1, mg.node_id(nx // 2, ny // 2, nz // 2, ny, nz)]
+    picks += list(rng.integers(0, m.n_nodes, 4))
+    worst = 0.0
+    for I, (cols, vals) in O.assemble_rows(m.xyz, m.tets, p.E, p.nu, picks).items():
+        for a in range(3):
+            sl = slice(rp[3 * I + a], rp[3 * I + a + 1])
+            np.testing.assert_array_equal(ci[sl], cols)
+            worst = max(worst, np.abs(va[sl] - vals[a]).max() / np.abs(vals[a]).max())
+    del rp, ci, va
+    u, info = ctx.solve(rtol=1e-8)
+    print(f"{m.n_nodes} nodes, {m.n_tets} tets: faces {s.n_faces}, nnz {s.nnz}, assembly "
+          f"{ctx.timings()['ms_assemble']:.2f} ms; sampled-row K error {worst:.2e}; "
+          f"{info['iters']} iterations, {info['ms_solve']:.0f} ms, relres {info['true_relres']:.2e}")
+    assert worst <= 1e-12 and info["converged"] and info["true_relres"] <= 1e-8

@@ -122,14 +122,28 @@ __global__ void k_edge_support(int64_t ne, const int32_t* __restrict__ etab,
   }
 }
 
-// Incidence entries: one per support slot (padding goes to bucket N).
-__global__ void k_edge_inc_entries(int64_t ne, const int32_t* __restrict__ esup, int64_t N,
-                                   int32_t* __restrict__ bucket, uint32_t* __restrict__ vals) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= ne * kEdgeSup) return;
-  const int v = esup[i];
-  bucket[i] = v >= 0 ? v : int(N);
-  vals[i] = uint32_t(i / kEdgeSup);
+// Support size of every edge.
+__global__ void k_edge_nsup(int64_t ne, const int32_t* __restrict__ esup,
+                            int32_t* __restrict__ nsup) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int n = 0;
+  for (int q = 0; q < kEdgeSup; ++q) n += esup[e * kEdgeSup + q] >= 0;
+  nsup[e] = n;
+}
+
+// Incidence entries: one per support node, at ofs[e] + q (no padding
+// entries, so no bucket collects the -1 slots).
+__global__ void k_edge_inc_entries(int64_t ne, const int32_t* __restrict__ esup,
+                                   const int32_t* __restrict__ ofs, int32_t* __restrict__ bucket,
+                                   uint32_t* __restrict__ vals) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int o = ofs[e], n = ofs[e + 1] - o;
+  for (int q = 0; q < n; ++q) {
+    bucket[o + q] = esup[e * kEdgeSup + q];
+    vals[o + q] = uint32_t(e);
+  }
 }
 
 // Per incidence (row I, edge k): the block slot in row I of each support
@@ -389,18 +403,24 @@ void build_edge_topology(Ctx& c) {
   SFEM_REQUIRE(!(e_err & 1), SFEM_EMESH, "edge domains: more than 12 tets around an edge");
   SFEM_REQUIRE(!(e_err & 2), SFEM_EMESH, "edge domains: an edge support exceeds 16 nodes");
   // 3. node -> edge incidence
-  const int64_t ni = et.ne * kEdgeSup;
-  DBuf<int32_t> ib;
+  DBuf<int32_t> nsup, sofs, ib;
   DBuf<uint32_t> iv;
+  nsup.reserve(et.ne + 1);
+  sofs.reserve(et.ne + 1);
+  k_edge_nsup<<<div_up(et.ne, kB), kB, 0, s>>>(et.ne, et.esup.get(), nsup.get());
+  SFEM_HIP(hipGetLastError());
+  exclusive_scan_i32(nsup.get(), sofs.get(), et.ne, s);
+  const int64_t ni = read1(sofs.get() + et.ne, s);
   ib.reserve(ni);
   iv.reserve(ni);
-  k_edge_inc_entries<<<div_up(ni, kB), kB, 0, s>>>(et.ne, et.esup.get(), N, ib.get(), iv.get());
+  k_edge_inc_entries<<<div_up(et.ne, kB), kB, 0, s>>>(et.ne, et.esup.get(), sofs.get(), ib.get(),
+                                                      iv.get());
   SFEM_HIP(hipGetLastError());
-  et.inc_ptr.reserve(N + 2);
+  et.inc_ptr.reserve(N + 1);
   et.inc.reserve(ni);
-  bucket_sort_u32(ib.get(), iv.get(), ni, int(N + 1), et.inc_ptr.get(),
-                  reinterpret_cast<uint32_t*>(et.inc.get()), s, int(N));
-  et.n_inc = read1(et.inc_ptr.get() + N, s);
+  bucket_sort_u32(ib.get(), iv.get(), ni, int(N), et.inc_ptr.get(),
+                  reinterpret_cast<uint32_t*>(et.inc.get()), s);
+  et.n_inc = ni;
   // 4. pattern, tiles, slots
   et.max_inc = build_pattern<kEdgeSup, kEdgeSup>(c, et.inc_ptr.get(), et.inc.get(),
                                                  et.esup.get());

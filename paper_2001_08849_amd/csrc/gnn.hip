@@ -35,6 +35,9 @@ constexpr int kGemmThreads = 256;  // 4 waves
 constexpr int kGemmGrid = 2048;    // cap of the row-tile GEMM grids
 constexpr int kWgradGrid = 256;    // workgroups (partials) of a weight gradient
 constexpr int kRedGrid = 256;      // partials of the small reductions
+// workgroups of the column-sum and small weight-gradient reductions over the
+// edges / nodes (memory-bound: enough workgroups to fill the chip)
+constexpr int kColGrid = 2048;
 constexpr int kMaxBatch = 64;      // pairs per minibatch
 
 __device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
@@ -220,6 +223,34 @@ __global__ void k_reduce_part(int nparts, int64_t len, const float* __restrict__
   out[j] = acc;
 }
 
+// out[j] = sum_b part[b * len + j] for few outputs and many partials: one
+// workgroup per output, a fixed-order strided sum and tree (deterministic).
+// With split (NI >= 0), the partials of a small weight gradient with bias:
+// outputs j = o * (NI + 1) + i go to W[o * NI + i] (i < NI) and b[o]
+// (i == NI).
+__global__ void __launch_bounds__(256)
+    k_reduce_wide(int nparts, int64_t len, const float* __restrict__ part, float* __restrict__ out,
+                  int NI, float* __restrict__ W, float* __restrict__ bias) {
+  __shared__ float sm[256];
+  const int64_t j = blockIdx.x;
+  float acc = 0.f;
+  for (int b = threadIdx.x; b < nparts; b += 256) acc += part[int64_t(b) * len + j];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (NI < 0) {
+    out[j] = sm[0];
+  } else {
+    const int o = int(j) / (NI + 1), i = int(j) % (NI + 1);
+    if (i < NI) W[o * NI + i] = sm[0];
+    else bias[o] = sm[0];
+  }
+}
+
 // Column sums of a [rows][64] array (bias gradients): partials per block.
 __global__ void __launch_bounds__(256)
     k_colsum64(int64_t rows, const float* __restrict__ g, float* __restrict__ part) {
@@ -276,18 +307,6 @@ __global__ void __launch_bounds__(256)
     const int t = threadIdx.x + 256 * u;
     if (t < NOUT) part[int64_t(blockIdx.x) * NOUT + t] = acc[u];
   }
-}
-
-// Sums k_wgrad_small partials into W [NO][NI] and, with NC = NI + 1, b [NO].
-__global__ void k_reduce_split(int nparts, int NO, int NI, int NC, const float* __restrict__ part,
-                               float* __restrict__ W, float* __restrict__ b) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NO * NC) return;
-  float acc = 0.f;
-  for (int p = 0; p < nparts; ++p) acc += part[int64_t(p) * NO * NC + t];
-  const int o = t / NC, i = t % NC;
-  if (i < NI) W[o * NI + i] = acc;
-  else b[o] = acc;
 }
 
 // ----------------------------------------------------------------- features
@@ -1076,12 +1095,14 @@ double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad) {
   SFEM_HIP(hipGetLastError());
 
   // ---- decoder
+  static_assert(size_t(kColGrid) * kH * (kFEdge + 1) <= size_t(kWgradGrid) * kH * 3 * kH,
+                "partials of the small reductions fit the weight-gradient buffer");
   g.wpart.reserve(size_t(kWgradGrid) * kH * 3 * kH);
   float* part = g.wpart.get();
   const float* eL = w.e.get() + kLayers * nb * kH;
-  const int gs = grid_for(nb, 2048, kRedGrid);
+  const int gs = grid_for(nb, 256, kColGrid);
   k_wgrad_small<9, kH, false><<<gs, 256, 0, s>>>(nb, dR, eL, part);
-  k_reduce_split<<<div_up(9 * kH, 256), 256, 0, s>>>(gs, 9, kH, kH, part, G + L.Wo, nullptr);
+  k_reduce_wide<<<9 * kH, 256, 0, s>>>(gs, 9 * kH, part, G + L.Wo, -1, nullptr, nullptr);
   k_decode_bwd<<<div_up(nb * kH, 256), 256, 0, s>>>(nb, dR, P + L.Wo, w.de.get());
   k_fill_f32<<<div_up(N * kH, 256), 256, 0, s>>>(N * kH, 0.f, w.dh.get());
   SFEM_HIP(hipGetLastError());
@@ -1089,7 +1110,7 @@ double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad) {
   // ---- message-passing layers, last first
   const int ge = tile_grid(nb, kGemmGrid), gn = tile_grid(N, kGemmGrid);
   const int gwe = tile_grid(nb, kWgradGrid), gwn = tile_grid(N, kWgradGrid);
-  const int gce = grid_for(nb, 1024, kRedGrid), gcn = grid_for(N, 1024, kRedGrid);
+  const int gce = grid_for(nb, 256, kColGrid), gcn = grid_for(N, 256, kColGrid);
   for (int l = kLayers - 1; l >= 0; --l) {
     const float* h_l = w.h.get() + l * N * kH;
     const float* e_l = w.e.get() + l * nb * kH;
@@ -1102,7 +1123,7 @@ double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad) {
                                                        part);
     k_reduce_part<<<div_up(kH * 2 * kH, 256), 256, 0, s>>>(gwn, kH * 2 * kH, part, G + L.U[l]);
     k_colsum64<<<gcn, 256, 0, s>>>(N, w.dt.get(), part);
-    k_reduce_part<<<1, kH, 0, s>>>(gcn, kH, part, G + L.c[l]);
+    k_reduce_wide<<<kH, 256, 0, s>>>(gcn, kH, part, G + L.c[l], -1, nullptr, nullptr);
     k_gemm_xw<2 * kH><<<gn, kGemmThreads, 0, s>>>(N, Rows64{w.dt.get()}, Pb + L.U[l],
                                                    NodeBwdEpi{w.dh.get(), w.da.get()});
     // edge update e += relu(W [h_I; h_J; e] + b), a = mean relu(z)
@@ -1112,7 +1133,7 @@ double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad) {
         nb, Rows64{w.dz.get()}, EdgeX{w.erow.get(), tp.bcol.get(), h_l, e_l}, part);
     k_reduce_part<<<div_up(kH * 3 * kH, 256), 256, 0, s>>>(gwe, kH * 3 * kH, part, G + L.W[l]);
     k_colsum64<<<gce, 256, 0, s>>>(nb, w.dz.get(), part);
-    k_reduce_part<<<1, kH, 0, s>>>(gce, kH, part, G + L.b[l]);
+    k_reduce_wide<<<kH, 256, 0, s>>>(gce, kH, part, G + L.b[l], -1, nullptr, nullptr);
     k_gemm_xw<3 * kH><<<ge, kGemmThreads, 0, s>>>(nb, Rows64{w.dz.get()}, Pb + L.W[l],
                                                    EdgeBwdEpi{w.dXh.get(), w.de.get()});
     k_dh_gather<<<div_up(N * 64, 256), 256, 0, s>>>(N, tp.bptr.get(), w.etr.get(), w.dXh.get(),
@@ -1123,13 +1144,13 @@ double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad) {
   // ---- encoders
   k_relu_bwd<<<div_up(nb * kH, 256), 256, 0, s>>>(nb * kH, w.de.get(), w.e.get(), w.dz.get());
   k_wgrad_small<kH, kFEdge, true><<<gs, 256, 0, s>>>(nb, w.dz.get(), w.y.get(), part);
-  k_reduce_split<<<div_up(kH * (kFEdge + 1), 256), 256, 0, s>>>(gs, kH, kFEdge, kFEdge + 1, part,
-                                                                G + L.We, G + L.be);
-  const int gsn = grid_for(N, 2048, kRedGrid);
+  k_reduce_wide<<<kH * (kFEdge + 1), 256, 0, s>>>(gs, kH * (kFEdge + 1), part, nullptr, kFEdge,
+                                                  G + L.We, G + L.be);
+  const int gsn = grid_for(N, 256, kColGrid);
   k_relu_bwd<<<div_up(N * kH, 256), 256, 0, s>>>(N * kH, w.dh.get(), w.h.get(), w.dt.get());
   k_wgrad_small<kH, kFNode, true><<<gsn, 256, 0, s>>>(N, w.dt.get(), w.x.get(), part);
-  k_reduce_split<<<div_up(kH * (kFNode + 1), 256), 256, 0, s>>>(gsn, kH, kFNode, kFNode + 1,
-                                                                part, G + L.Wn, G + L.bn);
+  k_reduce_wide<<<kH * (kFNode + 1), 256, 0, s>>>(gsn, kH * (kFNode + 1), part, nullptr, kFNode,
+                                                  G + L.Wn, G + L.bn);
   SFEM_HIP(hipGetLastError());
   return loss;
 }

@@ -400,7 +400,8 @@ int sfem_batch_sizes(sfem_batch* b, int* n_meshes, int64_t* n_nodes, int64_t* n_
  * 4-right-hand-side product is timed over `reps` launches (0: 5) of that
  * bucket alone: (lanes per node row in {8, 16, 32} on the CSR-order values,
  * or in {4, 8} on the packed layout, FP64 only) x (node rows per workgroup
- * in {16, 64, 256}).  The fastest is kept and cached for the process under
+ * in {16, 64, 256}, at least 256 / lanes so that no lane group idles).
+ * The fastest is kept and cached for the process under
  * the bucket's shape (bucket, log2 of its node rows, mean block degree).
  * With use_cache, a cached shape is reused without timing.  precision:
  * SFEM_ASM_F64 or SFEM_ASM_F32_COPY (CSR-order candidates only; an FP32

@@ -34,6 +34,7 @@ constexpr int kBThreads = 256;
 constexpr int kNumBuckets = 3;     // mesh sizes: < 8192, < 32768, >= 32768 nodes
 constexpr int kNumLpr = 3;
 constexpr int kLprs[kNumLpr] = {8, 16, 32};
+constexpr int kCU = 4;                       // columns per step in the CSR-order product
 constexpr int kNumPLpr = 2;                  // packed layout (FP64 values)
 constexpr int kPLprs[kNumPLpr] = {4, 8};
 constexpr int kNumRw = 3;
@@ -112,11 +113,11 @@ __global__ void __launch_bounds__(kBThreads)
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
-    // two columns per step (the second masked past the row), so each lane
-    // keeps twice the loads in flight
-    for (int c0 = sub; c0 < td; c0 += 2 * LPR) {
+    // kCU columns per step (masked past the row), so each lane keeps kCU
+    // columns' loads in flight
+    for (int c0 = sub; c0 < td; c0 += kCU * LPR) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kCU; ++h) {
         const int c = c0 + h * LPR;
         const bool in = c < td;
         const int cc = in ? c : c0;
@@ -637,8 +638,11 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
     for (int li = 0; li < n_cand; ++li)
       for (int ri = 0; ri < kNumRw; ++ri) {
         const bool pk = li >= kNumLpr;
+        const int lpr = pk ? kPLprs[li - kNumLpr] : kLprs[li];
+        // a workgroup has kBThreads / lpr row groups: fewer rows would idle some
+        if (kRws[ri] < kBThreads / lpr) continue;
         b.packed[bk] = pk;
-        b.lpr[bk] = pk ? kPLprs[li - kNumLpr] : kLprs[li];
+        b.lpr[bk] = lpr;
         b.rw[bk] = kRws[ri];
         build_table(c, b);
         bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, false);  // warm

@@ -502,15 +502,22 @@ def main():
     ctx.timer_start()
     asm_ms, solves = [], []
     for k in range(args.steps):
-        ms_asm, info = step(profile=True)
+        ms_asm, info = step()
         asm_ms.append(ms_asm)
         if info:
             solves.append(info)
         log(f"[bench] step {k}: assembly {ms_asm:.3f} ms" +
             (f", solve {info['ms_solve']:.1f} ms, {info['iters']} it, relres "
-             f"{info['true_relres']:.2e}, spmv {info['ms_spmv_avg'] * 1e3:.1f} us" if info else ""))
+             f"{info['true_relres']:.2e}" if info else ""))
     total_ms = ctx.timer_stop()
     ctx.synchronize()
+    # per-launch timing of the CG product (events around every launch, so
+    # every launch is eager): one more solve, outside the timed steps
+    prof = None
+    if not args.skip_solve:
+        _, prof = ctx.solve(rtol=1e-8, out=u, profile=True)
+        log(f"[bench] profiled solve: {prof['ms_solve']:.1f} ms, CG product "
+            f"{prof['ms_spmv_avg'] * 1e3:.1f} us per launch")
 
     stress = None
     if not args.skip_solve:
@@ -527,10 +534,17 @@ def main():
     lsolves = []
     if learned is not None and not args.skip_solve:
         net = learned["net"]
-        for k in range(max(1, args.steps)):
+        for k in range(max(1, args.steps) + 1):
+            # the last solve times every launch (eager), for the M-apply roofline
+            last = k == max(1, args.steps)
             ms_inf = net.apply(ctx)
-            _, info = ctx.solve(rtol=1e-8, out=u, precond=sfem.PRECOND_LEARNED, profile=True)
+            _, info = ctx.solve(rtol=1e-8, out=u, precond=sfem.PRECOND_LEARNED, profile=last)
             info["ms_inference"] = ms_inf
+            if last:
+                lprof = info
+                log(f"[bench] profiled learned solve: {info['ms_solve']:.1f} ms, M apply "
+                    f"{info['ms_mapply_avg'] * 1e3:.1f} us per launch")
+                continue
             lsolves.append(info)
             pinfo = ctx.precond_info()
             log(f"[bench] learned {k}: inference {ms_inf:.1f} ms (theta {pinfo['theta']:.3f}), "
@@ -576,7 +590,7 @@ def main():
             out["solve_s"]["learned_incl_inference"] = ls + li
             out["solve_iters"]["learned"] = lsolves[-1]["iters"]
             out["solve_true_relres"]["learned"] = lsolves[-1]["true_relres"]
-            mms = float(np.mean([i["ms_mapply_avg"] for i in lsolves]))
+            mms = lprof["ms_mapply_avg"]
             mb = mapply_bytes(m.n_nodes, s.nnz, s.n_blocks)
             ach_m = mb / (mms * 1e-3) / 1e9 if mms > 0 else None
             out["roofline_mapply"] = {
@@ -593,7 +607,7 @@ def main():
                 "speedup_vs_jacobi": out["solve_s"]["jacobi_f64"] / (ls + li),
                 "training": {k: v for k, v in learned.items() if k != "net"},
             }
-        spmv_ms = float(np.mean([i["ms_spmv_avg"] for i in solves]))
+        spmv_ms = prof["ms_spmv_avg"]
         ach = spmv_bytes / (spmv_ms * 1e-3) / 1e9
         out["roofline"] = {"kernel": f"k_cg_spmv<double,double> (row schedule "
                                      f"{tuned['f64'][0][0]})", "bound": "hbm",

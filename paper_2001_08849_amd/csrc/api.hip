@@ -174,6 +174,7 @@ void sfem_destroy(sfem_ctx* h) {
   if (c.tev0) (void)hipEventDestroy(c.tev0);
   if (c.tev1) (void)hipEventDestroy(c.tev1);
   for (hipEvent_t e : c.prof_ev) (void)hipEventDestroy(e);
+  c.drop_cg_graph();
   if (c.sc_host) (void)hipHostFree(c.sc_host);
   if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
   delete h;

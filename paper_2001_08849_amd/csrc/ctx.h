@@ -137,6 +137,19 @@ struct Ctx {
   DBuf<CgScalars> sc;
   CgScalars* sc_host = nullptr;  // pinned mirror
 
+  // one full check period of CG iterations captured as a hipGraph, with the
+  // addresses, sizes and schedule it was captured for
+  hipGraph_t cg_graph = nullptr;
+  hipGraphExec_t cg_exec = nullptr;
+  std::vector<const void*> cg_key;
+  void drop_cg_graph() {
+    if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
+    if (cg_graph) (void)hipGraphDestroy(cg_graph);
+    cg_exec = nullptr;
+    cg_graph = nullptr;
+    cg_key.clear();
+  }
+
   // row-kernel schedules (FP64 and FP32 matrices), set by the autotuner
   RowSched sched64{2, 4096};
   RowSched sched32{2, 4096};

@@ -80,9 +80,12 @@ int64_t gnn_generate_pairs(Ctx& c, int n_rhs, int snaps_per_rhs, uint64_t seed);
 void gnn_set_pairs(Ctx& c, int64_t n_pairs, const float* r, const float* e);
 
 // solve.hip: Jacobi PCG (FP64) of K x = b from x = 0 to ||b - K x|| <=
-// tol_abs; hook(done) runs after every `every` iterations with c.x current.
+// tol_abs; hook(done) runs after every check period of at most `every`
+// iterations with c.x current; a period also ends at next_stop(done) when
+// that is sooner (next_stop may be null).
 int jacobi_run(Ctx& c, const double* b, double tol_abs, int every, int max_iter,
-               const std::function<void(int)>& hook);
+               const std::function<void(int)>& hook,
+               const std::function<int(int)>* next_stop = nullptr);
 // z = M r with the learned preconditioner (FP64 vectors).
 void learned_apply(Ctx& c, const double* r, double* z);
 

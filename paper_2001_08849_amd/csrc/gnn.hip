@@ -20,6 +20,8 @@
 // are gathered while staging, never stored.  Scatter-adds of the backward
 // pass go through the transposed-edge map (edge (J,I) of edge (I,J)), so
 // every output has one writer and results are reproducible.
+#include <limits>
+
 #include "gnn.h"
 
 namespace sfem {
@@ -1271,12 +1273,16 @@ int64_t gnn_generate_pairs(Ctx& c, int n_rhs, int snaps, uint64_t seed) {
       ++got;
       ++next;
     }
-    jacobi_run(c, b.get(), tol, 1, 200000, [&](int done) {
+    // periods end at the snapshot iterations (and every 50 in between)
+    const std::function<int(int)> stop = [&](int) {
+      return next < at.size() ? at[next] : std::numeric_limits<int>::max();
+    };
+    jacobi_run(c, b.get(), tol, 50, 200000, [&](int done) {
       if (next < at.size() && done >= at[next]) {
         grab();
         ++next;
       }
-    });
+    }, &stop);
     // c.x = x*; e_j = x* - x_j, r_j = K e_j
     for (int j = 0; j < got; ++j) {
       k_sub<<<div_up(n, 256), 256, 0, s>>>(n, c.x.get(), xs.get() + int64_t(j) * n, e.get());

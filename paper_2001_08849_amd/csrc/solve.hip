@@ -859,6 +859,43 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   SFEM_HIP(hipGetLastError());
 }
 
+// One full check period of iterations replayed from a hipGraph (captured
+// on first use and whenever an address, size or schedule it launched with
+// has changed); the first period of a solve runs eagerly (it also builds
+// any packed copy the schedule needs, which must not be captured).  Small
+// meshes' iterations are launch-bound: five short kernels each.
+template <typename VT, typename P>
+void cg_period(Ctx& c, const CgBuffers& B, int iters, int& parity, bool eager) {
+  if (eager || c.profile) {
+    cg_iterations<VT, P>(c, B, iters, parity);
+    return;
+  }
+  const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
+  const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val);
+  const std::vector<const void*> key = {
+      B.val, B.dinv, B.x, B.r, B.z, B.p0, B.q, B.mval, B.mptr4, B.mcol4, B.msq, B.rh,
+      LY.ptr, LY.col, LY.val, c.sc.get(), c.partials.get(),
+      reinterpret_cast<const void*>(intptr_t(c.N)), reinterpret_cast<const void*>(intptr_t(iters)),
+      reinterpret_cast<const void*>(intptr_t(rs.variant * 100000 + rs.grid_cap)),
+      reinterpret_cast<const void*>(intptr_t(sizeof(VT) * 16 + sizeof(P)))};
+  if (!c.cg_exec || c.cg_key != key) {
+    c.drop_cg_graph();
+    SFEM_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      cg_iterations<VT, P>(c, B, iters, parity);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(c.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SFEM_HIP(hipStreamEndCapture(c.stream, &c.cg_graph));
+    SFEM_HIP(hipGraphInstantiate(&c.cg_exec, c.cg_graph, nullptr, nullptr, 0));
+    c.cg_key = key;
+  }
+  SFEM_HIP(hipGraphLaunch(c.cg_exec, c.stream));
+}
+
 // Adds the SpMV (and learned M) launches of the last chunk that did work (a
 // launch that returned at once because the solve had converged is not
 // counted).
@@ -926,7 +963,8 @@ __global__ void k_cg_clear(CgScalars* sc) {
 template <typename VT, typename P, typename VTR = VT>
 int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double tol_abs,
         int max_iter, int check_every, bool& met, bool& breakdown, bool replace = true,
-        const std::function<void(int)>* hook = nullptr) {
+        const std::function<void(int)>* hook = nullptr,
+        const std::function<int(int)>* next_stop = nullptr) {
   const int64_t n = c.n_dof();
   hipStream_t s = c.stream;
   const double tol2 = tol_abs * tol_abs;
@@ -953,8 +991,10 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
   double best = c.sc_host->rr;
   int stale = 0;  // checks without a new best, counted once near the tolerance
   while (!met && done < max_iter && stale < 40) {
-    const int chunk = std::min(check_every, max_iter - done);
-    cg_iterations<VT, P>(c, B, chunk, parity);
+    int chunk = std::min(check_every, max_iter - done);
+    // end the period at the caller's next stop (snapshots), if one is sooner
+    if (next_stop) chunk = std::max(1, std::min(chunk, (*next_stop)(done) - done));
+    cg_period<VT, P>(c, B, chunk, parity, done == 0 || chunk != check_every);
     if (replace) cg_replace<VTR, P>(c, B);
     read_scalars(c);
     const int before = done;
@@ -1333,13 +1373,15 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
 }
 
 int jacobi_run(Ctx& c, const double* b, double tol_abs, int every, int max_iter,
-               const std::function<void(int)>& hook) {
+               const std::function<void(int)>& hook,
+               const std::function<int(int)>* next_stop) {
   ensure_work(c, false);
   c.profile = false;
   CgBuffers B{c.val.get(), c.val.get(), c.dinv.get(), (void*)b, c.x.get(), c.r.get(),
               c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
   bool met = false, brk = false;
-  return pcg<double, double>(c, B, b, 1.0, tol_abs, max_iter, every, met, brk, true, &hook);
+  return pcg<double, double>(c, B, b, 1.0, tol_abs, max_iter, every, met, brk, true, &hook,
+                             next_stop);
 }
 
 void pack_pattern(Ctx& c) {

@@ -267,3 +267,16 @@ def test_training_gains_on_held_out_mesh(S):
         u, info = c32.solve(rtol=1e-8, mode=mode, precond=S.PRECOND_LEARNED)
         assert info["converged"] and info["true_relres"] <= 1e-8, (mode, info)
         assert np.linalg.norm(u - uj) / np.linalg.norm(uj) < 1e-6
+
+
+def test_learned_graph_periods_equal_eager(S, small):
+    """The learned flexible PCG replayed from hipGraph periods equals the
+    eager launches bit for bit."""
+    p, ctx, Kb, g = small
+    flat, _ = fp32_params(S, random_params(3, 0.3))
+    net = S.Gnn(0, seed=1)
+    net.set_params(flat)
+    net.apply(ctx)
+    ug, ig = ctx.solve(rtol=1e-10, precond=S.PRECOND_LEARNED)
+    ue, ie = ctx.solve(rtol=1e-10, precond=S.PRECOND_LEARNED, profile=True)
+    assert ig["iters"] == ie["iters"] and np.array_equal(ug, ue)

@@ -376,3 +376,19 @@ def test_mesh_beyond_two_million_nodes():
           f"{ctx.timings()['ms_assemble']:.2f} ms; sampled-row K error {worst:.2e}; "
           f"{info['iters']} iterations, {info['ms_solve']:.0f} ms, relres {info['true_relres']:.2e}")
     assert worst <= 1e-12 and info["converged"] and info["true_relres"] <= 1e-8
+
+
+def test_graph_replayed_periods_equal_eager_launches(c1):
+    """Full check periods replay from a hipGraph; with per-launch timing on,
+    every launch is eager.  Both runs take the same iterations and give
+    bit-identical displacements (Jacobi; FP32-matrix mode too)."""
+    sfem = _sfem()
+    ctx = gpu_ctx(c1.p, f32=True)
+    for mode in (sfem.MODE_F64, sfem.MODE_F32_RR):
+        ug, ig = ctx.solve(rtol=1e-8, mode=mode)
+        ue, ie = ctx.solve(rtol=1e-8, mode=mode, profile=True)
+        ug2, ig2 = ctx.solve(rtol=1e-8, mode=mode)      # replay of the kept graph
+        print(f"mode {mode}: graph {ig['iters']} it {ig['ms_solve']:.1f} ms, eager "
+              f"{ie['iters']} it {ie['ms_solve']:.1f} ms")
+        assert ig["iters"] == ie["iters"] == ig2["iters"]
+        assert np.array_equal(ug, ue) and np.array_equal(ug, ug2)

@@ -253,6 +253,17 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
+GRAPH_REPLAY = True
+
+
+def make_context(sfem):
+    """A library context on cuda:0 with the chosen PCG period launching."""
+    c = sfem.Context(0)
+    if not GRAPH_REPLAY:
+        c.set_graph_replay(False)
+    return c
+
+
 def train_network(args, mg, sfem, np):
     """Trains the learned preconditioner on blob-material cantilevers of
     140x14x14 cells (164,640 tets each): pairs from Jacobi-PCG runs, Adam on
@@ -265,7 +276,7 @@ def train_network(args, mg, sfem, np):
     t0 = time.time()
     ctxs, n_pairs = [], 0
     for mi in range(args.train_meshes):
-        c = sfem.Context(0)
+        c = make_context(sfem)
         sfem.setup_problem(c, mg.learned_c4(mi))
         n_pairs += c.generate_pairs(10, 64, seed=mi + 1)
         ctxs.append(c)
@@ -282,7 +293,7 @@ def train_network(args, mg, sfem, np):
         f"{losses[:20].mean():.4f} -> {losses[-100:].mean():.4f}")
     for c in ctxs:
         c.close()
-    held = sfem.Context(0)
+    held = make_context(sfem)
     sfem.setup_problem(held, mg.learned_c4(0, held_out=True))
     _, ij = held.solve(rtol=1e-8)
     net.apply(held)
@@ -310,7 +321,7 @@ def renumbering_leg(prob, sfem, np, sched):
     inv = np.empty_like(sh)
     inv[sh] = np.arange(N)
     xyz_s, tets_s = m.xyz[sh], inv[m.tets].astype(np.int32)      # synthetic input
-    ctx = sfem.Context(0)
+    ctx = make_context(sfem)
     ctx.rcm_permutation(N, tets_s)                                # warm-up
     perm, ms_rcm = ctx.rcm_permutation(N, tets_s)
     xyz_r, tets_r = ctx.permute_mesh(perm, xyz_s, tets_s)
@@ -322,7 +333,7 @@ def renumbering_leg(prob, sfem, np, sched):
     for name, (x, t) in meshes.items():
         new_of_old = np.empty(N, np.int64)
         new_of_old[old_of[name]] = np.arange(N)
-        c = sfem.Context(0)
+        c = make_context(sfem)
         c.set_mesh(x, t)
         c.set_material(prob.E, prob.nu)
         c.set_dirichlet(np.sort((3 * new_of_old[clamp][:, None] + np.arange(3)).ravel()))
@@ -348,7 +359,7 @@ def es_fem_leg(prob, sfem, np):
     """The same cantilever with edge-based smoothing domains (ES-FEM):
     topology, assembly (median of 3) and the Jacobi-PCG solve to 1e-8."""
     m = prob.mesh
-    c = sfem.Context(0)
+    c = make_context(sfem)
     c.set_smoothing_domain(sfem.DOMAIN_EDGE)
     sfem.setup_problem(c, prob)
     ms = []
@@ -427,7 +438,12 @@ def main():
     ap.add_argument("--profile-command", default="", help="command line recorded in summaries")
     ap.add_argument("--schedule", default="", metavar="VARIANT,GRID_CAP",
                     help="pin the FP64 row schedule instead of autotuning it")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="launch every PCG kernel one by one (for tracers that cannot follow "
+                         "hipGraph launches)")
     args = ap.parse_args()
+    global GRAPH_REPLAY
+    GRAPH_REPLAY = not args.no_graph_replay
     if args.copy_calibration:
         copy_calibration()
         return
@@ -450,7 +466,7 @@ def main():
     prob = mg.cantilever_c2()
     m = prob.mesh
     log(f"[bench] mesh {m.grid} N={m.n_nodes} T={m.n_tets} generated in {time.time() - t0:.1f}s")
-    ctx = sfem.Context(0)
+    ctx = make_context(sfem)
     ctx.set_mesh(m.xyz, m.tets)
     ctx.set_material(prob.E, prob.nu)
     ctx.set_dirichlet(prob.fixed_dofs())

@@ -71,6 +71,15 @@ int sfem_create(sfem_ctx** out, int device, void* hip_stream);
 void sfem_destroy(sfem_ctx* ctx);
 const char* sfem_last_error(const sfem_ctx* ctx);   /* valid until the next call */
 int sfem_set_stream(sfem_ctx* ctx, void* hip_stream);
+/* Graph replay of PCG check periods (default on): after the first period
+ * of a solve, each full period of check_every iterations is captured once
+ * as a hipGraph on the context stream and replayed while the buffers, sizes
+ * and row schedule stay the same.  enabled = 0 launches every kernel one by
+ * one instead (same results bit for bit), for tools that cannot follow
+ * graph launches; the captured graph is released.  Applies to sfem_solve
+ * and the training-pair solves of sfem_gnn_generate_pairs (the batched
+ * solve always runs as one graph). */
+int sfem_set_graph_replay(sfem_ctx* ctx, int enabled);
 
 /* ----------------------------------------------------------------------------
  * Mesh (Sec. 3.2: the matrices Node [N][3] and Element [T][4]).

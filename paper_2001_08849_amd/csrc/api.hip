@@ -193,6 +193,17 @@ int sfem_set_stream(sfem_ctx* h, void* hip_stream) {
   });
 }
 
+int sfem_set_graph_replay(sfem_ctx* h, int enabled) {
+  return guarded(h, [&](Ctx& c) {
+    c.graph_replay = enabled != 0;
+    if (!c.graph_replay) {
+      SFEM_HIP(hipStreamSynchronize(c.stream));
+      c.drop_cg_graph();
+    }
+    return SFEM_OK;
+  });
+}
+
 int sfem_set_mesh(sfem_ctx* h, int64_t n_nodes, const double* xyz, int64_t n_tets,
                   const int32_t* tets, int ptr_kind) {
   return guarded(h, [&](Ctx& c) {

@@ -139,6 +139,7 @@ struct Ctx {
 
   // one full check period of CG iterations captured as a hipGraph, with the
   // addresses, sizes and schedule it was captured for
+  bool graph_replay = true;
   hipGraph_t cg_graph = nullptr;
   hipGraphExec_t cg_exec = nullptr;
   std::vector<const void*> cg_key;

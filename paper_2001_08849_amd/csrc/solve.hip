@@ -866,7 +866,7 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
 // meshes' iterations are launch-bound: five short kernels each.
 template <typename VT, typename P>
 void cg_period(Ctx& c, const CgBuffers& B, int iters, int& parity, bool eager) {
-  if (eager || c.profile) {
+  if (eager || c.profile || !c.graph_replay) {
     cg_iterations<VT, P>(c, B, iters, parity);
     return;
   }

@@ -28,7 +28,8 @@ STATUS = {0: "SFEM_OK", -1: "SFEM_EINVAL", -2: "SFEM_EMESH", -3: "SFEM_ENOMEM",
           -4: "SFEM_EHIP", -5: "SFEM_ENOCONV", -6: "SFEM_ESTATE"}
 
 EXPORTS = [
-    "sfem_create", "sfem_destroy", "sfem_last_error", "sfem_set_stream", "sfem_set_mesh",
+    "sfem_create", "sfem_destroy", "sfem_last_error", "sfem_set_stream", "sfem_set_graph_replay",
+    "sfem_set_mesh",
     "sfem_set_material", "sfem_set_material_per_tet", "sfem_set_dirichlet",
     "sfem_set_bc_penalty", "sfem_set_nodal_load", "sfem_add_traction", "sfem_assemble",
     "sfem_get_sizes", "sfem_get_faces", "sfem_get_csr", "sfem_get_rhs", "sfem_spmv",
@@ -98,6 +99,7 @@ def lib() -> C.CDLL:
             "sfem_destroy": (None, [vp]),
             "sfem_last_error": (C.c_char_p, [vp]),
             "sfem_set_stream": (i32, [vp, vp]),
+            "sfem_set_graph_replay": (i32, [vp, i32]),
             "sfem_set_mesh": (i32, [vp, i64, vp, i64, vp, i32]),
             "sfem_set_material": (i32, [vp, dbl, dbl]),
             "sfem_set_material_per_tet": (i32, [vp, vp, vp, i32]),
@@ -237,6 +239,11 @@ class Context:
         return st
 
     # ------------------------------------------------------------ inputs
+    def set_graph_replay(self, enabled: bool):
+        """Replay full PCG check periods as a captured hipGraph (default) or
+        launch every kernel one by one (same results)."""
+        self._check(self._L.sfem_set_graph_replay(self._h, int(bool(enabled))))
+
     def set_stream(self, stream_handle: int):
         self._check(self._L.sfem_set_stream(self._h, C.c_void_p(stream_handle)))
 

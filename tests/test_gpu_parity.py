@@ -392,3 +392,8 @@ def test_graph_replayed_periods_equal_eager_launches(c1):
               f"{ie['iters']} it {ie['ms_solve']:.1f} ms")
         assert ig["iters"] == ie["iters"] == ig2["iters"]
         assert np.array_equal(ug, ue) and np.array_equal(ug, ug2)
+        # replay switched off: eager launches without timing, same result
+        ctx.set_graph_replay(False)
+        un, i_n = ctx.solve(rtol=1e-8, mode=mode)
+        ctx.set_graph_replay(True)
+        assert i_n["iters"] == ig["iters"] and np.array_equal(ug, un)

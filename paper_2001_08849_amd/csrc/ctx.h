@@ -42,7 +42,7 @@ struct Topology {
 // tets.
 constexpr int kEdgeSup = 16;   // support nodes of an edge domain, at most
 constexpr int kEdgeTets = 12;  // tets around one edge, at most
-constexpr int kEdgeRec = 4 + 3 * kEdgeSup;  // V_k, lam, mu, bound, b[kEdgeSup][3]
+constexpr int kEdgeRec = 4 + 3 * kEdgeSup;  // V_k, lam, mu, (unused), b[kEdgeSup][3]
 
 struct EdgeTopo {
   int64_t ne = 0;                // edges
@@ -54,6 +54,8 @@ struct EdgeTopo {
   DBuf<int32_t> inc_ptr, inc;    // node -> edges whose support holds it (ascending)
   DBuf<uint8_t> slot;            // [n_inc][kEdgeSup] block slot of each support node
   DBuf<double> rec;              // [ne][kEdgeRec], per assembly
+  DBuf<double> ebound;           // [ne] bound of one contribution of each edge, per assembly
+  DBuf<int16_t> rexp;            // [N] per-row fixed-point unit exponent, per assembly
 };
 
 // Row-kernel schedule: variant index (lanes per row, rows per group step)

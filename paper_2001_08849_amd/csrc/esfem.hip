@@ -177,15 +177,18 @@ __global__ void k_edge_slots(int64_t N, const int32_t* __restrict__ inc_ptr,
   }
 }
 
-// Edge records: V_k, lam_k, mu_k, the bound (|lam| + 2 mu) V_k max |b_q|^2
-// of one contribution, and b of each support node (zero past the support).
+// Edge records: V_k, lam_k, mu_k, a spare word, and b of each support node
+// (past the support the record is not written and never read); and in a
+// compact array of its own the bound (|lam| + 2 mu) V_k max |b_q|^2 of one
+// contribution of the edge.
 template <bool HET>
 __global__ void __launch_bounds__(kB)
     k_edge_geometry(int64_t ne, const int32_t* __restrict__ etab,
                     const uint64_t* __restrict__ ent, const int32_t* __restrict__ esup,
                     const int32_t* __restrict__ tets, const double* __restrict__ xyz,
                     double lam0, double mu0, const double* __restrict__ lam_t,
-                    const double* __restrict__ mu_t, double* __restrict__ rec) {
+                    const double* __restrict__ mu_t, double* __restrict__ rec,
+                    double* __restrict__ ebound) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int first = etab[4 * e + 2], cnt = etab[4 * e + 3];
@@ -226,24 +229,43 @@ __global__ void __launch_bounds__(kB)
 #pragma unroll
   for (int q = 0; q < kEdgeSup; ++q) {
     const double x = b[q][0] * iV, y = b[q][1] * iV, z = b[q][2] * iV;
-    out[4 + 3 * q] = x;
-    out[4 + 3 * q + 1] = y;
-    out[4 + 3 * q + 2] = z;
+    if (sup[q] >= 0) {  // the support is -1 padded at its end
+      out[4 + 3 * q] = x;
+      out[4 + 3 * q + 1] = y;
+      out[4 + 3 * q + 2] = z;
+    }
     bb = fmax(bb, x * x + y * y + z * z);
   }
   out[0] = V;
   out[1] = lam;
   out[2] = mu;
-  out[3] = (fabs(lam) + 2.0 * mu) * V * bb;
+  ebound[e] = (fabs(lam) + 2.0 * mu) * V * bb;
+}
+
+// Unit exponent of every node row: the largest contribution bound among the
+// row's edges is below 2^rexp (clamped so that 2^(50 - rexp) stays a normal
+// double).  One wave per row.
+__global__ void k_edge_row_exp(int64_t N, const int32_t* __restrict__ inc_ptr,
+                               const int32_t* __restrict__ inc, const double* __restrict__ ebound,
+                               int16_t* __restrict__ rexp) {
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (I >= N) return;
+  double bmax = 0.0;
+  for (int k = inc_ptr[I] + lane; k < inc_ptr[I + 1]; k += kWave)
+    bmax = fmax(bmax, ebound[inc[k]]);
+  bmax = wave_max(bmax);
+  const int ex = bmax > 0.0 ? ilogb(bmax) + 1 : 0;
+  if (lane == 0) rexp[I] = int16_t(ex < -973 ? -973 : ex);
 }
 
 // Tile assembly of the edge items (see the face assembly for the scheme and
 // the fixed-point unit: here a row's unit comes from the edge records'
 // bounds, every contribution of the row below 2^50 units).
-__global__ void __launch_bounds__(kAsmThreads)
+__global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(6)))
     k_assemble_edge(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
-                    const uint8_t* __restrict__ slot, const int32_t* __restrict__ esup,
-                    const double* __restrict__ rec, const int32_t* __restrict__ bptr,
+                    const uint8_t* __restrict__ slot, const double* __restrict__ rec,
+                    const int16_t* __restrict__ rexp, const int32_t* __restrict__ bptr,
                     const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
                     const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
                     float* __restrict__ val32) {
@@ -251,6 +273,7 @@ __global__ void __launch_bounds__(kAsmThreads)
   __shared__ int32_t sptr[kTileBlocks + 1];
   __shared__ int32_t sinc[kTileBlocks + 1];
   __shared__ int16_t sexp[kTileBlocks];
+  __shared__ uint8_t sdpos[kTileBlocks];  // per row: slot of its own (diagonal) block
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -266,16 +289,20 @@ __global__ void __launch_bounds__(kAsmThreads)
   for (int i = tid; i <= nn; i += kAsmThreads) {
     sptr[i] = bptr[n0 + i] - b0;
     sinc[i] = inc_ptr[n0 + i] - e0;
+    if (i < nn) {
+      sexp[i] = rexp[n0 + i];
+      // the row's own column among its ascending block columns
+      const int I = n0 + i, rb = bptr[I];
+      int lo = 0, hi = bptr[I + 1] - rb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (bcol[rb + mid] < I) lo = mid + 1;
+        else hi = mid;
+      }
+      sdpos[i] = uint8_t(lo);
+    }
   }
   const int n_items = e1 - e0;
-  __syncthreads();
-  for (int li = wid; li < nn; li += nwaves) {
-    double bmax = 0.0;
-    for (int k = sinc[li] + lane; k < sinc[li + 1]; k += kWave)
-      bmax = fmax(bmax, rec[int64_t(inc[e0 + k]) * kEdgeRec + 3]);
-    bmax = wave_max(bmax);
-    if (lane == 0) sexp[li] = int16_t(bmax > 0.0 ? ilogb(bmax) + 1 : 0);  // bmax < 2^sexp
-  }
   __syncthreads();
 
   int stride = 1;
@@ -292,34 +319,54 @@ __global__ void __launch_bounds__(kAsmThreads)
     pos += step;
     if (pos >= n_items) pos -= n_items;
     const int li = upper_index(sinc, nn, e - e0);
-    const int I = n0 + li;
     const int rb = sptr[li];
     const int deg = sptr[li + 1] - rb;
     const int64_t edge = inc[e];
     const double* r = rec + edge * kEdgeRec;
-    const int32_t* sup = esup + edge * kEdgeSup;
-    const uint8_t* sl = slot + int64_t(e) * kEdgeSup;
-    const double inv_u = ldexp(1.0, 50 - sexp[li]);
+    // the item's 16 slot bytes: the support's size ns (slots past it are
+    // kNoSlot) and the position p of row I in it (the slot of I's own block)
+    const uint4 sl4 = *reinterpret_cast<const uint4*>(slot + int64_t(e) * kEdgeSup);
+    const uint32_t sw[4] = {sl4.x, sl4.y, sl4.z, sl4.w};
+    const uint32_t dp = sdpos[li];
+    int p = 0, ns = 0;
+#pragma unroll
+    for (int q = 0; q < kEdgeSup; ++q) {
+      const uint32_t jj = (sw[q >> 2] >> (8 * (q & 3))) & 0xffu;
+      ns += jj != kNoSlot;
+      if (jj == dp) p = q;
+    }
+    // 2^(50 - sexp) built from its exponent bits (sexp is clamped to keep it normal)
+    const double inv_u = __longlong_as_double((long long)(1023 + 50 - sexp[li]) << 52);
     const double lV = r[1] * r[0] * inv_u, mV = r[2] * r[0] * inv_u;
-    int p = 0;
-    for (int q = 0; q < kEdgeSup; ++q)
-      if (sup[q] == I) p = q;
     const Vec3 bp = {r[4 + 3 * p], r[5 + 3 * p], r[6 + 3 * p]};
     const double lbp[3] = {lV * bp.x, lV * bp.y, lV * bp.z};
     const double mbp[3] = {mV * bp.x, mV * bp.y, mV * bp.z};
     unsigned long long* rowv = sval + 9 * rb;
-    for (int q = 0; q < kEdgeSup; ++q) {
-      const int jj = sl[q];
-      if (jj == kNoSlot) break;
-      const double bqa[3] = {r[4 + 3 * q], r[5 + 3 * q], r[6 + 3 * q]};
-      const double dS = fma(mV, bp.x * bqa[0] + bp.y * bqa[1] + bp.z * bqa[2], kShift);
-      unsigned long long* dst = rowv + 3 * jj;
+    // four support nodes per step, their gradients loaded together
+    for (int q0 = 0; q0 < ns; q0 += 4) {
+      const uint32_t w4 = q0 == 0 ? sw[0] : q0 == 4 ? sw[1] : q0 == 8 ? sw[2] : sw[3];
+      double bq[4][3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u < ns ? q0 + u : q0;
+        bq[u][0] = r[4 + 3 * q];
+        bq[u][1] = r[5 + 3 * q];
+        bq[u][2] = r[6 + 3 * q];
+      }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double t = fma(lbp[a], bqa[c], fma(mbp[c], bqa[a], a == c ? dS : kShift));
-          atomicAdd(dst + a * 3 * deg + c, unshift(t));
+      for (int u = 0; u < 4; ++u) {
+        if (q0 + u >= ns) break;
+        const int jj = int((w4 >> (8 * u)) & 0xffu);
+        const double* bqa = bq[u];
+        const double dS = fma(mV, bp.x * bqa[0] + bp.y * bqa[1] + bp.z * bqa[2], kShift);
+        unsigned long long* dst = rowv + 3 * jj;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double t = fma(lbp[a], bqa[c], fma(mbp[c], bqa[a], a == c ? dS : kShift));
+            atomicAdd(dst + a * 3 * deg + c, unshift(t));
+          }
         }
       }
     }
@@ -437,18 +484,24 @@ void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_
   EdgeTopo& et = c.et;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
   et.rec.reserve(et.ne * kEdgeRec);
+  et.ebound.reserve(et.ne);
   if (c.per_tet)
     k_edge_geometry<true><<<div_up(et.ne, kB), kB, 0, c.stream>>>(
         et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), c.lam0,
-        c.mu0, c.lam_t.get(), c.mu_t.get(), et.rec.get());
+        c.mu0, c.lam_t.get(), c.mu_t.get(), et.rec.get(), et.ebound.get());
   else
     k_edge_geometry<false><<<div_up(et.ne, kB), kB, 0, c.stream>>>(
         et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), c.lam0,
-        c.mu0, nullptr, nullptr, et.rec.get());
+        c.mu0, nullptr, nullptr, et.rec.get(), et.ebound.get());
+  SFEM_HIP(hipGetLastError());
+  et.rexp.reserve(c.N);
+  k_edge_row_exp<<<div_up(c.N * kWave, kB), kB, 0, c.stream>>>(c.N, et.inc_ptr.get(),
+                                                                 et.inc.get(), et.ebound.get(),
+                                                                 et.rexp.get());
   SFEM_HIP(hipGetLastError());
   k_assemble_edge<<<tp.n_tiles, kAsmThreads, 0, c.stream>>>(
-      et.inc_ptr.get(), et.inc.get(), et.slot.get(), et.esup.get(), et.rec.get(), tp.bptr.get(),
-      tp.bcol.get(), tp.tile_first.get(), fixed, c.penalty, val_out, val32_out);
+      et.inc_ptr.get(), et.inc.get(), et.slot.get(), et.rec.get(), et.rexp.get(), tp.bptr.get(), tp.bcol.get(), tp.tile_first.get(), fixed, c.penalty,
+      val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

@@ -55,7 +55,8 @@ struct EdgeTopo {
   DBuf<uint8_t> slot;            // [n_inc][kEdgeSup] block slot of each support node
   DBuf<double> rec;              // [ne][kEdgeRec], per assembly
   DBuf<double> ebound;           // [ne] bound of one contribution of each edge, per assembly
-  DBuf<int16_t> rexp;            // [N] per-row fixed-point unit exponent, per assembly
+  DBuf<int16_t> rexp;            // [N] per-row fixed-point unit exponent (per-tet materials)
+  DBuf<float> row_eg;            // [N] per-row geometric bound factor, with the topology
 };
 
 // Row-kernel schedule: variant index (lanes per row, rows per group step)

@@ -242,12 +242,22 @@ __global__ void __launch_bounds__(kB)
   ebound[e] = (fabs(lam) + 2.0 * mu) * V * bb;
 }
 
-// Unit exponent of every node row: the largest contribution bound among the
-// row's edges is below 2^rexp (clamped so that 2^(50 - rexp) stays a normal
-// double).  One wave per row.
-__global__ void k_edge_row_exp(int64_t N, const int32_t* __restrict__ inc_ptr,
-                               const int32_t* __restrict__ inc, const double* __restrict__ ebound,
-                               int16_t* __restrict__ rexp) {
+// Exponent e with bmax < 2^e, clamped so that 2^(50 - e) stays a normal
+// double (a larger e only coarsens the unit of absurdly small rows).
+__device__ __forceinline__ int16_t edge_exponent(double bmax) {
+  const int ex = bmax > 0.0 ? ilogb(bmax) + 1 : 0;
+  return int16_t(ex < -973 ? -973 : ex);
+}
+
+// Largest edge bound among each node row's edges (one wave per row): the
+// row's unit exponent (per assembly, per-tet materials), or with the
+// topology the geometric factor max V_k max |b_q|^2, rounded up to FP32 (one
+// material: the bound is (|lam| + 2 mu) times it).
+template <bool GEO>
+__global__ void k_edge_row_bound(int64_t N, const int32_t* __restrict__ inc_ptr,
+                                 const int32_t* __restrict__ inc,
+                                 const double* __restrict__ ebound, int16_t* __restrict__ rexp,
+                                 float* __restrict__ row_eg) {
   const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (I >= N) return;
@@ -255,8 +265,14 @@ __global__ void k_edge_row_exp(int64_t N, const int32_t* __restrict__ inc_ptr,
   for (int k = inc_ptr[I] + lane; k < inc_ptr[I + 1]; k += kWave)
     bmax = fmax(bmax, ebound[inc[k]]);
   bmax = wave_max(bmax);
-  const int ex = bmax > 0.0 ? ilogb(bmax) + 1 : 0;
-  if (lane == 0) rexp[I] = int16_t(ex < -973 ? -973 : ex);
+  if (lane != 0) return;
+  if (GEO) {
+    float v = float(bmax);
+    if (double(v) < bmax) v = nextafterf(v, INFINITY);
+    row_eg[I] = v;
+  } else {
+    rexp[I] = edge_exponent(bmax);
+  }
 }
 
 // Tile assembly of the edge items (see the face assembly for the scheme and
@@ -265,7 +281,8 @@ __global__ void k_edge_row_exp(int64_t N, const int32_t* __restrict__ inc_ptr,
 __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(6)))
     k_assemble_edge(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
                     const uint8_t* __restrict__ slot, const double* __restrict__ rec,
-                    const int16_t* __restrict__ rexp, const int32_t* __restrict__ bptr,
+                    const int16_t* __restrict__ rexp, const float* __restrict__ row_eg,
+                    double F, const int32_t* __restrict__ bptr,
                     const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
                     const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
                     float* __restrict__ val32) {
@@ -290,7 +307,9 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     sptr[i] = bptr[n0 + i] - b0;
     sinc[i] = inc_ptr[n0 + i] - e0;
     if (i < nn) {
-      sexp[i] = rexp[n0 + i];
+      // per-tet materials: the exponents of this assembly; one material:
+      // F = |lam| + 2 mu times the row's geometric factor
+      sexp[i] = row_eg ? edge_exponent(F * double(row_eg[n0 + i])) : rexp[n0 + i];
       // the row's own column among its ascending block columns
       const int I = n0 + i, rb = bptr[I];
       int lo = 0, hi = bptr[I + 1] - rb - 1;
@@ -335,17 +354,10 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
       ns += jj != kNoSlot;
       if (jj == dp) p = q;
     }
-    // 2^(50 - sexp) built from its exponent bits (sexp is clamped to keep it normal)
-    const double inv_u = __longlong_as_double((long long)(1023 + 50 - sexp[li]) << 52);
-    const double lV = r[1] * r[0] * inv_u, mV = r[2] * r[0] * inv_u;
-    const Vec3 bp = {r[4 + 3 * p], r[5 + 3 * p], r[6 + 3 * p]};
-    const double lbp[3] = {lV * bp.x, lV * bp.y, lV * bp.z};
-    const double mbp[3] = {mV * bp.x, mV * bp.y, mV * bp.z};
-    unsigned long long* rowv = sval + 9 * rb;
-    // four support nodes per step, their gradients loaded together
-    for (int q0 = 0; q0 < ns; q0 += 4) {
-      const uint32_t w4 = q0 == 0 ? sw[0] : q0 == 4 ? sw[1] : q0 == 8 ? sw[2] : sw[3];
-      double bq[4][3];
+    // gradients of four support nodes per step, the first four loaded
+    // together with the row's own
+    double bq[4][3];
+    auto load_group = [&](int q0) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = q0 + u < ns ? q0 + u : q0;
@@ -353,6 +365,17 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
         bq[u][1] = r[5 + 3 * q];
         bq[u][2] = r[6 + 3 * q];
       }
+    };
+    load_group(0);  // ns >= 1: the support holds I
+    // 2^(50 - sexp) built from its exponent bits (sexp is clamped to keep it normal)
+    const double inv_u = __longlong_as_double((long long)(1023 + 50 - sexp[li]) << 52);
+    const double lV = r[1] * r[0] * inv_u, mV = r[2] * r[0] * inv_u;
+    const Vec3 bp = {r[4 + 3 * p], r[5 + 3 * p], r[6 + 3 * p]};
+    const double lbp[3] = {lV * bp.x, lV * bp.y, lV * bp.z};
+    const double mbp[3] = {mV * bp.x, mV * bp.y, mV * bp.z};
+    unsigned long long* rowv = sval + 9 * rb;
+    for (int q0 = 0;;) {
+      const uint32_t w4 = q0 == 0 ? sw[0] : q0 == 4 ? sw[1] : q0 == 8 ? sw[2] : sw[3];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (q0 + u >= ns) break;
@@ -369,6 +392,9 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
           }
         }
       }
+      q0 += 4;
+      if (q0 >= ns) break;
+      load_group(q0);
     }
   }
 
@@ -476,6 +502,18 @@ void build_edge_topology(Ctx& c) {
                                                     et.esup.get(), tp.bptr.get(), tp.bcol.get(),
                                                     et.slot.get());
   SFEM_HIP(hipGetLastError());
+  // geometric row factors of the one-material units: the edge geometry with
+  // lam = 0, mu = 1/2 makes each edge bound V_k max |b_q|^2
+  et.rec.reserve(et.ne * kEdgeRec);
+  et.ebound.reserve(et.ne);
+  k_edge_geometry<false><<<div_up(et.ne, kB), kB, 0, s>>>(
+      et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), 0.0, 0.5,
+      nullptr, nullptr, et.rec.get(), et.ebound.get());
+  SFEM_HIP(hipGetLastError());
+  et.row_eg.reserve(N);
+  k_edge_row_bound<true><<<div_up(N * kWave, kB), kB, 0, s>>>(
+      N, et.inc_ptr.get(), et.inc.get(), et.ebound.get(), nullptr, et.row_eg.get());
+  SFEM_HIP(hipGetLastError());
   SFEM_HIP(hipStreamSynchronize(s));
 }
 
@@ -494,14 +532,17 @@ void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_
         et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), c.lam0,
         c.mu0, nullptr, nullptr, et.rec.get(), et.ebound.get());
   SFEM_HIP(hipGetLastError());
-  et.rexp.reserve(c.N);
-  k_edge_row_exp<<<div_up(c.N * kWave, kB), kB, 0, c.stream>>>(c.N, et.inc_ptr.get(),
-                                                                 et.inc.get(), et.ebound.get(),
-                                                                 et.rexp.get());
-  SFEM_HIP(hipGetLastError());
+  if (c.per_tet) {
+    et.rexp.reserve(c.N);
+    k_edge_row_bound<false><<<div_up(c.N * kWave, kB), kB, 0, c.stream>>>(
+        c.N, et.inc_ptr.get(), et.inc.get(), et.ebound.get(), et.rexp.get(), nullptr);
+    SFEM_HIP(hipGetLastError());
+  }
   k_assemble_edge<<<tp.n_tiles, kAsmThreads, 0, c.stream>>>(
-      et.inc_ptr.get(), et.inc.get(), et.slot.get(), et.rec.get(), et.rexp.get(), tp.bptr.get(), tp.bcol.get(), tp.tile_first.get(), fixed, c.penalty,
-      val_out, val32_out);
+      et.inc_ptr.get(), et.inc.get(), et.slot.get(), et.rec.get(),
+      c.per_tet ? et.rexp.get() : nullptr, c.per_tet ? nullptr : et.row_eg.get(),
+      std::fabs(c.lam0) + 2.0 * c.mu0, tp.bptr.get(), tp.bcol.get(), tp.tile_first.get(), fixed,
+      c.penalty, val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

@@ -438,6 +438,13 @@ struct BatchState {
   int bw0[kNumBuckets + 1] = {0, 0, 0, 0};
   DBuf<int2> wr, mw;
   DBuf<int32_t> wmesh;
+  // the elementwise kernels' own table (fixed kVRows-row chunks per mesh),
+  // so that their workgroup count does not follow the product schedule
+  std::vector<int2> h_vr, h_mv;
+  std::vector<int32_t> h_vmesh;
+  int n_vw = 0;
+  DBuf<int2> vr, mv;
+  DBuf<int32_t> vmesh;
   DBuf<double> F, X, R, Z, P, Q, part;
   DBuf<BScal> sc;
   BScal* sc_host = nullptr;
@@ -460,7 +467,30 @@ struct BatchState {
 
 namespace {
 
+// Rows per workgroup of the elementwise kernels (p update, x/r/z update,
+// start), 12 values per row: small enough that a lone large mesh still
+// spreads over the CUs late in a solve.
+constexpr int kVRows = 64;
+
 void build_table(Ctx& c, BatchState& b) {
+  b.h_vr.clear();
+  b.h_vmesh.clear();
+  b.h_mv.assign(b.n_meshes, int2{0, 0});
+  int v = 0;
+  for (int m = 0; m < b.n_meshes; ++m) {
+    const int first = v;
+    for (int64_t r = b.node0[m]; r < b.node0[m + 1]; r += kVRows) {
+      const int64_t r1 = std::min<int64_t>(r + kVRows, b.node0[m + 1]);
+      b.h_vr.push_back(int2{int(r), int(r1)});
+      b.h_vmesh.push_back(m);
+      ++v;
+    }
+    b.h_mv[m] = int2{first, v};
+  }
+  b.n_vw = v;
+  b.vr.reserve(std::max(1, v));
+  b.vmesh.reserve(std::max(1, v));
+  b.mv.reserve(std::max(1, b.n_meshes));
   b.h_wr.clear();
   b.h_wmesh.clear();
   b.h_mw.assign(b.n_meshes, int2{0, 0});
@@ -483,12 +513,18 @@ void build_table(Ctx& c, BatchState& b) {
   b.wr.reserve(std::max(1, w));
   b.wmesh.reserve(std::max(1, w));
   b.mw.reserve(std::max(1, b.n_meshes));
-  b.part.reserve(size_t(std::max(1, w)) * 8);
+  b.part.reserve(size_t(std::max(std::max(1, w), v)) * 8);  // either table's partials
   SFEM_HIP(hipMemcpyAsync(b.wr.get(), b.h_wr.data(), sizeof(int2) * w, hipMemcpyHostToDevice,
                           c.stream));
   SFEM_HIP(hipMemcpyAsync(b.wmesh.get(), b.h_wmesh.data(), sizeof(int32_t) * w,
                           hipMemcpyHostToDevice, c.stream));
   SFEM_HIP(hipMemcpyAsync(b.mw.get(), b.h_mw.data(), sizeof(int2) * b.n_meshes,
+                          hipMemcpyHostToDevice, c.stream));
+  SFEM_HIP(hipMemcpyAsync(b.vr.get(), b.h_vr.data(), sizeof(int2) * v, hipMemcpyHostToDevice,
+                          c.stream));
+  SFEM_HIP(hipMemcpyAsync(b.vmesh.get(), b.h_vmesh.data(), sizeof(int32_t) * v,
+                          hipMemcpyHostToDevice, c.stream));
+  SFEM_HIP(hipMemcpyAsync(b.mv.get(), b.h_mv.data(), sizeof(int2) * b.n_meshes,
                           hipMemcpyHostToDevice, c.stream));
   SFEM_HIP(hipStreamSynchronize(c.stream));
   b.drop_graph();
@@ -536,22 +572,25 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
   }
 }
 
+// The partials of kBAlpha / kBReplace come from the product's table, those
+// of kBStart / kBBeta from the elementwise one.
 void bfinal(Ctx& c, BatchState& b, BOp op, double rtol2, int max_stale) {
-  k_bfinal<<<b.n_meshes, kBThreads, 0, c.stream>>>(int(op), b.mw.get(), b.part.get(), b.sc.get(),
-                                                   rtol2, max_stale);
+  const int2* map = (op == kBAlpha || op == kBReplace) ? b.mw.get() : b.mv.get();
+  k_bfinal<<<b.n_meshes, kBThreads, 0, c.stream>>>(int(op), map, b.part.get(), b.sc.get(), rtol2,
+                                                   max_stale);
   SFEM_HIP(hipGetLastError());
 }
 
 // One check period: `iters` CG iterations, then the FP64 residual
 // replacement and the convergence test (kernel launches only: capturable).
 void period(Ctx& c, BatchState& b, bool f32, int iters, double rtol2, int max_stale) {
-  const int W = b.n_wg();
+  const int V = b.n_vw;
   for (int k = 0; k < iters; ++k) {
-    k_bp<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), b.wmesh.get(), b.sc.get(), b.Z.get(),
+    k_bp<<<V, kBThreads, 0, c.stream>>>(b.vr.get(), b.vmesh.get(), b.sc.get(), b.Z.get(),
                                         b.P.get());
     bspmm<0>(c, b, f32, b.P.get(), nullptr, b.Q.get(), nullptr);
     bfinal(c, b, kBAlpha, rtol2, max_stale);
-    k_bupdate<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), b.wmesh.get(), b.sc.get(),
+    k_bupdate<<<V, kBThreads, 0, c.stream>>>(b.vr.get(), b.vmesh.get(), b.sc.get(),
                                              c.dinv.get(), b.X.get(), b.R.get(), b.Z.get(),
                                              b.P.get(), b.Q.get(), b.part.get());
     bfinal(c, b, kBBeta, rtol2, max_stale);
@@ -609,8 +648,12 @@ static std::tuple<int, int, int> tune_key(Ctx& c, BatchState& b, int bk) {
 }
 
 // Times every (lanes per row, rows per workgroup) candidate for each
-// non-empty bucket unless the bucket's shape is cached (use_cache).
-// Returns the tuned product time in microseconds (all buckets).
+// non-empty bucket unless the bucket's shape is cached (use_cache).  A
+// candidate's cost is its product time with every system active plus its
+// time with only the bucket's largest mesh active: most iterations of a
+// batched solve run with the easy meshes already retired, where the
+// workgroups of finished meshes still cost their dispatch.  Returns the
+// tuned product time in microseconds (all buckets, all active).
 double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32) {
   if (reps <= 0) reps = 5;
   pack_values64(c);  // the packed candidates read it
@@ -631,6 +674,32 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
         continue;
       }
     }
+    // the tail state: only the bucket's largest mesh active (the solve's
+    // start resets every system's scalars)
+    {
+      int big = -1;
+      int64_t rows = -1;
+      for (int m = 0; m < b.n_meshes; ++m)
+        if (b.bucket[m] == bk && b.node0[m + 1] - b.node0[m] > rows) {
+          rows = b.node0[m + 1] - b.node0[m];
+          big = m;
+        }
+      std::vector<BScal> hs(size_t(b.n_meshes) * kNR, BScal{});
+      for (int k = 0; k < kNR; ++k) hs[size_t(big) * kNR + k].active = 1;
+      SFEM_HIP(hipMemcpy(b.sc.get(), hs.data(), sizeof(BScal) * hs.size(),
+                         hipMemcpyHostToDevice));
+    }
+    auto time_product = [&](bool tail) {
+      bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, tail);  // warm
+      SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+      for (int r = 0; r < reps; ++r)
+        bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, tail);
+      SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+      SFEM_HIP(hipEventSynchronize(c.ev1));
+      float ms = 0;
+      SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+      return double(ms);
+    };
     double best = 1e30;
     int bl = b.lpr[bk], br = b.rw[bk];
     bool bp = b.packed[bk];
@@ -645,14 +714,7 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
         b.lpr[bk] = lpr;
         b.rw[bk] = kRws[ri];
         build_table(c, b);
-        bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, false);  // warm
-        SFEM_HIP(hipEventRecord(c.ev0, c.stream));
-        for (int r = 0; r < reps; ++r)
-          bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, false);
-        SFEM_HIP(hipEventRecord(c.ev1, c.stream));
-        SFEM_HIP(hipEventSynchronize(c.ev1));
-        float ms = 0;
-        SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        const double ms = time_product(false) + time_product(true);
         if (ms < best) {
           best = ms;
           bl = b.lpr[bk];
@@ -685,13 +747,13 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
 int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int check_every,
                 bool use_graph, double* ms_out) {
   SFEM_REQUIRE(!f32 || c.have_f32, SFEM_ESTATE, "the FP32 mode needs an FP32 copy of K");
-  const int W = b.n_wg();
+  const int V = b.n_vw;
   const double rtol2 = rtol * rtol;
   const int max_stale = 40;
   const int n_sys = b.n_meshes * kNR;
   if (b.packed[0] || b.packed[1] || b.packed[2]) pack_values64(c);  // before any capture
   SFEM_HIP(hipEventRecord(c.ev0, c.stream));
-  k_bstart<<<W, kBThreads, 0, c.stream>>>(b.wr.get(), c.dinv.get(), b.F.get(), b.X.get(),
+  k_bstart<<<V, kBThreads, 0, c.stream>>>(b.vr.get(), c.dinv.get(), b.F.get(), b.X.get(),
                                           b.R.get(), b.Z.get(), b.P.get(), b.part.get());
   SFEM_HIP(hipGetLastError());
   bfinal(c, b, kBStart, rtol2, max_stale);

@@ -79,22 +79,36 @@ __device__ __forceinline__ bool mesh_done(const BScal* __restrict__ sc, int m) {
   return !(s[0].active | s[1].active | s[2].active | s[3].active);
 }
 
+// The work items a launch walks: with a list, the compacted items
+// list[base + i], i < *cnt (those of meshes still active when the list was
+// made); without one, the items base + i, i < n.  A workgroup takes items
+// blockIdx.x, blockIdx.x + gridDim.x, ...
+struct Work {
+  const int32_t* __restrict__ list;
+  const int32_t* __restrict__ cnt;
+  int base, n;
+  __device__ __forceinline__ int count() const { return list ? *cnt : n; }
+  __device__ __forceinline__ int item(int i) const { return list ? list[base + i] : base + i; }
+};
+
 // Product of K with a [3N][4] panel over the node rows [wr[w].x, wr[w].y)
-// of workgroup w = wbase + blockIdx.x.
+// of each work item w.
 //   EPI 0: Y = K X, partials (x.y) per load case.
 //   EPI 1: residual replacement Y = F - K X, Z = dinv Y, partials (y.y),
 //          (y.z) per load case.
 // Partials: part[w][k][2].
 template <typename VT, int LPR, int EPI>
 __global__ void __launch_bounds__(kBThreads)
-    k_bspmm(int wbase, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+    k_bspmm(Work wk, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
             const BScal* __restrict__ sc, const int32_t* __restrict__ bptr,
             const int32_t* __restrict__ bcol, const VT* __restrict__ val,
             const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ Y,
             double* __restrict__ Z, const double* __restrict__ dinv, double* __restrict__ part) {
   constexpr int G = kBThreads / LPR;
-  const int w = wbase + blockIdx.x;
-  if (mesh_done(sc, wmesh[w])) return;
+  const int n_items = wk.count();
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  const int w = wk.item(it);
+  if (mesh_done(sc, wmesh[w])) continue;
   const int2 rr = wr[w];
   const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
   double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -162,6 +176,8 @@ __global__ void __launch_bounds__(kBThreads)
     }
   }
   block_store8(pv, part + int64_t(w) * 8);
+  __syncthreads();  // the next item reuses block_store8's shared array
+  }
 }
 
 // The same product on the packed layout of the single-system row kernels
@@ -171,14 +187,16 @@ __global__ void __launch_bounds__(kBThreads)
 // 12 panel entries of its node (6 double2 loads) for 144 FMAs.
 template <int LPR, int EPI>
 __global__ void __launch_bounds__(kBThreads)
-    k_bspmm_p(int wbase, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+    k_bspmm_p(Work wk, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
               const BScal* __restrict__ sc, const int32_t* __restrict__ ptr4,
               const int32_t* __restrict__ col4, const double* __restrict__ valp,
               const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ Y,
               double* __restrict__ Z, const double* __restrict__ dinv, double* __restrict__ part) {
   constexpr int G = kBThreads / LPR;
-  const int w = wbase + blockIdx.x;
-  if (mesh_done(sc, wmesh[w])) return;
+  const int n_items = wk.count();
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  const int w = wk.item(it);
+  if (mesh_done(sc, wmesh[w])) continue;
   const int2 rr = wr[w];
   const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
   double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -256,48 +274,93 @@ __global__ void __launch_bounds__(kBThreads)
     }
   }
   block_store8(pv, part + int64_t(w) * 8);
+  __syncthreads();  // the next item reuses block_store8's shared array
+  }
 }
 
 // p = z + beta p on active systems.
 __global__ void __launch_bounds__(kBThreads)
-    k_bp(const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+    k_bp(Work wk, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
          const BScal* __restrict__ sc, const double* __restrict__ Z, double* __restrict__ P) {
-  const int w = blockIdx.x;
-  if (mesh_done(sc, wmesh[w])) return;
-  const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
-  const BScal* s = sc + wmesh[w] * kNR;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
-    const BScal& q = s[e % kNR];
-    if (q.active) P[e] = Z[e] + q.beta * P[e];
+  const int n_items = wk.count();
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int w = wk.item(it);
+    if (mesh_done(sc, wmesh[w])) continue;
+    const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
+    const BScal* s = sc + wmesh[w] * kNR;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
+      const BScal& q = s[e % kNR];
+      if (q.active) P[e] = Z[e] + q.beta * P[e];
+    }
   }
 }
 
 // x += alpha p; r -= alpha q; z = dinv r on active systems; partials (r.z),
 // (r.r) per load case.
 __global__ void __launch_bounds__(kBThreads)
-    k_bupdate(const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
+    k_bupdate(Work wk, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
               const BScal* __restrict__ sc, const double* __restrict__ dinv,
               double* __restrict__ X, double* __restrict__ R, double* __restrict__ Z,
               const double* __restrict__ P, const double* __restrict__ Q,
               double* __restrict__ part) {
-  const int w = blockIdx.x;
-  if (mesh_done(sc, wmesh[w])) return;
-  const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
-  const BScal* s = sc + wmesh[w] * kNR;
-  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
-    const int k = int(e % kNR);
-    const BScal& q = s[k];
-    if (!q.active) continue;
-    const double r = R[e] - q.alpha * Q[e];
-    const double z = dinv[e / kNR] * r;
-    X[e] += q.alpha * P[e];
-    R[e] = r;
-    Z[e] = z;
-    pv[2 * k] += r * z;
-    pv[2 * k + 1] += r * r;
+  const int n_items = wk.count();
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int w = wk.item(it);
+    if (mesh_done(sc, wmesh[w])) continue;
+    const int64_t e0 = int64_t(wr[w].x) * 3 * kNR, e1 = int64_t(wr[w].y) * 3 * kNR;
+    const BScal* s = sc + wmesh[w] * kNR;
+    double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBThreads) {
+      const int k = int(e % kNR);
+      const BScal& q = s[k];
+      if (!q.active) continue;
+      const double r = R[e] - q.alpha * Q[e];
+      const double z = dinv[e / kNR] * r;
+      X[e] += q.alpha * P[e];
+      R[e] = r;
+      Z[e] = z;
+      pv[2 * k] += r * z;
+      pv[2 * k + 1] += r * r;
+    }
+    block_store8(pv, part + int64_t(w) * 8);
+    __syncthreads();  // the next item reuses block_store8's shared array
   }
-  block_store8(pv, part + int64_t(w) * 8);
+}
+
+// Compacted work lists of the meshes still active: block j < kNumBuckets
+// lists the product items of bucket j's active meshes (ranges mw) at
+// list[base_j], block kNumBuckets the elementwise items (ranges mv) at
+// list[base_3]; cnt[j] is the length.  Meshes in ascending order, so the
+// list is a fixed function of the masks.
+__global__ void __launch_bounds__(kBThreads)
+    k_bcompact(int n_meshes, const int32_t* __restrict__ mbucket, const int2* __restrict__ mw,
+               const int2* __restrict__ mv, const BScal* __restrict__ sc, int4 base,
+               int32_t* __restrict__ list, int32_t* __restrict__ cnt) {
+  const int j = blockIdx.x;
+  const int ob = j == 0 ? base.x : j == 1 ? base.y : j == 2 ? base.z : base.w;
+  __shared__ int wsum[kBThreads / 64];
+  __shared__ int off;
+  if (threadIdx.x == 0) off = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int m0 = 0; m0 < n_meshes; m0 += kBThreads) {
+    const int m = m0 + threadIdx.x;
+    int2 rg = {0, 0};
+    if (m < n_meshes && !mesh_done(sc, m) && (j == kNumBuckets || mbucket[m] == j))
+      rg = j == kNumBuckets ? mv[m] : mw[m];
+    const int len = rg.y - rg.x;
+    const int inc = wave_inclusive_scan(len);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int pre = off;
+    for (int q = 0; q < wid; ++q) pre += wsum[q];
+    const int ex = pre + inc - len;
+    for (int t = 0; t < len; ++t) list[ob + ex + t] = rg.x + t;
+    __syncthreads();
+    if (threadIdx.x == kBThreads - 1) off = ex + len;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[j] = off;
 }
 
 // Start from x = 0: r = f, z = dinv f, p = 0; partials (r.z), (r.r).
@@ -445,6 +508,9 @@ struct BatchState {
   int n_vw = 0;
   DBuf<int2> vr, mv;
   DBuf<int32_t> vmesh;
+  // compacted lists of the items of meshes still active (products by bucket
+  // at bw0[bk], elementwise at n_wg()), remade at the start of each period
+  DBuf<int32_t> mbucket, alist, acnt;
   DBuf<double> F, X, R, Z, P, Q, part;
   DBuf<BScal> sc;
   BScal* sc_host = nullptr;
@@ -514,6 +580,11 @@ void build_table(Ctx& c, BatchState& b) {
   b.wmesh.reserve(std::max(1, w));
   b.mw.reserve(std::max(1, b.n_meshes));
   b.part.reserve(size_t(std::max(std::max(1, w), v)) * 8);  // either table's partials
+  b.alist.reserve(size_t(std::max(1, w + v)));
+  b.acnt.reserve(kNumBuckets + 1);
+  b.mbucket.reserve(std::max(1, b.n_meshes));
+  SFEM_HIP(hipMemcpyAsync(b.mbucket.get(), b.bucket.data(), sizeof(int32_t) * b.n_meshes,
+                          hipMemcpyHostToDevice, c.stream));
   SFEM_HIP(hipMemcpyAsync(b.wr.get(), b.h_wr.data(), sizeof(int2) * w, hipMemcpyHostToDevice,
                           c.stream));
   SFEM_HIP(hipMemcpyAsync(b.wmesh.get(), b.h_wmesh.data(), sizeof(int32_t) * w,
@@ -532,6 +603,24 @@ void build_table(Ctx& c, BatchState& b) {
 
 // One product of K (FP64 or FP32 values) with a panel, bucket by bucket,
 // each with its own lanes-per-row; only_bucket >= 0 restricts to one.
+// Workgroups of a list-driven launch, at most: enough to fill the chip while
+// every mesh is active, few enough that the late iterations of a solve do
+// not pay for dispatching the retired meshes' items.
+constexpr int kBGridCap = 4096;
+
+// Remakes the lists of the items of meshes still active (kernel only:
+// capturable).
+void compact(Ctx& c, BatchState& b) {
+  const int4 base = {b.bw0[0], b.bw0[1], b.bw0[2], b.n_wg()};
+  k_bcompact<<<kNumBuckets + 1, kBThreads, 0, c.stream>>>(b.n_meshes, b.mbucket.get(),
+                                                         b.mw.get(), b.mv.get(), b.sc.get(), base,
+                                                         b.alist.get(), b.acnt.get());
+  SFEM_HIP(hipGetLastError());
+}
+
+// One product, bucket by bucket.  use_sc: over the compacted lists (made by
+// compact() from the current masks; retired meshes skipped); otherwise over
+// every item with no masks.
 template <int EPI>
 void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, double* Y,
            double* Z, int only_bucket = -1, bool use_sc = true) {
@@ -539,13 +628,16 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
     if (only_bucket >= 0 && bk != only_bucket) continue;
     const int nw = b.bw0[bk + 1] - b.bw0[bk];
     if (nw == 0) continue;
+    const Work wk{use_sc ? b.alist.get() : nullptr, use_sc ? b.acnt.get() + bk : nullptr,
+                  b.bw0[bk], nw};
+    const int grid = use_sc ? std::min(nw, kBGridCap) : nw;
 #define L_(VT, VAL, LPR)                                                                   \
-  k_bspmm<VT, LPR, EPI><<<nw, kBThreads, 0, c.stream>>>(                                  \
-      b.bw0[bk], b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(), \
+  k_bspmm<VT, LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                \
+      wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(),     \
       c.topo.bcol.get(), VAL, X, F, Y, Z, c.dinv.get(), b.part.get())
 #define P_(LPR)                                                                              \
-  k_bspmm_p<LPR, EPI><<<nw, kBThreads, 0, c.stream>>>(                                      \
-      b.bw0[bk], b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.ptr4.get(),     \
+  k_bspmm_p<LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                    \
+      wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.ptr4.get(),           \
       c.col4.get(), c.valp.get(), X, F, Y, Z, c.dinv.get(), b.part.get())
     if (f32 && b.packed[bk]) {
       L_(float, c.val32.get(), 16);  // FP32 values keep the CSR order
@@ -585,12 +677,15 @@ void bfinal(Ctx& c, BatchState& b, BOp op, double rtol2, int max_stale) {
 // replacement and the convergence test (kernel launches only: capturable).
 void period(Ctx& c, BatchState& b, bool f32, int iters, double rtol2, int max_stale) {
   const int V = b.n_vw;
+  const Work vk{b.alist.get(), b.acnt.get() + kNumBuckets, b.n_wg(), V};
+  const int vgrid = std::min(V, kBGridCap);
+  compact(c, b);
   for (int k = 0; k < iters; ++k) {
-    k_bp<<<V, kBThreads, 0, c.stream>>>(b.vr.get(), b.vmesh.get(), b.sc.get(), b.Z.get(),
-                                        b.P.get());
+    k_bp<<<vgrid, kBThreads, 0, c.stream>>>(vk, b.vr.get(), b.vmesh.get(), b.sc.get(), b.Z.get(),
+                                            b.P.get());
     bspmm<0>(c, b, f32, b.P.get(), nullptr, b.Q.get(), nullptr);
     bfinal(c, b, kBAlpha, rtol2, max_stale);
-    k_bupdate<<<V, kBThreads, 0, c.stream>>>(b.vr.get(), b.vmesh.get(), b.sc.get(),
+    k_bupdate<<<vgrid, kBThreads, 0, c.stream>>>(vk, b.vr.get(), b.vmesh.get(), b.sc.get(),
                                              c.dinv.get(), b.X.get(), b.R.get(), b.Z.get(),
                                              b.P.get(), b.Q.get(), b.part.get());
     bfinal(c, b, kBBeta, rtol2, max_stale);
@@ -654,8 +749,17 @@ static std::tuple<int, int, int> tune_key(Ctx& c, BatchState& b, int bk) {
 // batched solve run with the easy meshes already retired, where the
 // workgroups of finished meshes still cost their dispatch.  Returns the
 // tuned product time in microseconds (all buckets, all active).
+// Uploads per-system scalars whose only meaningful field is the active flag
+// (tuning; a solve's start resets every system's scalars).
+static void set_masks(Ctx& c, BatchState& b, const std::vector<BScal>& mask) {
+  SFEM_HIP(hipMemcpyAsync(b.sc.get(), mask.data(), sizeof(BScal) * mask.size(),
+                          hipMemcpyHostToDevice, c.stream));
+}
+
 double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32) {
   if (reps <= 0) reps = 5;
+  std::vector<BScal> all_mask(size_t(b.n_meshes) * kNR, BScal{});
+  for (auto& q : all_mask) q.active = 1;
   pack_values64(c);  // the packed candidates read it
   SFEM_HIP(hipStreamSynchronize(c.stream));
   for (int bk = 0; bk < kNumBuckets; ++bk) {
@@ -674,8 +778,8 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
         continue;
       }
     }
-    // the tail state: only the bucket's largest mesh active (the solve's
-    // start resets every system's scalars)
+    // the tail state: only the bucket's largest mesh active
+    std::vector<BScal> tail_mask(size_t(b.n_meshes) * kNR, BScal{});
     {
       int big = -1;
       int64_t rows = -1;
@@ -684,16 +788,16 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
           rows = b.node0[m + 1] - b.node0[m];
           big = m;
         }
-      std::vector<BScal> hs(size_t(b.n_meshes) * kNR, BScal{});
-      for (int k = 0; k < kNR; ++k) hs[size_t(big) * kNR + k].active = 1;
-      SFEM_HIP(hipMemcpy(b.sc.get(), hs.data(), sizeof(BScal) * hs.size(),
-                         hipMemcpyHostToDevice));
+      for (int k = 0; k < kNR; ++k) tail_mask[size_t(big) * kNR + k].active = 1;
     }
-    auto time_product = [&](bool tail) {
-      bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, tail);  // warm
+    // the bucket's product over the lists compacted from a mask, as in a solve
+    auto time_product = [&](const std::vector<BScal>& mask) {
+      set_masks(c, b, mask);
+      compact(c, b);
+      bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk);  // warm
       SFEM_HIP(hipEventRecord(c.ev0, c.stream));
       for (int r = 0; r < reps; ++r)
-        bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk, tail);
+        bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, bk);
       SFEM_HIP(hipEventRecord(c.ev1, c.stream));
       SFEM_HIP(hipEventSynchronize(c.ev1));
       float ms = 0;
@@ -714,7 +818,7 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
         b.lpr[bk] = lpr;
         b.rw[bk] = kRws[ri];
         build_table(c, b);
-        const double ms = time_product(false) + time_product(true);
+        const double ms = time_product(all_mask) + time_product(tail_mask);
         if (ms < best) {
           best = ms;
           bl = b.lpr[bk];
@@ -730,11 +834,13 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
     g_tune_cache[key] = {bp ? -bl : bl, br};
   }
   build_table(c, b);
-  // time the tuned product over all buckets
-  bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, -1, false);
+  // time the tuned product over all buckets, every system active
+  set_masks(c, b, all_mask);
+  compact(c, b);
+  bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, -1);
   SFEM_HIP(hipEventRecord(c.ev0, c.stream));
   for (int r = 0; r < reps; ++r)
-    bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, -1, false);
+    bspmm<0>(c, b, f32, b.F.get(), nullptr, b.Q.get(), nullptr, -1);
   SFEM_HIP(hipEventRecord(c.ev1, c.stream));
   SFEM_HIP(hipEventSynchronize(c.ev1));
   float ms = 0;

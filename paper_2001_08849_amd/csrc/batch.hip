@@ -107,76 +107,76 @@ __global__ void __launch_bounds__(kBThreads)
   constexpr int G = kBThreads / LPR;
   const int n_items = wk.count();
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-  const int w = wk.item(it);
-  if (mesh_done(sc, wmesh[w])) continue;
-  const int2 rr = wr[w];
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
-  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int I0 = rr.x; I0 < rr.y; I0 += G) {
-    const int I = I0 + g;
-    const bool valid = I < rr.y;
-    int rb = 0, deg = 0;
-    if (valid) {
-      rb = bptr[I];
-      deg = bptr[I + 1] - rb;
-    }
-    const int td = 3 * deg;
-    const VT* v = val + 9 * int64_t(rb);
-    double acc[3][kNR];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
-    // kCU columns per step (masked past the row), so each lane keeps kCU
-    // columns' loads in flight
-    for (int c0 = sub; c0 < td; c0 += kCU * LPR) {
-#pragma unroll
-      for (int h = 0; h < kCU; ++h) {
-        const int c = c0 + h * LPR;
-        const bool in = c < td;
-        const int cc = in ? c : c0;
-        const int jj = cc / 3;
-        const int64_t col = 3 * int64_t(bcol[rb + jj]) + (cc - 3 * jj);
-        const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
-        const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
-        const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
-        const double m = in ? 1.0 : 0.0;
-        const double a3[3] = {m * double(v[cc]), m * double(v[td + cc]),
-                              m * double(v[2 * td + cc])};
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int k = 0; k < kNR; ++k) acc[a][k] += a3[a] * x4[k];
+    const int w = wk.item(it);
+    if (mesh_done(sc, wmesh[w])) continue;
+    const int2 rr = wr[w];
+    const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+    double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int I0 = rr.x; I0 < rr.y; I0 += G) {
+      const int I = I0 + g;
+      const bool valid = I < rr.y;
+      int rb = 0, deg = 0;
+      if (valid) {
+        rb = bptr[I];
+        deg = bptr[I + 1] - rb;
       }
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
-    if (valid && sub == 0) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * int64_t(I) + a;
-#pragma unroll
-        for (int k = 0; k < kNR; ++k) {
-          const int64_t e = i * kNR + k;
-          if constexpr (EPI == 0) {
-            Y[e] = acc[a][k];
-            pv[2 * k] += X[e] * acc[a][k];
-          } else {
-            const double r = F[e] - acc[a][k];
-            const double z = dinv[i] * r;
-            Y[e] = r;
-            Z[e] = z;
-            pv[2 * k] += r * r;
-            pv[2 * k + 1] += r * z;
+      const int td = 3 * deg;
+      const VT* v = val + 9 * int64_t(rb);
+      double acc[3][kNR];
+  #pragma unroll
+      for (int a = 0; a < 3; ++a)
+  #pragma unroll
+        for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
+      // kCU columns per step (masked past the row), so each lane keeps kCU
+      // columns' loads in flight
+      for (int c0 = sub; c0 < td; c0 += kCU * LPR) {
+  #pragma unroll
+        for (int h = 0; h < kCU; ++h) {
+          const int c = c0 + h * LPR;
+          const bool in = c < td;
+          const int cc = in ? c : c0;
+          const int jj = cc / 3;
+          const int64_t col = 3 * int64_t(bcol[rb + jj]) + (cc - 3 * jj);
+          const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
+          const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
+          const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
+          const double m = in ? 1.0 : 0.0;
+          const double a3[3] = {m * double(v[cc]), m * double(v[td + cc]),
+                                m * double(v[2 * td + cc])};
+  #pragma unroll
+          for (int a = 0; a < 3; ++a)
+  #pragma unroll
+            for (int k = 0; k < kNR; ++k) acc[a][k] += a3[a] * x4[k];
+        }
+      }
+  #pragma unroll
+      for (int a = 0; a < 3; ++a)
+  #pragma unroll
+        for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
+      if (valid && sub == 0) {
+  #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t i = 3 * int64_t(I) + a;
+  #pragma unroll
+          for (int k = 0; k < kNR; ++k) {
+            const int64_t e = i * kNR + k;
+            if constexpr (EPI == 0) {
+              Y[e] = acc[a][k];
+              pv[2 * k] += X[e] * acc[a][k];
+            } else {
+              const double r = F[e] - acc[a][k];
+              const double z = dinv[i] * r;
+              Y[e] = r;
+              Z[e] = z;
+              pv[2 * k] += r * r;
+              pv[2 * k + 1] += r * z;
+            }
           }
         }
       }
     }
-  }
-  block_store8(pv, part + int64_t(w) * 8);
-  __syncthreads();  // the next item reuses block_store8's shared array
+    block_store8(pv, part + int64_t(w) * 8);
+    __syncthreads();  // the next item reuses block_store8's shared array
   }
 }
 
@@ -195,86 +195,86 @@ __global__ void __launch_bounds__(kBThreads)
   constexpr int G = kBThreads / LPR;
   const int n_items = wk.count();
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-  const int w = wk.item(it);
-  if (mesh_done(sc, wmesh[w])) continue;
-  const int2 rr = wr[w];
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
-  double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int I0 = rr.x; I0 < rr.y; I0 += G) {
-    const int I = I0 + g;
-    const bool valid = I < rr.y;
-    int r4 = 0, d4 = 0;
-    if (valid) {
-      r4 = ptr4[I];
-      d4 = ptr4[I + 1] - r4;
-    }
-    const double* wv = valp + 9 * int64_t(r4);
-    double acc[3][kNR];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
-    for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
-      const int4 J = *reinterpret_cast<const int4*>(col4 + r4 + jb);
-      double m[9][4];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const double2 lo = *reinterpret_cast<const double2*>(wv + q * d4 + jb);
-        const double2 hi = *reinterpret_cast<const double2*>(wv + q * d4 + jb + 2);
-        m[q][0] = lo.x;
-        m[q][1] = lo.y;
-        m[q][2] = hi.x;
-        m[q][3] = hi.y;
+    const int w = wk.item(it);
+    if (mesh_done(sc, wmesh[w])) continue;
+    const int2 rr = wr[w];
+    const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+    double pv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int I0 = rr.x; I0 < rr.y; I0 += G) {
+      const int I = I0 + g;
+      const bool valid = I < rr.y;
+      int r4 = 0, d4 = 0;
+      if (valid) {
+        r4 = ptr4[I];
+        d4 = ptr4[I + 1] - r4;
       }
-      const int Js[4] = {J.x, J.y, J.z, J.w};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const double2* xp = reinterpret_cast<const double2*>(X + 12 * int64_t(Js[t]));
-        double x[3][kNR];
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          const double2 a = xp[2 * cc], b = xp[2 * cc + 1];
-          x[cc][0] = a.x;
-          x[cc][1] = a.y;
-          x[cc][2] = b.x;
-          x[cc][3] = b.y;
+      const double* wv = valp + 9 * int64_t(r4);
+      double acc[3][kNR];
+  #pragma unroll
+      for (int a = 0; a < 3; ++a)
+  #pragma unroll
+        for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
+      for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
+        const int4 J = *reinterpret_cast<const int4*>(col4 + r4 + jb);
+        double m[9][4];
+  #pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const double2 lo = *reinterpret_cast<const double2*>(wv + q * d4 + jb);
+          const double2 hi = *reinterpret_cast<const double2*>(wv + q * d4 + jb + 2);
+          m[q][0] = lo.x;
+          m[q][1] = lo.y;
+          m[q][2] = hi.x;
+          m[q][3] = hi.y;
         }
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-            for (int k = 0; k < kNR; ++k) acc[a][k] += m[3 * a + cc][t] * x[cc][k];
+        const int Js[4] = {J.x, J.y, J.z, J.w};
+  #pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double2* xp = reinterpret_cast<const double2*>(X + 12 * int64_t(Js[t]));
+          double x[3][kNR];
+  #pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            const double2 a = xp[2 * cc], b = xp[2 * cc + 1];
+            x[cc][0] = a.x;
+            x[cc][1] = a.y;
+            x[cc][2] = b.x;
+            x[cc][3] = b.y;
+          }
+  #pragma unroll
+          for (int a = 0; a < 3; ++a)
+  #pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+  #pragma unroll
+              for (int k = 0; k < kNR; ++k) acc[a][k] += m[3 * a + cc][t] * x[cc][k];
+        }
       }
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
-    if (valid && sub == 0) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * int64_t(I) + a;
-#pragma unroll
-        for (int k = 0; k < kNR; ++k) {
-          const int64_t e = i * kNR + k;
-          if constexpr (EPI == 0) {
-            Y[e] = acc[a][k];
-            pv[2 * k] += X[e] * acc[a][k];
-          } else {
-            const double r = F[e] - acc[a][k];
-            const double z = dinv[i] * r;
-            Y[e] = r;
-            Z[e] = z;
-            pv[2 * k] += r * r;
-            pv[2 * k + 1] += r * z;
+  #pragma unroll
+      for (int a = 0; a < 3; ++a)
+  #pragma unroll
+        for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
+      if (valid && sub == 0) {
+  #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t i = 3 * int64_t(I) + a;
+  #pragma unroll
+          for (int k = 0; k < kNR; ++k) {
+            const int64_t e = i * kNR + k;
+            if constexpr (EPI == 0) {
+              Y[e] = acc[a][k];
+              pv[2 * k] += X[e] * acc[a][k];
+            } else {
+              const double r = F[e] - acc[a][k];
+              const double z = dinv[i] * r;
+              Y[e] = r;
+              Z[e] = z;
+              pv[2 * k] += r * r;
+              pv[2 * k + 1] += r * z;
+            }
           }
         }
       }
     }
-  }
-  block_store8(pv, part + int64_t(w) * 8);
-  __syncthreads();  // the next item reuses block_store8's shared array
+    block_store8(pv, part + int64_t(w) * 8);
+    __syncthreads();  // the next item reuses block_store8's shared array
   }
 }
 

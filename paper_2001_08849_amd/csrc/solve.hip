@@ -485,8 +485,10 @@ __global__ void k_rh(int64_t n, const P* __restrict__ s, const P* __restrict__ r
 // previous z.  sc == nullptr: run unconditionally (start and replacement).
 constexpr int kMLanes = 8;  // lanes per node row: 32 blocks per step
 
+// 128 VGPRs at most: 4 waves per SIMD (unconstrained it takes 131, i.e. 3
+// waves, and runs ~4% slower).
 template <typename P>
-__global__ void __launch_bounds__(kRowWaves * kWave)
+__global__ void __launch_bounds__(kRowWaves * kWave) __attribute__((amdgpu_waves_per_eu(4)))
     k_mapply(int64_t N, const int32_t* __restrict__ ptr4, const int32_t* __restrict__ col4,
              const __bf16* __restrict__ mvalp, const P* __restrict__ s, const P* __restrict__ r,
              const P* __restrict__ rh, P* __restrict__ z, const CgScalars* __restrict__ sc,

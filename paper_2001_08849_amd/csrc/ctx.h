@@ -48,6 +48,7 @@ struct EdgeTopo {
   int64_t ne = 0;                // edges
   int64_t n_inc = 0;             // (node, edge) incidences: sum of support sizes
   int max_inc = 0;               // most edge domains holding one node
+  int max_sup = 0;               // largest support of an edge domain
   DBuf<int32_t> etab;            // [ne][4]: a < b, first entry, tet count
   DBuf<uint64_t> ent;            // tet entries (b << 32 | tet), grouped by edge
   DBuf<int32_t> esup;            // [ne][kEdgeSup] support nodes ascending, -1 padded

@@ -122,14 +122,15 @@ __global__ void k_edge_support(int64_t ne, const int32_t* __restrict__ etab,
   }
 }
 
-// Support size of every edge.
+// Support size of every edge, and the largest (atomicMax into *max_sup).
 __global__ void k_edge_nsup(int64_t ne, const int32_t* __restrict__ esup,
-                            int32_t* __restrict__ nsup) {
+                            int32_t* __restrict__ nsup, int32_t* __restrict__ max_sup) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   int n = 0;
   for (int q = 0; q < kEdgeSup; ++q) n += esup[e * kEdgeSup + q] >= 0;
   nsup[e] = n;
+  atomicMax(max_sup, n);
 }
 
 // Incidence entries: one per support node, at ofs[e] + q (no padding
@@ -181,7 +182,7 @@ __global__ void k_edge_slots(int64_t N, const int32_t* __restrict__ inc_ptr,
 // (past the support the record is not written and never read); and in a
 // compact array of its own the bound (|lam| + 2 mu) V_k max |b_q|^2 of one
 // contribution of the edge.
-template <bool HET>
+template <bool HET, int SUP>
 __global__ void __launch_bounds__(kB)
     k_edge_geometry(int64_t ne, const int32_t* __restrict__ etab,
                     const uint64_t* __restrict__ ent, const int32_t* __restrict__ esup,
@@ -192,12 +193,12 @@ __global__ void __launch_bounds__(kB)
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int first = etab[4 * e + 2], cnt = etab[4 * e + 3];
-  int sup[kEdgeSup];
+  int sup[SUP];
 #pragma unroll
-  for (int q = 0; q < kEdgeSup; ++q) sup[q] = esup[e * kEdgeSup + q];
-  double b[kEdgeSup][3];
+  for (int q = 0; q < SUP; ++q) sup[q] = esup[e * kEdgeSup + q];
+  double b[SUP][3];
 #pragma unroll
-  for (int q = 0; q < kEdgeSup; ++q) b[q][0] = b[q][1] = b[q][2] = 0.0;
+  for (int q = 0; q < SUP; ++q) b[q][0] = b[q][1] = b[q][2] = 0.0;
   double V = 0.0, lw = 0.0, mw = 0.0;
   for (int i = 0; i < cnt; ++i) {
     const int64_t t = int64_t(uint32_t(ent[first + i]));
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(kB)
     }
     const int vv[4] = {v0, v1, v2, v3};
 #pragma unroll
-    for (int q = 0; q < kEdgeSup; ++q)
+    for (int q = 0; q < SUP; ++q)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (sup[q] == vv[k]) {
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(kB)
   double* out = rec + e * kEdgeRec;
   double bb = 0.0;
 #pragma unroll
-  for (int q = 0; q < kEdgeSup; ++q) {
+  for (int q = 0; q < SUP; ++q) {
     const double x = b[q][0] * iV, y = b[q][1] * iV, z = b[q][2] * iV;
     if (sup[q] >= 0) {  // the support is -1 padded at its end
       out[4 + 3 * q] = x;
@@ -439,6 +440,29 @@ T read1(const T* d, hipStream_t s) {
 
 }  // namespace
 
+// Edge records and bounds (per-tet materials from c.lam_t / c.mu_t when
+// het).  Every support of these meshes fits 8 slots, the kernel tracks
+// only 8 (half the accumulators); otherwise all 16.
+static void edge_geometry(Ctx& c, hipStream_t s, bool het, double lam0, double mu0) {
+  EdgeTopo& et = c.et;
+  const double* lt = het ? c.lam_t.get() : nullptr;
+  const double* mt = het ? c.mu_t.get() : nullptr;
+#define G_(H, S)                                                                                \
+  k_edge_geometry<H, S><<<div_up(et.ne, kB), kB, 0, s>>>(et.ne, et.etab.get(), et.ent.get(),    \
+                                                         et.esup.get(), c.tets.get(),          \
+                                                         c.xyz.get(), lam0, mu0, lt, mt,       \
+                                                         et.rec.get(), et.ebound.get())
+  if (het) {
+    if (et.max_sup <= 8) G_(true, 8);
+    else G_(true, kEdgeSup);
+  } else {
+    if (et.max_sup <= 8) G_(false, 8);
+    else G_(false, kEdgeSup);
+  }
+#undef G_
+  SFEM_HIP(hipGetLastError());
+}
+
 void build_edge_topology(Ctx& c) {
   hipStream_t s = c.stream;
   EdgeTopo& et = c.et;
@@ -480,8 +504,10 @@ void build_edge_topology(Ctx& c) {
   DBuf<uint32_t> iv;
   nsup.reserve(et.ne + 1);
   sofs.reserve(et.ne + 1);
-  k_edge_nsup<<<div_up(et.ne, kB), kB, 0, s>>>(et.ne, et.esup.get(), nsup.get());
+  k_fill<<<1, 64, 0, s>>>(1, err.get(), 0);  // reused for the largest support
+  k_edge_nsup<<<div_up(et.ne, kB), kB, 0, s>>>(et.ne, et.esup.get(), nsup.get(), err.get());
   SFEM_HIP(hipGetLastError());
+  et.max_sup = read1(err.get(), s);
   exclusive_scan_i32(nsup.get(), sofs.get(), et.ne, s);
   const int64_t ni = read1(sofs.get() + et.ne, s);
   ib.reserve(ni);
@@ -506,10 +532,7 @@ void build_edge_topology(Ctx& c) {
   // lam = 0, mu = 1/2 makes each edge bound V_k max |b_q|^2
   et.rec.reserve(et.ne * kEdgeRec);
   et.ebound.reserve(et.ne);
-  k_edge_geometry<false><<<div_up(et.ne, kB), kB, 0, s>>>(
-      et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), 0.0, 0.5,
-      nullptr, nullptr, et.rec.get(), et.ebound.get());
-  SFEM_HIP(hipGetLastError());
+  edge_geometry(c, s, false, 0.0, 0.5);
   et.row_eg.reserve(N);
   k_edge_row_bound<true><<<div_up(N * kWave, kB), kB, 0, s>>>(
       N, et.inc_ptr.get(), et.inc.get(), et.ebound.get(), nullptr, et.row_eg.get());
@@ -523,15 +546,7 @@ void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
   et.rec.reserve(et.ne * kEdgeRec);
   et.ebound.reserve(et.ne);
-  if (c.per_tet)
-    k_edge_geometry<true><<<div_up(et.ne, kB), kB, 0, c.stream>>>(
-        et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), c.lam0,
-        c.mu0, c.lam_t.get(), c.mu_t.get(), et.rec.get(), et.ebound.get());
-  else
-    k_edge_geometry<false><<<div_up(et.ne, kB), kB, 0, c.stream>>>(
-        et.ne, et.etab.get(), et.ent.get(), et.esup.get(), c.tets.get(), c.xyz.get(), c.lam0,
-        c.mu0, nullptr, nullptr, et.rec.get(), et.ebound.get());
-  SFEM_HIP(hipGetLastError());
+  edge_geometry(c, c.stream, c.per_tet, c.lam0, c.mu0);
   if (c.per_tet) {
     et.rexp.reserve(c.N);
     k_edge_row_bound<false><<<div_up(c.N * kWave, kB), kB, 0, c.stream>>>(

@@ -66,6 +66,40 @@ def test_matches_oracle(S, case, het):
     assert ek <= 1e-12 and ekb <= 1e-12 and info["converged"] and eu <= 1e-8
 
 
+def fan_mesh(n=10, seed=0):
+    """n tets around the edge (0,0,0)-(0,0,1) through a jittered ring: that
+    edge's domain has a support of n + 2 nodes (structured meshes reach 8)."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * (np.arange(n) + rng.uniform(-0.2, 0.2, n)) / n
+    rad = rng.uniform(0.8, 1.2, n)
+    ring = np.stack([rad * np.cos(ang), rad * np.sin(ang), 0.5 + rng.uniform(-0.1, 0.1, n)], 1)
+    xyz = np.vstack([[0.0, 0.0, 0.0], [0.0, 0.0, 1.0], ring])
+    tets = np.array([[0, 1, 2 + i, 2 + (i + 1) % n] for i in range(n)], np.int32)
+    return xyz, tets
+
+
+@pytest.mark.parametrize("het", [False, True])
+def test_wide_edge_support_matches_oracle(S, het):
+    """A 12-node edge support: the geometry pass then tracks all 16 slots."""
+    xyz, tets = fan_mesh()
+    E, nu = 2.1e11, 0.3
+    if het:
+        rng = np.random.default_rng(5)
+        E = 10.0 ** rng.uniform(9, 11, len(tets))
+        nu = rng.uniform(0.2, 0.45, len(tets))
+    c = S.Context(0)
+    c.set_smoothing_domain(S.DOMAIN_EDGE)
+    c.set_mesh(xyz, tets)
+    c.set_material(E, nu)
+    c.assemble()
+    K = ES.assemble(xyz, tets, E, nu)
+    rp, ci, va = c.csr(S.K_UNCONSTRAINED)
+    assert np.array_equal(rp, K.indptr) and np.array_equal(ci, K.indices)
+    ek = row_rel_err(rp, va, K)
+    print(f"fan mesh ({'per-tet' if het else 'homogeneous'}): K error {ek:.2e}")
+    assert ek <= 1e-12
+
+
 def test_c2_sampled_rows_and_solve(S):
     p = mg.cantilever_c2()
     m = p.mesh

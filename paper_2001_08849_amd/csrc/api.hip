@@ -73,15 +73,13 @@ __global__ void k_check_index(const int32_t* idx, int64_t n, int64_t lim, int32_
 
 bool indices_ok(Ctx& c, const int32_t* dev_idx, int64_t n, int64_t lim) {
   if (n == 0) return true;
-  int32_t* err = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), c.stream));
-  SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c.stream));
-  k_check_index<<<sfem::div_up(n, 256), 256, 0, c.stream>>>(dev_idx, n, lim, err);
+  sfem::TmpBuf<int32_t> err(1, c.stream);
+  SFEM_HIP(hipMemsetAsync(err.get(), 0, sizeof(int32_t), c.stream));
+  k_check_index<<<sfem::div_up(n, 256), 256, 0, c.stream>>>(dev_idx, n, lim, err.get());
   SFEM_HIP(hipGetLastError());
   int32_t h = 0;
-  SFEM_HIP(hipMemcpyAsync(&h, err, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  SFEM_HIP(hipMemcpyAsync(&h, err.get(), sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
   SFEM_HIP(hipStreamSynchronize(c.stream));
-  SFEM_HIP(hipFreeAsync(err, c.stream));
   return h == 0;
 }
 
@@ -273,25 +271,19 @@ int sfem_set_material(sfem_ctx* h, double E, double nu) {
 int sfem_set_material_per_tet(sfem_ctx* h, const double* E, const double* nu, int ptr_kind) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
-    double *dE = nullptr, *dn = nullptr;
-    int32_t* err = nullptr;
-    SFEM_HIP(hipMallocAsync((void**)&dE, sizeof(double) * c.T, c.stream));
-    SFEM_HIP(hipMallocAsync((void**)&dn, sizeof(double) * c.T, c.stream));
-    SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), c.stream));
-    SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c.stream));
+    sfem::TmpBuf<double> dE(c.T, c.stream), dn(c.T, c.stream);
+    sfem::TmpBuf<int32_t> err(1, c.stream);
+    SFEM_HIP(hipMemsetAsync(err.get(), 0, sizeof(int32_t), c.stream));
     c.lam_t.reserve(c.T);
     c.mu_t.reserve(c.T);
-    upload(c, dE, E, c.T, ptr_kind);
-    upload(c, dn, nu, c.T, ptr_kind);
-    k_lame<<<sfem::div_up(c.T, 256), 256, 0, c.stream>>>(c.T, dE, dn, c.lam_t.get(), c.mu_t.get(),
-                                                          err);
+    upload(c, dE.get(), E, c.T, ptr_kind);
+    upload(c, dn.get(), nu, c.T, ptr_kind);
+    k_lame<<<sfem::div_up(c.T, 256), 256, 0, c.stream>>>(c.T, dE.get(), dn.get(), c.lam_t.get(),
+                                                          c.mu_t.get(), err.get());
     SFEM_HIP(hipGetLastError());
     int32_t he = 0;
-    SFEM_HIP(hipMemcpyAsync(&he, err, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    SFEM_HIP(hipMemcpyAsync(&he, err.get(), sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
     SFEM_HIP(hipStreamSynchronize(c.stream));
-    SFEM_HIP(hipFreeAsync(dE, c.stream));
-    SFEM_HIP(hipFreeAsync(dn, c.stream));
-    SFEM_HIP(hipFreeAsync(err, c.stream));
     SFEM_REQUIRE(he == 0, SFEM_EINVAL, "need E > 0 and -1 < nu < 0.5 for every tet");
     c.per_tet = true;
     c.have_material = true;
@@ -305,30 +297,23 @@ int sfem_set_dirichlet(sfem_ctx* h, int64_t n, const int32_t* dof, const double*
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
     SFEM_REQUIRE(n >= 0, SFEM_EINVAL, "negative count");
-    int32_t* ddof = nullptr;
-    double* dval = nullptr;
-    int32_t* flags = nullptr;
-    SFEM_HIP(hipMallocAsync((void**)&ddof, sizeof(int32_t) * (n ? n : 1), c.stream));
-    SFEM_HIP(hipMallocAsync((void**)&dval, sizeof(double) * (n ? n : 1), c.stream));
-    SFEM_HIP(hipMallocAsync((void**)&flags, sizeof(int32_t) * 4, c.stream));
-    SFEM_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, c.stream));
-    upload(c, ddof, dof, n, ptr_kind);
-    if (value) upload(c, dval, value, n, ptr_kind);
-    const bool ok = indices_ok(c, ddof, n, c.n_dof());
+    sfem::TmpBuf<int32_t> ddof(n, c.stream), flags(4, c.stream);
+    sfem::TmpBuf<double> dval(n, c.stream);
+    SFEM_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int32_t) * 4, c.stream));
+    upload(c, ddof.get(), dof, n, ptr_kind);
+    if (value) upload(c, dval.get(), value, n, ptr_kind);
+    const bool ok = indices_ok(c, ddof.get(), n, c.n_dof());
     if (ok) {
       SFEM_HIP(hipMemsetAsync(c.fixed.get(), 0, c.n_dof(), c.stream));
       SFEM_HIP(hipMemsetAsync(c.ubar.get(), 0, c.n_dof() * sizeof(double), c.stream));
       if (n)
-        k_set_fixed<<<sfem::div_up(n, 256), 256, 0, c.stream>>>(n, ddof, value ? dval : nullptr,
-                                                                 c.fixed.get(), c.ubar.get(), flags);
+        k_set_fixed<<<sfem::div_up(n, 256), 256, 0, c.stream>>>(
+            n, ddof.get(), value ? dval.get() : nullptr, c.fixed.get(), c.ubar.get(), flags.get());
       SFEM_HIP(hipGetLastError());
     }
     int32_t hf[4] = {0, 0, 0, 0};
-    SFEM_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c.stream));
+    SFEM_HIP(hipMemcpyAsync(hf, flags.get(), sizeof(hf), hipMemcpyDeviceToHost, c.stream));
     SFEM_HIP(hipStreamSynchronize(c.stream));
-    SFEM_HIP(hipFreeAsync(ddof, c.stream));
-    SFEM_HIP(hipFreeAsync(dval, c.stream));
-    SFEM_HIP(hipFreeAsync(flags, c.stream));
     SFEM_REQUIRE(ok, SFEM_EINVAL, "Dirichlet DOF index out of range");
     c.any_fixed = n > 0;
     c.any_nonzero_bc = hf[0] != 0;
@@ -360,16 +345,9 @@ int sfem_add_traction(sfem_ctx* h, int64_t n_tri, const int32_t* tri, const doub
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
     SFEM_REQUIRE(n_tri >= 0 && t && (tri || n_tri == 0), SFEM_EINVAL, "bad traction arguments");
     if (n_tri == 0) return SFEM_OK;
-    int32_t* dtri = nullptr;
-    SFEM_HIP(hipMallocAsync((void**)&dtri, sizeof(int32_t) * 3 * n_tri, c.stream));
-    upload(c, dtri, tri, 3 * n_tri, ptr_kind);
-    try {
-      sfem::traction_load(c, n_tri, dtri, t);
-    } catch (...) {
-      (void)hipFreeAsync(dtri, c.stream);
-      throw;
-    }
-    SFEM_HIP(hipFreeAsync(dtri, c.stream));
+    sfem::TmpBuf<int32_t> dtri(3 * n_tri, c.stream);
+    upload(c, dtri.get(), tri, 3 * n_tri, ptr_kind);
+    sfem::traction_load(c, n_tri, dtri.get(), t);
     c.assembled = false;
     return SFEM_OK;
   });

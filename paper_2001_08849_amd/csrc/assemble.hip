@@ -609,30 +609,21 @@ void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t
   if (n_tri <= 0) return;
   hipStream_t s = c.stream;
   const int B = 256;
-  int32_t *bucket = nullptr, *ptr = nullptr, *err = nullptr;
-  uint32_t *vals = nullptr, *sorted = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&bucket, sizeof(int32_t) * 3 * n_tri, s));
-  SFEM_HIP(hipMallocAsync((void**)&vals, sizeof(uint32_t) * 3 * n_tri, s));
-  SFEM_HIP(hipMallocAsync((void**)&sorted, sizeof(uint32_t) * 3 * n_tri, s));
-  SFEM_HIP(hipMallocAsync((void**)&ptr, sizeof(int32_t) * (c.N + 1), s));
-  SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), s));
-  SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
-  k_tri_entries<<<div_up(3 * n_tri, B), B, 0, s>>>(n_tri, tri_dev, c.N, bucket, vals, err);
+  TmpBuf<int32_t> bucket(3 * n_tri, s), ptr(c.N + 1, s), err(1, s);
+  TmpBuf<uint32_t> vals(3 * n_tri, s), sorted(3 * n_tri, s);
+  SFEM_HIP(hipMemsetAsync(err.get(), 0, sizeof(int32_t), s));
+  k_tri_entries<<<div_up(3 * n_tri, B), B, 0, s>>>(n_tri, tri_dev, c.N, bucket.get(), vals.get(),
+                                                   err.get());
   SFEM_HIP(hipGetLastError());
   int32_t h_err = 0;
-  SFEM_HIP(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SFEM_HIP(hipMemcpyAsync(&h_err, err.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
   SFEM_HIP(hipStreamSynchronize(s));
   if (!h_err) {
-    bucket_sort_u32(bucket, vals, 3 * n_tri, int(c.N), ptr, sorted, s);
-    k_traction_gather<<<div_up(c.N, B), B, 0, s>>>(c.N, ptr, sorted, tri_dev, c.xyz.get(), t[0],
-                                                   t[1], t[2], c.f_user.get());
+    bucket_sort_u32(bucket.get(), vals.get(), 3 * n_tri, int(c.N), ptr.get(), sorted.get(), s);
+    k_traction_gather<<<div_up(c.N, B), B, 0, s>>>(c.N, ptr.get(), sorted.get(), tri_dev,
+                                                   c.xyz.get(), t[0], t[1], t[2], c.f_user.get());
     SFEM_HIP(hipGetLastError());
   }
-  SFEM_HIP(hipFreeAsync(bucket, s));
-  SFEM_HIP(hipFreeAsync(vals, s));
-  SFEM_HIP(hipFreeAsync(sorted, s));
-  SFEM_HIP(hipFreeAsync(ptr, s));
-  SFEM_HIP(hipFreeAsync(err, s));
   SFEM_REQUIRE(!h_err, SFEM_EINVAL, "traction triangle node index out of range");
 }
 

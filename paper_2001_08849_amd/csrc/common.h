@@ -64,6 +64,30 @@ struct DBuf {
   T* get() const { return p; }
 };
 
+// Stream-ordered temporary (hipMallocAsync / hipFreeAsync on one stream),
+// freed when it goes out of scope, on error paths too; release() frees it
+// earlier.
+template <typename T>
+struct TmpBuf {
+  T* p = nullptr;
+  hipStream_t s = nullptr;
+  TmpBuf(size_t count, hipStream_t stream) : s(stream) {
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    if (hipMallocAsync(reinterpret_cast<void**>(&p), bytes, s) != hipSuccess) {
+      p = nullptr;
+      throw Error{SFEM_ENOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed"};
+    }
+  }
+  TmpBuf(const TmpBuf&) = delete;
+  TmpBuf& operator=(const TmpBuf&) = delete;
+  ~TmpBuf() { release(); }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+  }
+  T* get() const { return p; }
+};
+
 inline int div_up(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
 // ------------------------------------------------------------ device helpers

@@ -82,16 +82,12 @@ void exclusive_scan_impl(const T* in, T* out, int64_t n, hipStream_t s) {
     SFEM_HIP(hipGetLastError());
     return;
   }
-  T *sums = nullptr, *offs = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&sums, sizeof(T) * nt, s));
-  SFEM_HIP(hipMallocAsync((void**)&offs, sizeof(T) * (nt + 1), s));
-  k_tile_sums<T><<<nt, kScanThreads, 0, s>>>(in, n, sums);
+  TmpBuf<T> sums(nt, s), offs(nt + 1, s);
+  k_tile_sums<T><<<nt, kScanThreads, 0, s>>>(in, n, sums.get());
   SFEM_HIP(hipGetLastError());
-  exclusive_scan_impl<T>(sums, offs, nt, s);
-  k_tile_scan<T><<<nt, kScanThreads, 0, s>>>(in, n, offs, out);
+  exclusive_scan_impl<T>(sums.get(), offs.get(), nt, s);
+  k_tile_scan<T><<<nt, kScanThreads, 0, s>>>(in, n, offs.get(), out);
   SFEM_HIP(hipGetLastError());
-  SFEM_HIP(hipFreeAsync(sums, s));
-  SFEM_HIP(hipFreeAsync(offs, s));
 }
 
 // ------------------------------------------------------------ bucket sort
@@ -163,35 +159,29 @@ void segmented_sort_impl(const int32_t* ptr, int n_seg, const V* in, V* out, hip
 template <typename V>
 void bucket_sort_impl(const int32_t* bucket, const V* vals, int64_t n, int n_buckets, int32_t* ptr,
                       V* out, hipStream_t s, int n_sorted) {
-  int32_t *cnt = nullptr, *cursor = nullptr;
-  V* tmp = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&cnt, sizeof(int32_t) * (n_buckets + 1), s));
-  SFEM_HIP(hipMallocAsync((void**)&cursor, sizeof(int32_t) * (n_buckets + 1), s));
-  SFEM_HIP(hipMallocAsync((void**)&tmp, sizeof(V) * (n > 0 ? n : 1), s));
-  SFEM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n_buckets + 1), s));
+  TmpBuf<int32_t> cnt(n_buckets + 1, s), cursor(n_buckets + 1, s);
+  TmpBuf<V> tmp(n, s);
+  SFEM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * (n_buckets + 1), s));
   if (n > 0) {
-    k_count<<<div_up(n, 256), 256, 0, s>>>(bucket, n, cnt);
+    k_count<<<div_up(n, 256), 256, 0, s>>>(bucket, n, cnt.get());
     SFEM_HIP(hipGetLastError());
   }
-  exclusive_scan_impl<int32_t>(cnt, ptr, n_buckets, s);
-  SFEM_HIP(hipMemcpyAsync(cursor, ptr, sizeof(int32_t) * (n_buckets + 1),
+  exclusive_scan_impl<int32_t>(cnt.get(), ptr, n_buckets, s);
+  SFEM_HIP(hipMemcpyAsync(cursor.get(), ptr, sizeof(int32_t) * (n_buckets + 1),
                           hipMemcpyDeviceToDevice, s));
   if (n > 0) {
-    k_scatter<V><<<div_up(n, 256), 256, 0, s>>>(bucket, vals, n, cursor, tmp);
+    k_scatter<V><<<div_up(n, 256), 256, 0, s>>>(bucket, vals, n, cursor.get(), tmp.get());
     SFEM_HIP(hipGetLastError());
   }
-  segmented_sort_impl<V>(ptr, n_sorted, tmp, out, s);
+  segmented_sort_impl<V>(ptr, n_sorted, tmp.get(), out, s);
   if (n_sorted < n_buckets) {  // unsorted trailing buckets: plain copy
     int32_t first = 0;
     SFEM_HIP(hipMemcpyAsync(&first, ptr + n_sorted, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     SFEM_HIP(hipStreamSynchronize(s));
     if (n > first)
-      SFEM_HIP(hipMemcpyAsync(out + first, tmp + first, sizeof(V) * (n - first),
+      SFEM_HIP(hipMemcpyAsync(out + first, tmp.get() + first, sizeof(V) * (n - first),
                               hipMemcpyDeviceToDevice, s));
   }
-  SFEM_HIP(hipFreeAsync(cnt, s));
-  SFEM_HIP(hipFreeAsync(cursor, s));
-  SFEM_HIP(hipFreeAsync(tmp, s));
 }
 
 }  // namespace

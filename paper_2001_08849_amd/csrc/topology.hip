@@ -327,14 +327,13 @@ int build_pattern(Ctx& c, const int32_t* inc_ptr, const int32_t* inc, const int3
   Topology& tp = c.topo;
   const int64_t N = c.N;
   const int B = 256;
-  int32_t* deg = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&deg, sizeof(int32_t) * (N + 1), s));
+  TmpBuf<int32_t> deg(N + 1, s);
   tp.bptr.reserve(N + 1);
   const int pg = div_up(N, kPatWaves);
-  k_pattern<0, STRIDE, PER><<<pg, kPatWaves * kWave, 0, s>>>(inc_ptr, inc, rows, N, deg, nullptr,
-                                                               nullptr);
+  k_pattern<0, STRIDE, PER><<<pg, kPatWaves * kWave, 0, s>>>(inc_ptr, inc, rows, N, deg.get(),
+                                                               nullptr, nullptr);
   SFEM_HIP(hipGetLastError());
-  exclusive_scan_i32(deg, tp.bptr.get(), N, s);
+  exclusive_scan_i32(deg.get(), tp.bptr.get(), N, s);
   tp.nb = read_scalar(tp.bptr.get() + N, s);
   SFEM_REQUIRE(tp.nb >= N, SFEM_EMESH, "a node belongs to no tetrahedron");
   SFEM_REQUIRE(9 * tp.nb < (int64_t(1) << 31), SFEM_EINVAL,
@@ -343,17 +342,16 @@ int build_pattern(Ctx& c, const int32_t* inc_ptr, const int32_t* inc, const int3
   k_pattern<1, STRIDE, PER><<<pg, kPatWaves * kWave, 0, s>>>(inc_ptr, inc, rows, N, nullptr,
                                                                tp.bptr.get(), tp.bcol.get());
   SFEM_HIP(hipGetLastError());
-  SFEM_HIP(hipFreeAsync(deg, s));
+  deg.release();
 
-  int* md = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&md, 3 * sizeof(int), s));
-  SFEM_HIP(hipMemsetAsync(md, 0, 3 * sizeof(int), s));
-  k_maxdeg<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), inc_ptr, N, md);
+  TmpBuf<int> md(3, s);
+  SFEM_HIP(hipMemsetAsync(md.get(), 0, 3 * sizeof(int), s));
+  k_maxdeg<<<div_up(N, B), B, 0, s>>>(tp.bptr.get(), inc_ptr, N, md.get());
   SFEM_HIP(hipGetLastError());
-  tp.maxdeg = read_scalar(md, s);
-  const int isolated = read_scalar(md + 1, s);
-  const int max_inc = read_scalar(md + 2, s);
-  SFEM_HIP(hipFreeAsync(md, s));
+  tp.maxdeg = read_scalar(md.get(), s);
+  const int isolated = read_scalar(md.get() + 1, s);
+  const int max_inc = read_scalar(md.get() + 2, s);
+  md.release();
   SFEM_REQUIRE(!isolated, SFEM_EMESH, "a node belongs to no tetrahedron");
   SFEM_REQUIRE(tp.maxdeg <= kMaxDeg && 2 * tp.maxdeg < kTileBlocks, SFEM_EMESH,
                "a node has more than 64 neighbours (" + std::to_string(tp.maxdeg) + ")");
@@ -382,100 +380,75 @@ void build_topology(Ctx& c) {
   tp.T = T;
   const int B = 256;
 
-  int32_t* err = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&err, sizeof(int32_t), s));
-  SFEM_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
-  k_check_tets<<<div_up(T, B), B, 0, s>>>(c.xyz.get(), c.tets.get(), T, err);
+  TmpBuf<int32_t> err(1, s);
+  SFEM_HIP(hipMemsetAsync(err.get(), 0, sizeof(int32_t), s));
+  k_check_tets<<<div_up(T, B), B, 0, s>>>(c.xyz.get(), c.tets.get(), T, err.get());
   SFEM_HIP(hipGetLastError());
 
   // 1. faces
   const int64_t n4 = 4 * T;
-  int32_t* fb = nullptr;
-  uint64_t *fv = nullptr, *fs = nullptr;
-  int32_t *fptr = nullptr, *fcnt = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&fb, sizeof(int32_t) * n4, s));
-  SFEM_HIP(hipMallocAsync((void**)&fv, sizeof(uint64_t) * n4, s));
-  SFEM_HIP(hipMallocAsync((void**)&fs, sizeof(uint64_t) * n4, s));
-  SFEM_HIP(hipMallocAsync((void**)&fptr, sizeof(int32_t) * (N + 1), s));
-  SFEM_HIP(hipMallocAsync((void**)&fcnt, sizeof(int32_t) * (N + 1), s));
+  TmpBuf<int32_t> fb(n4, s), fptr(N + 1, s), fcnt(N + 1, s);
+  TmpBuf<uint64_t> fv(n4, s), fs(n4, s);
   // key base: the largest vertex-id spread of a tet (small for banded
   // numberings; a batch of meshes never has a tet spanning two meshes)
   {
     const int G = int(std::min<int64_t>(1024, div_up(T, B)));
-    int32_t* part = nullptr;
-    SFEM_HIP(hipMallocAsync((void**)&part, sizeof(int32_t) * G, s));
-    k_tet_spread<<<G, B, 0, s>>>(c.tets.get(), T, part);
+    TmpBuf<int32_t> part(G, s);
+    k_tet_spread<<<G, B, 0, s>>>(c.tets.get(), T, part.get());
     SFEM_HIP(hipGetLastError());
     std::vector<int32_t> hp(G);
-    SFEM_HIP(hipMemcpyAsync(hp.data(), part, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    SFEM_HIP(hipMemcpyAsync(hp.data(), part.get(), sizeof(int32_t) * G, hipMemcpyDeviceToHost,
+                            s));
     SFEM_HIP(hipStreamSynchronize(s));
-    SFEM_HIP(hipFreeAsync(part, s));
     tp.key_w = 1 + *std::max_element(hp.begin(), hp.end());
   }
   const uint64_t W = uint64_t(tp.key_w);
-  if (double(W) * double(W) * 4.0 * double(T) >= 9.2e18) {
-    (void)hipFreeAsync(err, s);
-    (void)hipFreeAsync(fb, s);
-    (void)hipFreeAsync(fv, s);
-    (void)hipFreeAsync(fs, s);
-    (void)hipFreeAsync(fptr, s);
-    (void)hipFreeAsync(fcnt, s);
+  if (double(W) * double(W) * 4.0 * double(T) >= 9.2e18)
     throw Error{SFEM_EINVAL, "face keys overflow: (largest tet vertex-id spread + 1)^2 * 4 n_tets "
                              "must be < 2^63 (renumber the nodes)"};
-  }
-  k_face_entries<<<div_up(T, B), B, 0, s>>>(c.tets.get(), T, W, fb, fv);
+  k_face_entries<<<div_up(T, B), B, 0, s>>>(c.tets.get(), T, W, fb.get(), fv.get());
   SFEM_HIP(hipGetLastError());
-  bucket_sort_u64(fb, fv, n4, int(N), fptr, fs, s);
-  k_face_count<<<div_up(N, B), B, 0, s>>>(fptr, fs, N, uint64_t(n4), fcnt, err);
+  bucket_sort_u64(fb.get(), fv.get(), n4, int(N), fptr.get(), fs.get(), s);
+  k_face_count<<<div_up(N, B), B, 0, s>>>(fptr.get(), fs.get(), N, uint64_t(n4), fcnt.get(),
+                                          err.get());
   SFEM_HIP(hipGetLastError());
-  int32_t* face_ofs = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&face_ofs, sizeof(int32_t) * (N + 1), s));
-  exclusive_scan_i32(fcnt, face_ofs, N, s);
-  int32_t h_err = read_scalar(err, s);
-  if (h_err) {
-    (void)hipFreeAsync(err, s);
-    (void)hipFreeAsync(fb, s);
-    (void)hipFreeAsync(fv, s);
-    (void)hipFreeAsync(fs, s);
-    (void)hipFreeAsync(fptr, s);
-    (void)hipFreeAsync(fcnt, s);
-    (void)hipFreeAsync(face_ofs, s);
+  TmpBuf<int32_t> face_ofs(N + 1, s);
+  exclusive_scan_i32(fcnt.get(), face_ofs.get(), N, s);
+  const int32_t h_err = read_scalar(err.get(), s);
+  if (h_err)
     throw Error{SFEM_EMESH, (h_err & 2) ? "degenerate (zero-volume) tetrahedron in mesh"
                                         : "non-manifold mesh: a face is shared by more than two tets"};
-  }
-  tp.nf = read_scalar(face_ofs + N, s);
+  tp.nf = read_scalar(face_ofs.get() + N, s);
   SFEM_REQUIRE(tp.nf >= 4, SFEM_EHIP, "face extraction produced no faces");
   tp.face.reserve(size_t(tp.nf) * kFaceStride);
-  unsigned long long* next = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&next, sizeof(unsigned long long), s));
-  SFEM_HIP(hipMemsetAsync(next, 0, sizeof(unsigned long long), s));
-  k_face_write<<<div_up(N, B), B, 0, s>>>(fptr, fs, face_ofs, c.tets.get(), N, W,
-                                          uint64_t(n4), tp.face.get(), next);
+  TmpBuf<unsigned long long> next(1, s);
+  SFEM_HIP(hipMemsetAsync(next.get(), 0, sizeof(unsigned long long), s));
+  k_face_write<<<div_up(N, B), B, 0, s>>>(fptr.get(), fs.get(), face_ofs.get(), c.tets.get(), N,
+                                          W, uint64_t(n4), tp.face.get(), next.get());
   SFEM_HIP(hipGetLastError());
-  tp.ne = int64_t(read_scalar(next, s));
-  SFEM_HIP(hipFreeAsync(fb, s));
-  SFEM_HIP(hipFreeAsync(fv, s));
-  SFEM_HIP(hipFreeAsync(fs, s));
-  SFEM_HIP(hipFreeAsync(fptr, s));
-  SFEM_HIP(hipFreeAsync(fcnt, s));
-  SFEM_HIP(hipFreeAsync(face_ofs, s));
-  SFEM_HIP(hipFreeAsync(next, s));
+  tp.ne = int64_t(read_scalar(next.get(), s));
+  // the face sort's buffers go before the incidence is built
+  fb.release();
+  fv.release();
+  fs.release();
+  fptr.release();
+  fcnt.release();
+  face_ofs.release();
+  next.release();
 
   // 2. node -> face incidence
   const int64_t n5 = 5 * tp.nf;
-  int32_t* ib = nullptr;
-  uint32_t* iv = nullptr;
-  SFEM_HIP(hipMallocAsync((void**)&ib, sizeof(int32_t) * n5, s));
-  SFEM_HIP(hipMallocAsync((void**)&iv, sizeof(uint32_t) * n5, s));
-  k_inc_entries<<<div_up(tp.nf, B), B, 0, s>>>(tp.face.get(), tp.nf, N, ib, iv);
+  TmpBuf<int32_t> ib(n5, s);
+  TmpBuf<uint32_t> iv(n5, s);
+  k_inc_entries<<<div_up(tp.nf, B), B, 0, s>>>(tp.face.get(), tp.nf, N, ib.get(), iv.get());
   SFEM_HIP(hipGetLastError());
   tp.inc_ptr.reserve(N + 2);
   tp.inc.reserve(n5);
   // the spare bucket N only collects padding and is never read: left unsorted
-  bucket_sort_u32(ib, iv, n5, int(N + 1), tp.inc_ptr.get(), reinterpret_cast<uint32_t*>(tp.inc.get()),
-                  s, int(N));
-  SFEM_HIP(hipFreeAsync(ib, s));
-  SFEM_HIP(hipFreeAsync(iv, s));
+  bucket_sort_u32(ib.get(), iv.get(), n5, int(N + 1), tp.inc_ptr.get(),
+                  reinterpret_cast<uint32_t*>(tp.inc.get()), s, int(N));
+  ib.release();
+  iv.release();
   tp.n_inc = read_scalar(tp.inc_ptr.get() + N, s);
 
   // 3.-4. block pattern of the face domains, assembly tiles
@@ -485,7 +458,7 @@ void build_topology(Ctx& c) {
                                                 tp.bptr.get(), tp.bcol.get(), N, tp.slot.get());
   SFEM_HIP(hipGetLastError());
   face_bounds(c);
-  SFEM_HIP(hipFreeAsync(err, s));
+  err.release();
   SFEM_HIP(hipStreamSynchronize(s));
   if (c.domain == SFEM_DOMAIN_EDGE) build_edge_topology(c);
   tp.valid = true;

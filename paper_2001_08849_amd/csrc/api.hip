@@ -111,6 +111,7 @@ void reset_problem(Ctx& c) {
   c.have_material = false;
   c.per_tet = false;
   c.any_fixed = c.any_nonzero_bc = false;
+  c.bc_row_valid = false;
   c.penalty = 0.0;
   c.assembled = false;
   c.val_has_bc = false;
@@ -316,6 +317,8 @@ int sfem_set_dirichlet(sfem_ctx* h, int64_t n, const int32_t* dof, const double*
     SFEM_HIP(hipStreamSynchronize(c.stream));
     SFEM_REQUIRE(ok, SFEM_EINVAL, "Dirichlet DOF index out of range");
     c.any_fixed = n > 0;
+    c.bc_row_valid = false;
+    if (c.any_fixed) sfem::bc_rows(c);  // with the BCs, not in the assembly
     c.any_nonzero_bc = hf[0] != 0;
     c.assembled = false;
     return SFEM_OK;

@@ -176,8 +176,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
                const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
                const float* __restrict__ row_vg, double lam0, double mu0,
                const double* __restrict__ lam_t, const double* __restrict__ mu_t,
-               const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
-               float* __restrict__ val32) {
+               const uint8_t* __restrict__ fixed, const uint8_t* __restrict__ bc_row,
+               double penalty, double* __restrict__ val, float* __restrict__ val32) {
   __shared__ unsigned long long sval[kTileBlocks * 9];  // fixed point, units of u
   __shared__ int32_t sptr[kTileBlocks + 1];  // block offsets of the tile's rows
   __shared__ int32_t sinc[kTileBlocks + 1];  // incidence offsets of the tile's rows
@@ -278,7 +278,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     }
   }
 
-  // stream the finished rows out, applying the essential BCs
+  // stream the finished rows out, applying the essential BCs (only rows
+  // that touch a prescribed DOF can need them)
   __syncthreads();
   for (int li = wid; li < nn; li += nwaves) {
     const int I = n0 + li;
@@ -288,9 +289,10 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     const float inv3d = 1.0f / float(three_deg);
     const int64_t gbase = 9 * (int64_t(b0) + rb);
     const double u = ldexp(1.0, sexp[li] - 50);
+    const bool rbc = fixed && bc_row[I];
     for (int k = lane; k < 9 * deg; k += kWave) {
       double v = double((long long)sval[9 * rb + k]) * u;
-      if (fixed) {
+      if (rbc) {
         const int a = int((float(k) + 0.5f) * inv3d);
         const int r = k - a * three_deg;
         const int jj = r / 3;
@@ -308,6 +310,23 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
       if (val32) val32[gbase + k] = float(v);
     }
   }
+}
+
+// Rows that can need the BC rule: node I or a block column J of its row
+// has a prescribed DOF.  One wave per row.
+__global__ void k_bc_rows(int64_t N, const int32_t* __restrict__ bptr,
+                          const int32_t* __restrict__ bcol, const uint8_t* __restrict__ fixed,
+                          uint8_t* __restrict__ bc_row) {
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (I >= N) return;
+  int any = 0;
+  for (int j = bptr[I] + lane; j < bptr[I + 1]; j += kWave) {
+    const int64_t J3 = 3 * int64_t(bcol[j]);
+    any |= fixed[J3] | fixed[J3 + 1] | fixed[J3 + 2];
+  }
+  any = wave_max(any);
+  if (lane == 0) bc_row[I] = uint8_t(any);
 }
 
 // In-place elimination on an assembled unconstrained matrix (used when the
@@ -450,6 +469,19 @@ __global__ void k_traction_gather(int64_t N, const int32_t* __restrict__ ptr,
 
 }  // namespace
 
+const uint8_t* bc_rows(Ctx& c) {
+  if (!c.bc_row_valid) {
+    const Topology& tp = c.topo;
+    c.bc_row.reserve(tp.N);
+    k_bc_rows<<<div_up(tp.N * kWave, 256), 256, 0, c.stream>>>(tp.N, tp.bptr.get(),
+                                                                tp.bcol.get(), c.fixed.get(),
+                                                                c.bc_row.get());
+    SFEM_HIP(hipGetLastError());
+    c.bc_row_valid = true;
+  }
+  return c.bc_row.get();
+}
+
 void face_bounds(Ctx& c) {
   Topology& tp = c.topo;
   k_face_bound<<<div_up(tp.nf, 256), 256, 0, c.stream>>>(c.xyz.get(), tp.nf, tp.face.get());
@@ -466,17 +498,18 @@ void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask)
   }
   const Topology& tp = c.topo;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
+  const uint8_t* brow = fixed ? bc_rows(c) : nullptr;
   dim3 grid(tp.n_tiles), block(kAsmThreads);
   if (c.per_tet)
     k_assemble<true><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
         tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, c.lam_t.get(),
-        c.mu_t.get(), fixed, c.penalty, val_out, val32_out);
+        c.mu_t.get(), fixed, brow, c.penalty, val_out, val32_out);
   else
     k_assemble<false><<<grid, block, 0, c.stream>>>(
         c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
         tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, nullptr, nullptr,
-        fixed, c.penalty, val_out, val32_out);
+        fixed, brow, c.penalty, val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

@@ -100,6 +100,11 @@ struct Ctx {
 
   // BCs and loads
   DBuf<uint8_t> fixed;           // [3N] 1 if the DOF is prescribed
+  // [N] 1 if node row I or one of its block columns has a prescribed DOF
+  // (only those rows can need the BC rule when K is written); remade after
+  // the BCs or the pattern change
+  DBuf<uint8_t> bc_row;
+  bool bc_row_valid = false;
   DBuf<double> ubar;             // [3N] prescribed values (0 where free)
   bool any_fixed = false, any_nonzero_bc = false;
   double penalty = 0.0;          // > 0: penalty form instead of elimination
@@ -189,6 +194,7 @@ void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_
 // assemble.hip
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 void bc_mask_values(Ctx& c);
+const uint8_t* bc_rows(Ctx& c);  // c.bc_row, remade if stale
 void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t[3]);
 void face_stress(Ctx& c, const double* u, double* eps, double* sig);
 void scalar_csr_pattern(Ctx& c, int32_t* row_ptr, int32_t* col_idx);

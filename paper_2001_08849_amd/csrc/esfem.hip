@@ -285,8 +285,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
                     const int16_t* __restrict__ rexp, const float* __restrict__ row_eg,
                     double F, const int32_t* __restrict__ bptr,
                     const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
-                    const uint8_t* __restrict__ fixed, double penalty, double* __restrict__ val,
-                    float* __restrict__ val32) {
+                    const uint8_t* __restrict__ fixed, const uint8_t* __restrict__ bc_row,
+                    double penalty, double* __restrict__ val, float* __restrict__ val32) {
   __shared__ unsigned long long sval[kTileBlocks * 9];
   __shared__ int32_t sptr[kTileBlocks + 1];
   __shared__ int32_t sinc[kTileBlocks + 1];
@@ -408,9 +408,10 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     const float inv3d = 1.0f / float(three_deg);
     const int64_t gbase = 9 * (int64_t(b0) + rb);
     const double u = ldexp(1.0, sexp[li] - 50);
+    const bool rbc = fixed && bc_row[I];  // only rows touching a prescribed DOF
     for (int k = lane; k < 9 * deg; k += kWave) {
       double v = double((long long)sval[9 * rb + k]) * u;
-      if (fixed) {
+      if (rbc) {
         const int a = int((float(k) + 0.5f) * inv3d);
         const int rr = k - a * three_deg;
         const int jj = rr / 3;
@@ -557,7 +558,7 @@ void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_
       et.inc_ptr.get(), et.inc.get(), et.slot.get(), et.rec.get(),
       c.per_tet ? et.rexp.get() : nullptr, c.per_tet ? nullptr : et.row_eg.get(),
       std::fabs(c.lam0) + 2.0 * c.mu0, tp.bptr.get(), tp.bcol.get(), tp.tile_first.get(), fixed,
-      c.penalty, val_out, val32_out);
+      fixed ? bc_rows(c) : nullptr, c.penalty, val_out, val32_out);
   SFEM_HIP(hipGetLastError());
 }
 

@@ -187,7 +187,10 @@ def summarize_profiles(prof_dir, command_note):
             fh.write(f"# {title}\n\n")
             fh.write(f"Command: `{command_note}`\n\n")
             fh.write("| kernel | calls | total ms | average us | % |\n|---|---|---|---|---|\n")
-            for r in rows[:30]:
+            # the 30 largest, plus every hot-path kernel however small its share
+            hot = ("k_assemble", "k_face_stress", "k_mapply", "k_cg_spmv", "k_edge_")
+            sel = rows[:30] + [r for r in rows[30:] if any(h in r["Name"] for h in hot)]
+            for r in sel:
                 nm = _short(r["Name"])
                 fh.write(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                          f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")

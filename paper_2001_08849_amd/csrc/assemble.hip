@@ -172,9 +172,10 @@ template <bool HET>
 __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(6)))
     k_assemble(const double* __restrict__ xyz, const int32_t* __restrict__ face,
                const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
-               const uint32_t* __restrict__ slot, const int32_t* __restrict__ bptr,
-               const int32_t* __restrict__ bcol, const int32_t* __restrict__ tile_first,
-               const float* __restrict__ row_vg, double lam0, double mu0,
+               const uint32_t* __restrict__ slot, const uint16_t* __restrict__ irow,
+               const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+               const int32_t* __restrict__ tile_first, const float* __restrict__ row_vg,
+               double lam0, double mu0,
                const double* __restrict__ lam_t, const double* __restrict__ mu_t,
                const uint8_t* __restrict__ fixed, const uint8_t* __restrict__ bc_row,
                double penalty, double* __restrict__ val, float* __restrict__ val32) {
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     const int e = e0 + pos;
     pos += step;
     if (pos >= n_items) pos -= n_items;
-    const int li = upper_index(sinc, nn, e - e0);
+    const int li = irow[e];
     const int I = n0 + li;
     const int rb = sptr[li];
     const int deg = sptr[li + 1] - rb;
@@ -502,12 +503,14 @@ void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask)
   dim3 grid(tp.n_tiles), block(kAsmThreads);
   if (c.per_tet)
     k_assemble<true><<<grid, block, 0, c.stream>>>(
-        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
+        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.irow.get(),
+        tp.bptr.get(),
         tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, c.lam_t.get(),
         c.mu_t.get(), fixed, brow, c.penalty, val_out, val32_out);
   else
     k_assemble<false><<<grid, block, 0, c.stream>>>(
-        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.bptr.get(),
+        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.irow.get(),
+        tp.bptr.get(),
         tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, nullptr, nullptr,
         fixed, brow, c.penalty, val_out, val32_out);
   SFEM_HIP(hipGetLastError());

@@ -33,6 +33,7 @@ struct Topology {
   DBuf<int32_t> bptr;            // [N+1] block-row offsets
   DBuf<int32_t> bcol;            // [nb] block column (node) ids, ascending per row
   DBuf<int32_t> tile_first;      // [n_tiles+1] first node of each tile
+  DBuf<uint16_t> irow;           // per incidence: its row's index within the row's tile
   DBuf<float> row_vg;            // [N] largest face bound max(V_i G_i) of each row
   bool valid = false;
 };

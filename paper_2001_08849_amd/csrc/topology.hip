@@ -253,6 +253,24 @@ __global__ void k_tiles(const int32_t* __restrict__ bptr, int64_t N, int C,
   if (I == N - 1) tile_first[n_tiles] = int(N);
 }
 
+// Per incidence entry of row I: I's index within its assembly tile (a
+// tile holds at most kTileBlocks rows).  One wave per row.
+__global__ void k_inc_rows(int64_t N, const int32_t* __restrict__ inc_ptr,
+                           const int32_t* __restrict__ tile_first, int n_tiles,
+                           uint16_t* __restrict__ irow) {
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (I >= N) return;
+  int lo = 0, hi = n_tiles - 1;  // the last tile t with tile_first[t] <= I
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_first[mid] <= int(I)) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint16_t li = uint16_t(int(I) - tile_first[lo]);
+  for (int e = inc_ptr[I] + lane; e < inc_ptr[I + 1]; e += kWave) irow[e] = li;
+}
+
 // Slot map: for incidence entry e = (row node I, face f), the positions of
 // f's support nodes among row I's block columns, 6 bits each (slot q in
 // bits 6q..6q+5).  One wave per node row.
@@ -456,6 +474,10 @@ void build_topology(Ctx& c) {
   tp.slot.reserve(tp.n_inc);
   k_slot_map<<<div_up(N * kWave, B), B, 0, s>>>(tp.inc_ptr.get(), tp.inc.get(), tp.face.get(),
                                                 tp.bptr.get(), tp.bcol.get(), N, tp.slot.get());
+  SFEM_HIP(hipGetLastError());
+  tp.irow.reserve(tp.n_inc);
+  k_inc_rows<<<div_up(N * kWave, B), B, 0, s>>>(N, tp.inc_ptr.get(), tp.tile_first.get(),
+                                                tp.n_tiles, tp.irow.get());
   SFEM_HIP(hipGetLastError());
   face_bounds(c);
   err.release();

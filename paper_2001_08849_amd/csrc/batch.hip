@@ -327,17 +327,24 @@ __global__ void __launch_bounds__(kBThreads)
   }
 }
 
-// Compacted work lists of the meshes still active: block j < kNumBuckets
-// lists the product items of bucket j's active meshes (ranges mw) at
-// list[base_j], block kNumBuckets the elementwise items (ranges mv) at
-// list[base_3]; cnt[j] is the length.  Meshes in ascending order, so the
-// list is a fixed function of the masks.
+// Compacted work lists of the meshes still active, one per block j: j <
+// kNumBuckets lists the product items of bucket j's active meshes (ranges
+// mw), j = kNumBuckets the elementwise items (ranges mv), j = kNumBuckets + 1
+// the product items of every active mesh (for one launch over all buckets
+// when they share a schedule).  List j starts at list[base.b[j]] and has
+// cnt[j] entries.  Meshes in ascending order, so each list is a fixed
+// function of the masks.
+constexpr int kNumLists = kNumBuckets + 2;
+struct ListBase {
+  int b[kNumLists];
+};
+
 __global__ void __launch_bounds__(kBThreads)
     k_bcompact(int n_meshes, const int32_t* __restrict__ mbucket, const int2* __restrict__ mw,
-               const int2* __restrict__ mv, const BScal* __restrict__ sc, int4 base,
+               const int2* __restrict__ mv, const BScal* __restrict__ sc, ListBase base,
                int32_t* __restrict__ list, int32_t* __restrict__ cnt) {
   const int j = blockIdx.x;
-  const int ob = j == 0 ? base.x : j == 1 ? base.y : j == 2 ? base.z : base.w;
+  const int ob = base.b[j];
   __shared__ int wsum[kBThreads / 64];
   __shared__ int off;
   if (threadIdx.x == 0) off = 0;
@@ -346,7 +353,7 @@ __global__ void __launch_bounds__(kBThreads)
   for (int m0 = 0; m0 < n_meshes; m0 += kBThreads) {
     const int m = m0 + threadIdx.x;
     int2 rg = {0, 0};
-    if (m < n_meshes && !mesh_done(sc, m) && (j == kNumBuckets || mbucket[m] == j))
+    if (m < n_meshes && !mesh_done(sc, m) && (j >= kNumBuckets || mbucket[m] == j))
       rg = j == kNumBuckets ? mv[m] : mw[m];
     const int len = rg.y - rg.x;
     const int inc = wave_inclusive_scan(len);
@@ -580,8 +587,8 @@ void build_table(Ctx& c, BatchState& b) {
   b.wmesh.reserve(std::max(1, w));
   b.mw.reserve(std::max(1, b.n_meshes));
   b.part.reserve(size_t(std::max(std::max(1, w), v)) * 8);  // either table's partials
-  b.alist.reserve(size_t(std::max(1, w + v)));
-  b.acnt.reserve(kNumBuckets + 1);
+  b.alist.reserve(size_t(std::max(1, 2 * w + v)));
+  b.acnt.reserve(kNumLists);
   b.mbucket.reserve(std::max(1, b.n_meshes));
   SFEM_HIP(hipMemcpyAsync(b.mbucket.get(), b.bucket.data(), sizeof(int32_t) * b.n_meshes,
                           hipMemcpyHostToDevice, c.stream));
@@ -611,8 +618,8 @@ constexpr int kBGridCap = 4096;
 // Remakes the lists of the items of meshes still active (kernel only:
 // capturable).
 void compact(Ctx& c, BatchState& b) {
-  const int4 base = {b.bw0[0], b.bw0[1], b.bw0[2], b.n_wg()};
-  k_bcompact<<<kNumBuckets + 1, kBThreads, 0, c.stream>>>(b.n_meshes, b.mbucket.get(),
+  const ListBase base = {{b.bw0[0], b.bw0[1], b.bw0[2], b.n_wg(), b.n_wg() + b.n_vw}};
+  k_bcompact<<<kNumLists, kBThreads, 0, c.stream>>>(b.n_meshes, b.mbucket.get(),
                                                          b.mw.get(), b.mv.get(), b.sc.get(), base,
                                                          b.alist.get(), b.acnt.get());
   SFEM_HIP(hipGetLastError());
@@ -624,12 +631,24 @@ void compact(Ctx& c, BatchState& b) {
 template <int EPI>
 void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, double* Y,
            double* Z, int only_bucket = -1, bool use_sc = true) {
+  // every non-empty bucket on one schedule: one launch over the merged list
+  int first = -1;
+  bool uniform = true;
+  for (int bk = 0; bk < kNumBuckets; ++bk) {
+    if (b.bw0[bk + 1] == b.bw0[bk]) continue;
+    if (first < 0) first = bk;
+    else uniform = uniform && b.lpr[bk] == b.lpr[first] && b.packed[bk] == b.packed[first];
+  }
+  const bool merged = use_sc && only_bucket < 0 && uniform && first >= 0;
   for (int bk = 0; bk < kNumBuckets; ++bk) {
     if (only_bucket >= 0 && bk != only_bucket) continue;
-    const int nw = b.bw0[bk + 1] - b.bw0[bk];
+    if (merged && bk != first) continue;
+    const int nw = merged ? b.n_wg() : b.bw0[bk + 1] - b.bw0[bk];
     if (nw == 0) continue;
-    const Work wk{use_sc ? b.alist.get() : nullptr, use_sc ? b.acnt.get() + bk : nullptr,
-                  b.bw0[bk], nw};
+    const Work wk = merged ? Work{b.alist.get(), b.acnt.get() + kNumBuckets + 1,
+                                  b.n_wg() + b.n_vw, nw}
+                           : Work{use_sc ? b.alist.get() : nullptr,
+                                  use_sc ? b.acnt.get() + bk : nullptr, b.bw0[bk], nw};
     const int grid = use_sc ? std::min(nw, kBGridCap) : nw;
 #define L_(VT, VAL, LPR)                                                                   \
   k_bspmm<VT, LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                \

@@ -44,6 +44,9 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
   sup[4] = r1.x;
   const bool interior = r1.x >= 0;
   Vec3 A = load3(xyz, r0.x), B = load3(xyz, r0.y), C = load3(xyz, r0.z), D = load3(xyz, r0.w);
+  // the second tet's far node, gathered with the others (a valid node id on
+  // exterior faces too, where it is not used)
+  const Vec3 E = load3(xyz, interior ? r1.x : r0.w);
   Vec3 g1[4];
   double V1;
   tet_grads(A, B, C, D, g1, V1);
@@ -61,7 +64,6 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
     }
     return 4;
   }
-  Vec3 E = load3(xyz, r1.x);
   Vec3 g2[4];
   double V2;
   tet_grads(A, B, C, E, g2, V2);
@@ -593,12 +595,14 @@ __global__ void __launch_bounds__(256)
   int sup[5];
   Vec3 b[5];
   double Vk, lam, mu;
-  const int n = face_geometry<HET>(face + f * kFaceStride, xyz, lam0, mu0, lam_t, mu_t, sup, b,
-                                   Vk, lam, mu);
-  // displacement gradient G[a][c] = sum_I u_I[a] b_I[c]
+  face_geometry<HET>(face + f * kFaceStride, xyz, lam0, mu0, lam_t, mu_t, sup, b, Vk, lam, mu);
+  // displacement gradient G[a][c] = sum_I u_I[a] b_I[c], all five gathers
+  // issued together (an exterior face's fifth gradient is zero: its slot
+  // gathers a support node and adds exactly nothing)
   double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int I = 0; I < n; ++I) {
-    const double* uI = u + 3 * int64_t(sup[I]);
+#pragma unroll
+  for (int I = 0; I < 5; ++I) {
+    const double* uI = u + 3 * int64_t(sup[I] >= 0 ? sup[I] : sup[0]);
     const double ua[3] = {uI[0], uI[1], uI[2]};
     const double bc[3] = {b[I].x, b[I].y, b[I].z};
 #pragma unroll

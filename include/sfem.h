@@ -410,7 +410,10 @@ int sfem_batch_sizes(sfem_batch* b, int* n_meshes, int64_t* n_nodes, int64_t* n_
  * bucket alone: (lanes per node row in {8, 16, 32} on the CSR-order values,
  * or in {4, 8} on the packed layout, FP64 only) x (node rows per workgroup
  * in {16, 64, 256}, at least 256 / lanes so that no lane group idles).
- * The fastest is kept and cached for the process under
+ * A candidate's cost is its time with every system active plus its time
+ * with only the bucket's largest mesh active (late in a solve most meshes
+ * have finished); the solver's own compacted work lists are used for both.
+ * The cheapest is kept and cached for the process under
  * the bucket's shape (bucket, log2 of its node rows, mean block degree).
  * With use_cache, a cached shape is reused without timing.  precision:
  * SFEM_ASM_F64 or SFEM_ASM_F32_COPY (CSR-order candidates only; an FP32
@@ -441,7 +444,13 @@ typedef struct {
   double worst_relres;
 } sfem_batch_info;
 
-/* Solves all systems; SFEM_ENOCONV if any did not converge. */
+/* Solves all systems by CG with Jacobi preconditioning, every system from
+ * x = 0, in check periods: each period runs check_every iterations of the
+ * 4-right-hand-side product and the per-system updates, then the FP64
+ * residual replacement and the convergence test.  A mesh whose 4 systems
+ * have all finished (converged, broken down or stagnated) drops out of the
+ * work lists remade at the start of the next period.  SFEM_ENOCONV if any
+ * system did not converge. */
 int sfem_batch_solve(sfem_batch* b, const sfem_batch_opts* opts, sfem_batch_info* info);
 /* Displacements of (mesh, load case): float64 [3 n_nodes(mesh)]. */
 int sfem_batch_get_solution(sfem_batch* b, int mesh, int rhs, double* u, int ptr_kind);

@@ -383,6 +383,27 @@ def es_fem_leg(prob, sfem, np):
     return res
 
 
+def mixed_precision_leg(ctx, sfem, u, inner_rtol):
+    """FP32/FP64 refinement on the same cantilever, outside the timed steps:
+    K assembled again with its FP32 copy and both row schedules retuned, then
+    the FP32-inner-CG refinement (FP64 outer residuals) and the CG with FP32
+    products and FP64 residual replacement, once each, each judged by the FP64
+    true relative residual (1e-8)."""
+    ctx.assemble(f32_copy=True)
+    tuned = ctx.autotune(reps=3)
+    _, ir = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_IR, inner_rtol=inner_rtol)
+    _, rr = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_RR)
+    log(f"[bench] FP32 + FP64 refinement: {ir['ms_solve']:.0f} ms, {ir['iters']} it, "
+        f"{ir['outer_steps']} outer; FP32 products + FP64 replacement: {rr['ms_solve']:.0f} ms, "
+        f"{rr['iters']} it")
+    res = {"row_schedule_f32": list(tuned["f32"][0]) if tuned.get("f32") else None}
+    for name, i in (("f32_inner_f64_refinement", ir), ("f32_products_f64_replacement", rr)):
+        res[name] = {"solve_s": i["ms_solve"] * 1e-3, "iters": i["iters"],
+                     "outer_steps": i["outer_steps"], "true_relres": i["true_relres"],
+                     "converged": bool(i["converged"])}
+    return res
+
+
 def batch_leg(mg, sfem, np):
     """The batched workload: 64 meshes (1.9k-288k tets, 4.0M in all) x 4
     load cases, one block-diagonal system, tuned 4-RHS product, hipGraph
@@ -424,6 +445,8 @@ def main():
     ap.add_argument("--skip-solve", action="store_true", help="assembly only (profiling)")
     ap.add_argument("--f32-ir", action="store_true", help="also time the FP32+FP64-IR solve")
     ap.add_argument("--inner-rtol", type=float, default=1e-2)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32/FP64 refinement leg")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-mesh x 4-load-case batched solve")
     ap.add_argument("--no-es-fem", action="store_true",
@@ -570,6 +593,12 @@ def main():
                 f"solve {info['ms_solve']:.1f} ms, {info['iters']} it, relres "
                 f"{info['true_relres']:.2e}, fell back {info['fell_back']}")
 
+    # theta of the learned M, read before the refinement leg re-assembles K
+    theta = ctx.precond_info()["theta"] if lsolves else None
+    mixed = None
+    if not args.skip_solve and not args.no_mixed and not args.f32_ir:
+        mixed = mixed_precision_leg(ctx, sfem, u, args.inner_rtol)
+
     asm_med = float(np.median(asm_ms))
     faces_per_s = s.n_faces / (asm_med * 1e-3)
     asm_bytes, spmv_bytes, _ = algorithmic_bytes(m.n_nodes, m.n_tets, s.n_faces, s.nnz,
@@ -621,7 +650,7 @@ def main():
             out["learned"] = {
                 "solver": "flexible PCG, K FP64, learned M (S' BF16 in the padded node-row layout, network BF16-MFMA), "
                           "FP64 vectors and dots, true relres <= 1e-8",
-                "inference_s": li, "theta": ctx.precond_info()["theta"],
+                "inference_s": li, "theta": theta,
                 "fell_back": lsolves[-1]["fell_back"],
                 "speedup_vs_jacobi": out["solve_s"]["jacobi_f64"] / (ls + li),
                 "training": {k: v for k, v in learned.items() if k != "net"},
@@ -652,6 +681,8 @@ def main():
         "peak_random_measured_per_s": 5.1 * clk, "frac_random_measured": rate / (5.1 * clk)}
     if stress:
         out["stress_recovery"] = stress
+    if mixed:
+        out["mixed_precision"] = mixed
     if not args.no_batch and not args.skip_solve:
         out["batch_c3"] = batch_leg(mg, sfem, np)
     if not args.no_es_fem and not args.skip_solve:

@@ -25,9 +25,14 @@ It is a plain, slow, literal reading of the paper (juSFEM, arXiv 2001.08849):
   solve, a banded Cholesky solve (both exact up to rounding) and Jacobi PCG
   judged by the true residual.
 
-Readings taken where the paper is silent or garbled are listed in the design doc
-(exterior Gauss values, outward normal of the smoothing domain, D matrix,
-heterogeneous material, elimination as default BC, consistent traction).
+Where the paper is silent or garbled this module takes these readings: an
+exterior face's domain ABCF is bounded by the face ABC itself and the three
+triangles through F, whose Gauss values follow the rule behind Table 1 (the
+shape functions at each triangle's centroid); normals point out of the smoothing domain;
+D is the standard isotropic matrix in the Voigt order of Eq. 4 (xx, yy, zz,
+yz, xz, xy, engineering shears); a per-tet material enters as the
+volume-weighted Lame constants of the domain; essential BCs are eliminated
+by default; a uniform traction gives each node of a loaded triangle t A / 3.
 """
 from __future__ import annotations
 

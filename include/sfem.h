@@ -211,7 +211,8 @@ typedef struct {
   int mode;           /* SFEM_MODE_* */
   double rtol;        /* on the FP64 true relative residual */
   int max_iter;       /* cap on inner iterations (all outer steps) */
-  int check_every;    /* true-residual period in iterations (0: 50) */
+  int check_every;    /* true-residual period in iterations (0: 100 in
+                         SFEM_MODE_F64, 50 in the FP32 modes) */
   double inner_rtol;  /* F32_IR inner tolerance (0: 1e-2) */
   int max_outer;      /* F32_IR outer-step cap (0: 30) */
   int profile;        /* nonzero: time every SpMV launch with HIP events */

@@ -1249,7 +1249,10 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
                "SFEM_PRECOND_LEARNED needs sfem_gnn_apply on this context first");
   const bool f32 = o.mode == SFEM_MODE_F32_IR;
   ensure_work(c, f32);
-  const int check_every = o.check_every > 0 ? o.check_every : 50;
+  // FP64 products: 100-iteration periods (fewer replacements and host
+  // reads; measured 1-2% faster than 50 for Jacobi and learned M at 1.9M
+  // tets).  FP32 products: 50, to bound their drift between replacements.
+  const int check_every = o.check_every > 0 ? o.check_every : (o.mode == SFEM_MODE_F64 ? 100 : 50);
   const int max_iter = o.max_iter > 0 ? o.max_iter : 100000;
   c.profile = o.profile != 0;
   c.prof_ms = 0;

@@ -594,28 +594,33 @@ enum FinalizeOp {
 };
 
 // One workgroup: adds the partials of the previous kernel in a fixed order
-// and updates the CG scalars.
+// and updates the CG scalars.  The flag and the scalars it reads are loaded
+// together with the partials, so that the launch waits on one memory
+// latency rather than three (flag, then partials, then scalars); a
+// converged solve discards what it loaded.
 __global__ void __launch_bounds__(1024)
     k_finalize(int op, const double* __restrict__ partials, int nparts, CgScalars* __restrict__ sc) {
-  if ((op == kFinAlpha || op == kFinBeta || op == kFinBetaFlex) && sc->converged) return;
+  const int converged = sc->converged;
+  const double rz = sc->rz, iters = sc->aux[0], tol2 = sc->aux[1];
   const int nv = op == kFinAlpha ? 1 : (op >= kFinBetaFlex ? 3 : 2);
   double v[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nparts; b += blockDim.x)
     for (int i = 0; i < nv; ++i) v[i] += partials[b * nv + i];
+  if ((op == kFinAlpha || op == kFinBeta || op == kFinBetaFlex) && converged) return;
   block_sum<3>(v);
   if (threadIdx.x != 0) return;
   switch (op) {
     case kFinAlpha:
       sc->pq = v[0];
-      sc->alpha = sc->rz / v[0];
+      sc->alpha = rz / v[0];
       if (!(v[0] > 0.0) || !isfinite(sc->alpha)) sc->converged = 2;
       break;
     case kFinBeta:
-      sc->beta = v[0] / sc->rz;
+      sc->beta = v[0] / rz;
       sc->rz = v[0];
       sc->rr = v[1];
-      sc->aux[0] += 1.0;                         // iteration count
-      if (v[1] <= sc->aux[1]) sc->converged = 1;  // aux[1]: tolerance^2 on r.r
+      sc->aux[0] = iters + 1.0;                         // iteration count
+      if (v[1] <= tol2) sc->converged = 1;  // aux[1]: tolerance^2 on r.r
       if (!isfinite(v[1])) sc->converged = 2;
       break;
     case kFinReplace:
@@ -637,11 +642,11 @@ __global__ void __launch_bounds__(1024)
     case kFinBetaFlex:
       // r.M r must stay positive: otherwise M is not positive definite
       // along r and the solve reports a breakdown (the host falls back)
-      sc->beta = (v[0] - v[2]) / sc->rz;
+      sc->beta = (v[0] - v[2]) / rz;
       sc->rz = v[0];
       sc->rr = v[1];
-      sc->aux[0] += 1.0;
-      if (v[1] <= sc->aux[1]) sc->converged = 1;
+      sc->aux[0] = iters + 1.0;
+      if (v[1] <= tol2) sc->converged = 1;
       else if (!(v[0] > 0.0) || !isfinite(v[0]) || !isfinite(sc->beta)) sc->converged = 2;
       break;
     case kFinStartM:

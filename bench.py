@@ -370,7 +370,7 @@ def es_fem_leg(prob, sfem, np):
         c.assemble()
         ms.append(c.timings()["ms_assemble"])
     s = c.sizes()
-    tuned = c.autotune(reps=3)
+    tuned = c.autotune(reps=10)
     _, info = c.solve(rtol=1e-8)
     asm = float(np.median(ms))
     abytes = 24 * m.n_nodes + 16 * m.n_tets + 8 * s.nnz

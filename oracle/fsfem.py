@@ -328,6 +328,30 @@ def assemble_rows(xyz, tets, E, nu, nodes, faces=None):
     return out
 
 
+def apply_stiffness(xyz, tets, E, nu, u, faces=None, tet_vol=None):
+    """y = K u without forming K: the sum over smoothing domains of K_k u_k
+    (Eq. 8 / Eq. 9), each K_k the dense 12x12 or 15x15 block of
+    face_stiffness acting on the displacements of the domain's support
+    nodes.  `faces` may hold any subset of the face table (a chunk of rows);
+    the result is then that subset's share of K u."""
+    if faces is None:
+        faces = extract_faces(tets)
+    tab = faces["table"]
+    if tet_vol is None:
+        tet_vol = tet_volume(xyz[tets])
+    u = np.asarray(u, dtype=np.float64)
+    y = np.zeros(u.size)
+    for blk in (tab[tab[:, 4] < 0], tab[tab[:, 4] >= 0]):
+        if not blk.shape[0]:
+            continue
+        K, nodes = face_stiffness(xyz, tets, blk, E, nu, tet_vol)
+        m = nodes.shape[1]
+        dof = (3 * nodes[:, :, None] + np.arange(3)).reshape(-1, 3 * m)
+        yk = np.einsum("fij,fj->fi", K, u[dof])
+        y += np.bincount(dof.reshape(-1), yk.reshape(-1), minlength=u.size)
+    return y
+
+
 # --------------------------------------------------------------- plain FEM-T4
 def face_strain_stress(xyz, tets, E, nu, u, faces=None):
     """Post-processing (Sec. 3.4): the smoothed strain of every smoothing
@@ -442,33 +466,76 @@ def solve_dense(K, f) -> np.ndarray:
 
 def solve_banded(K: sp.csr_matrix, f: np.ndarray) -> np.ndarray:
     """Exact (up to rounding) SPD solve by banded Cholesky (LAPACK pbsv):
-    the x-slowest node numbering keeps the band narrow."""
-    from scipy.linalg import solveh_banded
+    the x-slowest node numbering keeps the band narrow.  The band is stored
+    column-major and factorised in place, so the 1.92M-tet cantilever
+    (bandwidth 5,171 DOFs, 42 GB of band) needs one copy of it."""
     C = K.tocoo()
-    bw = int(np.max(np.abs(C.row - C.col)))
+    bw = int(np.max(np.abs(C.row.astype(np.int64) - C.col)))
     n = K.shape[0]
-    ab = np.zeros((bw + 1, n))
+    ab = np.zeros((bw + 1, n), order="F")
     up = C.col >= C.row
-    r, c, v = C.row[up], C.col[up], C.data[up]
+    r, c, v = C.row[up].astype(np.int64), C.col[up].astype(np.int64), C.data[up]
+    del C, up
     ab[bw + r - c, c] = v
+    del r, c, v
     return solve_banded_ab(ab, f)
 
 
 def solve_banded_ab(ab, f):
     from scipy.linalg import solveh_banded
-    return solveh_banded(ab, f, lower=False, check_finite=False)
+    return solveh_banded(ab, f, lower=False, check_finite=False, overwrite_ab=True)
 
 
-def pcg_jacobi(K, f, rtol=1e-8, max_iter=100000, x0=None, check_every=50):
+def block_row_sums(K: sp.csr_matrix) -> np.ndarray:
+    """R [N, 3, 3] with R_I[a, c] = sum_J K[3I+a, 3J+c]: the 3x3 blocks of a
+    node row summed, i.e. the row's response to a unit translation along c.
+    Each sum is exactly rounded (math.fsum), so R is the row sum of the
+    stored values to one FP64 rounding of R itself."""
+    import math
+    C = K.tocoo()
+    n = K.shape[0]
+    key = 3 * C.row.astype(np.int64) + C.col.astype(np.int64) % 3
+    order = np.argsort(key, kind="stable")
+    key, data = key[order], C.data[order].tolist()
+    bounds = np.flatnonzero(np.concatenate([[True], key[1:] != key[:-1], [True]])).tolist()
+    R = np.zeros(3 * n)
+    for s, e in zip(bounds[:-1], bounds[1:]):
+        R[key[s]] = math.fsum(data[s:e])
+    return R.reshape(n // 3, 3, 3)
+
+
+def apply_translation_form(K: sp.csr_matrix, u: np.ndarray, R=None) -> np.ndarray:
+    """K u written as (K u)_{3I+a} = sum_(J,c) K[3I+a, 3J+c] (u_{3J+c} - u_{3I+c})
+    + sum_c R_I[a, c] u_{3I+c} (R = block_row_sums(K)): the same number in
+    exact arithmetic.  K maps rigid translations to (nearly) zero, so for a
+    smooth u the plain sum cancels terms of size |K||u| down to a small
+    result and keeps their rounding, eps |K| |u|; here the large terms only
+    meet neighbour differences and the rounding is eps |K| |u_J - u_I|."""
+    if R is None:
+        R = block_row_sums(K)
+    C = K.tocoo()
+    n = K.shape[0]
+    rows = C.row.astype(np.int64)
+    own = 3 * (rows // 3) + C.col.astype(np.int64) % 3
+    y = np.bincount(rows, C.data * (u[C.col] - u[own]), minlength=n)
+    return y + np.einsum("iac,ic->ia", R, u.reshape(-1, 3)).reshape(-1)
+
+
+def pcg_jacobi(K, f, rtol=1e-8, max_iter=100000, x0=None, check_every=50, residual=None):
     """Jacobi-preconditioned CG, x0 = 0, stopped when the TRUE relative
     residual ||f - K x|| / ||f|| <= rtol; the true residual replaces the
     recursive one every `check_every` iterations and whenever the recursive
-    one claims convergence.  Returns (x, iterations, true relres)."""
+    one claims convergence.  `residual(x)` (default f - K @ x) computes the
+    true residual, e.g. with apply_translation_form.  Returns (x,
+    iterations, true relres by that residual)."""
     n = K.shape[0]
+    if residual is None:
+        def residual(v):
+            return f - K @ v
     x = np.zeros(n) if x0 is None else x0.copy()
     Dinv = 1.0 / K.diagonal()
     nf = np.linalg.norm(f)
-    r = f - K @ x
+    r = residual(x)
     z = Dinv * r
     p = z.copy()
     rz = r @ z
@@ -480,14 +547,14 @@ def pcg_jacobi(K, f, rtol=1e-8, max_iter=100000, x0=None, check_every=50):
         r -= alpha * q
         it += 1
         if np.linalg.norm(r) <= rtol * nf or it % check_every == 0:
-            r = f - K @ x
+            r = residual(x)
             if np.linalg.norm(r) <= rtol * nf:
                 break
         z = Dinv * r
         rz_new = r @ z
         p = z + (rz_new / rz) * p
         rz = rz_new
-    return x, it, rel_residual(K, x, f)
+    return x, it, float(np.linalg.norm(residual(x)) / nf)
 
 
 # ------------------------------------------------------------ convenience

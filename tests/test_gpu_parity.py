@@ -208,6 +208,33 @@ def test_penalty_bc_matches_oracle():
     assert e <= 1e-12 and eu <= 1e-8
 
 
+def test_penalty_bc_nonzero_values_matches_oracle():
+    """Penalty form with prescribed values ubar != 0: K_ii += alpha and
+    f_i = alpha ubar_i on the GPU equal the oracle's, and so does u."""
+    sfem = _sfem()
+    cs = Case(mg.cantilever_scaled(9, 3, 3, jitter=0.15, seed=4, L=(3.0, 1.0, 1.0)))
+    dofs = cs.p.fixed_dofs()
+    ubar = np.random.default_rng(6).uniform(-1e-4, 1e-4, dofs.size)
+    alpha = 1e4 * cs.K.diagonal().max()
+    Kp, fp = O.apply_penalty(cs.K, cs.f, dofs, alpha, ubar)
+    ctx = sfem.Context(0)
+    m = cs.p.mesh
+    ctx.set_mesh(m.xyz, m.tets)
+    ctx.set_material(cs.p.E, cs.p.nu)
+    ctx.set_dirichlet(dofs, ubar)
+    ctx.set_bc_penalty(alpha)
+    ctx.add_traction(m.end_tris, cs.p.traction)
+    ctx.assemble()
+    rp, ci, va = ctx.csr(sfem.K_WITH_BC)
+    e = row_rel_err(rp, va, Kp)
+    ef = np.abs(ctx.rhs() - fp).max() / np.abs(fp).max()
+    u, info = ctx.solve(rtol=1e-12)
+    ud = O.solve_dense(Kp, fp)
+    eu = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+    print(f"penalty BC, ubar != 0: K error {e:.2e}; rhs error {ef:.2e}; u error {eu:.2e}")
+    assert e <= 1e-12 and ef <= 1e-14 and eu <= 1e-8
+
+
 def test_mesh_errors():
     sfem = _sfem()
     ctx = sfem.Context(0)

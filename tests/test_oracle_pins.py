@@ -276,6 +276,39 @@ def test_traction_total_force():
     np.testing.assert_allclose(f.reshape(-1, 3).sum(0), t * 0.7 * 1.3, rtol=1e-13)
 
 
+def test_traction_per_vertex_by_hand():
+    """Consistent load t A / 3 (Eq. 11 area) on two triangles worked by hand:
+    ABC with A = (0,0,0), B = (3,0,0), C = (0,4,0) has area 6; BDC with
+    D = (3,8,0) has |BD x BC| / 2 = |(0,8,0) x (-3,4,0)| / 2 = 12.  So A gets
+    2t, B and C 2t + 4t = 6t, D 4t, and the unused node nothing."""
+    xyz = np.array([[0, 0, 0], [3, 0, 0], [0, 4, 0], [3, 8, 0], [9, 9, 9]], dtype=np.float64)
+    tris = np.array([[0, 1, 2], [1, 3, 2]])
+    t = np.array([1.0, -2.0, 5.0])
+    f = O.traction_load(xyz, tris, t).reshape(-1, 3)
+    expect = np.array([2, 6, 6, 4, 0], dtype=np.float64)[:, None] * t
+    np.testing.assert_allclose(f, expect, rtol=0, atol=1e-14)
+
+
+def test_penalty_nonzero_values_approach_elimination(c0_K):
+    """Penalty with prescribed values ubar != 0 (K_ii += alpha, f_i = alpha
+    ubar_i) tends to elimination with the same values as alpha grows, with
+    an error that falls like 1/alpha; the fixed DOFs take ubar."""
+    p, K = c0_K
+    f = O.traction_load(p.mesh.xyz, p.mesh.end_tris, p.traction)
+    dofs = p.fixed_dofs()
+    ubar = np.random.default_rng(5).uniform(-1e-3, 1e-3, dofs.size)
+    Kb, fb = O.apply_dirichlet(K, f, dofs, ubar)
+    ue = O.solve_dense(Kb, fb)
+    np.testing.assert_allclose(ue[dofs], ubar, rtol=0, atol=1e-15)
+    errs = []
+    for scale in (1e4, 1e6, 1e8):
+        Kp, fp = O.apply_penalty(K, f, dofs, scale * K.diagonal().max(), ubar)
+        up = O.solve_dense(Kp, fp)
+        errs.append(np.linalg.norm(up - ue) / np.linalg.norm(ue))
+    assert errs[2] < 1e-6
+    assert errs[1] < 2e-2 * errs[0] and errs[2] < 2e-2 * errs[1]
+
+
 def test_penalty_approaches_elimination(c0_K):
     p, K = c0_K
     f = O.traction_load(p.mesh.xyz, p.mesh.end_tris, p.traction)
@@ -387,3 +420,90 @@ def test_face_strain_patch_and_rigid_motions():
     er, sr = O.face_strain_stress(m.xyz, m.tets, E, nu, ur)
     # roundoff only: |u| ~ 1 over cells of ~0.5 gives strains ~1e-15
     assert np.abs(er).max() < 1e-13 and np.abs(sr).max() < 1e-13 * E.max()
+
+
+# ------------------------------------------------- products without a CSR
+def _jittered_blob():
+    p = mg.cantilever_scaled(6, 3, 4, jitter=0.2, seed=11, L=(3.0, 1.0, 1.4))
+    T = p.mesh.n_tets
+    rng = np.random.default_rng(12)
+    return p, 10.0 ** rng.uniform(9, 11, T), rng.uniform(0.25, 0.45, T)
+
+
+def test_apply_stiffness_equals_assembled_product():
+    """sum_k K_k u_k over the face table (no CSR) equals the assembled K u,
+    also when the face table is split into chunks whose shares are summed."""
+    p, E, nu = _jittered_blob()
+    m = p.mesh
+    faces = O.extract_faces(m.tets)
+    K = O.assemble(m.xyz, m.tets, E, nu, faces)
+    u = np.random.default_rng(13).standard_normal(K.shape[0])
+    y = O.apply_stiffness(m.xyz, m.tets, E, nu, u, faces)
+    ref = K @ u
+    tab = faces["table"]
+    half = tab.shape[0] // 3
+    y2 = sum(O.apply_stiffness(m.xyz, m.tets, E, nu, u, {"table": t})
+             for t in (tab[:half], tab[half:]))
+    scale = np.abs(K) @ np.abs(u)
+    assert np.abs(y - ref).max() <= 1e-13 * scale.max()
+    assert np.abs(y2 - ref).max() <= 1e-13 * scale.max()
+
+
+def test_block_row_sums_exact():
+    """R_I[a, c] = sum_J K[3I+a, 3J+c] against exactly rounded sums (fsum)
+    of the dense matrix, on the BC-applied stiffness."""
+    import math
+    Kb, fb, _ = O.problem_system(mg.cantilever_c0())
+    R = O.block_row_sums(Kb)
+    D = Kb.toarray()
+    N = D.shape[0] // 3
+    for I in range(N):
+        for a in range(3):
+            for c in range(3):
+                exact = math.fsum(D[3 * I + a, c::3])
+                assert R[I, a, c] == exact
+
+
+def test_translation_form_equals_plain_product():
+    """On a random vector the translation form of K u equals the plain
+    product to within the plain product's own rounding."""
+    p, E, nu = _jittered_blob()
+    m = p.mesh
+    K = O.assemble(m.xyz, m.tets, E, nu)
+    f = O.traction_load(m.xyz, m.end_tris, p.traction)
+    Kb, _ = O.apply_dirichlet(K, f, p.fixed_dofs())
+    u = np.random.default_rng(14).standard_normal(K.shape[0])
+    y = O.apply_translation_form(Kb, u)
+    scale = (np.abs(Kb) @ np.abs(u)).max()
+    assert np.abs(y - Kb @ u).max() <= 1e-14 * scale
+
+
+def test_translation_form_is_accurate_on_offset_fields():
+    """A linear field with a large rigid offset, u = A x + c.  The product
+    of the stored K with it, computed exactly in rational arithmetic on
+    interior rows, is a small difference of terms of size |K| |c|: the plain
+    product's rounding is of that size, eps |K| |c|, the translation form's
+    only eps |K| |A| h (neighbour differences), so it is far closer."""
+    from fractions import Fraction
+    p, E, nu = _jittered_blob()
+    m = p.mesh
+    K = O.assemble(m.xyz, m.tets, 210e9, 0.3)
+    A = np.array([[1e-3, 2e-4, -3e-4], [5e-4, -1e-3, 1e-4], [2e-4, 3e-4, 7e-4]])
+    u = (m.xyz @ A.T + np.array([1e3, -2e3, 5e2])).reshape(-1)
+    inner = np.ones(m.n_nodes, dtype=bool)
+    for ax in range(3):
+        inner &= ~np.isclose(m.xyz[:, ax], 0.0) & ~np.isclose(m.xyz[:, ax], m.lengths[ax])
+    rows = (3 * np.flatnonzero(inner)[:8, None] + np.arange(3)).reshape(-1)
+    plain, tf = K @ u, O.apply_translation_form(K, u)
+    ep = et = 0.0
+    for i in rows:
+        lo, hi = K.indptr[i], K.indptr[i + 1]
+        exact = float(sum(Fraction(float(v)) * Fraction(float(u[j]))
+                          for v, j in zip(K.data[lo:hi], K.indices[lo:hi])))
+        ep = max(ep, abs(plain[i] - exact))
+        et = max(et, abs(tf[i] - exact))
+    scale = (np.abs(K) @ np.full(K.shape[0], np.abs(A).max())).max()   # |K| |A| (1 m)
+    print(f"interior rows of K (A x + c), error vs exact: plain {ep:.2e}, "
+          f"translation form {et:.2e}; |K||A| {scale:.2e}")
+    assert ep > 1e3 * et
+    assert et <= 1e-14 * scale

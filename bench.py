@@ -38,14 +38,25 @@ def log(*a):
 
 def algorithmic_bytes(N, T, nf, nnz, nb, f32_copy=False, per_tet=False):
     """Bytes the method itself must move per launch (no re-reads, no
-    intermediates): assembly reads coordinates and the face table and writes
-    every CSR value once; the CG SpMV reads each value once, the block
-    column list, the row offsets, x, and writes y."""
+    intermediates).  Assembly: coordinates, tets and the face table read,
+    every CSR value written once.  The CG product counted as a scalar CSR
+    SpMV (12 bytes per nonzero: FP64 value + int32 column, row offsets, x
+    read and y written once), the reference count the roofline uses; the
+    library's block format moves less (its own count: format_bytes)."""
     n = 3 * N
-    asm = 24 * N + 32 * nf + 8 * nnz + (4 * nnz if f32_copy else 0) + (16 * T if per_tet else 0)
-    spmv64 = 8 * nnz + 4 * nb + 4 * (N + 1) + 8 * n + 8 * n
-    spmv32 = 4 * nnz + 4 * nb + 4 * (N + 1) + 4 * n + 4 * n
+    asm = 24 * N + 16 * T + 32 * nf + 8 * nnz + (4 * nnz if f32_copy else 0) + \
+        (16 * T if per_tet else 0)
+    spmv64 = 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
+    spmv32 = 8 * nnz + 4 * (n + 1) + 4 * n + 4 * n
     return asm, spmv64, spmv32
+
+
+def format_bytes(N, nnz, nb):
+    """What the block-pattern product itself must read and write: each FP64
+    value once, one int32 block column per 9 values, node-row offsets, x
+    once and y once."""
+    n = 3 * N
+    return 8 * nnz + 4 * nb + 4 * (N + 1) + 8 * n + 8 * n
 
 
 def mapply_bytes(N, nnz, nb):
@@ -200,46 +211,129 @@ CPU_SNIPPET = r"""
 import os, sys, time, json
 sys.path.insert(0, {root!r})
 import numpy as np
+import scipy.sparse as sp
 from oracle import fsfem as O
 from paper_2001_08849_amd import meshgen as mg
-p = mg.cantilever_c2()
-m = p.mesh
-faces = O.extract_faces(m.tets)["table"]          # topology, not timed
-S = {sample}
-sub = faces[:S]
-t0 = time.perf_counter()
-vol = O.tet_volume(m.xyz[m.tets])
-parts = []
-for blk in (sub[sub[:, 4] < 0], sub[sub[:, 4] >= 0]):
-    if blk.shape[0]:
-        K, nodes = O.face_stiffness(m.xyz, m.tets, blk, p.E, p.nu, vol)
-        parts.append(O._coo_block(K, nodes))
-import scipy.sparse as sp
-I = np.concatenate([q[0] for q in parts]); J = np.concatenate([q[1] for q in parts])
-V = np.concatenate([q[2] for q in parts])
-Ks = sp.coo_matrix((V, (I, J)), shape=(3 * m.n_nodes,) * 2).tocsr()
-dt = time.perf_counter() - t0
-print(json.dumps({{"faces": int(S), "seconds": dt, "faces_per_s": S / dt}}))
+
+W = {{}}
+
+def init(xyz, tets, E, nu, vol, n):
+    W.update(xyz=xyz, tets=tets, E=E, nu=nu, vol=vol, n=n)
+
+def assemble_share(sub):
+    xyz, tets, E, nu, vol, n = W["xyz"], W["tets"], W["E"], W["nu"], W["vol"], W["n"]
+    parts = []
+    for blk in (sub[sub[:, 4] < 0], sub[sub[:, 4] >= 0]):
+        if blk.shape[0]:
+            K, nodes = O.face_stiffness(xyz, tets, blk, E, nu, vol)
+            parts.append(O._coo_block(K, nodes))
+    I = np.concatenate([q[0] for q in parts]); J = np.concatenate([q[1] for q in parts])
+    V = np.concatenate([q[2] for q in parts])
+    return sp.coo_matrix((V, (I, J)), shape=(n, n)).tocsr().nnz
+
+if __name__ == "__main__":
+    what = {what!r}
+    out = {{}}
+    p = mg.cantilever_c2()
+    m = p.mesh
+    n = 3 * m.n_nodes
+    faces = O.extract_faces(m.tets)["table"]          # topology, not timed
+    S = {sample}
+    sub = faces[:S]
+    if what == "single":
+        t0 = time.perf_counter()
+        vol = O.tet_volume(m.xyz[m.tets])
+        init(m.xyz, m.tets, p.E, p.nu, vol, n)
+        assemble_share(sub)
+        dt = time.perf_counter() - t0
+        out = {{"faces": int(S), "seconds": dt, "faces_per_s": S / dt}}
+        # Jacobi PCG of the 60k-tet cantilever, solve only (assembly untimed)
+        p1 = mg.cantilever_c1()
+        Kb, fb, _ = O.problem_system(p1)
+        t0 = time.perf_counter()
+        x, it, rr = O.pcg_jacobi(Kb, fb, rtol=1e-8)
+        dt = time.perf_counter() - t0
+        out["c1_jacobi"] = {{"seconds": dt, "iters": it, "true_relres": rr, "nnz": int(Kb.nnz)}}
+    else:
+        import multiprocessing as mpr
+        w = int(what)
+        vol = O.tet_volume(m.xyz[m.tets])
+        chunks = np.array_split(sub, 4 * w)
+        with mpr.get_context("spawn").Pool(w, initializer=init,
+                                           initargs=(m.xyz, m.tets, p.E, p.nu, vol, n)) as pool:
+            pool.map(assemble_share, [sub[:64]] * w)       # workers started and warm
+            t0 = time.perf_counter()
+            pool.map(assemble_share, chunks)
+            dt = time.perf_counter() - t0
+        out = {{"faces": int(S), "seconds": dt, "faces_per_s": S / dt, "workers": w}}
+    print(json.dumps(out))
 """
 
 
-def cpu_baseline(sample_faces: int):
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample_faces: int, c2_iters=None, c2_nnz=None):
+    """The FP64 oracle on the host cores: numeric assembly of a sample of
+    the 1.92M-tet cantilever's faces on one thread (the reported value) and
+    on every available core (one process each, face chunks), plus the
+    oracle's Jacobi PCG of the 60k-tet cantilever on one thread (solve only),
+    from which the 1.92M-tet solve is extrapolated by nnz and the GPU's
+    iteration count (not measured: it would take the oracle ~20 minutes)."""
+    one = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
                MKL_NUM_THREADS="1", NUMEXPR_NUM_THREADS="1")
-    code = CPU_SNIPPET.format(root=ROOT, sample=sample_faces)
-    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=600)
-    if res.returncode != 0:
-        log("cpu baseline failed:", res.stderr[-2000:])
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(16, cores))
+
+    import tempfile
+
+    def run(what):
+        # a script file, not -c: the worker processes re-import it by path
+        code = CPU_SNIPPET.format(root=ROOT, sample=sample_faces, what=what)
+        with tempfile.TemporaryDirectory() as tmp:
+            path = os.path.join(tmp, "oracle_cpu_baseline.py")
+            with open(path, "w") as fh:
+                fh.write(code)
+            res = subprocess.run([sys.executable, path], capture_output=True, text=True,
+                                 env=one, timeout=900)
+        if res.returncode != 0:
+            log("cpu baseline failed:", res.stderr[-2000:])
+            return None
+        return json.loads(res.stdout.strip().splitlines()[-1])
+
+    rec = run("single")
+    if rec is None:
         return None
-    rec = json.loads(res.stdout.strip().splitlines()[-1])
-    return {
+    par = run(str(workers))
+    out = {
         "value": rec["faces_per_s"], "unit": "faces/s", "cores": 1, "kind": "oracle",
         "sample": (f"FP64 oracle numeric assembly (Eq. 7 + Table 1 smoothed gradients, "
                    f"Eq. 9 face stiffness, Eq. 12 COO -> CSR) of the first {rec['faces']} "
                    f"faces of the 1.92M-tet cantilever, topology excluded; "
                    f"{rec['seconds']:.1f} s on one host thread"),
+        "cpu_model": _cpu_model(), "host_cores_available": cores,
     }
+    if par:
+        out["all_cores"] = {"value": par["faces_per_s"], "unit": "faces/s",
+                            "cores": par["workers"], "seconds": par["seconds"],
+                            "how": "the same faces in chunks over one process per core"}
+    j = rec["c1_jacobi"]
+    out["oracle_jacobi_c1"] = dict(j, cores=1, what="scipy CSR Jacobi PCG of the 60k-tet "
+                                                    "cantilever to a true relres of 1e-8, "
+                                                    "solve only")
+    if c2_iters and c2_nnz:
+        per_it = j["seconds"] / j["iters"] * c2_nnz / j["nnz"]
+        out["oracle_jacobi_c2_extrapolated"] = {
+            "seconds": per_it * c2_iters, "per_iteration_s": per_it, "iters": c2_iters,
+            "how": "c1 seconds per iteration x nnz ratio x the GPU's c2 iteration count"}
+    return out
 
 
 def copy_calibration():
@@ -271,6 +365,11 @@ def train_network(args, mg, sfem, np):
     """Trains the learned preconditioner on blob-material cantilevers of
     140x14x14 cells (164,640 tets each): pairs from Jacobi-PCG runs, Adam on
     the device.  Returns the network and the training record."""
+    if args.weights:
+        net = sfem.Gnn(0, seed=5)
+        net.load(args.weights)
+        log(f"[bench] network loaded from {args.weights} (no pairs or training)")
+        return {"net": net, "loaded_from": args.weights, "pairs": 0, "steps": 0}
     if args.train_steps <= 0:
         # untrained network (M = Jacobi exactly): exercises the learned
         # solve's kernels at full size without the training meshes
@@ -296,6 +395,9 @@ def train_network(args, mg, sfem, np):
         f"{losses[:20].mean():.4f} -> {losses[-100:].mean():.4f}")
     for c in ctxs:
         c.close()
+    if args.save_weights:
+        net.save(args.save_weights)
+        log(f"[bench] network written to {args.save_weights}")
     held = make_context(sfem)
     sfem.setup_problem(held, mg.learned_c4(0, held_out=True))
     _, ij = held.solve(rtol=1e-8)
@@ -383,12 +485,18 @@ def es_fem_leg(prob, sfem, np):
     return res
 
 
-def mixed_precision_leg(ctx, sfem, u, inner_rtol):
-    """FP32/FP64 refinement on the same cantilever, outside the timed steps:
-    K assembled again with its FP32 copy and both row schedules retuned, then
-    the FP32-inner-CG refinement (FP64 outer residuals) and the CG with FP32
-    products and FP64 residual replacement, once each, each judged by the FP64
-    true relative residual (1e-8)."""
+def mixed_precision_leg(ctx, sfem, u, inner_rtol, net, np, uref, reps=3):
+    """FP32 matrix values with FP64 refinement on the same cantilever,
+    outside the timed steps: K assembled again with its FP32 copy and both
+    row schedules retuned; then, each judged by the FP64 true relative
+    residual (1e-8):
+      - FP32-inner-CG refinement (FP64 outer residuals), once;
+      - CG with FP32 products and FP64 residual replacement, restarted in
+        FP64 at 1e-3, once;
+      - CG with FP32 values in the translation form of the product, FP64
+        vectors and residual replacement, no restart: Jacobi and (with a
+        network) the learned M, median of `reps` solves each (the learned
+        one plus its inference)."""
     ctx.assemble(f32_copy=True)
     tuned = ctx.autotune(reps=3)
     _, ir = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_IR, inner_rtol=inner_rtol)
@@ -401,7 +509,56 @@ def mixed_precision_leg(ctx, sfem, u, inner_rtol):
         res[name] = {"solve_s": i["ms_solve"] * 1e-3, "iters": i["iters"],
                      "outer_steps": i["outer_steps"], "true_relres": i["true_relres"],
                      "converged": bool(i["converged"])}
+    runs = []
+    for _ in range(reps):
+        _, i = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF)
+        runs.append(i)
+    i = runs[-1]
+    res["f32_translation_form_jacobi"] = {
+        "solve_s": float(np.median([r["ms_solve"] for r in runs])) * 1e-3, "iters": i["iters"],
+        "true_relres": i["true_relres"], "converged": bool(i["converged"]),
+        "u_error_vs_oracle": u_error(np, u, uref)}
+    log(f"[bench] FP32 translation-form products, Jacobi: "
+        f"{res['f32_translation_form_jacobi']['solve_s'] * 1e3:.0f} ms, {i['iters']} it, relres "
+        f"{i['true_relres']:.2e}")
+    if net is not None:
+        runs = []
+        for _ in range(reps):
+            ms_inf = net.apply(ctx)
+            _, i = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF,
+                             precond=sfem.PRECOND_LEARNED)
+            i["ms_inference"] = ms_inf
+            runs.append(i)
+        i = runs[-1]
+        ls = float(np.median([r["ms_solve"] for r in runs])) * 1e-3
+        li = float(np.median([r["ms_inference"] for r in runs])) * 1e-3
+        res["f32_translation_form_learned"] = {
+            "solve_s": ls, "inference_s": li, "solve_incl_inference_s": ls + li,
+            "iters": i["iters"], "true_relres": i["true_relres"],
+            "converged": bool(i["converged"]), "fell_back": i["fell_back"],
+            "u_error_vs_oracle": u_error(np, u, uref)}
+        log(f"[bench] FP32 translation-form products, learned M: {ls * 1e3:.0f} ms + inference "
+            f"{li * 1e3:.0f} ms, {i['iters']} it, relres {i['true_relres']:.2e}, fell back "
+            f"{i['fell_back']}")
     return res
+
+
+REF_U = os.path.join(ROOT, "tests", "golden", "c2_u_ref.npz")
+
+
+def load_uref(np):
+    """The oracle's displacements of the 1.92M-tet cantilever (written by
+    tests/golden/make_c2_reference.py), if present."""
+    if not os.path.exists(REF_U):
+        return None
+    return np.load(REF_U)["u"]
+
+
+def u_error(np, u, uref):
+    """Relative L2 distance of u from the oracle's displacements."""
+    if uref is None:
+        return None
+    return float(np.linalg.norm(u - uref) / np.linalg.norm(uref))
 
 
 def batch_leg(mg, sfem, np):
@@ -457,6 +614,10 @@ def main():
                     help="skip training and the learned-preconditioner solve")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--train-meshes", type=int, default=4)
+    ap.add_argument("--weights", default="", metavar="PATH",
+                    help="load the network from this weights file instead of training it")
+    ap.add_argument("--save-weights", default="", metavar="PATH",
+                    help="write the trained network to this weights file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -540,6 +701,7 @@ def main():
         log(f"[bench] warmup {w}: assembly {ms_asm:.3f} ms" +
             (f", solve {info['ms_solve']:.1f} ms ({info['iters']} it)" if info else ""))
 
+    uref = load_uref(np)
     ctx.synchronize()
     ctx.timer_start()
     asm_ms, solves = [], []
@@ -553,6 +715,7 @@ def main():
              f"{info['true_relres']:.2e}" if info else ""))
     total_ms = ctx.timer_stop()
     ctx.synchronize()
+    err_jacobi = u_error(np, u, uref) if solves else None
     # per-launch timing of the CG product (events around every launch, so
     # every launch is eager): one more solve, outside the timed steps
     prof = None
@@ -587,6 +750,7 @@ def main():
                 log(f"[bench] profiled learned solve: {info['ms_solve']:.1f} ms, M apply "
                     f"{info['ms_mapply_avg'] * 1e3:.1f} us per launch")
                 continue
+            info["u_error_vs_oracle"] = u_error(np, u, uref)
             lsolves.append(info)
             pinfo = ctx.precond_info()
             log(f"[bench] learned {k}: inference {ms_inf:.1f} ms (theta {pinfo['theta']:.3f}), "
@@ -597,7 +761,8 @@ def main():
     theta = ctx.precond_info()["theta"] if lsolves else None
     mixed = None
     if not args.skip_solve and not args.no_mixed and not args.f32_ir:
-        mixed = mixed_precision_leg(ctx, sfem, u, args.inner_rtol)
+        mixed = mixed_precision_leg(ctx, sfem, u, args.inner_rtol,
+                                    learned["net"] if learned else None, np, uref)
 
     asm_med = float(np.median(asm_ms))
     faces_per_s = s.n_faces / (asm_med * 1e-3)
@@ -631,6 +796,10 @@ def main():
         out["solve_s"] = {"jacobi_f64": float(np.median([i["ms_solve"] for i in solves])) / 1e3}
         out["solve_iters"] = {"jacobi_f64": solves[-1]["iters"]}
         out["solve_true_relres"] = {"jacobi_f64": solves[-1]["true_relres"]}
+        out["u_error_vs_oracle"] = {
+            "jacobi_f64": err_jacobi,
+            "reference": "tests/golden/c2_u_ref.npz (FP64 oracle: PCG + translation-form "
+                         "refinement, own error estimate in c2_u_ref.txt)"}
         if lsolves:
             ls = float(np.median([i["ms_solve"] for i in lsolves])) / 1e3
             li = float(np.median([i["ms_inference"] for i in lsolves])) / 1e3
@@ -638,6 +807,7 @@ def main():
             out["solve_s"]["learned_incl_inference"] = ls + li
             out["solve_iters"]["learned"] = lsolves[-1]["iters"]
             out["solve_true_relres"]["learned"] = lsolves[-1]["true_relres"]
+            out["u_error_vs_oracle"]["learned"] = lsolves[-1]["u_error_vs_oracle"]
             mms = lprof["ms_mapply_avg"]
             mb = mapply_bytes(m.n_nodes, s.nnz, s.n_blocks)
             ach_m = mb / (mms * 1e-3) / 1e9 if mms > 0 else None
@@ -657,12 +827,17 @@ def main():
             }
         spmv_ms = prof["ms_spmv_avg"]
         ach = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+        fb = format_bytes(m.n_nodes, s.nnz, s.n_blocks)
         out["roofline"] = {"kernel": f"k_cg_spmv<double,double> (row schedule "
                                      f"{tuned['f64'][0][0]})", "bound": "hbm",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS,
                            "traffic": read_traffic("cg_spmv_f64_c2"),
-                           "bytes_per_launch": spmv_bytes, "us_per_launch": spmv_ms * 1e3}
+                           "bytes_per_launch": spmv_bytes,
+                           "bytes_note": "scalar CSR SpMV count: 12 nnz + 4 (n+1) + 16 n",
+                           "format_bytes_per_launch": fb,
+                           "format_frac": fb / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "us_per_launch": spmv_ms * 1e3}
     ach_a = asm_bytes / (asm_med * 1e-3) / 1e9
     out["roofline_assembly"] = {"kernel": "k_assemble<false>", "bound": "hbm", "achieved": ach_a,
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_a / HBM_PEAK_GBS,
@@ -690,8 +865,9 @@ def main():
     if not args.no_renumbering and not args.skip_solve:
         out["renumbering"] = renumbering_leg(prob, sfem, np, tuned["f64"][0])
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle, 1 thread) ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        log("[bench] cpu baseline (oracle: 1 thread and all cores) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample,
+                                           solves[-1]["iters"] if solves else None, s.nnz)
     out["context"] = {"paper_assembly_faces_per_s_24core": 4.2e5,
                       "paper_note": "derived: ~4.15M faces / ~10 s on a 24-core Xeon 5118, "
                                     "TetGen mesh of 2.08M tets, direct solver; not comparable"}

@@ -60,7 +60,7 @@ enum {
 
 /* Solver choices (sfem_solve_opts). */
 enum { SFEM_PRECOND_JACOBI = 0, SFEM_PRECOND_LEARNED = 1 };
-enum { SFEM_MODE_F64 = 0, SFEM_MODE_F32_IR = 1, SFEM_MODE_F32_RR = 2 };
+enum { SFEM_MODE_F64 = 0, SFEM_MODE_F32_IR = 1, SFEM_MODE_F32_RR = 2, SFEM_MODE_F32_TF = 3 };
 
 /* ----------------------------------------------------------------------------
  * Context.  `device` is a HIP device ordinal; `hip_stream` is a hipStream_t
@@ -330,6 +330,20 @@ const char* sfem_gnn_last_error(const sfem_gnn* g);
  * set_params also resets the Adam state. */
 int sfem_gnn_get_params(sfem_gnn* g, float* params, int64_t n);
 int sfem_gnn_set_params(sfem_gnn* g, const float* params, int64_t n);
+
+/* Weights file of a network (so that a trained network is not retrained).
+ * Layout: eight little-endian uint32 header words -- magic 0x4e474653 (the
+ * bytes "SFGN"), format version 1, width 64, layers 4, node features 8,
+ * edge features 12, parameter count (sfem_gnn_num_params()), 0 -- then the
+ * parameters as little-endian float32 in the order of sfem_gnn_get_params.
+ * save writes the FP32 master copy; load checks every header word, the
+ * length and that each value is finite, then sets the parameters and resets
+ * the Adam state (as sfem_gnn_set_params).  Errors (SFEM_EINVAL, message in
+ * sfem_gnn_last_error): unopenable file, short write, wrong magic, another
+ * version or network shape, truncated or oversized file, non-finite value.
+ * A failed load leaves the network unchanged. */
+int sfem_precond_save(sfem_gnn* g, const char* path);
+int sfem_precond_load(sfem_gnn* g, const char* path);
 
 /* Training pairs of a context: r, e float32 [n_pairs][3 n_nodes] (ptr_kind),
  * copied; r should be K_bc e.  Replaces earlier pairs. */

@@ -118,6 +118,19 @@ def relu(v):
     return np.maximum(v, 0.0)
 
 
+def sum_by_row(g: Graph, v):
+    """out[I] = sum of v over the edges (I, J) of node row I.  Edges are
+    stored row by row (block CSR) and every row holds at least its self
+    edge, so the rows are the consecutive segments starting at bptr."""
+    return np.add.reduceat(v, g.bptr[:-1], axis=0)
+
+
+def sum_by_col(g: Graph, v):
+    """out[I] = sum of v over the edges (J, I) whose column is I: the
+    transposes of row I's edges, tr[k] for k in row I."""
+    return np.add.reduceat(v[g.tr], g.bptr[:-1], axis=0)
+
+
 def forward(P, g: Graph, layers: int = N_LAYERS):
     """Returns S' blocks [nb,3,3] and a cache for backward."""
     c = {}
@@ -129,9 +142,7 @@ def forward(P, g: Graph, layers: int = N_LAYERS):
         z = X @ P[f"W{l}"].T + P[f"b{l}"]
         m = relu(z)
         e = e + m
-        a = np.zeros_like(h)
-        np.add.at(a, g.row, m)
-        a /= g.deg[:, None]
+        a = sum_by_row(g, m) / g.deg[:, None]
         Y = np.concatenate([h, a], axis=1)
         t = Y @ P[f"U{l}"].T + P[f"c{l}"]
         h = h + relu(t)
@@ -178,8 +189,7 @@ def apply_M(g: Graph, Sp, r):
     N = g.N
     rb = rh.reshape((N, 3) + rh.shape[1:])
     contrib = np.einsum("kab,kb...->ka...", Sp, rb[g.bcol])
-    yb = y.reshape((N, 3) + rh.shape[1:])
-    np.add.at(yb, g.row, contrib)
+    yb = y.reshape((N, 3) + rh.shape[1:]) + sum_by_row(g, contrib)
     return (yb.reshape(rh.shape).T * s).T
 
 
@@ -233,8 +243,7 @@ def backward(P, g: Graph, K, Rm, Em, layers: int = N_LAYERS):
         grads[f"W{l}"] = dz.T @ X
         grads[f"b{l}"] = dz.sum(axis=0)
         dX = dz @ P[f"W{l}"]
-        np.add.at(dh, g.row, dX[:, :Hw])
-        np.add.at(dh, g.bcol, dX[:, Hw:2 * Hw])
+        dh = dh + sum_by_row(g, dX[:, :Hw]) + sum_by_col(g, dX[:, Hw:2 * Hw])
         de = de + dX[:, 2 * Hw:]
     dz0 = de * (c["e0"] > 0)
     grads["We"] = dz0.T @ g.y

@@ -1,6 +1,11 @@
 // extern "C" entry points of include/sfem.h.  Every call catches the
 // library's internal errors and turns them into an sfem_status plus a
 // message kept on the context.
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
 #include "handles.h"
 
 using sfem::Ctx;
@@ -365,6 +370,7 @@ int sfem_assemble(sfem_ctx* h, int flags) {
     c.have_learned = false;
     c.gnn.reset();
     c.packed64 = c.packed32 = false;
+    c.have_rsum = false;
     const int64_t nnz = 9 * c.topo.nb;
     c.val.reserve(nnz);
     const bool f32 = (flags & SFEM_ASM_F32_COPY) != 0;
@@ -730,6 +736,75 @@ int sfem_gnn_set_params(sfem_gnn* h, const float* params, int64_t n) {
     SFEM_HIP(hipDeviceSynchronize());
     const std::vector<float> zero(n, 0.f);
     SFEM_HIP(hipMemcpy(g.params.get(), params, sizeof(float) * n, hipMemcpyHostToDevice));
+    SFEM_HIP(hipMemcpy(g.adam_m.get(), zero.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    SFEM_HIP(hipMemcpy(g.adam_v.get(), zero.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    g.adam_t = 0;
+    return SFEM_OK;
+  });
+}
+
+// Weights file: eight little-endian uint32 header words (magic "SFGN",
+// format version, width, layers, node features, edge features, parameter
+// count, 0), then the parameters as float32 in the order of
+// sfem_gnn_get_params.
+namespace {
+constexpr uint32_t kWeightsMagic = 0x4e474653u;  // bytes 'S' 'F' 'G' 'N'
+constexpr uint32_t kWeightsVersion = 1;
+
+void weights_header(uint32_t (&h)[8]) {
+  const uint32_t n = uint32_t(sfem::param_layout().total);
+  const uint32_t v[8] = {kWeightsMagic, kWeightsVersion, uint32_t(sfem::kH),
+                         uint32_t(sfem::kLayers), uint32_t(sfem::kFNode),
+                         uint32_t(sfem::kFEdge), n, 0u};
+  for (int i = 0; i < 8; ++i) h[i] = v[i];
+}
+}  // namespace
+
+int sfem_precond_save(sfem_gnn* h, const char* path) {
+  return gnn_guarded(h, [&](sfem::Gnn& g) {
+    SFEM_REQUIRE(path != nullptr, SFEM_EINVAL, "null path");
+    const int64_t n = sfem::param_layout().total;
+    std::vector<float> host(n);
+    SFEM_HIP(hipDeviceSynchronize());
+    SFEM_HIP(hipMemcpy(host.data(), g.params.get(), sizeof(float) * n, hipMemcpyDeviceToHost));
+    uint32_t hdr[8];
+    weights_header(hdr);
+    FILE* f = std::fopen(path, "wb");
+    SFEM_REQUIRE(f != nullptr, SFEM_EINVAL, std::string("cannot open for writing: ") + path);
+    const bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+                    std::fwrite(host.data(), sizeof(float), size_t(n), f) == size_t(n);
+    const bool closed = std::fclose(f) == 0;
+    SFEM_REQUIRE(ok && closed, SFEM_EINVAL, std::string("write failed: ") + path);
+    return SFEM_OK;
+  });
+}
+
+int sfem_precond_load(sfem_gnn* h, const char* path) {
+  return gnn_guarded(h, [&](sfem::Gnn& g) {
+    SFEM_REQUIRE(path != nullptr, SFEM_EINVAL, "null path");
+    FILE* f = std::fopen(path, "rb");
+    SFEM_REQUIRE(f != nullptr, SFEM_EINVAL, std::string("cannot open: ") + path);
+    const int64_t n = sfem::param_layout().total;
+    uint32_t hdr[8], want[8];
+    weights_header(want);
+    std::vector<float> host(n);
+    const bool got_hdr = std::fread(hdr, sizeof(hdr), 1, f) == 1;
+    bool same = got_hdr;
+    for (int i = 0; same && i < 8; ++i) same = hdr[i] == want[i];
+    const bool got = same && std::fread(host.data(), sizeof(float), size_t(n), f) == size_t(n);
+    const bool at_end = got && std::fgetc(f) == EOF;
+    std::fclose(f);
+    SFEM_REQUIRE(got_hdr && hdr[0] == kWeightsMagic, SFEM_EINVAL,
+                 std::string("not a weights file: ") + path);
+    SFEM_REQUIRE(same, SFEM_EINVAL,
+                 std::string("weights file of another format version or network shape: ") + path);
+    SFEM_REQUIRE(got && at_end, SFEM_EINVAL, std::string("truncated or oversized weights file: ") + path);
+    for (int64_t i = 0; i < n; ++i)
+      SFEM_REQUIRE(std::isfinite(host[i]), SFEM_EINVAL,
+                   std::string("non-finite parameter in weights file: ") + path);
+    SFEM_HIP(hipDeviceSynchronize());
+    const std::vector<float> zero(n, 0.f);
+    SFEM_HIP(hipMemcpy(g.params.get(), host.data(), sizeof(float) * n, hipMemcpyHostToDevice));
     SFEM_HIP(hipMemcpy(g.adam_m.get(), zero.data(), sizeof(float) * n, hipMemcpyHostToDevice));
     SFEM_HIP(hipMemcpy(g.adam_v.get(), zero.data(), sizeof(float) * n, hipMemcpyHostToDevice));
     g.adam_t = 0;

@@ -129,6 +129,12 @@ struct Ctx {
   bool packed64 = false, packed32 = false;
   DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
   DBuf<float> dinv32;
+  // [N][9] block row sums of K_bc: R_I[a][c] = sum_J K_bc[3I+a][3J+c] (the
+  // row's response to a unit translation along c), each compensated-summed
+  // and rounded once; they let products run in the translation form
+  // (valid while have_rsum, remade after every assembly)
+  DBuf<double> rsum;
+  bool have_rsum = false;
 
   // learned preconditioner M = diag(msqrt) (I + S') diag(msqrt), S' in the
   // scalar-CSR value layout of K

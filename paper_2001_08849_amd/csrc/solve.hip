@@ -2,19 +2,28 @@
 // solve of K u = f (the paper solves with a direct method; this library
 // replaces it by PCG judged by the FP64 true residual).
 //
-// SpMV: one wavefront per node row I.  The 3 scalar rows 3I..3I+2 are
-// contiguous in the CSR values (9 deg(I) numbers), so the wave streams them
-// with unit stride; the column of value k is 3*bcol[jj] + c, read from the
-// node's block-column list (9 values share one entry), and the three row
-// sums are reduced with wavefront shuffles.
+// Products: a group of LPR lanes (4 to 64, a power of two) per node row I.
+// The three scalar rows 3I..3I+2 share the row's block-column list, so one
+// gather of x_J serves three sums, reduced across the group with shuffles.
+// Two value layouts: the CSR order of the scalar matrix (row schedules 0-13:
+// one or two rows per step, an unrolled column loop, nontemporal value
+// loads), and a packed copy in which node row I is a [9][deg rounded up to
+// 4] array read four blocks per lane with 16-byte loads (schedules 14-16).
+// The autotuner times every schedule inside PCG iterations and keeps the
+// fastest.  Grids are XCD-banded (for_rows).  The translation form
+// (row3p's DIFF) multiplies neighbour differences x_J - x_I and adds
+// R_I x_I, the FP64 block row sum: the true residual of every solve and the
+// products of SFEM_MODE_F32_TF use it.
 //
 // PCG: x0 = 0; each iteration is
 //   p = z + beta p;   q = K p with (p.q) -> alpha;   x, r, z updates with
 //   (r.z), (r.r) -> beta and a device-side convergence flag.
-// Dot products are FP64 partial sums per workgroup; the last workgroup to
-// finish (atomic ticket) reduces the partials in a fixed order, so results
-// are bit-reproducible.  Every `check_every` iterations the residual is
-// replaced by the true one, r = f - K x, whose norm the host reads.
+// Dot products are FP64 partial sums per workgroup, added in a fixed order
+// by a separate one-workgroup k_finalize launch (no device-scope fences;
+// results are bit-reproducible).  Every `check_every` iterations the
+// residual is replaced by the true one, r = f - K x, whose norm the host
+// reads; the iterations of a check period are replayed from a captured
+// hipGraph after the first period.
 #include "gnn.h"
 
 namespace sfem {
@@ -279,15 +288,30 @@ __device__ __forceinline__ void load4(const float* p, double (&v)[4]) {
 // [9][d4] per row): a lane takes 4 blocks per step with one int4 column
 // load and nine 4-wide value loads (36 entries; the CSR-order layout needs
 // 60 loads for as many).
-template <typename VT, int LPR, class XF>
+//
+// DIFF: the translation form.  The row multiplies the neighbour differences
+// x_J - x_I instead of x_J; the caller adds R_I x_I (R_I = sum_J K_IJ, the
+// FP64 block row sum) to complete K x.  K maps rigid translations to
+// (nearly) zero, so the plain sum cancels terms of size |K||x| down to a
+// small result and keeps their rounding; here the matrix values only meet
+// differences, and their rounding (FP64 arithmetic, or FP32 values) is
+// relative to |x_J - x_I|, which is small wherever x is smooth.  Padding
+// blocks (column I, value 0) give I - I = 0.
+template <typename VT, int LPR, bool DIFF, class XF>
 __device__ __forceinline__ void row3p(int I, bool valid, int sub, const int32_t* __restrict__ ptr4,
                                       const int32_t* __restrict__ col4,
                                       const VT* __restrict__ valp, const XF& x, double& y0,
                                       double& y1, double& y2) {
   int r4 = 0, d4 = 0;
+  double xi0 = 0.0, xi1 = 0.0, xi2 = 0.0;
   if (valid) {
     r4 = ptr4[I];
     d4 = ptr4[I + 1] - r4;
+    if constexpr (DIFF) {
+      xi0 = double(x(3 * int64_t(I)));
+      xi1 = double(x(3 * int64_t(I) + 1));
+      xi2 = double(x(3 * int64_t(I) + 2));
+    }
   }
   const VT* w = valp + 9 * int64_t(r4);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -300,7 +324,12 @@ __device__ __forceinline__ void row3p(int I, bool valid, int sub, const int32_t*
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t j3 = 3 * int64_t(Js[t]);
-      const double x0 = double(x(j3)), x1 = double(x(j3 + 1)), x2 = double(x(j3 + 2));
+      double x0 = double(x(j3)), x1 = double(x(j3 + 1)), x2 = double(x(j3 + 2));
+      if constexpr (DIFF) {
+        x0 -= xi0;
+        x1 -= xi1;
+        x2 -= xi2;
+      }
       a0 += m[0][t] * x0 + m[1][t] * x1 + m[2][t] * x2;
       a1 += m[3][t] * x0 + m[4][t] * x1 + m[5][t] * x2;
       a2 += m[6][t] * x0 + m[7][t] * x1 + m[8][t] * x2;
@@ -314,8 +343,9 @@ __device__ __forceinline__ void row3p(int I, bool valid, int sub, const int32_t*
 // Row schedule: LPR lanes per node row; MODE bit 0: two rows per group
 // per step, bit 1: one row with the unrolled column loop, bit 2:
 // nontemporal matrix-value loads, bit 3: the packed layout (bptr, bcol, val
-// are then ptr4, col4 and the packed values).  epi(I, y) runs for each
-// valid row in the group's first lane.
+// are then ptr4, col4 and the packed values), bit 4 (with bit 3): the
+// translation form of row3p (the epilogue then adds R_I x_I).  epi(I, y)
+// runs for each valid row in the group's first lane.
 template <typename VT, int LPR, int MODE, class XF, class Epi>
 __device__ __forceinline__ void row_apply(int64_t N, const int32_t* __restrict__ bptr,
                                           const int32_t* __restrict__ bcol,
@@ -324,7 +354,7 @@ __device__ __forceinline__ void row_apply(int64_t N, const int32_t* __restrict__
   if constexpr ((MODE & 8) != 0) {
     for_rows<LPR>(N, [&](int I, bool valid, int sub) {
       double y[3];
-      row3p<VT, LPR>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
+      row3p<VT, LPR, (MODE & 16) != 0>(I, valid, sub, bptr, bcol, val, xf, y[0], y[1], y[2]);
       if (valid && sub == 0) epi(I, y);
     });
   } else if constexpr ((MODE & 1) != 0) {
@@ -381,6 +411,20 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double* partials
     for (int i = 0; i < NV; ++i) partials[blockIdx.x * NV + i] = v[i];
 }
 
+// y += R_I x_I: the translation part of K x in the translation form
+// (MODE bit 4); rsum holds R_I row-major per node.
+template <int MODE, typename P>
+__device__ __forceinline__ void add_translation(int I, const double* __restrict__ rsum,
+                                                const P* __restrict__ x, double (&y)[3]) {
+  if constexpr ((MODE & 16) != 0) {
+    const double* R = rsum + 9 * int64_t(I);
+    const double x0 = double(x[3 * int64_t(I)]), x1 = double(x[3 * int64_t(I) + 1]),
+                 x2 = double(x[3 * int64_t(I) + 2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[a] += R[3 * a] * x0 + R[3 * a + 1] * x1 + R[3 * a + 2] * x2;
+  }
+}
+
 template <typename VT, typename XT, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
@@ -405,16 +449,19 @@ __global__ void __launch_bounds__(kVecThreads)
     p[i] = z[i] + beta * p[i];
 }
 
-// q = K p, partial (p.q).
+// q = K p, partial (p.q).  MODE bit 4: the translation form (rsum: R).
 template <typename VT, typename P, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
               const VT* __restrict__ val, const P* __restrict__ p, P* __restrict__ q,
-              const CgScalars* __restrict__ sc, double* __restrict__ partials) {
+              const CgScalars* __restrict__ sc, double* __restrict__ partials,
+              const double* __restrict__ rsum) {
   if (sc->converged) return;
   const PlainX<P> xf{p};
   double v[1] = {0.0};
-  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
+  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&yr)[3]) {
+    double y[3] = {yr[0], yr[1], yr[2]};
+    add_translation<MODE>(I, rsum, p, y);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -512,15 +559,18 @@ __global__ void __launch_bounds__(kRowWaves * kWave) __attribute__((amdgpu_waves
 }
 
 // Residual replacement: r = b - K x, z = dinv r; partials (r.r), (r.z).
+// MODE bit 4: K x in the translation form (rsum: R).
 template <typename VT, typename P, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_replace(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                  const VT* __restrict__ val, const P* __restrict__ b, const P* __restrict__ x,
                  P* __restrict__ r, P* __restrict__ z, const P* __restrict__ dinv,
-                 double* __restrict__ partials) {
+                 double* __restrict__ partials, const double* __restrict__ rsum) {
   const PlainX<P> xf{x};
   double v[2] = {0.0, 0.0};
-  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
+  row_apply<VT, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&yr)[3]) {
+    double y[3] = {yr[0], yr[1], yr[2]};
+    add_translation<MODE>(I, rsum, x, y);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -536,15 +586,18 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
 }
 
 // FP64 residual of the outer problem: r = f - K u; partials ||r||^2, ||f||^2.
+// MODE bit 4: K u in the translation form (rsum: R).
 template <int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_resid64(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
               const double* __restrict__ val, const double* __restrict__ f,
               const double* __restrict__ u, double* __restrict__ r,
-              double* __restrict__ partials) {
+              double* __restrict__ partials, const double* __restrict__ rsum) {
   const PlainX<double> xf{u};
   double v[2] = {0.0, 0.0};
-  row_apply<double, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&y)[3]) {
+  row_apply<double, LPR, MODE>(N, bptr, bcol, val, xf, [&](int I, const double (&yr)[3]) {
+    double y[3] = {yr[0], yr[1], yr[2]};
+    add_translation<MODE>(I, rsum, u, y);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * int64_t(I) + a;
@@ -716,6 +769,42 @@ int row_grid(int64_t N, const RowSched& rs) {
     default: LAUNCH(16, 8); break;          \
   }
 
+// Launch KERNEL<prefix..., LPR, 24> (packed layout, translation form) for
+// a packed schedule's lanes per row.
+#define SFEM_TF_SWITCH(lpr, LAUNCH) \
+  switch (lpr) {                    \
+    case 4: LAUNCH(4, 24); break;   \
+    case 16: LAUNCH(16, 24); break; \
+    default: LAUNCH(8, 24); break;  \
+  }
+
+// The schedule the translation form runs with: rs itself if it is a packed
+// schedule, else the packed one with 8 lanes per row (same grid cap).
+RowSched tf_sched(const RowSched& rs) {
+  return (kSched[rs.variant].mode & 8) ? rs : RowSched{15, rs.grid_cap};
+}
+
+// R_I = sum_J K_IJ per node row, one thread per (I, a, c): the row's deg
+// values of component (a, c), Neumaier-compensated (exact to one rounding
+// of R plus O(deg eps^2) sum |K_IJ|).
+__global__ void k_rowsum(int64_t N, const int32_t* __restrict__ bptr,
+                         const double* __restrict__ val, double* __restrict__ rsum) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= 9 * N) return;
+  const int64_t I = t / 9;
+  const int q = int(t - 9 * I), a = q / 3, c = q - 3 * a;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb;
+  const double* v = val + 9 * int64_t(rb) + a * 3 * deg + c;
+  double sum = 0.0, comp = 0.0;
+  for (int j = 0; j < deg; ++j) {
+    const double x = v[3 * j];
+    const double t2 = sum + x;
+    comp += fabs(sum) >= fabs(x) ? (sum - t2) + x : (x - t2) + sum;
+    sum = t2;
+  }
+  rsum[t] = sum + comp;
+}
+
 // Pattern tables of the packed layout (once per mesh).
 __global__ void k_deg4(int64_t N, const int32_t* __restrict__ bptr, int32_t* __restrict__ d4) {
   int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -796,7 +885,18 @@ struct CgBuffers {
   const int32_t* mcol4 = nullptr;
   const void* msq = nullptr;          // its diag(K)^-1/2, typed like the vectors
   void* rh = nullptr;                 // s r, typed like the vectors
+  const double* rsum = nullptr;       // set: products in the translation form
 };
+
+// Block row sums R of the FP64 K_bc (once per assembly).
+void ensure_rowsum(Ctx& c) {
+  if (c.have_rsum) return;
+  c.rsum.reserve(9 * c.N);
+  k_rowsum<<<div_up(9 * c.N, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.val.get(),
+                                                        c.rsum.get());
+  SFEM_HIP(hipGetLastError());
+  c.have_rsum = true;
+}
 
 int mapply_parts(Ctx& c) {
   const RowSched rs{0, kRowGridMax};
@@ -828,7 +928,7 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   const int64_t N = c.N, n = c.n_dof();
   hipStream_t s = c.stream;
   const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
-  const int rg = row_grid(N, rs);
+  const int rg = row_grid(N, B.rsum ? tf_sched(rs) : rs);
   const int vg = vec_grid(n);
   if (c.profile)
     while (int(c.prof_ev.size()) < 4 * iters) {
@@ -838,15 +938,20 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
     }
   (void)parity;
   P* p = (P*)B.p0;
-  const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val);
+  const RowSched rt = tf_sched(rs);
+  const Lay<VT> LY = lay<VT>(c, B.rsum ? rt : rs, (const VT*)B.val);
   for (int k = 0; k < iters; ++k) {
     k_cg_p<P><<<vg, kVecThreads, 0, s>>>(n, (const P*)B.z, p, c.sc.get());
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k], s));
 #define L_(LPR, MODE)                                                                          \
   k_cg_spmv<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(N, LY.ptr, LY.col, LY.val, p,     \
                                                                 (P*)B.q, c.sc.get(),           \
-                                                                c.partials.get())
-    SFEM_SCHED_SWITCH(rs.variant, L_)
+                                                                c.partials.get(), B.rsum)
+    if (B.rsum) {
+      SFEM_TF_SWITCH(kSched[rt.variant].lpr, L_)
+    } else {
+      SFEM_SCHED_SWITCH(rs.variant, L_)
+    }
 #undef L_
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k + 1], s));
     finalize(c, kFinAlpha, rg);
@@ -878,9 +983,9 @@ void cg_period(Ctx& c, const CgBuffers& B, int iters, int& parity, bool eager) {
     return;
   }
   const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
-  const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val);
+  const Lay<VT> LY = lay<VT>(c, B.rsum ? tf_sched(rs) : rs, (const VT*)B.val);
   const std::vector<const void*> key = {
-      B.val, B.dinv, B.x, B.r, B.z, B.p0, B.q, B.mval, B.mptr4, B.mcol4, B.msq, B.rh,
+      B.val, B.dinv, B.x, B.r, B.z, B.p0, B.q, B.mval, B.mptr4, B.mcol4, B.msq, B.rh, B.rsum,
       LY.ptr, LY.col, LY.val, c.sc.get(), c.partials.get(),
       reinterpret_cast<const void*>(intptr_t(c.N)), reinterpret_cast<const void*>(intptr_t(iters)),
       reinterpret_cast<const void*>(intptr_t(rs.variant * 100000 + rs.grid_cap)),
@@ -923,16 +1028,34 @@ void collect_profile(Ctx& c, int iters, int done_before, int done_after, bool le
   }
 }
 
+// The replacement residual b - K x.  With the FP64 K_bc (every solve that
+// replaces: VT = double) it is computed in the translation form, whose
+// rounding is relative to the neighbour differences of x: the FP64 true
+// residual then resolves levels far below eps || |K| |x| || / ||b||, the
+// floor of the plain sum (3.7e-9 relative on the 1.92M-tet cantilever).
 template <typename VT, typename P>
 void cg_replace(Ctx& c, const CgBuffers& B) {
   const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
-  const int rg = row_grid(c.N, rs);
-  const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val_true);
+  int rg = row_grid(c.N, rs);
 #define L_(LPR, MODE)                                                                          \
   k_cg_replace<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, c.stream>>>(                     \
       c.N, LY.ptr, LY.col, LY.val, (const P*)B.b, (const P*)B.x, (P*)B.r, (P*)B.z,            \
-      (const P*)B.dinv, c.partials.get())
-  SFEM_SCHED_SWITCH(rs.variant, L_)
+      (const P*)B.dinv, c.partials.get(), c.rsum.get())
+  if constexpr (sizeof(VT) == 8) {
+    const bool own = (const void*)B.val_true == (const void*)c.val.get();
+    if (own) ensure_rowsum(c);
+    const RowSched rt = tf_sched(rs);
+    const Lay<VT> LY = lay<VT>(c, own ? rt : rs, (const VT*)B.val_true);
+    if (own) {
+      rg = row_grid(c.N, rt);
+      SFEM_TF_SWITCH(kSched[rt.variant].lpr, L_)
+    } else {
+      SFEM_SCHED_SWITCH(rs.variant, L_)
+    }
+  } else {
+    const Lay<VT> LY = lay<VT>(c, rs, (const VT*)B.val_true);
+    SFEM_SCHED_SWITCH(rs.variant, L_)
+  }
 #undef L_
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinReplace, rg);
@@ -1154,13 +1277,16 @@ void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
   c.profile = prof;
 }
 
+// r = f - K u with the FP64 K_bc, in the translation form (see cg_replace).
 void resid64(Ctx& c, const double* u, double* r) {
-  const int rg = row_grid(c.N, c.sched64);
-  const Lay<double> LY = lay<double>(c, c.sched64, c.val.get());
+  ensure_rowsum(c);
+  const RowSched rt = tf_sched(c.sched64);
+  const int rg = row_grid(c.N, rt);
+  const Lay<double> LY = lay<double>(c, rt, c.val.get());
 #define L_(LPR, MODE)                                                                 \
   k_resid64<LPR, MODE><<<rg, kRowWaves * kWave, 0, c.stream>>>(                       \
-      c.N, LY.ptr, LY.col, LY.val, c.f_bc.get(), u, r, c.partials.get())
-  SFEM_SCHED_SWITCH(c.sched64.variant, L_)
+      c.N, LY.ptr, LY.col, LY.val, c.f_bc.get(), u, r, c.partials.get(), c.rsum.get())
+  SFEM_TF_SWITCH(kSched[rt.variant].lpr, L_)
 #undef L_
   SFEM_HIP(hipGetLastError());
   finalize(c, kFinResid, rg);
@@ -1245,7 +1371,7 @@ static int jacobi_fallback(Ctx& c, const CgBuffers& B, double tol_abs, int max_i
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   const int64_t n = c.n_dof();
   SFEM_REQUIRE(o.mode == SFEM_MODE_F64 || o.mode == SFEM_MODE_F32_IR ||
-                   o.mode == SFEM_MODE_F32_RR,
+                   o.mode == SFEM_MODE_F32_RR || o.mode == SFEM_MODE_F32_TF,
                SFEM_EINVAL, "unknown solve mode");
   SFEM_REQUIRE(o.precond == SFEM_PRECOND_JACOBI || o.precond == SFEM_PRECOND_LEARNED,
                SFEM_EINVAL, "unknown preconditioner");
@@ -1275,16 +1401,26 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
   int status = SFEM_OK;
   if (fnorm == 0.0) {
     info.converged = 1;
-  } else if (o.mode == SFEM_MODE_F64 || o.mode == SFEM_MODE_F32_RR) {
+  } else if (o.mode == SFEM_MODE_F64 || o.mode == SFEM_MODE_F32_RR ||
+             o.mode == SFEM_MODE_F32_TF) {
     // F32_RR: K32 products, FP64 vectors and dots; every check_every
     // iterations the residual is replaced by the FP64 one, f - K64 x, which
-    // is the refinement step and the convergence test
+    // is the refinement step and the convergence test.
+    // F32_TF: the same with the K32 products in the translation form,
+    // q_I = sum_J K32_IJ (p_J - p_I) + R_I p_I (R_I the FP64 block row
+    // sums of K64), to the end: no restart.
     const bool rr = o.mode == SFEM_MODE_F32_RR;
-    SFEM_REQUIRE(!rr || c.have_f32, SFEM_ESTATE,
-                 "SFEM_MODE_F32_RR needs sfem_assemble(..., SFEM_ASM_F32_COPY)");
-    CgBuffers B{rr ? (const void*)c.val32.get() : (const void*)c.val.get(),
+    const bool tf = o.mode == SFEM_MODE_F32_TF;
+    SFEM_REQUIRE(!(rr || tf) || c.have_f32, SFEM_ESTATE,
+                 "SFEM_MODE_F32_RR and SFEM_MODE_F32_TF need sfem_assemble(..., "
+                 "SFEM_ASM_F32_COPY)");
+    CgBuffers B{(rr || tf) ? (const void*)c.val32.get() : (const void*)c.val.get(),
                 c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
                 c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
+    if (tf) {
+      ensure_rowsum(c);
+      B.rsum = c.rsum.get();
+    }
     if (learned) {
       B.mval = c.mvalp.get();
       B.mptr4 = c.ptr4.get();
@@ -1309,6 +1445,9 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
                                brk);
         met = met2;
       }
+    } else if (tf) {
+      info.iters = pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
+                                              check_every, met, brk);
     } else {
       info.iters = pcg<double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
                                        check_every, met, brk);
@@ -1318,7 +1457,7 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
       info.iters += jacobi_fallback(c, B, o.rtol * fnorm, max_iter - info.iters, check_every,
                                     met);
     }
-    info.outer_steps = rr ? info.iters / check_every + 1 : 1;
+    info.outer_steps = (rr || tf) ? info.iters / check_every + 1 : 1;
     info.true_relres = true_residual(c, c.x.get());
     info.converged = info.true_relres <= o.rtol;
   } else {

@@ -20,7 +20,7 @@ PTR_HOST, PTR_DEVICE = 0, 1
 K_UNCONSTRAINED, K_WITH_BC = 0, 1
 ASM_F64, ASM_F32_COPY = 0, 1
 PRECOND_JACOBI, PRECOND_LEARNED = 0, 1
-MODE_F64, MODE_F32_IR, MODE_F32_RR = 0, 1, 2
+MODE_F64, MODE_F32_IR, MODE_F32_RR, MODE_F32_TF = 0, 1, 2, 3
 NUM_SCHEDULES = 17
 DOMAIN_FACE, DOMAIN_EDGE = 0, 1
 
@@ -45,6 +45,7 @@ EXPORTS = [
     "sfem_batch_get_system_info", "sfem_tetgen_read", "sfem_tetgen_last_error",
     "sfem_tetgen_sizes", "sfem_tetgen_get", "sfem_tetgen_free", "sfem_rcm_permutation",
     "sfem_permute_mesh", "sfem_set_smoothing_domain", "sfem_batch_set_schedule",
+    "sfem_precond_save", "sfem_precond_load",
 ]
 
 
@@ -127,6 +128,8 @@ def lib() -> C.CDLL:
             "sfem_gnn_last_error": (C.c_char_p, [vp]),
             "sfem_gnn_get_params": (i32, [vp, vp, i64]),
             "sfem_gnn_set_params": (i32, [vp, vp, i64]),
+            "sfem_precond_save": (i32, [vp, C.c_char_p]),
+            "sfem_precond_load": (i32, [vp, C.c_char_p]),
             "sfem_gnn_set_pairs": (i32, [vp, i64, vp, vp, i32]),
             "sfem_gnn_generate_pairs": (i32, [vp, i32, i32, C.c_uint64, C.POINTER(i64)]),
             "sfem_gnn_loss_grad": (i32, [vp, vp, vp, i32, C.POINTER(dbl), vp]),
@@ -493,6 +496,14 @@ class Gnn:
     def set_params(self, p):
         p = np.ascontiguousarray(p, dtype=np.float32)
         self._check(self._L.sfem_gnn_set_params(self._h, p.ctypes.data_as(C.c_void_p), p.size))
+
+    def save(self, path):
+        """Writes the weights file (sfem_precond_save)."""
+        self._check(self._L.sfem_precond_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Reads a weights file into the network (sfem_precond_load)."""
+        self._check(self._L.sfem_precond_load(self._h, os.fsencode(path)))
 
     def loss_grad(self, ctx: Context, ids, grad: bool = True):
         ids = np.ascontiguousarray(ids, dtype=np.int32)

@@ -384,6 +384,21 @@ int sfem_get_precond(sfem_ctx* ctx, float* correction, double* dinv_sqrt, int pt
 /* z = M r (float64 [3 n_nodes]) with the learned preconditioner. */
 int sfem_precond_apply(sfem_ctx* ctx, const double* r, double* z, int ptr_kind);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): z = M r as
+ * sfem_precond_apply, but r and z must be device memory of the context's
+ * GPU, the work is only enqueued on the context stream (no synchronisation),
+ * and nothing is allocated or freed: the work memory (3 n_nodes + up to
+ * 3 x 4096 doubles) is a static 8 MiB device array of the library, one per
+ * GPU, held until the process ends.  Limit: n_nodes <= 345,429.  All calls
+ * on one GPU share that array, so calls that overlap in time on one GPU
+ * (other streams, threads or contexts) race; calls ordered on one stream do
+ * not.  The results equal sfem_precond_apply's bit for bit.  Errors, in this
+ * order: SFEM_EINVAL (mesh beyond the limit), SFEM_ESTATE (no
+ * sfem_gnn_apply on this context), SFEM_EINVAL (null, host or other-GPU
+ * pointer). */
+int sfem_precond_apply_noalloc(sfem_ctx* ctx, const double* r, double* z);
+
 /* ----------------------------------------------------------------------------
  * Batched solves: many meshes, up to four load cases each, in one solve
  * (an extension; the paper solves one mesh).  The meshes are concatenated

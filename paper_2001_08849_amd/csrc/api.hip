@@ -155,6 +155,8 @@ int sfem_create(sfem_ctx** out, int device, void* hip_stream) {
     SFEM_HIP(hipEventCreate(&c.tev0));
     SFEM_HIP(hipEventCreate(&c.tev1));
     SFEM_HIP(hipHostMalloc((void**)&c.sc_host, sizeof(sfem::CgScalars), hipHostMallocDefault));
+    // this device's scratch address for the allocation-free entry point
+    sfem::scratch_init(device);
     c.sc.reserve(1);
     SFEM_HIP(hipMemsetAsync(c.sc.get(), 0, sizeof(sfem::CgScalars), c.stream));
     SFEM_HIP(hipStreamSynchronize(c.stream));
@@ -942,6 +944,13 @@ int sfem_precond_apply(sfem_ctx* h, const double* r, double* z, int ptr_kind) {
     sfem::learned_apply(c, dr.get(), dz.get());
     download(c, z, dz.get(), n, ptr_kind);
     SFEM_HIP(hipStreamSynchronize(c.stream));
+    return SFEM_OK;
+  });
+}
+
+int sfem_precond_apply_noalloc(sfem_ctx* h, const double* r, double* z) {
+  return guarded(h, [&](Ctx& c) {
+    sfem::precond_apply_noalloc(c, r, z);
     return SFEM_OK;
   });
 }

@@ -219,6 +219,11 @@ void pack_values_f32(Ctx& c, const float* csr, float* packed);
 void pack_values_bf16(Ctx& c, const float* csr, __bf16* packed);
 // solve.hip
 int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info);
+int64_t learned_apply_partials(Ctx& c);
+void learned_apply_into(Ctx& c, const double* r, double* z, double* rh, double* partials);
+// noalloc.hip: the static device scratch of the allocation-free entry point
+void scratch_init(int device);
+void precond_apply_noalloc(Ctx& c, const double* r, double* z);
 double true_residual(Ctx& c, const double* u);
 void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32);
 

@@ -908,8 +908,10 @@ int mapply_parts(Ctx& c) {
 
 // z = M r; with fresh_rh the scaled residual rh = s r is formed first (it
 // is otherwise maintained by k_cg_xr).
+// partials: 3 mapply_parts(c) doubles (null: the context's).
 template <typename P>
-void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fresh_rh) {
+void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fresh_rh,
+            double* partials = nullptr) {
   const int64_t n = c.n_dof();
   if (fresh_rh) {
     k_rh<P><<<div_up(n, 256), 256, 0, c.stream>>>(n, (const P*)B.msq, r, (P*)B.rh);
@@ -917,7 +919,7 @@ void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fre
   }
   k_mapply<P><<<mapply_parts(c), kRowWaves * kWave, 0, c.stream>>>(
       c.N, B.mptr4, B.mcol4, B.mval, (const P*)B.msq, r, (const P*)B.rh, z,
-      guarded ? c.sc.get() : nullptr, c.partials.get());
+      guarded ? c.sc.get() : nullptr, partials ? partials : c.partials.get());
   SFEM_HIP(hipGetLastError());
 }
 
@@ -1609,6 +1611,21 @@ void ensure_packed32(Ctx& c) {
 
 void pack_values64(Ctx& c) { ensure_packed64(c); }
 
+
+// z = M r with caller-provided work memory: rh (3 N doubles) and partials
+// (learned_apply_partials(c) doubles).  Allocates nothing.
+int64_t learned_apply_partials(Ctx& c) { return 3 * int64_t(mapply_parts(c)); }
+
+void learned_apply_into(Ctx& c, const double* r, double* z, double* rh, double* partials) {
+  SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");
+  CgBuffers B{};
+  B.mval = c.mvalp.get();
+  B.mptr4 = c.ptr4.get();
+  B.mcol4 = c.col4.get();
+  B.msq = c.msqrt.get();
+  B.rh = rh;
+  mapply<double>(c, B, r, z, false, true, partials);
+}
 
 void learned_apply(Ctx& c, const double* r, double* z) {
   SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");

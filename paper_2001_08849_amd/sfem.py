@@ -45,7 +45,7 @@ EXPORTS = [
     "sfem_batch_get_system_info", "sfem_tetgen_read", "sfem_tetgen_last_error",
     "sfem_tetgen_sizes", "sfem_tetgen_get", "sfem_tetgen_free", "sfem_rcm_permutation",
     "sfem_permute_mesh", "sfem_set_smoothing_domain", "sfem_batch_set_schedule",
-    "sfem_precond_save", "sfem_precond_load",
+    "sfem_precond_save", "sfem_precond_load", "sfem_precond_apply_noalloc",
 ]
 
 
@@ -137,6 +137,7 @@ def lib() -> C.CDLL:
             "sfem_gnn_apply": (i32, [vp, vp, C.POINTER(dbl)]),
             "sfem_get_precond": (i32, [vp, vp, vp, i32]),
             "sfem_precond_apply": (i32, [vp, vp, vp, i32]),
+            "sfem_precond_apply_noalloc": (i32, [vp, vp, vp]),
             "sfem_get_precond_info": (i32, [vp] + [C.POINTER(dbl)] * 3),
             "sfem_face_stress": (i32, [vp, vp, vp, vp, i32, C.POINTER(dbl)]),
             "sfem_batch_create": (i32, [C.POINTER(vp), i32]),
@@ -455,6 +456,12 @@ class Context:
         pr, kr, a = _arg(r, np.float64)
         self._check(self._L.sfem_precond_apply(self._h, pr, z.ctypes.data_as(C.c_void_p), kr))
         return z
+
+    def precond_apply_noalloc(self, r_dev: int, z_dev: int):
+        """z = M r between two device buffers (raw addresses) without any
+        allocation by the library; enqueued on the context stream only."""
+        self._check(self._L.sfem_precond_apply_noalloc(self._h, C.c_void_p(r_dev),
+                                                       C.c_void_p(z_dev)))
 
 
 class Gnn:

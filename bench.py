@@ -522,24 +522,37 @@ def mixed_precision_leg(ctx, sfem, u, inner_rtol, net, np, uref, reps=3):
         f"{res['f32_translation_form_jacobi']['solve_s'] * 1e3:.0f} ms, {i['iters']} it, relres "
         f"{i['true_relres']:.2e}")
     if net is not None:
+        # the switch level: FP64 products until the true relres reaches
+        # f32_from, FP32 translation-form products after (0: from the start)
+        trial = {}
+        for lvl in (0.0, 1e-1, 1e-2, 1e-3):
+            net.apply(ctx)
+            _, i = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF,
+                             precond=sfem.PRECOND_LEARNED, f32_from=lvl)
+            trial[lvl] = i
+            log(f"[bench] learned M, FP32 translation-form products from relres {lvl:g}: "
+                f"{i['ms_solve']:.0f} ms, {i['iters']} it, fell back {i['fell_back']}")
+        best = min(trial, key=lambda k: trial[k]["ms_solve"] if trial[k]["converged"] else 1e30)
         runs = []
         for _ in range(reps):
             ms_inf = net.apply(ctx)
             _, i = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF,
-                             precond=sfem.PRECOND_LEARNED)
+                             precond=sfem.PRECOND_LEARNED, f32_from=best)
             i["ms_inference"] = ms_inf
             runs.append(i)
         i = runs[-1]
         ls = float(np.median([r["ms_solve"] for r in runs])) * 1e-3
         li = float(np.median([r["ms_inference"] for r in runs])) * 1e-3
         res["f32_translation_form_learned"] = {
-            "solve_s": ls, "inference_s": li, "solve_incl_inference_s": ls + li,
+            "f32_from": best, "solve_s": ls, "inference_s": li, "solve_incl_inference_s": ls + li,
             "iters": i["iters"], "true_relres": i["true_relres"],
             "converged": bool(i["converged"]), "fell_back": i["fell_back"],
-            "u_error_vs_oracle": u_error(np, u, uref)}
-        log(f"[bench] FP32 translation-form products, learned M: {ls * 1e3:.0f} ms + inference "
-            f"{li * 1e3:.0f} ms, {i['iters']} it, relres {i['true_relres']:.2e}, fell back "
-            f"{i['fell_back']}")
+            "u_error_vs_oracle": u_error(np, u, uref),
+            "switch_levels_tried": {f"{k:g}": {"solve_s": v["ms_solve"] * 1e-3,
+                                               "iters": v["iters"]} for k, v in trial.items()}}
+        log(f"[bench] learned M, FP32 translation-form products from relres {best:g}: "
+            f"{ls * 1e3:.0f} ms + inference {li * 1e3:.0f} ms, {i['iters']} it, relres "
+            f"{i['true_relres']:.2e}, fell back {i['fell_back']}")
     return res
 
 
@@ -858,6 +871,16 @@ def main():
         out["stress_recovery"] = stress
     if mixed:
         out["mixed_precision"] = mixed
+        if solves:
+            out["solve_s"]["jacobi_f32_translation_form"] = \
+                mixed["f32_translation_form_jacobi"]["solve_s"]
+            out["solve_iters"]["jacobi_f32_translation_form"] = \
+                mixed["f32_translation_form_jacobi"]["iters"]
+            ml = mixed.get("f32_translation_form_learned")
+            if ml:
+                out["solve_s"]["learned_f32_translation_form_incl_inference"] = \
+                    ml["solve_incl_inference_s"]
+                out["solve_iters"]["learned_f32_translation_form"] = ml["iters"]
     if not args.no_batch and not args.skip_solve:
         out["batch_c3"] = batch_leg(mg, sfem, np)
     if not args.no_es_fem and not args.skip_solve:

@@ -49,13 +49,22 @@ typedef enum {
 
 enum { SFEM_PTR_HOST = 0, SFEM_PTR_DEVICE = 1 };
 
-/* Which matrix sfem_get_csr returns. */
-enum { SFEM_K_UNCONSTRAINED = 0, SFEM_K_WITH_BC = 1 };
+/* Which matrix sfem_get_csr returns (SFEM_K_F32: the FP32 copy of the
+ * BC-applied K, its values widened to float64; needs an FP32 assembly). */
+enum { SFEM_K_UNCONSTRAINED = 0, SFEM_K_WITH_BC = 1, SFEM_K_F32 = 2 };
 
 /* sfem_assemble flags. */
 enum {
   SFEM_ASM_F64 = 0,       /* FP64 values only */
-  SFEM_ASM_F32_COPY = 1   /* also keep an FP32 copy (used by SFEM_MODE_F32_IR) */
+  SFEM_ASM_F32_COPY = 1,  /* also keep an FP32 copy (the FP64 values rounded;
+                             used by the FP32 solve modes) */
+  SFEM_ASM_F32_ARITH = 2  /* an FP32 copy assembled with FP32 face arithmetic:
+                             FP64 only for tet volumes and inverse Jacobians;
+                             the smoothed gradients, V_k, the Lame constants
+                             and the 3x3 blocks in FP32, each contribution
+                             rounded once to the row's fixed-point unit and
+                             summed exactly (a second pass after the FP64
+                             one; face-based domains only) */
 };
 
 /* Solver choices (sfem_solve_opts). */
@@ -193,6 +202,18 @@ int sfem_spmv(sfem_ctx* ctx, const double* x, double* y, int ptr_kind);
  *                      FP32-matrix PCG solve of K d = r whose recursive
  *                      residual falls by inner_rtol (dot products in FP64),
  *                      u += d.  Needs SFEM_ASM_F32_COPY.
+ *   SFEM_MODE_F32_TF : PCG with FP64 vectors, dots and residual replacement
+ *                      (every check_every iterations, the convergence test)
+ *                      and FP32-matrix products in the translation form:
+ *                      q_I = sum_J K32_IJ (p_J - p_I) + R_I p_I, R_I =
+ *                      sum_J K_IJ the FP64 block row sums.  K maps rigid
+ *                      translations to (nearly) zero, so the FP32 rounding
+ *                      of the values only meets neighbour differences of p
+ *                      and perturbs the smooth, slowly converging modes far
+ *                      less than a plain FP32 product; the recurrence runs
+ *                      to rtol without a restart.  With f32_from the first
+ *                      part of the solve uses FP64 products.  Needs
+ *                      SFEM_ASM_F32_COPY.
  *   SFEM_MODE_F32_RR : PCG with FP64 vectors and dots and FP32-matrix
  *                      products, the residual replaced every check_every
  *                      iterations by the FP64 residual f - K u, until the
@@ -217,6 +238,10 @@ typedef struct {
   int max_outer;      /* F32_IR outer-step cap (0: 30) */
   int profile;        /* nonzero: time every SpMV launch with HIP events */
   double f32_until;   /* F32_RR: FP32 products down to this relres (0: 1e-3) */
+  double f32_from;    /* F32_TF: FP64 products until the FP64 true relres
+                         reaches this level, then FP32 translation-form
+                         products continuing the same recurrence (0, or
+                         >= 1: FP32 from the first iteration) */
 } sfem_solve_opts;
 
 typedef struct {

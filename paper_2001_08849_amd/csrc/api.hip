@@ -375,17 +375,30 @@ int sfem_assemble(sfem_ctx* h, int flags) {
     c.have_rsum = false;
     const int64_t nnz = 9 * c.topo.nb;
     c.val.reserve(nnz);
-    const bool f32 = (flags & SFEM_ASM_F32_COPY) != 0;
+    SFEM_REQUIRE((flags & ~(SFEM_ASM_F32_COPY | SFEM_ASM_F32_ARITH)) == 0, SFEM_EINVAL,
+                 "unknown assembly flag");
+    const bool f32_arith = (flags & SFEM_ASM_F32_ARITH) != 0;
+    const bool f32 = (flags & SFEM_ASM_F32_COPY) != 0 || f32_arith;
     if (f32) c.val32.reserve(nnz);
     c.have_f32 = f32;
     c.w.reserve(c.n_dof());
     c.q.reserve(c.n_dof());
     const bool two_step = c.any_fixed && c.any_nonzero_bc && c.penalty <= 0.0;
+    // the packed tables (once per mesh; a host read) before the timed region
+    if (!two_step && c.domain == SFEM_DOMAIN_FACE) sfem::pack_pattern(c);
     SFEM_HIP(hipEventRecord(c.ev0, c.stream));
-    sfem::assemble_values(c, c.val.get(), f32 ? c.val32.get() : nullptr, !two_step);
+    // the solver's packed copy is written by the same pass, except when the
+    // BCs are applied afterwards (it is then packed from the masked values)
+    sfem::assemble_values(c, c.val.get(), f32 ? c.val32.get() : nullptr, !two_step, !two_step,
+                          f32_arith);
     SFEM_HIP(hipEventRecord(c.ev1, c.stream));
     sfem::rhs_with_bc(c);
-    if (two_step) sfem::bc_mask_values(c);
+    if (two_step) {
+      sfem::bc_mask_values(c);
+      // a packed copy made from the unconstrained values (rhs_with_bc's
+      // product under a packed schedule) is stale now
+      c.packed64 = c.packed32 = false;
+    }
     sfem::extract_dinv(c);
     SFEM_HIP(hipEventSynchronize(c.ev1));
     float ms = 0;
@@ -424,12 +437,20 @@ int sfem_get_faces(sfem_ctx* h, int32_t* table, int ptr_kind) {
   });
 }
 
+namespace {
+__global__ void k_widen(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = double(a[i]);
+}
+}  // namespace
+
 int sfem_get_csr(sfem_ctx* h, int32_t* row_ptr, int32_t* col_idx, double* val, int which,
                  int ptr_kind) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first");
-    SFEM_REQUIRE(which == SFEM_K_UNCONSTRAINED || which == SFEM_K_WITH_BC, SFEM_EINVAL,
-                 "bad `which`");
+    SFEM_REQUIRE(which == SFEM_K_UNCONSTRAINED || which == SFEM_K_WITH_BC ||
+                     which == SFEM_K_F32,
+                 SFEM_EINVAL, "bad `which`");
     const int64_t nnz = 9 * c.topo.nb, n = c.n_dof();
     if (row_ptr || col_idx) {
       sfem::DBuf<int32_t> rp, ci;
@@ -442,7 +463,14 @@ int sfem_get_csr(sfem_ctx* h, int32_t* row_ptr, int32_t* col_idx, double* val, i
     }
     if (val) {
       SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "call sfem_assemble first");
-      if (which == SFEM_K_WITH_BC || !c.val_has_bc) {
+      if (which == SFEM_K_F32) {
+        SFEM_REQUIRE(c.have_f32, SFEM_ESTATE, "no FP32 copy: assemble with SFEM_ASM_F32_*");
+        sfem::DBuf<double> tmp;
+        tmp.reserve(nnz);
+        k_widen<<<sfem::div_up(nnz, 256), 256, 0, c.stream>>>(nnz, c.val32.get(), tmp.get());
+        SFEM_HIP(hipGetLastError());
+        download(c, val, tmp.get(), nnz, ptr_kind);
+      } else if (which == SFEM_K_WITH_BC || !c.val_has_bc) {
         download(c, val, c.val.get(), nnz, ptr_kind);
       } else {
         sfem::DBuf<double> tmp;

@@ -86,6 +86,66 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
   return 5;
 }
 
+// The same smoothing domain with FP32 arithmetic after the tet volumes and
+// inverse Jacobians: V_1, V_2 and the tet gradients come from tet_grads in
+// FP64; the volume weights, the smoothed gradients b, V_k and the Lame
+// constants are formed in FP32.
+struct F3 {
+  float x, y, z;
+};
+
+template <bool HET>
+__device__ __forceinline__ int face_geometry32(const int32_t* __restrict__ row,
+                                               const double* __restrict__ xyz, double lam0,
+                                               double mu0, const double* __restrict__ lam_t,
+                                               const double* __restrict__ mu_t, int sup[5],
+                                               F3 b[5], float& Vk, float& lam, float& mu) {
+  int4 r0 = *reinterpret_cast<const int4*>(row);
+  int4 r1 = *reinterpret_cast<const int4*>(row + 4);
+  sup[0] = r0.x;
+  sup[1] = r0.y;
+  sup[2] = r0.z;
+  sup[3] = r0.w;
+  sup[4] = r1.x;
+  const bool interior = r1.x >= 0;
+  Vec3 A = load3(xyz, r0.x), B = load3(xyz, r0.y), C = load3(xyz, r0.z), D = load3(xyz, r0.w);
+  const Vec3 E = load3(xyz, interior ? r1.x : r0.w);
+  Vec3 g1[4];
+  double V1;
+  tet_grads(A, B, C, D, g1, V1);
+  if (!interior) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = {float(g1[i].x), float(g1[i].y), float(g1[i].z)};
+    b[4] = {0.f, 0.f, 0.f};
+    Vk = 0.25f * float(V1);
+    lam = HET ? float(lam_t[r1.y]) : float(lam0);
+    mu = HET ? float(mu_t[r1.y]) : float(mu0);
+    return 4;
+  }
+  Vec3 g2[4];
+  double V2;
+  tet_grads(A, B, C, E, g2, V2);
+  const float v1 = float(V1), v2 = float(V2);
+  const float W = v1 + v2;
+  const float iW = 1.0f / W;
+  const float w1 = v1 * iW, w2 = v2 * iW;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    b[i] = {w1 * float(g1[i].x) + w2 * float(g2[i].x), w1 * float(g1[i].y) + w2 * float(g2[i].y),
+            w1 * float(g1[i].z) + w2 * float(g2[i].z)};
+  b[3] = {w1 * float(g1[3].x), w1 * float(g1[3].y), w1 * float(g1[3].z)};
+  b[4] = {w2 * float(g2[3].x), w2 * float(g2[3].y), w2 * float(g2[3].z)};
+  Vk = 0.25f * W;
+  if (HET) {
+    lam = w1 * float(lam_t[r1.y]) + w2 * float(lam_t[r1.z]);
+    mu = w1 * float(mu_t[r1.y]) + w2 * float(mu_t[r1.z]);
+  } else {
+    lam = float(lam0);
+    mu = float(mu0);
+  }
+  return 5;
+}
+
 // Position of node J among the ascending block columns cols[0..deg).
 // Exponent e of a row's unit 2^(e - 50): 0.5 bmax < 2^e (half the largest
 // face bound bounds every contribution), clamped so that 2^(50 - e) stays a
@@ -166,11 +226,31 @@ __global__ void __launch_bounds__(256)
   row[7] = __float_as_int(v32);
 }
 
+// The essential-BC rule for the value v at (row, col) of a row that touches
+// a prescribed DOF: penalty adds alpha on a fixed diagonal; elimination
+// zeroes the off-diagonal entries of fixed rows and columns.
+__device__ __forceinline__ double bc_value(double v, int row, int col,
+                                           const uint8_t* __restrict__ fixed, double penalty) {
+  const bool fr = fixed[row], fc = fixed[col];
+  if (penalty > 0.0) {
+    if (fr && row == col) v += penalty;
+  } else if ((fr || fc) && row != col) {
+    v = 0.0;
+  }
+  return v;
+}
+
 // One workgroup per tile of node rows.  Work item = incidence entry e of a
 // row I in the tile, i.e. a (row, face) pair: the face's smoothed gradients
 // are evaluated in registers and the row's 4 or 5 blocks K_{I,J} are added
 // into the LDS copy of the rows with the column slots from the slot map.
-template <bool HET>
+// The finished rows are written in the CSR order of the scalar matrix and,
+// with valp, also in the solver's packed layout (node row I as a [9][d4]
+// array at 9 ptr4[I], component-major, zero padding past deg).
+// F32: FP32 face arithmetic after the FP64 tet geometry (face_geometry32);
+// each FP32 contribution is rounded to the row's unit once and summed
+// exactly as in the FP64 kernel; only the FP32 outputs are written.
+template <bool HET, bool F32>
 __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(6)))
     k_assemble(const double* __restrict__ xyz, const int32_t* __restrict__ face,
                const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
@@ -180,7 +260,9 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
                double lam0, double mu0,
                const double* __restrict__ lam_t, const double* __restrict__ mu_t,
                const uint8_t* __restrict__ fixed, const uint8_t* __restrict__ bc_row,
-               double penalty, double* __restrict__ val, float* __restrict__ val32) {
+               double penalty, double* __restrict__ val, float* __restrict__ val32,
+               const int32_t* __restrict__ ptr4, double* __restrict__ valp,
+               float* __restrict__ valp32) {
   __shared__ unsigned long long sval[kTileBlocks * 9];  // fixed point, units of u
   __shared__ int32_t sptr[kTileBlocks + 1];  // block offsets of the tile's rows
   __shared__ int32_t sinc[kTileBlocks + 1];  // incidence offsets of the tile's rows
@@ -248,12 +330,46 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     const int deg = sptr[li + 1] - rb;
     const uint32_t code = slot[e];
     int sup[5];
+    // 2^(50 - sexp) built from its exponent bits (sexp is clamped to keep it normal)
+    const double inv_u = __longlong_as_double((long long)(1023 + 50 - sexp[li]) << 52);
+    if constexpr (F32) {
+      F3 b[5];
+      float Vk, lam, mu;
+      const int n = face_geometry32<HET>(face + int64_t(inc[e]) * kFaceStride, xyz, lam0, mu0,
+                                         lam_t, mu_t, sup, b, Vk, lam, mu);
+      // in units of the row's u; the power of two is applied in FP64 (it
+      // may lie outside the FP32 range), the products stay below 2^50
+      const float lV = float(double(lam * Vk) * inv_u), mV = float(double(mu * Vk) * inv_u);
+      F3 bp = b[0];
+#pragma unroll
+      for (int p = 1; p < 5; ++p)
+        if (sup[p] == I) bp = b[p];
+      const float lbp[3] = {lV * bp.x, lV * bp.y, lV * bp.z};
+      const float mbp[3] = {mV * bp.x, mV * bp.y, mV * bp.z};
+      unsigned long long* rowv = sval + 9 * rb;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        if (q >= n) continue;
+        const int jj = int((code >> (6 * q)) & 63u);
+        const float bqa[3] = {b[q].x, b[q].y, b[q].z};
+        const float dS = mV * (bp.x * bqa[0] + bp.y * bqa[1] + bp.z * bqa[2]);
+        unsigned long long* dst = rowv + 3 * jj;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float t = fmaf(lbp[a], bqa[c], fmaf(mbp[c], bqa[a], a == c ? dS : 0.0f));
+            // one FP64 addition rounds the FP32 value to an integer number of units
+            atomicAdd(dst + a * 3 * deg + c, unshift(double(t) + kShift));
+          }
+        }
+      }
+      continue;
+    }
     Vec3 b[5];
     double Vk, lam, mu;
     const int n = face_geometry<HET>(face + int64_t(inc[e]) * kFaceStride, xyz, lam0, mu0, lam_t,
                                      mu_t, sup, b, Vk, lam, mu);
-    // 2^(50 - sexp) built from its exponent bits (sexp is clamped to keep it normal)
-    const double inv_u = __longlong_as_double((long long)(1023 + 50 - sexp[li]) << 52);
     const double lV = lam * Vk * inv_u, mV = mu * Vk * inv_u;  // in units of the row's u
     Vec3 bp = b[0];
 #pragma unroll
@@ -300,17 +416,28 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
         const int r = k - a * three_deg;
         const int jj = r / 3;
         const int c = r - 3 * jj;
-        const int row = 3 * I + a;
-        const int col = 3 * bcol[b0 + rb + jj] + c;
-        const bool fr = fixed[row], fc = fixed[col];
-        if (penalty > 0.0) {
-          if (fr && row == col) v += penalty;
-        } else if ((fr || fc) && row != col) {
-          v = 0.0;
-        }
+        v = bc_value(v, 3 * I + a, 3 * bcol[b0 + rb + jj] + c, fixed, penalty);
       }
-      val[gbase + k] = v;
+      if (val) val[gbase + k] = v;
       if (val32) val32[gbase + k] = float(v);
+    }
+    if (!valp && !valp32) continue;
+    // the same row in the packed layout: entry (q = 3a + c, block j) at
+    // q d4 + j, read back from LDS in that order so the stores coalesce
+    const int r4 = ptr4[I], d4 = ptr4[I + 1] - r4;
+    const float inv_d4 = 1.0f / float(d4);
+    const int64_t pbase = 9 * int64_t(r4);
+    for (int kp = lane; kp < 9 * d4; kp += kWave) {
+      const int q = int((float(kp) + 0.5f) * inv_d4);
+      const int j = kp - q * d4;
+      double v = 0.0;
+      if (j < deg) {
+        const int a = q / 3, c = q - 3 * a;
+        v = double((long long)sval[9 * rb + a * three_deg + 3 * j + c]) * u;
+        if (rbc) v = bc_value(v, 3 * I + a, 3 * bcol[b0 + rb + j] + c, fixed, penalty);
+      }
+      if (valp) valp[pbase + kp] = v;
+      if (valp32) valp32[pbase + kp] = float(v);
     }
   }
 }
@@ -494,28 +621,54 @@ void face_bounds(Ctx& c) {
   SFEM_HIP(hipGetLastError());
 }
 
-void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask) {
+// With `packed` (face domains), the kernel also writes the packed copies
+// c.valp (and c.valp32 with an FP32 copy) and marks them valid.  With
+// f32_arith the FP32 copy comes from a second pass with FP32 face arithmetic
+// instead of the rounded FP64 values.
+void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask, bool packed,
+                     bool f32_arith) {
   if (c.domain == SFEM_DOMAIN_EDGE) {
+    SFEM_REQUIRE(!f32_arith, SFEM_EINVAL,
+                 "FP32 face arithmetic is for face-based smoothing domains");
     assemble_edge_values(c, val_out, val32_out, apply_mask);
     return;
+  }
+  double* valp = nullptr;
+  float* valp32 = nullptr;
+  if (packed) {
+    pack_pattern(c);
+    valp = c.valp.reserve(9 * c.nb4);
+    if (val32_out) valp32 = c.valp32.reserve(9 * c.nb4);
   }
   const Topology& tp = c.topo;
   const uint8_t* fixed = (apply_mask && c.any_fixed) ? c.fixed.get() : nullptr;
   const uint8_t* brow = fixed ? bc_rows(c) : nullptr;
+  const double* lam_t = c.per_tet ? c.lam_t.get() : nullptr;
+  const double* mu_t = c.per_tet ? c.mu_t.get() : nullptr;
   dim3 grid(tp.n_tiles), block(kAsmThreads);
-  if (c.per_tet)
-    k_assemble<true><<<grid, block, 0, c.stream>>>(
-        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.irow.get(),
-        tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, c.lam_t.get(),
-        c.mu_t.get(), fixed, brow, c.penalty, val_out, val32_out);
-  else
-    k_assemble<false><<<grid, block, 0, c.stream>>>(
-        c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.irow.get(),
-        tp.bptr.get(),
-        tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, nullptr, nullptr,
-        fixed, brow, c.penalty, val_out, val32_out);
+#define L_(HET, F32, V, V32, VP, VP32)                                                             \
+  k_assemble<HET, F32><<<grid, block, 0, c.stream>>>(                                             \
+      c.xyz.get(), tp.face.get(), tp.inc_ptr.get(), tp.inc.get(), tp.slot.get(), tp.irow.get(),   \
+      tp.bptr.get(), tp.bcol.get(), tp.tile_first.get(), tp.row_vg.get(), c.lam0, c.mu0, lam_t,  \
+      mu_t, fixed, brow, c.penalty, V, V32, c.ptr4.get(), VP, VP32)
+  if (!f32_arith) {
+    if (c.per_tet) L_(true, false, val_out, val32_out, valp, valp32);
+    else L_(false, false, val_out, val32_out, valp, valp32);
+  } else {
+    if (c.per_tet) {
+      L_(true, false, val_out, nullptr, valp, nullptr);
+      L_(true, true, nullptr, val32_out, nullptr, valp32);
+    } else {
+      L_(false, false, val_out, nullptr, valp, nullptr);
+      L_(false, true, nullptr, val32_out, nullptr, valp32);
+    }
+  }
+#undef L_
   SFEM_HIP(hipGetLastError());
+  if (packed) {
+    c.packed64 = true;
+    c.packed32 = valp32 != nullptr;
+  }
 }
 
 void bc_mask_values(Ctx& c) {

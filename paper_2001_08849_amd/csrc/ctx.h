@@ -199,7 +199,8 @@ int build_pattern(Ctx& c, const int32_t* inc_ptr, const int32_t* inc, const int3
 void build_edge_topology(Ctx& c);
 void assemble_edge_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
 // assemble.hip
-void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask);
+void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask,
+                     bool packed = false, bool f32_arith = false);
 void bc_mask_values(Ctx& c);
 const uint8_t* bc_rows(Ctx& c);  // c.bc_row, remade if stale
 void traction_load(Ctx& c, int64_t n_tri, const int32_t* tri_dev, const double t[3]);

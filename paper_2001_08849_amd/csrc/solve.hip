@@ -1092,11 +1092,18 @@ __global__ void k_cg_clear(CgScalars* sc) {
 // refinement, whose accuracy the FP64 outer residual judges) it stops on the
 // recursive residual, which keeps falling below the working precision's
 // floor.  b is FP64 (scaled into P).  Returns the iterations done.
+//
+// late (with replace): once the true residual has reached sqrt(late_tol2),
+// the remaining periods run late's products (FP32 values, VT = float) and
+// continue the same recurrence: x, r, z, p and the scalars carry over (the
+// product's rounding matters least late in the solve, when the updates are
+// small; early in the solve it costs conjugacy).
 template <typename VT, typename P, typename VTR = VT>
 int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double tol_abs,
         int max_iter, int check_every, bool& met, bool& breakdown, bool replace = true,
         const std::function<void(int)>* hook = nullptr,
-        const std::function<int(int)>* next_stop = nullptr) {
+        const std::function<int(int)>* next_stop = nullptr,
+        const CgBuffers* late = nullptr, double late_tol2 = 0.0) {
   const int64_t n = c.n_dof();
   hipStream_t s = c.stream;
   const double tol2 = tol_abs * tol_abs;
@@ -1122,11 +1129,18 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
   int done = 0, parity = 0;
   double best = c.sc_host->rr;
   int stale = 0;  // checks without a new best, counted once near the tolerance
+  bool in_late = false, late_eager = false;
   while (!met && done < max_iter && stale < 40) {
     int chunk = std::min(check_every, max_iter - done);
     // end the period at the caller's next stop (snapshots), if one is sooner
     if (next_stop) chunk = std::max(1, std::min(chunk, (*next_stop)(done) - done));
-    cg_period<VT, P>(c, B, chunk, parity, done == 0 || chunk != check_every);
+    if (in_late) {
+      // the first late period runs eagerly: it builds the packed FP32 copy
+      cg_period<float, P>(c, *late, chunk, parity, late_eager || chunk != check_every);
+      late_eager = false;
+    } else {
+      cg_period<VT, P>(c, B, chunk, parity, done == 0 || chunk != check_every);
+    }
     if (replace) cg_replace<VTR, P>(c, B);
     read_scalars(c);
     const int before = done;
@@ -1140,6 +1154,7 @@ int pcg(Ctx& c, const CgBuffers& B, const double* b64, double inv_scale, double 
       continue;
     }
     met = c.sc_host->rr_true <= tol2;
+    if (late && !in_late && c.sc_host->rr_true <= late_tol2) in_late = late_eager = true;
     if (c.sc_host->rr_true < best) {
       best = c.sc_host->rr_true;
       stale = 0;
@@ -1447,6 +1462,15 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
                                brk);
         met = met2;
       }
+    } else if (tf && o.f32_from > o.rtol && o.f32_from < 1.0) {
+      // FP64 products down to f32_from, then FP32 translation-form ones
+      CgBuffers B64 = B;
+      B64.val = c.val.get();
+      B64.rsum = nullptr;
+      const double lt = o.f32_from * fnorm;
+      info.iters = pcg<double, double>(c, B64, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
+                                       check_every, met, brk, true, nullptr, nullptr, &B,
+                                       lt * lt);
     } else if (tf) {
       info.iters = pcg<float, double, double>(c, B, c.f_bc.get(), 1.0, o.rtol * fnorm, max_iter,
                                               check_every, met, brk);

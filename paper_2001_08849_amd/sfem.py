@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsfem.so")
 
 PTR_HOST, PTR_DEVICE = 0, 1
-K_UNCONSTRAINED, K_WITH_BC = 0, 1
-ASM_F64, ASM_F32_COPY = 0, 1
+K_UNCONSTRAINED, K_WITH_BC, K_F32 = 0, 1, 2
+ASM_F64, ASM_F32_COPY, ASM_F32_ARITH = 0, 1, 2
 PRECOND_JACOBI, PRECOND_LEARNED = 0, 1
 MODE_F64, MODE_F32_IR, MODE_F32_RR, MODE_F32_TF = 0, 1, 2, 3
 NUM_SCHEDULES = 17
@@ -58,7 +58,8 @@ class SfemError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("precond", C.c_int), ("mode", C.c_int), ("rtol", C.c_double),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int), ("profile", C.c_int), ("f32_until", C.c_double)]
+                ("max_outer", C.c_int), ("profile", C.c_int), ("f32_until", C.c_double),
+                ("f32_from", C.c_double)]
 
 
 class BatchOpts(C.Structure):
@@ -285,8 +286,11 @@ class Context:
         self._check(self._L.sfem_add_traction(self._h, int(len(tris)), pt, tv, kt))
 
     # ------------------------------------------------------------ compute
-    def assemble(self, f32_copy: bool = False):
-        self._check(self._L.sfem_assemble(self._h, ASM_F32_COPY if f32_copy else ASM_F64))
+    def assemble(self, f32_copy: bool = False, f32_arith: bool = False):
+        """f32_copy: keep an FP32 copy (the FP64 values rounded); f32_arith:
+        an FP32 copy from FP32 face arithmetic (a second pass)."""
+        flags = ASM_F32_ARITH if f32_arith else (ASM_F32_COPY if f32_copy else ASM_F64)
+        self._check(self._L.sfem_assemble(self._h, flags))
 
     def sizes(self) -> Sizes:
         v = [C.c_int64() for _ in range(5)]
@@ -332,9 +336,9 @@ class Context:
     def solve(self, rtol: float = 1e-8, mode: int = MODE_F64, precond: int = PRECOND_JACOBI,
               max_iter: int = 0, check_every: int = 0, inner_rtol: float = 0.0,
               max_outer: int = 0, out=None, raise_on_noconv: bool = False,
-              profile: bool = False, f32_until: float = 0.0):
+              profile: bool = False, f32_until: float = 0.0, f32_from: float = 0.0):
         opts = SolveOpts(precond, mode, rtol, max_iter, check_every, inner_rtol, max_outer,
-                         int(profile), f32_until)
+                         int(profile), f32_until, f32_from)
         info = SolveInfo()
         if out is None:
             out = np.empty(self.sizes().n_rows, dtype=np.float64)

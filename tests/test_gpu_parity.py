@@ -183,6 +183,52 @@ def test_c1_f32_translation_form(c1):
     assert abs(rr_same - info["true_relres"]) <= 1e-4 * rr_same
     assert rr_oracle <= info["true_relres"] + 1.01 * dKu
     assert info["iters"] <= 2 * i64["iters"]
+    # FP64 products down to 1e-2, then FP32 translation-form ones
+    u2, i2 = ctx.solve(rtol=1e-8, mode=sfem.MODE_F32_TF, f32_from=1e-2)
+    e2 = np.linalg.norm(u2 - ub) / np.linalg.norm(ub)
+    print(f"c1: FP64 then FP32 translation form from 1e-2: {i2['iters']} iterations, "
+          f"u error vs banded {e2:.2e}")
+    assert i2["converged"] and e2 <= 1e-8 and i2["iters"] <= 2 * i64["iters"]
+
+
+def test_f32_face_arithmetic(small):
+    """SFEM_ASM_F32_ARITH: the FP32 copy assembled with FP32 face arithmetic
+    (FP64 only for the tet volumes and inverse Jacobians).  A contribution
+    carries about eight FP32 roundings (volume weights, smoothed gradients,
+    lambda V_k and mu V_k, the block's three terms), about 2^-21 of the
+    row's largest contribution, and an entry sums up to ~20 contributions
+    exactly: the bar is 2e-5 of the row's largest entry against the FP64
+    oracle.  The rounded FP64 copy (SFEM_ASM_F32_COPY) is within one FP32
+    rounding, 2^-24 = 6e-8; the two copies are different computations."""
+    name, cs = small
+    sfem = _sfem()
+    ctx = gpu_ctx(cs.p)
+    ctx.assemble(f32_arith=True)
+    rp, ci, va = ctx.csr(sfem.K_WITH_BC)
+    _, _, v32 = ctx.csr(sfem.K_F32)
+    e64 = row_rel_err(rp, va, cs.Kb)
+    e32 = row_rel_err(rp, v32, cs.Kb)
+    ctx.assemble(f32_copy=True)
+    _, _, vr = ctx.csr(sfem.K_F32)
+    er = row_rel_err(rp, vr, cs.Kb)
+    print(f"{name}: FP32 face arithmetic row-relative error {e32:.2e}; rounded FP64 copy "
+          f"{er:.2e}; FP64 {e64:.2e}")
+    assert e64 <= 1e-12 and er <= 6.1e-8 and e32 <= 2e-5
+    assert not np.array_equal(v32, vr)
+
+
+def test_c1_f32_face_arithmetic_solve(c1):
+    """Translation-form FP32 products with the FP32-arithmetic copy reach the
+    oracle's displacements to 1e-8 (the FP64 residual judges)."""
+    sfem = _sfem()
+    ctx = gpu_ctx(c1.p)
+    ctx.assemble(f32_arith=True)
+    u, info = ctx.solve(rtol=1e-8, mode=sfem.MODE_F32_TF)
+    ub = O.solve_banded(c1.Kb, c1.fb)
+    err = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+    print(f"c1: FP32-arithmetic K, translation-form products: {info['iters']} iterations, "
+          f"u error vs banded {err:.2e}")
+    assert info["converged"] and err <= 1e-8
 
 
 def test_heterogeneous_material():
@@ -220,6 +266,15 @@ def test_patch_test_nonzero_dirichlet():
     err = np.abs(u - uex).max() / np.abs(uex).max()
     print(f"patch test: rhs error {ef:.2e}; max error {err:.2e} (relres {info['true_relres']:.2e})")
     assert ef <= 1e-13 and err <= 1e-10
+    # again under a packed row schedule: the copy the solver reads must hold
+    # the values after elimination (the right-hand side's product is taken
+    # with the unconstrained values first)
+    ctx.set_schedule(15, 4096)
+    ctx.assemble()
+    u2, i2 = ctx.solve(rtol=1e-12)
+    err2 = np.abs(u2 - uex).max() / np.abs(uex).max()
+    print(f"patch test, packed schedule: max error {err2:.2e}")
+    assert err2 <= 1e-10
 
 
 def test_penalty_bc_matches_oracle():

@@ -68,10 +68,16 @@ def mapply_bytes(N, nnz, nb):
 
 
 KERNEL_SOURCES = {
-    "cg_spmv_f64_c2": ("k_cg_spmv<double, double", "paper_2001_08849_amd/csrc/solve.hip"),
-    "assemble_c2": ("k_assemble<false>", "paper_2001_08849_amd/csrc/assemble.hip"),
+    "cg_spmv_f64_c2": ("k_cg_spmv<double, double, 8, 8>", "paper_2001_08849_amd/csrc/solve.hip"),
+    "cg_spmv_f32_tf_c2": ("k_cg_spmv<float, double, 8, 24>",
+                          "paper_2001_08849_amd/csrc/solve.hip"),
+    "assemble_c2": ("k_assemble<false, false>", "paper_2001_08849_amd/csrc/assemble.hip"),
     "mapply_c2": ("k_mapply<double>", "paper_2001_08849_amd/csrc/solve.hip"),
 }
+# instruction and stall counters summarised per kernel (one rocprofv3 pass:
+# at most 8 SQ counters)
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT",
+               "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"]
 
 
 def _sha(path):
@@ -122,15 +128,17 @@ def _short(name):
     return name.split("(")[0]
 
 
-def _counter_means(csv_path):
+def _counter_means(csv_path, counter=None):
     """Mean counter value per kernel name over its dispatches at the grid it
     was launched with most often (the solver's launches; the autotuner also
-    tries other grid caps)."""
+    tries other grid caps).  counter: only that counter's rows."""
     import collections
     import csv
     per = collections.defaultdict(float)
     name, grid = {}, {}
     for r in csv.DictReader(open(csv_path)):
+        if counter is not None and r.get("Counter_Name") != counter:
+            continue
         per[r["Dispatch_Id"]] += float(r["Counter_Value"])
         name[r["Dispatch_Id"]] = r["Kernel_Name"]
         grid[r["Dispatch_Id"]] = int(r.get("Grid_Size", 0) or 0)
@@ -182,6 +190,9 @@ def summarize_profiles(prof_dir, command_note):
             fh.write("# FETCH_SIZE / WRITE_SIZE (KiB per dispatch, mean) scaled by what the same\n"
                      "# counters read for a plain 1 GiB copy; stale once the source hash changes.\n")
             fh.write(json.dumps(rec, indent=1) + "\n")
+    sq = glob.glob(os.path.join(prof_dir, "sq", "*counter_collection.csv"))
+    if sq:
+        summarize_sq(sq[0], command_note)
     tables = [("ktrace", "kernels_c2.md",
                "rocprofv3 kernel statistics, 1.92M-tet cantilever benchmark (untrained "
                "network: every launch at full size)"),
@@ -205,6 +216,43 @@ def summarize_profiles(prof_dir, command_note):
                 nm = _short(r["Name"])
                 fh.write(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                          f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
+
+
+def summarize_sq(csv_path, command_note):
+    """profiles/counters_c2.md: per hot kernel, the SQ counters of one pass
+    (means per dispatch) and what they say: VALU instructions per wave,
+    VALU busy (active VALU cycles over busy cycles x SIMDs), the share of
+    wave cycles spent waiting on any outstanding instruction, LDS
+    instructions per wave and LDS bank-conflict cycles per LDS instruction."""
+    vals = {c: _counter_means(csv_path, c) for c in SQ_COUNTERS}
+    rows = []
+    for tag, (pattern, _src) in KERNEL_SOURCES.items():
+        kn = sorted((k for k in vals["SQ_WAVES"] if pattern in _short(k)),
+                    key=lambda k: -vals["SQ_WAVES"][k][1])
+        if not kn:
+            continue
+        k = kn[0]
+        g = {c: vals[c].get(k, (float("nan"), 0))[0] for c in SQ_COUNTERS}
+        waves = g["SQ_WAVES"] or float("nan")
+        rows.append((_short(k), g,
+                     g["SQ_INSTS_VALU"] / waves, g["SQ_INSTS_LDS"] / waves,
+                     g["SQ_LDS_BANK_CONFLICT"] / max(g["SQ_INSTS_LDS"], 1.0),
+                     g["SQ_WAIT_INST_ANY"] / max(g["SQ_WAVE_CYCLES"], 1.0),
+                     g["SQ_ACTIVE_INST_VALU"] / max(g["SQ_WAVE_CYCLES"], 1.0)))
+    with open(os.path.join(PROFILE_DIR, "counters_c2.md"), "w") as fh:
+        fh.write("# rocprofv3 SQ counters of the hot kernels, 1.92M-tet cantilever\n\n")
+        fh.write(f"Command: `{command_note}`\n\n")
+        fh.write("Means per dispatch at the solver's grid.  Ratios: VALU and LDS instructions "
+                 "per wave; bank-conflict cycles per LDS instruction; the share of wave cycles "
+                 "with a wave waiting on any outstanding instruction (SQ_WAIT_INST_ANY / "
+                 "SQ_WAVE_CYCLES) and issuing VALU work (SQ_ACTIVE_INST_VALU / "
+                 "SQ_WAVE_CYCLES).\n\n")
+        fh.write("| kernel | " + " | ".join(SQ_COUNTERS) + " | VALU/wave | LDS/wave | "
+                 "conflict cyc/LDS inst | wait share | VALU share |\n")
+        fh.write("|---" * (len(SQ_COUNTERS) + 6) + "|\n")
+        for nm, g, vw, lw, bc, ws, vs in rows:
+            fh.write(f"| {nm} | " + " | ".join(f"{g[c]:.4g}" for c in SQ_COUNTERS) +
+                     f" | {vw:.1f} | {lw:.1f} | {bc:.2f} | {ws:.2f} | {vs:.2f} |\n")
 
 
 CPU_SNIPPET = r"""
@@ -518,6 +566,9 @@ def mixed_precision_leg(ctx, sfem, u, inner_rtol, net, np, uref, reps=3):
         "solve_s": float(np.median([r["ms_solve"] for r in runs])) * 1e-3, "iters": i["iters"],
         "true_relres": i["true_relres"], "converged": bool(i["converged"]),
         "u_error_vs_oracle": u_error(np, u, uref)}
+    # every product launch timed (eager launches), for its roofline
+    _, pi = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF, profile=True)
+    res["f32_translation_form_jacobi"]["product_us_per_launch"] = pi["ms_spmv_avg"] * 1e3
     log(f"[bench] FP32 translation-form products, Jacobi: "
         f"{res['f32_translation_form_jacobi']['solve_s'] * 1e3:.0f} ms, {i['iters']} it, relres "
         f"{i['true_relres']:.2e}")
@@ -602,6 +653,18 @@ def batch_leg(mg, sfem, np):
     log(f"[bench] batch: {sz['meshes']} meshes x 4 load cases, {sz['tets']} tets, solve "
         f"{info['ms_solve']:.0f} ms, max {info['max_iters']} iterations, 4-RHS product {us:.0f} us "
         f"({ach:.0f} GB/s)")
+    # the stated precision of this workload: FP32 products inside FP64
+    # residual replacement (every system judged by its FP64 true residual)
+    b.close()
+    b32 = sfem.batch_from_items(items, f32_copy=True)
+    us32 = b32.autotune(reps=3, f32=True)
+    i32 = b32.solve(rtol=1e-8, mode=sfem.MODE_F32_RR, use_graph=True)
+    res["f32_products_f64_replacement"] = {
+        "solve_ms": i32["ms_solve"], "periods": i32["periods"], "max_iters": i32["max_iters"],
+        "worst_relres": i32["worst_relres"], "all_converged": bool(i32["all_converged"]),
+        "spmm4_us": us32}
+    log(f"[bench] batch, FP32 products + FP64 replacement: solve {i32['ms_solve']:.0f} ms, max "
+        f"{i32['max_iters']} iterations, 4-RHS product {us32:.0f} us")
     return res
 
 
@@ -638,6 +701,9 @@ def main():
     ap.add_argument("--profile-command", default="", help="command line recorded in summaries")
     ap.add_argument("--schedule", default="", metavar="VARIANT,GRID_CAP",
                     help="pin the FP64 row schedule instead of autotuning it")
+    ap.add_argument("--tf-solve", action="store_true",
+                    help="after the timed steps, one Jacobi solve with FP32 translation-form "
+                         "products (profiling; the full leg is --no-mixed's)")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="launch every PCG kernel one by one (for tracers that cannot follow "
                          "hipGraph launches)")
@@ -736,6 +802,13 @@ def main():
         _, prof = ctx.solve(rtol=1e-8, out=u, profile=True)
         log(f"[bench] profiled solve: {prof['ms_solve']:.1f} ms, CG product "
             f"{prof['ms_spmv_avg'] * 1e3:.1f} us per launch")
+
+    if args.tf_solve and not args.skip_solve:
+        ctx.assemble(f32_copy=True)
+        _, itf = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF, profile=True)
+        log(f"[bench] FP32 translation-form solve (profiled): {itf['ms_solve']:.1f} ms, "
+            f"{itf['iters']} it, product {itf['ms_spmv_avg'] * 1e3:.1f} us per launch")
+        ctx.assemble()
 
     stress = None
     if not args.skip_solve:
@@ -871,6 +944,22 @@ def main():
         out["stress_recovery"] = stress
     if mixed:
         out["mixed_precision"] = mixed
+        pus = mixed["f32_translation_form_jacobi"].get("product_us_per_launch")
+        if pus:
+            _, _, sb32 = algorithmic_bytes(m.n_nodes, m.n_tets, s.n_faces, s.nnz, s.n_blocks)
+            n = 3 * m.n_nodes
+            # the kernel's own bytes: FP32 values (packed, padding included),
+            # packed block columns, row offsets, R, x read and q written in FP64
+            own = 4 * s.nnz + 4 * s.n_blocks + 4 * (m.n_nodes + 1) + 72 * m.n_nodes + 16 * n
+            ach = sb32 / (pus * 1e-6) / 1e9
+            out["roofline_f32_tf"] = {
+                "kernel": "k_cg_spmv<float, double, 8, 24>", "bound": "hbm", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": read_traffic("cg_spmv_f32_tf_c2"), "bytes_per_launch": sb32,
+                "bytes_note": "scalar CSR FP32 SpMV count: 8 nnz + 4 (n+1) + 8 n",
+                "format_bytes_per_launch": own,
+                "format_frac": own / (pus * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                "us_per_launch": pus}
         if solves:
             out["solve_s"]["jacobi_f32_translation_form"] = \
                 mixed["f32_translation_form_jacobi"]["solve_s"]

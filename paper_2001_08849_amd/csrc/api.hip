@@ -389,8 +389,11 @@ int sfem_assemble(sfem_ctx* h, int flags) {
     SFEM_HIP(hipEventRecord(c.ev0, c.stream));
     // the solver's packed copy is written by the same pass, except when the
     // BCs are applied afterwards (it is then packed from the masked values)
-    sfem::assemble_values(c, c.val.get(), f32 ? c.val32.get() : nullptr, !two_step, !two_step,
-                          f32_arith);
+    // face domains without two-step BCs: only the packed copy the solver
+    // reads is written (the CSR order is made on demand)
+    const bool packed_only = !two_step && c.domain == SFEM_DOMAIN_FACE;
+    sfem::assemble_values(c, packed_only ? nullptr : c.val.get(), f32 ? c.val32.get() : nullptr,
+                          !two_step, !two_step, f32_arith);
     SFEM_HIP(hipEventRecord(c.ev1, c.stream));
     sfem::rhs_with_bc(c);
     if (two_step) {
@@ -471,6 +474,7 @@ int sfem_get_csr(sfem_ctx* h, int32_t* row_ptr, int32_t* col_idx, double* val, i
         SFEM_HIP(hipGetLastError());
         download(c, val, tmp.get(), nnz, ptr_kind);
       } else if (which == SFEM_K_WITH_BC || !c.val_has_bc) {
+        sfem::ensure_csr64(c);
         download(c, val, c.val.get(), nnz, ptr_kind);
       } else {
         sfem::DBuf<double> tmp;

@@ -146,7 +146,6 @@ __device__ __forceinline__ int face_geometry32(const int32_t* __restrict__ row,
   return 5;
 }
 
-// Position of node J among the ascending block columns cols[0..deg).
 // Exponent e of a row's unit 2^(e - 50): 0.5 bmax < 2^e (half the largest
 // face bound bounds every contribution), clamped so that 2^(50 - e) stays a
 // normal double (a larger e only coarsens the unit of absurdly small rows).
@@ -167,15 +166,6 @@ __global__ void k_row_bound(int64_t N, const int32_t* __restrict__ inc_ptr,
   row_vg[I] = m;
 }
 
-__device__ __forceinline__ int find_col(const int32_t* cols, int deg, int J) {
-  int lo = 0, hi = deg - 1;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (cols[mid] < J) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
 
 // ---------------------------------------------------------- fixed-point unit
 // A tile accumulates in 64-bit integers (LDS integer atomics are about twice
@@ -409,7 +399,7 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
     const int64_t gbase = 9 * (int64_t(b0) + rb);
     const double u = ldexp(1.0, sexp[li] - 50);
     const bool rbc = fixed && bc_row[I];
-    for (int k = lane; k < 9 * deg; k += kWave) {
+    for (int k = lane; (val || val32) && k < 9 * deg; k += kWave) {
       double v = double((long long)sval[9 * rb + k]) * u;
       if (rbc) {
         const int a = int((float(k) + 0.5f) * inv3d);
@@ -508,16 +498,6 @@ __global__ void k_rhs_bc(int64_t n, const double* __restrict__ f, const double* 
 }
 
 // diag[3I+a] = K(3I+a, 3I+a) from the node's own block.
-__global__ void k_diag(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-                       const double* __restrict__ val, double* __restrict__ diag) {
-  int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (I >= N) return;
-  const int rb = bptr[I];
-  const int deg = bptr[I + 1] - rb;
-  const int jj = find_col(bcol + rb, deg, int(I));
-  for (int a = 0; a < 3; ++a) diag[3 * I + a] = val[9 * int64_t(rb) + a * 3 * deg + 3 * jj + a];
-}
-
 __global__ void k_invert(int64_t n, const double* __restrict__ d, double* __restrict__ inv,
                          float* __restrict__ inv32) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -625,13 +605,27 @@ void face_bounds(Ctx& c) {
 // c.valp (and c.valp32 with an FP32 copy) and marks them valid.  With
 // f32_arith the FP32 copy comes from a second pass with FP32 face arithmetic
 // instead of the rounded FP64 values.
+//
+// val_out == c.val: the CSR order is written and marked current; null: only
+// the packed copy (packed must be set); another buffer: a scratch matrix
+// (the unconstrained K for sfem_get_csr), nothing is marked.
 void assemble_values(Ctx& c, double* val_out, float* val32_out, bool apply_mask, bool packed,
                      bool f32_arith) {
+  if (val_out == c.val.get() && val_out) {
+    c.csr64 = true;
+    c.packed64 = c.packed32 = false;
+  }
   if (c.domain == SFEM_DOMAIN_EDGE) {
     SFEM_REQUIRE(!f32_arith, SFEM_EINVAL,
                  "FP32 face arithmetic is for face-based smoothing domains");
+    SFEM_REQUIRE(val_out != nullptr, SFEM_EINVAL, "the edge assembly writes the CSR order");
     assemble_edge_values(c, val_out, val32_out, apply_mask);
     return;
+  }
+  SFEM_REQUIRE(val_out != nullptr || packed, SFEM_EINVAL, "no output for the assembly");
+  if (!val_out) {
+    c.csr64 = false;
+    c.packed64 = c.packed32 = false;
   }
   double* valp = nullptr;
   float* valp32 = nullptr;
@@ -693,9 +687,7 @@ void rhs_with_bc(Ctx& c) {
   }
   double* kub = nullptr;
   double* diag = c.w.reserve(n);  // unconstrained diagonal
-  k_diag<<<div_up(c.N, B), B, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
-                                            c.val.get(), diag);
-  SFEM_HIP(hipGetLastError());
+  matrix_diagonal(c, diag);
   if (c.any_nonzero_bc && c.penalty <= 0.0) {
     kub = c.q.reserve(n);
     spmv_f64(c, c.val.get(), c.ubar.get(), kub, c.stream);
@@ -711,8 +703,7 @@ void extract_dinv(Ctx& c) {
   c.dinv.reserve(n);
   c.dinv32.reserve(n);
   double* diag = c.w.reserve(n);
-  k_diag<<<div_up(c.N, B), B, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
-                                            c.val.get(), diag);
+  matrix_diagonal(c, diag);
   SFEM_HIP(hipGetLastError());
   k_invert<<<div_up(n, B), B, 0, c.stream>>>(n, diag, c.dinv.get(), c.dinv32.get());
   SFEM_HIP(hipGetLastError());

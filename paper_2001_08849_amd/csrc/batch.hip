@@ -1099,6 +1099,7 @@ int sfem_batch_build(sfem_batch* h, int flags) {
       check(b, sfem_set_dirichlet(ch, int64_t(fixed.size()), fixed.data(), nullptr, SFEM_PTR_HOST));
     check(b, sfem_assemble(ch, flags));
     sfem::Ctx& c = ch->c;
+    sfem::ensure_csr64(c);  // the batched products read the CSR order
     sfem::BatchState& s = *b.st;
     s.n_meshes = int(b.meshes.size());
     s.node0 = node0;

@@ -127,6 +127,9 @@ struct Ctx {
   DBuf<double> valp;             // K_bc packed (valid while packed64)
   DBuf<float> valp32;            // FP32 copy packed (valid while packed32)
   bool packed64 = false, packed32 = false;
+  // val holds the current K_bc (the face assembly writes only the packed
+  // copy; the CSR order is made from it when a caller needs it)
+  bool csr64 = false;
   DBuf<double> dinv;             // Jacobi: 1 / diag(K_bc)
   DBuf<float> dinv32;
   // [N][9] block row sums of K_bc: R_I[a][c] = sum_J K_bc[3I+a][3J+c] (the
@@ -216,6 +219,9 @@ void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream
 // Packed layout: pattern tables (once per mesh) and a value repack.
 void pack_pattern(Ctx& c);
 void pack_values64(Ctx& c);  // packed copy of the FP64 K (once per assembly)
+void ensure_csr64(Ctx& c);   // CSR-order FP64 K from the packed copy, if stale
+// diag(K_bc) from whichever copy of K is current
+void matrix_diagonal(Ctx& c, double* diag);
 void pack_values_f32(Ctx& c, const float* csr, float* packed);
 void pack_values_bf16(Ctx& c, const float* csr, __bf16* packed);
 // solve.hip

@@ -895,6 +895,7 @@ GnnWork& gnn_work(Ctx& c) {
 }
 
 void gnn_features(Ctx& c) {
+  ensure_csr64(c);  // the features read K in CSR order
   SFEM_REQUIRE(c.assembled, SFEM_ESTATE, "assemble K first");
   GnnWork& w = gnn_work(c);
   const Topology& tp = c.topo;
@@ -1038,6 +1039,7 @@ void gnn_precondition(Ctx& c, Gnn& g) {
 }
 
 double gnn_loss_grad(Ctx& c, Gnn& g, const int32_t* ids, int B, bool grad) {
+  ensure_csr64(c);  // K (M r - e) in CSR order
   GnnWork& w = gnn_work(c);
   SFEM_REQUIRE(w.n_pairs > 0, SFEM_ESTATE, "no training pairs on this context");
   SFEM_REQUIRE(B >= 1 && B <= kMaxBatch, SFEM_EINVAL, "batch size must be in [1, 64]");

@@ -784,20 +784,21 @@ RowSched tf_sched(const RowSched& rs) {
   return (kSched[rs.variant].mode & 8) ? rs : RowSched{15, rs.grid_cap};
 }
 
-// R_I = sum_J K_IJ per node row, one thread per (I, a, c): the row's deg
-// values of component (a, c), Neumaier-compensated (exact to one rounding
-// of R plus O(deg eps^2) sum |K_IJ|).
-__global__ void k_rowsum(int64_t N, const int32_t* __restrict__ bptr,
-                         const double* __restrict__ val, double* __restrict__ rsum) {
+// R_I = sum_J K_IJ per node row, one thread per (I, q = 3a + c): the
+// row's d4 packed values of component q (the padding adds zeros),
+// Neumaier-compensated (exact to one rounding of R plus O(deg eps^2)
+// sum |K_IJ|).
+__global__ void k_rowsum(int64_t N, const int32_t* __restrict__ ptr4,
+                         const double* __restrict__ valp, double* __restrict__ rsum) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= 9 * N) return;
   const int64_t I = t / 9;
-  const int q = int(t - 9 * I), a = q / 3, c = q - 3 * a;
-  const int rb = bptr[I], deg = bptr[I + 1] - rb;
-  const double* v = val + 9 * int64_t(rb) + a * 3 * deg + c;
+  const int q = int(t - 9 * I);
+  const int r4 = ptr4[I], d4 = ptr4[I + 1] - r4;
+  const double* v = valp + 9 * int64_t(r4) + int64_t(q) * d4;
   double sum = 0.0, comp = 0.0;
-  for (int j = 0; j < deg; ++j) {
-    const double x = v[3 * j];
+  for (int j = 0; j < d4; ++j) {
+    const double x = v[j];
     const double t2 = sum + x;
     comp += fabs(sum) >= fabs(x) ? (sum - t2) + x : (x - t2) + sum;
     sum = t2;
@@ -850,7 +851,10 @@ void ensure_packed32(Ctx& c);
 
 template <typename VT>
 Lay<VT> lay(Ctx& c, const RowSched& rs, const VT* csr_val) {
-  if (!(kSched[rs.variant].mode & 8)) return {c.topo.bptr.get(), c.topo.bcol.get(), csr_val};
+  if (!(kSched[rs.variant].mode & 8)) {
+    if ((const void*)csr_val == (const void*)c.val.get()) ensure_csr64(c);
+    return {c.topo.bptr.get(), c.topo.bcol.get(), csr_val};
+  }
   const void* pv = nullptr;
   if ((const void*)csr_val == (const void*)c.val.get()) {
     ensure_packed64(c);
@@ -891,8 +895,9 @@ struct CgBuffers {
 // Block row sums R of the FP64 K_bc (once per assembly).
 void ensure_rowsum(Ctx& c) {
   if (c.have_rsum) return;
+  ensure_packed64(c);
   c.rsum.reserve(9 * c.N);
-  k_rowsum<<<div_up(9 * c.N, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.val.get(),
+  k_rowsum<<<div_up(9 * c.N, 256), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.valp.get(),
                                                         c.rsum.get());
   SFEM_HIP(hipGetLastError());
   c.have_rsum = true;
@@ -1611,8 +1616,78 @@ void pack_values_f32(Ctx& c, const float* csr, float* packed) {
 }
 
 namespace {
+// Packed layout -> CSR order; one wave per node row.
+__global__ void k_unpack(int64_t N, const int32_t* __restrict__ bptr,
+                         const int32_t* __restrict__ p4, const double* __restrict__ packed,
+                         double* __restrict__ csr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t I = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 64;
+  if (I >= N) return;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb, r4 = p4[I], d4 = p4[I + 1] - r4;
+  const double* src = packed + 9 * int64_t(r4);
+  double* dst = csr + 9 * int64_t(rb);
+  const int three_deg = 3 * deg;
+  for (int k = lane; k < 9 * deg; k += 64) {
+    const int a = k / three_deg, r = k - a * three_deg;
+    const int j = r / 3, cc = r - 3 * j;
+    dst[k] = src[(3 * a + cc) * d4 + j];
+  }
+}
+
+// diag(K) from the packed copy: the row's self block is its first block
+// column equal to I (the padding repeats I after the real columns).
+__global__ void k_diag_packed(int64_t N, const int32_t* __restrict__ p4,
+                              const int32_t* __restrict__ c4, const double* __restrict__ packed,
+                              double* __restrict__ diag) {
+  const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int r4 = p4[I], d4 = p4[I + 1] - r4;
+  int j = 0;
+  while (j < d4 - 1 && c4[r4 + j] != int(I)) ++j;
+  const double* row = packed + 9 * int64_t(r4);
+  for (int a = 0; a < 3; ++a) diag[3 * I + a] = row[4 * a * d4 + j];
+}
+}  // namespace
+
+void ensure_csr64(Ctx& c) {
+  if (c.csr64) return;
+  SFEM_REQUIRE(c.packed64, SFEM_ESTATE, "no current copy of K");
+  c.val.reserve(9 * c.topo.nb);
+  k_unpack<<<div_up(c.N * 64, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.ptr4.get(),
+                                                          c.valp.get(), c.val.get());
+  SFEM_HIP(hipGetLastError());
+  c.csr64 = true;
+}
+
+namespace {
+__global__ void k_diag_csr(int64_t N, const int32_t* __restrict__ bptr,
+                           const int32_t* __restrict__ bcol, const double* __restrict__ val,
+                           double* __restrict__ diag) {
+  const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int rb = bptr[I], deg = bptr[I + 1] - rb;
+  int jj = 0;
+  while (jj < deg - 1 && bcol[rb + jj] != int(I)) ++jj;
+  for (int a = 0; a < 3; ++a) diag[3 * I + a] = val[9 * int64_t(rb) + a * 3 * deg + 3 * jj + a];
+}
+}  // namespace
+
+void matrix_diagonal(Ctx& c, double* diag) {
+  if (c.csr64) {
+    k_diag_csr<<<div_up(c.N, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(), c.topo.bcol.get(),
+                                                        c.val.get(), diag);
+  } else {
+    SFEM_REQUIRE(c.packed64, SFEM_ESTATE, "no current copy of K");
+    k_diag_packed<<<div_up(c.N, 256), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.col4.get(),
+                                                           c.valp.get(), diag);
+  }
+  SFEM_HIP(hipGetLastError());
+}
+
+namespace {
 void ensure_packed64(Ctx& c) {
   if (c.packed64) return;
+  SFEM_REQUIRE(c.csr64, SFEM_ESTATE, "no current copy of K");
   pack_pattern(c);
   c.valp.reserve(9 * c.nb4);
   k_pack<double><<<div_up(c.N * 64, 256), 256, 0, c.stream>>>(c.N, c.topo.bptr.get(),

@@ -93,13 +93,19 @@ def test_graph_replay_equals_eager_launches(S, small_items):
 
 
 def test_fp32_products_with_fp64_replacement(S, small_items):
+    """FP32 products, FP64 vectors and FP64 residual replacement: every
+    system of every mesh reaches the oracle's u to 1e-9 (the FP64 batch
+    reaches 8e-11)."""
     b = S.batch_from_items(small_items, f32_copy=True)
     info = b.solve(rtol=1e-8, mode=S.MODE_F32_RR)
     assert info["all_converged"] == 1 and info["worst_relres"] <= 1e-8
-    it = small_items[0]
-    refs = oracle_solutions(it)
-    for k in range(4):
-        assert rel(b.solution(0, k, it.mesh.n_nodes), refs[k]) < 1e-6
+    worst = 0.0
+    for mi, it in enumerate(small_items):
+        refs = oracle_solutions(it)
+        for k in range(4):
+            worst = max(worst, rel(b.solution(mi, k, it.mesh.n_nodes), refs[k]))
+    print(f"batched FP32 products: worst u error vs the oracle {worst:.2e}")
+    assert worst <= 1e-9
 
 
 def test_autotuner_buckets_and_cache(S):
@@ -175,8 +181,17 @@ def test_full_c3_batch(S):
     si = b.system_info()
     assert np.all(si["relres"] <= 1e-8) and not np.any(si["breakdown"])
     sizes = np.array([it.mesh.n_tets for it in items])
-    for mi in np.argsort(sizes)[:2]:
-        refs = oracle_solutions(items[mi])
-        for k in range(4):
-            err = rel(b.solution(int(mi), k, items[mi].mesh.n_nodes), refs[k])
-            assert err < 1e-7, (mi, k, err)
+    pick = np.argsort(sizes)[:2]
+    refs = {int(mi): oracle_solutions(items[mi]) for mi in pick}
+    worst = max(rel(b.solution(mi, k, items[mi].mesh.n_nodes), refs[mi][k])
+                for mi in refs for k in range(4))
+    # the same batch with FP32 products and FP64 residual replacement
+    b32 = S.batch_from_items(items, f32_copy=True)
+    b32.autotune(reps=3, f32=True)
+    i32 = b32.solve(rtol=1e-8, mode=S.MODE_F32_RR, use_graph=True)
+    worst32 = max(rel(b32.solution(mi, k, items[mi].mesh.n_nodes), refs[mi][k])
+                  for mi in refs for k in range(4))
+    print(f"c3: sampled u error vs the oracle: FP64 {worst:.2e}; FP32 products "
+          f"{worst32:.2e} ({i32['ms_solve']:.0f} ms, max iters {i32['max_iters']})")
+    assert worst <= 1e-8
+    assert i32["all_converged"] == 1 and i32["worst_relres"] <= 1e-8 and worst32 <= 1e-8

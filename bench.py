@@ -71,6 +71,10 @@ KERNEL_SOURCES = {
     "cg_spmv_f64_c2": ("k_cg_spmv<double, double, 8, 8>", "paper_2001_08849_amd/csrc/solve.hip"),
     "cg_spmv_f32_tf_c2": ("k_cg_spmv<float, double, 8, 24>",
                           "paper_2001_08849_amd/csrc/solve.hip"),
+    "cg_spmv_lds_f64_c2": ("k_cg_spmv_lds<double, double, 8, false>",
+                           "paper_2001_08849_amd/csrc/solve.hip"),
+    "cg_spmv_lds_f32_tf_c2": ("k_cg_spmv_lds<float, double, 8, true>",
+                              "paper_2001_08849_amd/csrc/solve.hip"),
     "assemble_c2": ("k_assemble<false, false>", "paper_2001_08849_amd/csrc/assemble.hip"),
     "mapply_c2": ("k_mapply<double>", "paper_2001_08849_amd/csrc/solve.hip"),
 }
@@ -570,8 +574,9 @@ def mixed_precision_leg(ctx, sfem, u, inner_rtol, net, np, uref, reps=3):
     _, pi = ctx.solve(rtol=1e-8, out=u, mode=sfem.MODE_F32_TF, profile=True)
     res["f32_translation_form_jacobi"]["product_us_per_launch"] = pi["ms_spmv_avg"] * 1e3
     log(f"[bench] FP32 translation-form products, Jacobi: "
-        f"{res['f32_translation_form_jacobi']['solve_s'] * 1e3:.0f} ms, {i['iters']} it, relres "
-        f"{i['true_relres']:.2e}")
+        f"{res['f32_translation_form_jacobi']['solve_s'] * 1e3:.0f} ms, "
+        f"{res['f32_translation_form_jacobi']['iters']} it, relres "
+        f"{res['f32_translation_form_jacobi']['true_relres']:.2e}")
     if net is not None:
         # the switch level: FP64 products until the true relres reaches
         # f32_from, FP32 translation-form products after (0: from the start)

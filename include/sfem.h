@@ -286,12 +286,19 @@ int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
  *   13    32 lanes, two rows, nontemporal matrix-value loads;
  *   14-16 4/8/16 lanes, packed layout: a copy of the values made once per
  *         assembly in which each node row is a [9][deg rounded up to 4]
- *         array, read 4 blocks per lane with 16-byte loads.
+ *         array, read 4 blocks per lane with 16-byte loads;
+ *   17    8 lanes, packed layout, x staged in LDS: a workgroup takes 128
+ *         consecutive node rows, loads the x entries they gather (a window
+ *         of at most 1,024 nodes, tables made once per mesh) into LDS, then
+ *         runs its rows against it (the CG product; the other row kernels
+ *         run schedule 15 for it).  Unavailable (SFEM_EINVAL from
+ *         sfem_set_schedule, skipped by the autotuner) when a chunk's
+ *         window exceeds 1,024 nodes, e.g. under an arbitrary numbering.
  * `grid_cap` caps the workgroups launched.  precision: SFEM_ASM_F64 or
  * SFEM_ASM_F32_COPY (the schedule of FP32 matrices, also used by the learned
  * M).  All schedules compute the same products up to floating-point
  * summation order. */
-enum { SFEM_NUM_SCHEDULES = 17 };
+enum { SFEM_NUM_SCHEDULES = 18 };
 int sfem_set_schedule(sfem_ctx* ctx, int precision, int variant, int grid_cap);
 int sfem_get_schedule(sfem_ctx* ctx, int precision, int* variant, int* grid_cap);
 
@@ -497,6 +504,9 @@ typedef struct {
   int all_converged;
   int max_iters;      /* most iterations of any system */
   double worst_relres;
+  int fp64_from_period; /* SFEM_MODE_F32_RR: the check period after which the
+                           batch continued with FP64 products because a
+                           system stagnated with FP32 ones (0: never) */
 } sfem_batch_info;
 
 /* Solves all systems by CG with Jacobi preconditioning, every system from
@@ -504,8 +514,12 @@ typedef struct {
  * 4-right-hand-side product and the per-system updates, then the FP64
  * residual replacement and the convergence test.  A mesh whose 4 systems
  * have all finished (converged, broken down or stagnated) drops out of the
- * work lists remade at the start of the next period.  SFEM_ENOCONV if any
- * system did not converge. */
+ * work lists remade at the start of the next period.  In SFEM_MODE_F32_RR a
+ * system past relres 1e-3 whose residual makes no new minimum for 10 checks
+ * (FP32 products too coarse for its conditioning) makes the whole batch
+ * continue with FP64 products, every active system restarting CG from its
+ * current x.
+ * SFEM_ENOCONV if any system did not converge. */
 int sfem_batch_solve(sfem_batch* b, const sfem_batch_opts* opts, sfem_batch_info* info);
 /* Displacements of (mesh, load case): float64 [3 n_nodes(mesh)]. */
 int sfem_batch_get_solution(sfem_batch* b, int mesh, int rhs, double* u, int ptr_kind);

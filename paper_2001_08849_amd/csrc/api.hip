@@ -112,6 +112,7 @@ __global__ void k_set_fixed(int64_t n, const int32_t* dof, const double* value, 
 void reset_problem(Ctx& c) {
   c.have_learned = false;
   c.nb4 = 0;
+  c.lds_tables = 0;
   c.gnn.reset();
   c.have_material = false;
   c.per_tet = false;
@@ -663,6 +664,11 @@ int sfem_set_schedule(sfem_ctx* h, int precision, int variant, int grid_cap) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(variant >= 0 && variant < sfem::kNumSched && grid_cap >= 8, SFEM_EINVAL,
                  "bad schedule");
+    if (variant == sfem::kNumSched - 1) {
+      SFEM_REQUIRE(c.topo.valid, SFEM_ESTATE, "set a mesh first (schedule 17 needs its tables)");
+      SFEM_REQUIRE(sfem::ensure_lds_tables(c), SFEM_EINVAL,
+                   "schedule 17 unavailable: a chunk's x window exceeds 1,024 nodes");
+    }
     const sfem::RowSched rs{variant, grid_cap};
     if (precision == SFEM_ASM_F32_COPY) c.sched32 = rs;
     else c.sched64 = rs;

@@ -43,6 +43,7 @@ constexpr int kRws[kNumRw] = {16, 64, 256};
 struct BScal {
   double rz, pq, alpha, beta, rr, rr_true, ff, tol2, best;
   int active, iters, breakdown, stale;
+  int need64, pad;  // stagnated with FP32 products: the batch continues with FP64 ones
 };
 
 enum BOp { kBStart = 0, kBAlpha = 1, kBBeta = 2, kBReplace = 3 };
@@ -97,13 +98,17 @@ struct Work {
 //   EPI 1: residual replacement Y = F - K X, Z = dinv Y, partials (y.y),
 //          (y.z) per load case.
 // Partials: part[w][k][2].
-template <typename VT, int LPR, int EPI>
+// DIFF: the translation form, Y_I = sum_J K_IJ (X_J - X_I) + R_I X_I with
+// rsum = R (the FP64 block row sums): the FP32 values' rounding then meets
+// neighbour differences only (see the single-system product).
+template <typename VT, int LPR, int EPI, bool DIFF = false>
 __global__ void __launch_bounds__(kBThreads)
     k_bspmm(Work wk, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
             const BScal* __restrict__ sc, const int32_t* __restrict__ bptr,
             const int32_t* __restrict__ bcol, const VT* __restrict__ val,
             const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ Y,
-            double* __restrict__ Z, const double* __restrict__ dinv, double* __restrict__ part) {
+            double* __restrict__ Z, const double* __restrict__ dinv, double* __restrict__ part,
+            const double* __restrict__ rsum = nullptr) {
   constexpr int G = kBThreads / LPR;
   const int n_items = wk.count();
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -127,6 +132,12 @@ __global__ void __launch_bounds__(kBThreads)
       for (int a = 0; a < 3; ++a)
   #pragma unroll
         for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
+      double xi[3][kNR];  // X_I (DIFF)
+  #pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+  #pragma unroll
+        for (int k = 0; k < kNR; ++k)
+          xi[cc][k] = (DIFF && valid) ? X[(3 * int64_t(I) + cc) * kNR + k] : 0.0;
       // kCU columns per step (masked past the row), so each lane keeps kCU
       // columns' loads in flight
       for (int c0 = sub; c0 < td; c0 += kCU * LPR) {
@@ -136,10 +147,16 @@ __global__ void __launch_bounds__(kBThreads)
           const bool in = c < td;
           const int cc = in ? c : c0;
           const int jj = cc / 3;
-          const int64_t col = 3 * int64_t(bcol[rb + jj]) + (cc - 3 * jj);
+          const int comp = cc - 3 * jj;
+          const int64_t col = 3 * int64_t(bcol[rb + jj]) + comp;
           const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
           const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
-          const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
+          double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
+          if constexpr (DIFF) {
+  #pragma unroll
+            for (int k = 0; k < kNR; ++k)
+              x4[k] -= comp == 0 ? xi[0][k] : (comp == 1 ? xi[1][k] : xi[2][k]);
+          }
           const double m = in ? 1.0 : 0.0;
           const double a3[3] = {m * double(v[cc]), m * double(v[td + cc]),
                                 m * double(v[2 * td + cc])};
@@ -154,6 +171,14 @@ __global__ void __launch_bounds__(kBThreads)
   #pragma unroll
         for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
       if (valid && sub == 0) {
+        if constexpr (DIFF) {
+          const double* R = rsum + 9 * int64_t(I);
+  #pragma unroll
+          for (int a = 0; a < 3; ++a)
+  #pragma unroll
+            for (int k = 0; k < kNR; ++k)
+              acc[a][k] += R[3 * a] * xi[0][k] + R[3 * a + 1] * xi[1][k] + R[3 * a + 2] * xi[2][k];
+        }
   #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const int64_t i = 3 * int64_t(I) + a;
@@ -398,7 +423,7 @@ __global__ void __launch_bounds__(kBThreads)
 // Finished systems are final and left untouched.
 __global__ void __launch_bounds__(kBThreads)
     k_bfinal(int op, const int2* __restrict__ mw, const double* __restrict__ part,
-             BScal* __restrict__ sc, double rtol2, int max_stale) {
+             BScal* __restrict__ sc, double rtol2, int max_stale, int f32) {
   const int m = blockIdx.x;
   BScal* sys = sc + m * kNR;
   if (op != kBStart && mesh_done(sc, m)) return;
@@ -427,6 +452,7 @@ __global__ void __launch_bounds__(kBThreads)
       c.iters = 0;
       c.breakdown = 0;
       c.stale = 0;
+      c.need64 = 0;
       c.active = (v1 > 0.0 && v1 > c.tol2) ? 1 : 0;
       break;
     case kBAlpha:  // v0 = p.K p
@@ -457,6 +483,15 @@ __global__ void __launch_bounds__(kBThreads)
       } else if (v0 < c.best) {
         c.best = v0;
         c.stale = 0;
+      } else if (f32 && c.best <= 1e-6 * c.ff) {
+        // past relres 1e-3 with no new minimum for max_stale / 4 checks:
+        // FP32 products cannot take this system further (too ill-conditioned
+        // for their rounding).  It stays active and the host moves the batch
+        // to FP64 products (k_brestart) before the next period.
+        if (++c.stale >= max_stale / 4) {
+          c.need64 = 1;
+          c.stale = 0;
+        }
       } else if (c.best <= 1e4 * c.tol2 && ++c.stale >= max_stale) {
         // stagnation counts only near the tolerance: CG residual norms may
         // rise far above their start before they fall
@@ -654,21 +689,27 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
   k_bspmm<VT, LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                \
       wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(),     \
       c.topo.bcol.get(), VAL, X, F, Y, Z, c.dinv.get(), b.part.get())
+  // FP32 values: the translation form (R made with the assembly)
+#define T_(LPR)                                                                             \
+  k_bspmm<float, LPR, EPI, true><<<grid, kBThreads, 0, c.stream>>>(                       \
+      wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(),     \
+      c.topo.bcol.get(), c.val32.get(), X, F, Y, Z, c.dinv.get(), b.part.get(), c.rsum.get())
 #define P_(LPR)                                                                              \
   k_bspmm_p<LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                    \
       wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.ptr4.get(),           \
       c.col4.get(), c.valp.get(), X, F, Y, Z, c.dinv.get(), b.part.get())
+    if (f32) SFEM_REQUIRE(c.have_rsum, SFEM_ESTATE, "block row sums of K missing");
     if (f32 && b.packed[bk]) {
-      L_(float, c.val32.get(), 16);  // FP32 values keep the CSR order
+      T_(16);  // FP32 values keep the CSR order
     } else if (b.packed[bk]) {
       SFEM_REQUIRE(c.packed64, SFEM_ESTATE, "packed copy of K missing");
       if (b.lpr[bk] == 4) P_(4);
       else P_(8);
     } else if (f32) {
       switch (b.lpr[bk]) {
-        case 8: L_(float, c.val32.get(), 8); break;
-        case 16: L_(float, c.val32.get(), 16); break;
-        default: L_(float, c.val32.get(), 32); break;
+        case 8: T_(8); break;
+        case 16: T_(16); break;
+        default: T_(32); break;
       }
     } else {
       switch (b.lpr[bk]) {
@@ -678,6 +719,7 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
       }
     }
 #undef L_
+#undef T_
 #undef P_
     SFEM_HIP(hipGetLastError());
   }
@@ -685,10 +727,24 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
 
 // The partials of kBAlpha / kBReplace come from the product's table, those
 // of kBStart / kBBeta from the elementwise one.
-void bfinal(Ctx& c, BatchState& b, BOp op, double rtol2, int max_stale) {
+// Every active system restarts CG from its x and true residual (beta = 0):
+// on the move from FP32 to FP64 products.  Directions made with the FP32
+// products and the residual jumps of their replacements have lost the
+// conjugacy that continuing them in FP64 would assume (on the most
+// ill-conditioned meshes continuing them converged far slower than a
+// restart).
+__global__ void k_brestart(int n_sys, BScal* __restrict__ sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_sys && sc[s].active) {
+    sc[s].beta = 0.0;
+    sc[s].stale = 0;
+  }
+}
+
+void bfinal(Ctx& c, BatchState& b, BOp op, double rtol2, int max_stale, bool f32 = false) {
   const int2* map = (op == kBAlpha || op == kBReplace) ? b.mw.get() : b.mv.get();
   k_bfinal<<<b.n_meshes, kBThreads, 0, c.stream>>>(int(op), map, b.part.get(), b.sc.get(), rtol2,
-                                                   max_stale);
+                                                   max_stale, int(f32));
   SFEM_HIP(hipGetLastError());
 }
 
@@ -710,7 +766,7 @@ void period(Ctx& c, BatchState& b, bool f32, int iters, double rtol2, int max_st
     bfinal(c, b, kBBeta, rtol2, max_stale);
   }
   bspmm<1>(c, b, false, b.X.get(), b.F.get(), b.R.get(), b.Z.get());
-  bfinal(c, b, kBReplace, rtol2, max_stale);
+  bfinal(c, b, kBReplace, rtol2, max_stale, f32);
   SFEM_HIP(hipGetLastError());
 }
 
@@ -870,23 +926,25 @@ double batch_autotune(Ctx& c, BatchState& b, int reps, bool use_cache, bool f32)
 // Solves every (mesh, load case) system.  Returns the number of check
 // periods run; the per-system scalars are left in b.sc_host.
 int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int check_every,
-                bool use_graph, double* ms_out) {
+                bool use_graph, double* ms_out, int* fp64_from) {
   SFEM_REQUIRE(!f32 || c.have_f32, SFEM_ESTATE, "the FP32 mode needs an FP32 copy of K");
   const int V = b.n_vw;
   const double rtol2 = rtol * rtol;
   const int max_stale = 40;
   const int n_sys = b.n_meshes * kNR;
   if (b.packed[0] || b.packed[1] || b.packed[2]) pack_values64(c);  // before any capture
+  if (fp64_from) *fp64_from = 0;
   SFEM_HIP(hipEventRecord(c.ev0, c.stream));
   k_bstart<<<V, kBThreads, 0, c.stream>>>(b.vr.get(), c.dinv.get(), b.F.get(), b.X.get(),
                                           b.R.get(), b.Z.get(), b.P.get(), b.part.get());
   SFEM_HIP(hipGetLastError());
   bfinal(c, b, kBStart, rtol2, max_stale);
-  if (use_graph && (b.graph_key[0] != int(f32) || b.graph_key[1] != check_every)) {
+  auto capture = [&](bool prec32) {
+    if (!use_graph || (b.graph_key[0] == int(prec32) && b.graph_key[1] == check_every)) return;
     b.drop_graph();
     SFEM_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
     try {
-      period(c, b, f32, check_every, rtol2, max_stale);
+      period(c, b, prec32, check_every, rtol2, max_stale);
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(c.stream, &g);
@@ -895,9 +953,10 @@ int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int 
     }
     SFEM_HIP(hipStreamEndCapture(c.stream, &b.graph));
     SFEM_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-    b.graph_key[0] = int(f32);
+    b.graph_key[0] = int(prec32);
     b.graph_key[1] = check_every;
-  }
+  };
+  capture(f32);
   int periods = 0;
   for (int done = 0; done < max_iter; done += check_every) {
     if (use_graph) SFEM_HIP(hipGraphLaunch(b.exec, c.stream));
@@ -906,9 +965,21 @@ int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int 
     SFEM_HIP(hipMemcpyAsync(b.sc_host, b.sc.get(), sizeof(BScal) * n_sys,
                             hipMemcpyDeviceToHost, c.stream));
     SFEM_HIP(hipStreamSynchronize(c.stream));
-    bool any = false;
-    for (int s = 0; s < n_sys; ++s) any = any || b.sc_host[s].active;
+    bool any = false, need64 = false;
+    for (int s = 0; s < n_sys; ++s) {
+      any = any || b.sc_host[s].active;
+      need64 = need64 || (b.sc_host[s].active && b.sc_host[s].need64);
+    }
     if (!any) break;
+    if (f32 && need64) {
+      // a system stagnated with FP32 products: the rest of the solve runs
+      // FP64 products, every active system restarted from its x
+      f32 = false;
+      if (fp64_from) *fp64_from = periods;
+      k_brestart<<<div_up(n_sys, 256), 256, 0, c.stream>>>(n_sys, b.sc.get());
+      SFEM_HIP(hipGetLastError());
+      capture(false);
+    }
   }
   SFEM_HIP(hipEventRecord(c.ev1, c.stream));
   SFEM_HIP(hipEventSynchronize(c.ev1));
@@ -1100,6 +1171,7 @@ int sfem_batch_build(sfem_batch* h, int flags) {
     check(b, sfem_assemble(ch, flags));
     sfem::Ctx& c = ch->c;
     sfem::ensure_csr64(c);  // the batched products read the CSR order
+    if (c.have_f32) sfem::ensure_rowsum(c);  // FP32 products in the translation form
     sfem::BatchState& s = *b.st;
     s.n_meshes = int(b.meshes.size());
     s.node0 = node0;
@@ -1197,8 +1269,9 @@ int sfem_batch_solve(sfem_batch* h, const sfem_batch_opts* o, sfem_batch_info* i
     const int every = o->check_every > 0 ? o->check_every : 50;
     const int max_iter = o->max_iter > 0 ? o->max_iter : 100000;
     double ms = 0;
+    int fp64_from = 0;
     const int periods = sfem::batch_solve(b.ctx->c, *b.st, o->mode == SFEM_MODE_F32_RR, o->rtol,
-                                          max_iter, every, o->use_graph != 0, &ms);
+                                          max_iter, every, o->use_graph != 0, &ms, &fp64_from);
     int all = 1, worst_it = 0;
     double worst = 0.0;
     for (int s = 0; s < b.st->n_meshes * 4; ++s) {
@@ -1215,6 +1288,7 @@ int sfem_batch_solve(sfem_batch* h, const sfem_batch_opts* o, sfem_batch_info* i
       info->all_converged = all;
       info->max_iters = worst_it;
       info->worst_relres = worst;
+      info->fp64_from_period = fp64_from;
     }
     return all ? SFEM_OK : SFEM_ENOCONV;
   });

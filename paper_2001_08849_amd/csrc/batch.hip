@@ -555,13 +555,16 @@ struct BatchState {
   DBuf<int32_t> mbucket, alist, acnt;
   DBuf<double> F, X, R, Z, P, Q, part;
   DBuf<BScal> sc;
-  BScal* sc_host = nullptr;
+  BScal* sc_host = nullptr;          // two slots of n_sys: period p's flags in slot p % 2
+  hipEvent_t flags_ready[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_key[2] = {-1, -1};       // (mode, check_every) of the captured period
   ~BatchState() {
     drop_graph();
     if (sc_host) (void)hipHostFree(sc_host);
+    for (hipEvent_t e : flags_ready)
+      if (e) (void)hipEventDestroy(e);
   }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -782,8 +785,10 @@ void batch_prepare(Ctx& c, BatchState& b) {
   for (auto* v : {&b.F, &b.X, &b.R, &b.Z, &b.P, &b.Q}) v->reserve(size_t(n) * kNR);
   b.sc.reserve(size_t(b.n_meshes) * kNR);
   if (!b.sc_host)
-    SFEM_HIP(hipHostMalloc((void**)&b.sc_host, sizeof(BScal) * b.n_meshes * kNR,
+    SFEM_HIP(hipHostMalloc((void**)&b.sc_host, 2 * sizeof(BScal) * b.n_meshes * kNR,
                            hipHostMallocDefault));
+  for (hipEvent_t& e : b.flags_ready)
+    if (!e) SFEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   k_bzero<<<div_up(n * kNR, 256), 256, 0, c.stream>>>(n * kNR, b.F.get());
   SFEM_HIP(hipGetLastError());
   build_table(c, b);
@@ -957,30 +962,46 @@ int batch_solve(Ctx& c, BatchState& b, bool f32, double rtol, int max_iter, int 
     b.graph_key[1] = check_every;
   };
   capture(f32);
-  int periods = 0;
-  for (int done = 0; done < max_iter; done += check_every) {
+  // Period p copies the systems' flags into host slot p % 2 and records
+  // flags_ready[p % 2].  Period p + 1 is enqueued before the host waits for
+  // period p's flags, so the GPU never idles while the host reads them; a
+  // period enqueued after every system has finished walks empty work lists.
+  const size_t slot_bytes = sizeof(BScal) * n_sys;
+  auto enqueue = [&](int p) {
     if (use_graph) SFEM_HIP(hipGraphLaunch(b.exec, c.stream));
     else period(c, b, f32, check_every, rtol2, max_stale);
-    ++periods;
-    SFEM_HIP(hipMemcpyAsync(b.sc_host, b.sc.get(), sizeof(BScal) * n_sys,
+    SFEM_HIP(hipMemcpyAsync(b.sc_host + (p & 1) * n_sys, b.sc.get(), slot_bytes,
                             hipMemcpyDeviceToHost, c.stream));
-    SFEM_HIP(hipStreamSynchronize(c.stream));
+    SFEM_HIP(hipEventRecord(b.flags_ready[p & 1], c.stream));
+  };
+  const int max_periods = std::max(1, div_up(max_iter, check_every));
+  int periods = 0;
+  enqueue(periods++);
+  for (int p = 0; p < max_periods; ++p) {
+    if (periods < max_periods) enqueue(periods++);
+    SFEM_HIP(hipEventSynchronize(b.flags_ready[p & 1]));
+    const BScal* fl = b.sc_host + (p & 1) * n_sys;
     bool any = false, need64 = false;
     for (int s = 0; s < n_sys; ++s) {
-      any = any || b.sc_host[s].active;
-      need64 = need64 || (b.sc_host[s].active && b.sc_host[s].need64);
+      any = any || fl[s].active;
+      need64 = need64 || (fl[s].active && fl[s].need64);
     }
     if (!any) break;
     if (f32 && need64) {
       // a system stagnated with FP32 products: the rest of the solve runs
-      // FP64 products, every active system restarted from its x
+      // FP64 products, every active system restarted from its x (after the
+      // period already enqueued, whose graph must finish before the
+      // recapture)
       f32 = false;
       if (fp64_from) *fp64_from = periods;
+      SFEM_HIP(hipStreamSynchronize(c.stream));
       k_brestart<<<div_up(n_sys, 256), 256, 0, c.stream>>>(n_sys, b.sc.get());
       SFEM_HIP(hipGetLastError());
       capture(false);
     }
   }
+  // the final per-system scalars, for the info calls
+  SFEM_HIP(hipMemcpyAsync(b.sc_host, b.sc.get(), slot_bytes, hipMemcpyDeviceToHost, c.stream));
   SFEM_HIP(hipEventRecord(c.ev1, c.stream));
   SFEM_HIP(hipEventSynchronize(c.ev1));
   float ms = 0;

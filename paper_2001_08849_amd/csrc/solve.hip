@@ -1462,12 +1462,12 @@ __global__ void k_ones(int64_t n, double* __restrict__ u) {
 // FP64: `reps` Jacobi-PCG iterations on the context's matrix from a fixed
 // start (b = 1), i.e. the product inside the loop where the vector kernels
 // share the caches (an isolated product favours other schedules); the time
-// per iteration is reported.  FP32 (if present): `reps` isolated products.
+// per iteration is reported.  FP32 (if present): the same iterations with
+// the FP32 values in the translation form (FP64 vectors), the FP32 copy's
+// main use, over the packed schedules (the only ones with that form).
 void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
   const int64_t n = c.n_dof();
   ensure_work(c, false);
-  c.x32.reserve(n);
-  c.q32.reserve(n);
   k_zero<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.x.get());
   k_ones<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.w.get());
   SFEM_HIP(hipGetLastError());
@@ -1478,31 +1478,34 @@ void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
   for (int prec = 0; prec < (c.have_f32 ? 2 : 1); ++prec) {
     double best = 1e30;
     RowSched pick = prec ? c.sched32 : keep64;
+    if (prec == 1) ensure_rowsum(c);
     for (int v = 0; v < kNumSched; ++v)
       for (int cap : caps) {
         if ((kSched[v].mode & 32) && !ensure_lds_tables(c)) continue;
+        if (prec == 1 && !(kSched[v].mode & 8)) continue;
         const RowSched rs{v, cap};
         double us = 0.0;
+        (prec == 0 ? c.sched64 : c.sched32) = rs;
+        CgBuffers B{prec == 0 ? (const void*)c.val.get() : (const void*)c.val32.get(),
+                    c.val.get(), c.dinv.get(), c.w.get(), c.x.get(), c.r.get(),
+                    c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
+        if (prec == 1) B.rsum = c.rsum.get();
+        const int vg = vec_grid(n);
+        k_cg_start<double><<<vg, kVecThreads, 0, c.stream>>>(
+            n, c.w.get(), 1.0, nullptr, c.x.get(), c.r.get(), c.z.get(), c.p.get(), c.p2.get(),
+            c.dinv.get(), c.partials.get());
+        finalize(c, kFinStart, vg);
+        k_cg_arm<<<1, 64, 0, c.stream>>>(c.sc.get(), 0.0);
+        int parity = 0;
         if (prec == 0) {
-          c.sched64 = rs;
-          CgBuffers B{c.val.get(), c.val.get(), c.dinv.get(), c.w.get(), c.x.get(), c.r.get(),
-                      c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
-          const int vg = vec_grid(n);
-          k_cg_start<double><<<vg, kVecThreads, 0, c.stream>>>(
-              n, c.w.get(), 1.0, nullptr, c.x.get(), c.r.get(), c.z.get(), c.p.get(), c.p2.get(),
-              c.dinv.get(), c.partials.get());
-          finalize(c, kFinStart, vg);
-          k_cg_arm<<<1, 64, 0, c.stream>>>(c.sc.get(), 0.0);
-          int parity = 0;
           cg_iterations<double, double>(c, B, 2, parity);  // warm
           SFEM_HIP(hipEventRecord(c.ev0, c.stream));
           cg_iterations<double, double>(c, B, reps, parity);
           SFEM_HIP(hipEventRecord(c.ev1, c.stream));
         } else {
-          spmv_f32_sched(c, rs, c.val32.get(), c.x32.get(), c.q32.get(), c.stream);  // warm
+          cg_iterations<float, double>(c, B, 2, parity);  // warm
           SFEM_HIP(hipEventRecord(c.ev0, c.stream));
-          for (int r = 0; r < reps; ++r)
-            spmv_f32_sched(c, rs, c.val32.get(), c.x32.get(), c.q32.get(), c.stream);
+          cg_iterations<float, double>(c, B, reps, parity);
           SFEM_HIP(hipEventRecord(c.ev1, c.stream));
         }
         SFEM_HIP(hipEventSynchronize(c.ev1));

@@ -409,6 +409,20 @@ int sfem_gnn_apply(sfem_gnn* g, sfem_ctx* ctx, double* ms);
 /* theta and the Lanczos estimates of the extreme eigenvalues of S from the
  * last sfem_gnn_apply (pointers may be NULL). */
 int sfem_get_precond_info(sfem_ctx* ctx, double* theta, double* lambda_min, double* lambda_max);
+/* The kernel that applies M = D^-1/2 (I + theta S) D^-1/2 (Sec. 3.3's
+ * preconditioned solve; the network only fills S): variant 0 walks node rows
+ * of the packed BF16 copy of theta S gathering r_hat = D^-1/2 r from HBM; 1
+ * stages r_hat in LDS per chunk of 128 rows (the window tables of row
+ * schedule 17; unavailable when a chunk gathers more than 1,024 nodes).
+ * The first sfem_gnn_apply on a mesh times both (10 applies each, after
+ * its own timed inference) and keeps the faster.
+ * set: variant 0 or 1 forces one (times it), -1 times both again; errors
+ * SFEM_EINVAL (unknown variant, or 1 unavailable), SFEM_ESTATE (no M).
+ * get: the variant in use and both times in microseconds (0: not timed).
+ * Both give the same z = M r bit for bit; the dot products of the learned
+ * solve are grouped per workgroup differently. */
+int sfem_set_precond_kernel(sfem_ctx* ctx, int variant);
+int sfem_get_precond_kernel(sfem_ctx* ctx, int* variant, double* us_rows, double* us_lds);
 
 /* The learned preconditioner of a context: the correction theta S (float32
  * [nnz], in the order of sfem_get_csr's values; the solver applies these

@@ -158,6 +158,11 @@ struct Ctx {
   DBuf<float> mval;
   DBuf<__bf16> mvalp;            // the same values, BF16, in the packed layout
   DBuf<double> msqrt;
+  // M apply kernel: rows (k_mapply) or rh staged in LDS per chunk of rows
+  // (k_mapply_lds, needs the window tables); chosen by timing both after the
+  // first M of a mesh is built (mapply_us: their times, 0 if not timed)
+  bool mapply_lds = false, mapply_tuned = false;
+  double mapply_us[2] = {0.0, 0.0};
   DBuf<float> msqrt32;
   std::shared_ptr<GnnWork> gnn;  // features, activations and training pairs
 
@@ -233,6 +238,9 @@ void pack_pattern(Ctx& c);
 void pack_values64(Ctx& c);  // packed copy of the FP64 K (once per assembly)
 void ensure_csr64(Ctx& c);   // CSR-order FP64 K from the packed copy, if stale
 bool ensure_lds_tables(Ctx& c);  // window tables of schedule 17; false: unavailable
+// Times both M apply kernels on the current M and keeps the faster (or the
+// one forced: variant 0 rows, 1 LDS-staged; -1 time both).
+void tune_mapply(Ctx& c, int variant = -1);
 void ensure_rowsum(Ctx& c);      // block row sums R of K_bc (once per assembly)
 // diag(K_bc) from whichever copy of K is current
 void matrix_diagonal(Ctx& c, double* diag);

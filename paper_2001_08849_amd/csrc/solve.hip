@@ -669,6 +669,62 @@ __global__ void __launch_bounds__(kLdsThreads)
   store_partials<1>(v, partials);
 }
 
+// The learned M apply of k_mapply with rh staged in LDS per chunk of rows
+// (the window tables of schedule 17; the same row sums in the same order).
+template <typename P>
+__global__ void __launch_bounds__(kLdsThreads)
+    k_mapply_lds(int64_t N, const int32_t* __restrict__ ptr4, const uint16_t* __restrict__ lcol4,
+                 const __bf16* __restrict__ mvalp, const int32_t* __restrict__ wcol,
+                 const int32_t* __restrict__ wcnt, const P* __restrict__ s,
+                 const P* __restrict__ r, const P* __restrict__ rh, P* __restrict__ z,
+                 const CgScalars* __restrict__ sc, double* __restrict__ partials) {
+  if (sc && sc->converged) return;
+  __shared__ double xs[3 * kWindow];
+  constexpr int LPR = 8;
+  constexpr int G = kLdsThreads / LPR;
+  const int tid = threadIdx.x;
+  const int g = tid / LPR, sub = tid % LPR;
+  const int64_t n_chunks = (N + kChunkRows - 1) / kChunkRows;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = gridDim.x / kXcds;  // grid % 8 == 0
+  const int64_t span = (n_chunks + kXcds - 1) / kXcds;
+  const int64_t c_lo = xcd * span;
+  const int64_t c_hi = c_lo + span < n_chunks ? c_lo + span : n_chunks;
+  double v[3] = {0.0, 0.0, 0.0};
+  const double none[3] = {0.0, 0.0, 0.0};
+  for (int64_t ch = c_lo + blockIdx.x / kXcds; ch < c_hi; ch += per_xcd) {
+    const int cnt = wcnt[ch];
+    const int32_t* W = wcol + ch * kWindow;
+    for (int i = tid; i < 3 * cnt; i += kLdsThreads) {
+      const int k = i / 3;
+      xs[i] = double(rh[3 * int64_t(W[k]) + (i - 3 * k)]);
+    }
+    __syncthreads();
+    const int64_t r0 = ch * kChunkRows;
+    for (int rr = 0; rr < kChunkRows; rr += G) {
+      const int64_t I = r0 + rr + g;
+      const bool valid = I < N;
+      const int Ii = valid ? int(I) : 0;
+      double y[3];
+      row3p_lds<__bf16, LPR, false>(Ii, valid, sub, ptr4, lcol4, mvalp, xs, none, y);
+      if (valid && sub == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t i = 3 * int64_t(Ii) + a;
+          const double ri = double(r[i]);
+          const P zi = P(double(s[i]) * (double(rh[i]) + y[a]));
+          v[0] += ri * double(zi);
+          v[1] += ri * ri;
+          v[2] += ri * double(z[i]);
+          z[i] = zi;
+        }
+      }
+    }
+    __syncthreads();  // the window is rewritten by the next chunk
+  }
+  store_partials<3>(v, partials);
+}
+
 // x += alpha p; r -= alpha q; z = dinv r; partials (r.z), (r.r)
 template <typename P>
 __global__ void __launch_bounds__(kVecThreads)
@@ -1115,7 +1171,10 @@ void ensure_rowsum(Ctx& c) {
 
 namespace {
 
+int lds_grid(Ctx& c, const RowSched& rs);
+
 int mapply_parts(Ctx& c) {
+  if (c.mapply_lds) return lds_grid(c, RowSched{17, kRowGridMax});
   const RowSched rs{0, kRowGridMax};
   const int64_t rows_per_block = int64_t(kRowWaves) * (kWave / kMLanes);
   int g = div_up(c.N, rows_per_block);
@@ -1134,9 +1193,15 @@ void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fre
     k_rh<P><<<div_up(n, 256), 256, 0, c.stream>>>(n, (const P*)B.msq, r, (P*)B.rh);
     SFEM_HIP(hipGetLastError());
   }
-  k_mapply<P><<<mapply_parts(c), kRowWaves * kWave, 0, c.stream>>>(
-      c.N, B.mptr4, B.mcol4, B.mval, (const P*)B.msq, r, (const P*)B.rh, z,
-      guarded ? c.sc.get() : nullptr, partials ? partials : c.partials.get());
+  if (c.mapply_lds) {
+    k_mapply_lds<P><<<mapply_parts(c), kLdsThreads, 0, c.stream>>>(
+        c.N, B.mptr4, c.lcol4.get(), B.mval, c.wcol.get(), c.wcnt.get(), (const P*)B.msq, r,
+        (const P*)B.rh, z, guarded ? c.sc.get() : nullptr, partials ? partials : c.partials.get());
+  } else {
+    k_mapply<P><<<mapply_parts(c), kRowWaves * kWave, 0, c.stream>>>(
+        c.N, B.mptr4, B.mcol4, B.mval, (const P*)B.msq, r, (const P*)B.rh, z,
+        guarded ? c.sc.get() : nullptr, partials ? partials : c.partials.get());
+  }
   SFEM_HIP(hipGetLastError());
 }
 
@@ -1221,7 +1286,8 @@ void cg_period(Ctx& c, const CgBuffers& B, int iters, int& parity, bool eager) {
       LY.ptr, LY.col, LY.val, c.sc.get(), c.partials.get(),
       reinterpret_cast<const void*>(intptr_t(c.N)), reinterpret_cast<const void*>(intptr_t(iters)),
       reinterpret_cast<const void*>(intptr_t(rs.variant * 100000 + rs.grid_cap)),
-      reinterpret_cast<const void*>(intptr_t(sizeof(VT) * 16 + sizeof(P)))};
+      reinterpret_cast<const void*>(intptr_t(sizeof(VT) * 16 + sizeof(P))),
+      reinterpret_cast<const void*>(intptr_t(c.mapply_lds))};
   if (!c.cg_exec || c.cg_key != key) {
     c.drop_cg_graph();
     SFEM_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
@@ -1972,6 +2038,41 @@ void learned_apply_into(Ctx& c, const double* r, double* z, double* rh, double* 
   B.msq = c.msqrt.get();
   B.rh = rh;
   mapply<double>(c, B, r, z, false, true, partials);
+}
+
+void tune_mapply(Ctx& c, int variant) {
+  SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");
+  SFEM_REQUIRE(variant >= -1 && variant <= 1, SFEM_EINVAL, "M apply variant must be -1, 0 or 1");
+  const bool lds_ok = ensure_lds_tables(c);
+  SFEM_REQUIRE(variant != 1 || lds_ok, SFEM_EINVAL,
+               "a chunk of rows gathers more than the LDS window holds");
+  ensure_work(c, false);
+  const int64_t n = c.n_dof();
+  CgBuffers B{};
+  B.mval = c.mvalp.get();
+  B.mptr4 = c.ptr4.get();
+  B.mcol4 = c.col4.get();
+  B.msq = c.msqrt.get();
+  B.rh = c.rh.get();
+  k_ones<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.r.get());
+  SFEM_HIP(hipGetLastError());
+  c.mapply_us[0] = c.mapply_us[1] = 0.0;
+  constexpr int kReps = 10;
+  for (int v = 0; v < 2; ++v) {
+    if (v == 1 && !lds_ok) break;
+    if (variant >= 0 && v != variant) continue;
+    c.mapply_lds = v == 1;
+    mapply<double>(c, B, c.r.get(), c.z.get(), false, true);  // warm
+    SFEM_HIP(hipEventRecord(c.ev0, c.stream));
+    for (int k = 0; k < kReps; ++k) mapply<double>(c, B, c.r.get(), c.z.get(), false, false);
+    SFEM_HIP(hipEventRecord(c.ev1, c.stream));
+    SFEM_HIP(hipEventSynchronize(c.ev1));
+    float ms = 0;
+    SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    c.mapply_us[v] = 1e3 * ms / kReps;
+  }
+  c.mapply_lds = variant >= 0 ? variant == 1
+                              : (c.mapply_us[1] > 0.0 && c.mapply_us[1] < c.mapply_us[0]);
 }
 
 void learned_apply(Ctx& c, const double* r, double* z) {

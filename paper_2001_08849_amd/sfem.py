@@ -39,6 +39,7 @@ EXPORTS = [
     "sfem_gnn_get_params", "sfem_gnn_set_params", "sfem_gnn_set_pairs",
     "sfem_gnn_generate_pairs", "sfem_gnn_loss_grad", "sfem_gnn_train", "sfem_gnn_apply",
     "sfem_get_precond", "sfem_precond_apply", "sfem_get_precond_info", "sfem_face_stress",
+    "sfem_set_precond_kernel", "sfem_get_precond_kernel",
     "sfem_batch_create", "sfem_batch_destroy", "sfem_batch_last_error", "sfem_batch_add_mesh",
     "sfem_batch_add_traction", "sfem_batch_build", "sfem_batch_sizes", "sfem_batch_autotune",
     "sfem_batch_get_schedule", "sfem_batch_solve", "sfem_batch_get_solution",
@@ -141,6 +142,9 @@ def lib() -> C.CDLL:
             "sfem_precond_apply": (i32, [vp, vp, vp, i32]),
             "sfem_precond_apply_noalloc": (i32, [vp, vp, vp]),
             "sfem_get_precond_info": (i32, [vp] + [C.POINTER(dbl)] * 3),
+            "sfem_set_precond_kernel": (i32, [vp, i32]),
+            "sfem_get_precond_kernel": (i32, [vp, C.POINTER(i32), C.POINTER(dbl),
+                                              C.POINTER(dbl)]),
             "sfem_face_stress": (i32, [vp, vp, vp, vp, i32, C.POINTER(dbl)]),
             "sfem_batch_create": (i32, [C.POINTER(vp), i32]),
             "sfem_batch_destroy": (None, [vp]),
@@ -455,6 +459,16 @@ class Context:
         t, a, b = C.c_double(), C.c_double(), C.c_double()
         self._check(self._L.sfem_get_precond_info(self._h, C.byref(t), C.byref(a), C.byref(b)))
         return {"theta": t.value, "lambda_min": a.value, "lambda_max": b.value}
+
+    def set_precond_kernel(self, variant: int):
+        """M apply kernel: 0 rows, 1 rh staged in LDS, -1 time both and keep the faster."""
+        self._check(self._L.sfem_set_precond_kernel(self._h, int(variant)))
+
+    def precond_kernel(self):
+        """{'variant', 'us_rows', 'us_lds'}: the M apply kernel in use and both timings."""
+        v, a, b = C.c_int(), C.c_double(), C.c_double()
+        self._check(self._L.sfem_get_precond_kernel(self._h, C.byref(v), C.byref(a), C.byref(b)))
+        return {"variant": v.value, "us_rows": a.value, "us_lds": b.value}
 
     def precond_apply(self, r):
         z = np.empty(self.sizes().n_rows, dtype=np.float64)

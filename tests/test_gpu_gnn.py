@@ -389,3 +389,37 @@ def test_weights_file_round_trip(S, small, tmp_path):
         assert np.array_equal(b.params().view(np.uint32), keep.view(np.uint32)), name
     with pytest.raises(S.SfemError, match="EINVAL"):
         b.load(tmp_path / "missing.sfgn")
+
+
+def test_lds_staged_m_apply(S):
+    """The M apply with r_hat staged in LDS per chunk of rows gives z = M r
+    bit for bit as the row kernel; learned solves under either reach the
+    oracle's u; sfem_gnn_apply timed both."""
+    p = mg.learned_small(2, grid=(40, 6, 6))
+    ctx = S.Context(0)
+    S.setup_problem(ctx, p)
+    Kb, fb = ref_system(p)
+    ub = O.solve_banded(Kb, fb)
+    flat, _ = fp32_params(S, random_params(3, 0.3))
+    net = S.Gnn(0, seed=1)
+    net.set_params(flat)
+    net.apply(ctx)
+    info = ctx.precond_kernel()
+    assert info["variant"] in (0, 1) and info["us_rows"] > 0 and info["us_lds"] > 0
+    r = np.random.default_rng(4).standard_normal(Kb.shape[0])
+    out = {}
+    for v in (0, 1):
+        ctx.set_precond_kernel(v)
+        assert ctx.precond_kernel()["variant"] == v
+        z = ctx.precond_apply(r)
+        u, i = ctx.solve(rtol=1e-10, precond=S.PRECOND_LEARNED)
+        err = np.linalg.norm(u - ub) / np.linalg.norm(ub)
+        out[v] = (z, i["iters"], err)
+        assert i["converged"] and not i["fell_back"] and err <= 1e-8
+    print(f"M apply: rows {info['us_rows']:.1f} us, LDS-staged {info['us_lds']:.1f} us "
+          f"(picked {info['variant']}); learned solve iterations {out[0][1]} / {out[1][1]}, "
+          f"u error vs banded {out[0][2]:.1e} / {out[1][2]:.1e}")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert abs(out[0][1] - out[1][1]) <= 0.05 * out[0][1] + 5
+    with pytest.raises(S.SfemError, match="EINVAL"):
+        ctx.set_precond_kernel(2)

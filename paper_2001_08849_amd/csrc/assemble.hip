@@ -47,43 +47,39 @@ __device__ __forceinline__ int face_geometry(const int32_t* __restrict__ row,
   // the second tet's far node, gathered with the others (a valid node id on
   // exterior faces too, where it is not used)
   const Vec3 E = load3(xyz, interior ? r1.x : r0.w);
-  Vec3 g1[4];
-  double V1;
-  tet_grads(A, B, C, D, g1, V1);
-  if (!interior) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b[i] = g1[i];
-    b[4] = {0, 0, 0};
-    Vk = 0.25 * V1;
-    if (HET) {
-      lam = lam_t[r1.y];
-      mu = mu_t[r1.y];
-    } else {
-      lam = lam0;
-      mu = mu0;
-    }
-    return 4;
-  }
-  Vec3 g2[4];
-  double V2;
-  tet_grads(A, B, C, E, g2, V2);
-  const double W = V1 + V2;
-  const double iW = 1.0 / W;
-  const double w1 = V1 * iW, w2 = V2 * iW;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-    b[i] = {w1 * g1[i].x + w2 * g2[i].x, w1 * g1[i].y + w2 * g2[i].y, w1 * g1[i].z + w2 * g2[i].z};
-  b[3] = {w1 * g1[3].x, w1 * g1[3].y, w1 * g1[3].z};
-  b[4] = {w2 * g2[3].x, w2 * g2[3].y, w2 * g2[3].z};
-  Vk = 0.25 * W;
+  // The two tets share the face (A, B, C): with e1 = B - A, e2 = C - A,
+  // n = e1 x e2 and the far-node offsets f_t = D - A, E - A, tet t's
+  // gradients are (e2 x f_t, f_t x e1, n) / det_t for B, C and its far node,
+  // det_t = f_t . n, and its volume |det_t| / 6.  The weights V_t / (V_1 +
+  // V_2) then give, with k_t = sgn(det_t) / (|det_1| + |det_2|) and
+  // g = k_1 f_1 + k_2 f_2:  b_B = e2 x g,  b_C = g x e1,  b_D = k_1 n,
+  // b_E = k_2 n,  b_A = -(b_B + b_C + b_D + b_E)  (each tet's gradients sum
+  // to zero): one division per face.  An exterior face takes the same path
+  // with k_2 = 0, so a wave mixing both kinds runs it once.
+  const Vec3 e1 = sub(B, A), e2 = sub(C, A);
+  const Vec3 n = cross(e1, e2);
+  const Vec3 f1 = sub(D, A), f2 = sub(E, A);
+  const double d1 = dot(f1, n), d2 = dot(f2, n);
+  const double a1 = fabs(d1), a2 = interior ? fabs(d2) : 0.0;
+  const double inv = 1.0 / (a1 + a2);
+  const double k1 = copysign(inv, d1), k2 = interior ? copysign(inv, d2) : 0.0;
+  const Vec3 g = {k1 * f1.x + k2 * f2.x, k1 * f1.y + k2 * f2.y, k1 * f1.z + k2 * f2.z};
+  b[1] = cross(e2, g);
+  b[2] = cross(g, e1);
+  b[3] = {k1 * n.x, k1 * n.y, k1 * n.z};
+  b[4] = {k2 * n.x, k2 * n.y, k2 * n.z};
+  b[0] = {-(b[1].x + b[2].x + b[3].x + b[4].x), -(b[1].y + b[2].y + b[3].y + b[4].y),
+          -(b[1].z + b[2].z + b[3].z + b[4].z)};
+  Vk = (a1 + a2) * (1.0 / 24.0);
   if (HET) {
-    lam = w1 * lam_t[r1.y] + w2 * lam_t[r1.z];
-    mu = w1 * mu_t[r1.y] + w2 * mu_t[r1.z];
+    const double w1 = a1 * inv, w2 = a2 * inv;
+    lam = w1 * lam_t[r1.y] + w2 * lam_t[interior ? r1.z : r1.y];
+    mu = w1 * mu_t[r1.y] + w2 * mu_t[interior ? r1.z : r1.y];
   } else {
     lam = lam0;
     mu = mu0;
   }
-  return 5;
+  return interior ? 5 : 4;
 }
 
 // The same smoothing domain with FP32 arithmetic after the tet volumes and

@@ -8,9 +8,11 @@
 // Two value layouts: the CSR order of the scalar matrix (row schedules 0-13:
 // one or two rows per step, an unrolled column loop, nontemporal value
 // loads), and a packed copy in which node row I is a [9][deg rounded up to
-// 4] array read four blocks per lane with 16-byte loads (schedules 14-16).
-// The autotuner times every schedule inside PCG iterations and keeps the
-// fastest.  Grids are XCD-banded (for_rows).  The translation form
+// 4] array read four blocks per lane with 16-byte loads (schedules 14-16;
+// schedule 17 also stages the x entries a chunk of 128 rows gathers in
+// LDS).  The autotuner times every schedule inside PCG iterations and keeps
+// the fastest.  The learned M's apply has the same two forms (k_mapply,
+// k_mapply_lds), the faster kept per mesh.  Grids are XCD-banded (for_rows).  The translation form
 // (row3p's DIFF) multiplies neighbour differences x_J - x_I and adds
 // R_I x_I, the FP64 block row sum: the true residual of every solve and the
 // products of SFEM_MODE_F32_TF use it.

@@ -276,7 +276,8 @@ int sfem_face_stress(sfem_ctx* ctx, const double* u, double* strain, double* str
  * most recent numeric assembly (HIP events on the context stream). */
 int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
 
-/* Row-kernel schedules (SpMV, residual, CG product and learned-M kernels):
+/* Row-kernel schedules (SpMV, residual and CG product kernels; the learned
+ * M's apply has its own two kernels, see sfem_set_precond_kernel):
  * `variant` in [0, SFEM_NUM_SCHEDULES) picks lanes per node row and a loop
  * shape:
  *   0-3   8/16/32/64 lanes, one row per lane group and step;
@@ -295,9 +296,9 @@ int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
  *         sfem_set_schedule, skipped by the autotuner) when a chunk's
  *         window exceeds 1,024 nodes, e.g. under an arbitrary numbering.
  * `grid_cap` caps the workgroups launched.  precision: SFEM_ASM_F64 or
- * SFEM_ASM_F32_COPY (the schedule of FP32 matrices, also used by the learned
- * M).  All schedules compute the same products up to floating-point
- * summation order. */
+ * SFEM_ASM_F32_COPY (the schedule of the FP32 products of the
+ * SFEM_MODE_F32_* solves).  All schedules compute the same products up to
+ * floating-point summation order. */
 enum { SFEM_NUM_SCHEDULES = 18 };
 int sfem_set_schedule(sfem_ctx* ctx, int precision, int variant, int grid_cap);
 int sfem_get_schedule(sfem_ctx* ctx, int precision, int* variant, int* grid_cap);

@@ -105,14 +105,21 @@ struct Rows64 {  // a plain [rows][64] array
 };
 
 // Row-major BF16 tile: dst[r * ld + k] = L(r0 + r, k), zero past `rows`.
+// Each row is split over TPR consecutive threads, each taking a contiguous
+// run of the row (one row's gather indices per thread).
 template <int KD, class Ld>
 __device__ __forceinline__ void stage_rows(__bf16* dst, int ld, const Ld& L, int64_t r0,
                                            int64_t rows) {
   constexpr int Q = KD / 4;
-  for (int i = threadIdx.x; i < kTile * Q; i += kGemmThreads) {
-    const int r = i / Q, k = 4 * (i % Q);
-    const float4 v = (r0 + r < rows) ? L.get4(r0 + r, k) : make_float4(0.f, 0.f, 0.f, 0.f);
-    *reinterpret_cast<bf16x4*>(dst + r * ld + k) =
+  constexpr int TPR = kGemmThreads / kTile;
+  constexpr int PER = Q / TPR;
+  static_assert(kGemmThreads % kTile == 0 && Q % TPR == 0, "tile inputs must split evenly");
+  const int r = threadIdx.x / TPR, k0 = 4 * PER * (threadIdx.x % TPR);
+  const int64_t row = r0 + r;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const float4 v = row < rows ? L.get4(row, k0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    *reinterpret_cast<bf16x4*>(dst + r * ld + k0 + 4 * j) =
         bf16x4{__bf16(v.x), __bf16(v.y), __bf16(v.z), __bf16(v.w)};
   }
 }
@@ -133,11 +140,23 @@ __device__ __forceinline__ void stage_cols(__bf16* dst, int ld, const Ld& L, int
 }
 
 // ------------------------------------------------------------------ GEMMs
-// Y = X W^T, W: [64][KD] BF16 (row o = output feature).  epi(row, o, y).
+// Y = X W^T, W: [64][KD] BF16 (row o = output feature).
+// epi.pre(row, o): the output's residual input, loaded before the MFMA;
+// epi(row, o, y, pre).
+// Software-pipelined over the workgroup's row tiles: the next tile's rows are
+// loaded into registers (and this tile's residual inputs, issued first so
+// that waiting for them does not wait for the prefetch) while this tile's
+// MFMA runs; the registers go to LDS after the tile is done.
 template <int KD, class Ld, class Epi>
 __global__ void __launch_bounds__(kGemmThreads)
     k_gemm_xwT(int64_t rows, Ld L, const __bf16* __restrict__ W, Epi epi) {
   constexpr int LD = KD + 8;  // padded LDS row (bank spread), 16-byte multiple
+  constexpr int Q = KD / 4;
+  // each row's inputs are split over TPR consecutive threads, PER float4
+  // each, contiguous (a thread gathers from one row: one set of indices)
+  constexpr int TPR = kGemmThreads / kTile;
+  constexpr int PER = Q / TPR;
+  static_assert(kGemmThreads % kTile == 0 && Q % TPR == 0, "tile inputs must split evenly");
   __shared__ __align__(16) __bf16 sW[kH * LD];
   __shared__ __align__(16) __bf16 sX[kTile * LD];
   for (int i = threadIdx.x; i < kH * KD / 8; i += kGemmThreads) {
@@ -145,16 +164,43 @@ __global__ void __launch_bounds__(kGemmThreads)
     *reinterpret_cast<bf16x8*>(sW + o * LD + k) = *reinterpret_cast<const bf16x8*>(W + o * KD + k);
   }
   const int64_t ntiles = (rows + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  float4 pf[PER];
+  const int fr = threadIdx.x / TPR, fk = 4 * PER * (threadIdx.x % TPR);
+  auto fetch = [&](int64_t t) {
+    const int64_t row = t * kTile + fr;
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      pf[j] = row < rows ? L.get4(row, fk + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t tile = blockIdx.x;
+  if (tile < ntiles) fetch(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * kTile;
+    __syncthreads();  // the previous tile's MFMA reads of sX are done
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      *reinterpret_cast<bf16x4*>(sX + fr * LD + fk + 4 * j) =
+          bf16x4{__bf16(pf[j].x), __bf16(pf[j].y), __bf16(pf[j].z), __bf16(pf[j].w)};
     __syncthreads();
-    stage_rows<KD>(sX, LD, L, r0, rows);
-    __syncthreads();
+    float res[16];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + 4 * (l >> 4) + v, o = 16 * jt + (l & 15);
+        res[4 * jt + v] = r0 + r < rows ? epi.pre(r0 + r, o) : 0.f;
+      }
+    if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
     f32x4 acc[4] = {};
     mfma_tile<KD>(sX, LD, sW, LD, acc);
-    tile_out(acc, [&](int r, int o, float v) {
-      if (r0 + r < rows) epi(r0 + r, o, v);
-    });
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + 4 * (l >> 4) + v, o = 16 * jt + (l & 15);
+        if (r0 + r < rows) epi(r0 + r, o, acc[jt][v], res[4 * jt + v]);
+      }
   }
 }
 
@@ -455,10 +501,11 @@ struct EdgeFwdEpi {
   const float* __restrict__ e_in;
   float* __restrict__ z;
   float* __restrict__ e_out;
-  __device__ __forceinline__ void operator()(int64_t b, int o, float v) const {
+  __device__ __forceinline__ float pre(int64_t b, int o) const { return e_in[b * kH + o]; }
+  __device__ __forceinline__ void operator()(int64_t b, int o, float v, float ein) const {
     const float zz = v + bias[o];
     z[b * kH + o] = zz;
-    e_out[b * kH + o] = e_in[b * kH + o] + relu(zz);
+    e_out[b * kH + o] = ein + relu(zz);
   }
 };
 
@@ -468,10 +515,11 @@ struct NodeFwdEpi {
   const float* __restrict__ h_in;
   float* __restrict__ t;
   float* __restrict__ h_out;
-  __device__ __forceinline__ void operator()(int64_t I, int o, float v) const {
+  __device__ __forceinline__ float pre(int64_t I, int o) const { return h_in[I * kH + o]; }
+  __device__ __forceinline__ void operator()(int64_t I, int o, float v, float hin) const {
     const float tt = v + bias[o];
     t[I * kH + o] = tt;
-    h_out[I * kH + o] = h_in[I * kH + o] + relu(tt);
+    h_out[I * kH + o] = hin + relu(tt);
   }
 };
 

@@ -104,40 +104,61 @@ struct Rows64 {  // a plain [rows][64] array
   }
 };
 
-// Row-major BF16 tile: dst[r * ld + k] = L(r0 + r, k), zero past `rows`.
-// Each row is split over TPR consecutive threads, each taking a contiguous
-// run of the row (one row's gather indices per thread).
+// Row-major BF16 tile staging, split in two for software pipelining:
+// fetch() loads the inputs L(r0 + r, k) of a tile into registers (zero past
+// `rows`), store() writes them to LDS at dst[r * ld + k].  Each row is split
+// over TPR consecutive threads, each taking a contiguous run of the row (one
+// row's gather indices per thread).
 template <int KD, class Ld>
-__device__ __forceinline__ void stage_rows(__bf16* dst, int ld, const Ld& L, int64_t r0,
-                                           int64_t rows) {
-  constexpr int Q = KD / 4;
-  constexpr int TPR = kGemmThreads / kTile;
-  constexpr int PER = Q / TPR;
-  static_assert(kGemmThreads % kTile == 0 && Q % TPR == 0, "tile inputs must split evenly");
-  const int r = threadIdx.x / TPR, k0 = 4 * PER * (threadIdx.x % TPR);
-  const int64_t row = r0 + r;
+struct RowsPrefetch {
+  static constexpr int Q = KD / 4;
+  static constexpr int TPR = kGemmThreads / kTile;
+  static constexpr int PER = Q / TPR;
+  float4 v[PER];
+  __device__ __forceinline__ void fetch(const Ld& L, int64_t r0, int64_t rows) {
+    const int r = threadIdx.x / TPR, k0 = 4 * PER * (threadIdx.x % TPR);
+    const int64_t row = r0 + r;
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const float4 v = row < rows ? L.get4(row, k0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
-    *reinterpret_cast<bf16x4*>(dst + r * ld + k0 + 4 * j) =
-        bf16x4{__bf16(v.x), __bf16(v.y), __bf16(v.z), __bf16(v.w)};
+    for (int j = 0; j < PER; ++j)
+      v[j] = row < rows ? L.get4(row, k0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
   }
-}
+  __device__ __forceinline__ void store(__bf16* dst, int ld) const {
+    const int r = threadIdx.x / TPR, k0 = 4 * PER * (threadIdx.x % TPR);
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      *reinterpret_cast<bf16x4*>(dst + r * ld + k0 + 4 * j) =
+          bf16x4{__bf16(v[j].x), __bf16(v[j].y), __bf16(v[j].z), __bf16(v[j].w)};
+  }
+};
 
-// Transposed BF16 tile: dst[k * ld + r] = L(r0 + r, k) (consecutive lanes
-// take consecutive rows, so the 2-byte LDS writes do not collide).
+// Transposed BF16 tile staging, split the same way: dst[k * ld + r] =
+// L(r0 + r, k) (consecutive lanes take consecutive rows, so the 2-byte LDS
+// writes do not collide).
 template <int KD, class Ld>
-__device__ __forceinline__ void stage_cols(__bf16* dst, int ld, const Ld& L, int64_t r0,
-                                           int64_t rows) {
-  for (int i = threadIdx.x; i < kTile * (KD / 4); i += kGemmThreads) {
-    const int r = i % kTile, k = 4 * (i / kTile);
-    const float4 v = (r0 + r < rows) ? L.get4(r0 + r, k) : make_float4(0.f, 0.f, 0.f, 0.f);
-    dst[(k + 0) * ld + r] = __bf16(v.x);
-    dst[(k + 1) * ld + r] = __bf16(v.y);
-    dst[(k + 2) * ld + r] = __bf16(v.z);
-    dst[(k + 3) * ld + r] = __bf16(v.w);
+struct ColsPrefetch {
+  static constexpr int PER = kTile * (KD / 4) / kGemmThreads;
+  static_assert(kTile * (KD / 4) % kGemmThreads == 0, "tile inputs must split evenly");
+  float4 v[PER];
+  __device__ __forceinline__ void fetch(const Ld& L, int64_t r0, int64_t rows) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = threadIdx.x + j * kGemmThreads;
+      const int r = i % kTile, k = 4 * (i / kTile);
+      v[j] = (r0 + r < rows) ? L.get4(r0 + r, k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
-}
+  __device__ __forceinline__ void store(__bf16* dst, int ld) const {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = threadIdx.x + j * kGemmThreads;
+      const int r = i % kTile, k = 4 * (i / kTile);
+      dst[(k + 0) * ld + r] = __bf16(v[j].x);
+      dst[(k + 1) * ld + r] = __bf16(v[j].y);
+      dst[(k + 2) * ld + r] = __bf16(v[j].z);
+      dst[(k + 3) * ld + r] = __bf16(v[j].w);
+    }
+  }
+};
 
 // ------------------------------------------------------------------ GEMMs
 // Y = X W^T, W: [64][KD] BF16 (row o = output feature).
@@ -151,12 +172,6 @@ template <int KD, class Ld, class Epi>
 __global__ void __launch_bounds__(kGemmThreads)
     k_gemm_xwT(int64_t rows, Ld L, const __bf16* __restrict__ W, Epi epi) {
   constexpr int LD = KD + 8;  // padded LDS row (bank spread), 16-byte multiple
-  constexpr int Q = KD / 4;
-  // each row's inputs are split over TPR consecutive threads, PER float4
-  // each, contiguous (a thread gathers from one row: one set of indices)
-  constexpr int TPR = kGemmThreads / kTile;
-  constexpr int PER = Q / TPR;
-  static_assert(kGemmThreads % kTile == 0 && Q % TPR == 0, "tile inputs must split evenly");
   __shared__ __align__(16) __bf16 sW[kH * LD];
   __shared__ __align__(16) __bf16 sX[kTile * LD];
   for (int i = threadIdx.x; i < kH * KD / 8; i += kGemmThreads) {
@@ -164,24 +179,14 @@ __global__ void __launch_bounds__(kGemmThreads)
     *reinterpret_cast<bf16x8*>(sW + o * LD + k) = *reinterpret_cast<const bf16x8*>(W + o * KD + k);
   }
   const int64_t ntiles = (rows + kTile - 1) / kTile;
-  float4 pf[PER];
-  const int fr = threadIdx.x / TPR, fk = 4 * PER * (threadIdx.x % TPR);
-  auto fetch = [&](int64_t t) {
-    const int64_t row = t * kTile + fr;
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-      pf[j] = row < rows ? L.get4(row, fk + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
-  };
+  RowsPrefetch<KD, Ld> pf;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) fetch(tile);
+  if (tile < ntiles) pf.fetch(L, tile * kTile, rows);
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * kTile;
     __syncthreads();  // the previous tile's MFMA reads of sX are done
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-      *reinterpret_cast<bf16x4*>(sX + fr * LD + fk + 4 * j) =
-          bf16x4{__bf16(pf[j].x), __bf16(pf[j].y), __bf16(pf[j].z), __bf16(pf[j].w)};
+    pf.store(sX, LD);
     __syncthreads();
     float res[16];
 #pragma unroll
@@ -191,7 +196,7 @@ __global__ void __launch_bounds__(kGemmThreads)
         const int r = 16 * w + 4 * (l >> 4) + v, o = 16 * jt + (l & 15);
         res[4 * jt + v] = r0 + r < rows ? epi.pre(r0 + r, o) : 0.f;
       }
-    if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
+    if (tile + gridDim.x < ntiles) pf.fetch(L, (tile + gridDim.x) * kTile, rows);
     f32x4 acc[4] = {};
     mfma_tile<KD>(sX, LD, sW, LD, acc);
 #pragma unroll
@@ -216,11 +221,15 @@ __global__ void __launch_bounds__(kGemmThreads)
     sWt[j * LD + k] = W[i];
   }
   const int64_t ntiles = (rows + kTile - 1) / kTile;
+  // the next tile's rows load into registers during this tile's MFMA
+  RowsPrefetch<kH, Ld> pf;
+  if (int64_t(blockIdx.x) < ntiles) pf.fetch(L, int64_t(blockIdx.x) * kTile, rows);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * kTile;
     __syncthreads();
-    stage_rows<kH>(sA, LD, L, r0, rows);
+    pf.store(sA, LD);
     __syncthreads();
+    if (tile + gridDim.x < ntiles) pf.fetch(L, (tile + gridDim.x) * kTile, rows);
 #pragma unroll
     for (int jc = 0; jc < KO / 64; ++jc) {
       f32x4 acc[4] = {};
@@ -246,12 +255,22 @@ __global__ void __launch_bounds__(kGemmThreads)
 #pragma unroll
     for (int jt = 0; jt < 4; ++jt) acc[jc][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t ntiles = (rows + kTile - 1) / kTile;
+  // the next tile's columns load into registers during this tile's MFMA
+  ColsPrefetch<kH, LG> pg;
+  ColsPrefetch<KD, LX> px;
+  if (int64_t(blockIdx.x) < ntiles) {
+    pg.fetch(G, int64_t(blockIdx.x) * kTile, rows);
+    px.fetch(X, int64_t(blockIdx.x) * kTile, rows);
+  }
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * kTile;
     __syncthreads();
-    stage_cols<kH>(sGt, LD, G, r0, rows);
-    stage_cols<KD>(sXt, LD, X, r0, rows);
+    pg.store(sGt, LD);
+    px.store(sXt, LD);
     __syncthreads();
+    if (tile + gridDim.x < ntiles) {
+      pg.fetch(G, (tile + gridDim.x) * kTile, rows);
+      px.fetch(X, (tile + gridDim.x) * kTile, rows);
+    }
 #pragma unroll
     for (int jc = 0; jc < KD / 64; ++jc) mfma_tile<kTile>(sGt, LD, sXt + jc * 64 * LD, LD, acc[jc]);
   }

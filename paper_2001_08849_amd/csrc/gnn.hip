@@ -501,17 +501,42 @@ __global__ void k_edge_features(int64_t nb, const int32_t* __restrict__ erow,
 // ------------------------------------------------------------------ forward
 // out[r][o] = relu(sum_i W[o][i] in[r][i] + b[o]), fan-in F (FP32: the
 // encoders are too narrow for the matrix cores).
+// Workgroups of the encoders: 16 rows each, up to 8,192.
+inline int enc_grid(int64_t rows) {
+  return int(std::max<int64_t>(1, std::min<int64_t>(div_up(rows, 16), 8192)));
+}
+
+// A thread computes four consecutive outputs of a row (one 16-byte store),
+// its weights held in registers across a grid-stride loop over rows.
 template <int F>
-__global__ void k_encode(int64_t rows, const float* __restrict__ in, const float* __restrict__ W,
-                         const float* __restrict__ b, float* __restrict__ out) {
-  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= rows * kH) return;
-  const int64_t r = t / kH;
-  const int o = int(t % kH);
-  float acc = b[o];
+__global__ void __launch_bounds__(256)
+    k_encode(int64_t rows, const float* __restrict__ in, const float* __restrict__ W,
+             const float* __restrict__ b, float* __restrict__ out) {
+  constexpr int kQ = kH / 4;  // threads per row
+  const int o0 = 4 * (threadIdx.x % kQ);
+  float w[4][F], bias[4];
 #pragma unroll
-  for (int i = 0; i < F; ++i) acc += W[o * F + i] * in[r * F + i];
-  out[t] = relu(acc);
+  for (int c = 0; c < 4; ++c) {
+    bias[c] = b[o0 + c];
+#pragma unroll
+    for (int i = 0; i < F; ++i) w[c][i] = W[(o0 + c) * F + i];
+  }
+  const int64_t stride = int64_t(gridDim.x) * (blockDim.x / kQ);
+  for (int64_t r = int64_t(blockIdx.x) * (blockDim.x / kQ) + threadIdx.x / kQ; r < rows;
+       r += stride) {
+    float x[F];
+#pragma unroll
+    for (int i = 0; i < F; ++i) x[i] = in[r * F + i];
+    float acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      acc[c] = bias[c];
+#pragma unroll
+      for (int i = 0; i < F; ++i) acc[c] += w[c][i] * x[i];
+    }
+    *reinterpret_cast<float4*>(out + r * kH + o0) =
+        make_float4(relu(acc[0]), relu(acc[1]), relu(acc[2]), relu(acc[3]));
+  }
 }
 
 // Edge layer epilogue: z = y + b;  e_out = e_in + relu(z).
@@ -553,16 +578,32 @@ __global__ void k_aggregate(int64_t N, const int32_t* __restrict__ bptr,
   a[I * kH + lane] = acc / float(bptr[I + 1] - bptr[I]);
 }
 
-// R_IJ = Wo e_IJ (3x3 row-major per edge).
-__global__ void k_decode(int64_t nb, const float* __restrict__ e, const float* __restrict__ Wo,
-                         float* __restrict__ R) {
-  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nb * 9) return;
-  const int64_t b = t / 9;
-  const int q = int(t % 9);
-  float acc = 0.f;
-  for (int i = 0; i < kH; ++i) acc += Wo[q * kH + i] * e[b * kH + i];
-  R[t] = acc;
+// R_IJ = Wo e_IJ (3x3 row-major per edge): a thread per edge, its row of e
+// read once with 16-byte loads, Wo from LDS.
+__global__ void __launch_bounds__(256)
+    k_decode(int64_t nb, const float* __restrict__ e, const float* __restrict__ Wo,
+             float* __restrict__ R) {
+  __shared__ float sWo[9 * kH];
+  for (int i = threadIdx.x; i < 9 * kH; i += blockDim.x) sWo[i] = Wo[i];
+  __syncthreads();
+  for (int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < nb;
+       b += int64_t(gridDim.x) * blockDim.x) {
+    float acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    const float4* row = reinterpret_cast<const float4*>(e + b * kH);
+#pragma unroll 4
+    for (int i4 = 0; i4 < kH / 4; ++i4) {
+      const float4 v = row[i4];
+      const float ev[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[q] += sWo[q * kH + 4 * i4 + u] * ev[u];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R[b * 9 + q] = acc[q];
+  }
 }
 
 // S'_IJ = (R_IJ + R_JI^T) / 2, zero on fixed DOFs, into the scalar-CSR layout.
@@ -1024,9 +1065,9 @@ void gnn_forward(Ctx& c, Gnn& g, bool keep) {
   const float* P = g.params.get();
   k_to_bf16<<<div_up(L.total, 256), 256, 0, s>>>(L.total, P, g.params_bf16.get());
   const __bf16* Pb = g.params_bf16.get();
-  k_encode<kFNode><<<div_up(N * kH, 256), 256, 0, s>>>(N, w.x.get(), P + L.Wn, P + L.bn,
+  k_encode<kFNode><<<enc_grid(N), 256, 0, s>>>(N, w.x.get(), P + L.Wn, P + L.bn,
                                                        w.h.get());
-  k_encode<kFEdge><<<div_up(nb * kH, 256), 256, 0, s>>>(nb, w.y.get(), P + L.We, P + L.be,
+  k_encode<kFEdge><<<enc_grid(nb), 256, 0, s>>>(nb, w.y.get(), P + L.We, P + L.be,
                                                         w.e.get());
   SFEM_HIP(hipGetLastError());
   const int ge = tile_grid(nb, kGemmGrid), gn = tile_grid(N, kGemmGrid);
@@ -1049,7 +1090,8 @@ void gnn_forward(Ctx& c, Gnn& g, bool keep) {
     SFEM_HIP(hipGetLastError());
   }
   const int sl = keep ? kLayers : (kLayers & 1);
-  k_decode<<<div_up(nb * 9, 256), 256, 0, s>>>(nb, w.e.get() + sl * nb * kH, P + L.Wo,
+  k_decode<<<int(std::max<int64_t>(1, std::min<int64_t>(div_up(nb, 256), 8192))), 256, 0, s>>>(
+      nb, w.e.get() + sl * nb * kH, P + L.Wo,
                                                w.dS.get());
   k_symmetrize<<<div_up(nb * 9, 256), 256, 0, s>>>(
       nb, w.erow.get(), tp.bptr.get(), tp.bcol.get(), w.etr.get(),

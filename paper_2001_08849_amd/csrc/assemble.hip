@@ -25,7 +25,7 @@ namespace sfem {
 
 namespace {
 
-constexpr int kAsmThreads = 512;
+constexpr int kAsmThreads = 256;
 
 // Smoothed gradients b[0..n-1] of the face's support nodes (A, B, C, D[, E]),
 // V_k, and the domain's Lame constants.

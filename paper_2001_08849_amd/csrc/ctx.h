@@ -8,7 +8,7 @@ namespace sfem {
 
 // Numeric-assembly tile: a run of consecutive node rows whose 3x3 blocks
 // (and their FP64 values) fit in LDS.  kTileBlocks is the block capacity.
-constexpr int kTileBlocks = 640;
+constexpr int kTileBlocks = 320;
 // Largest node degree (3x3 blocks in a row) the slot map can encode.
 constexpr int kMaxDeg = 64;
 

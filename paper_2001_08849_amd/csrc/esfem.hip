@@ -26,7 +26,7 @@ namespace sfem {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kAsmThreads = 512;
+constexpr int kAsmThreads = 256;
 constexpr uint8_t kNoSlot = 0xff;
 
 __global__ void k_fill(int64_t n, int32_t* __restrict__ a, int32_t v) {

@@ -69,7 +69,7 @@ def mapply_bytes(N, nnz, nb):
 
 KERNEL_SOURCES = {
     "cg_spmv_f64_c2": ("k_cg_spmv<double, double, 8, 8>", "paper_2001_08849_amd/csrc/solve.hip"),
-    "cg_spmv_f32_tf_c2": ("k_cg_spmv<float, double, 8, 24>",
+    "cg_spmv_f32_tf_c2": ("k_cg_spmv<float, double, 8, 72>",
                           "paper_2001_08849_amd/csrc/solve.hip"),
     "cg_spmv_lds_f64_c2": ("k_cg_spmv_lds<double, double, 8, false>",
                            "paper_2001_08849_amd/csrc/solve.hip"),
@@ -959,11 +959,11 @@ def main():
             _, _, sb32 = algorithmic_bytes(m.n_nodes, m.n_tets, s.n_faces, s.nnz, s.n_blocks)
             n = 3 * m.n_nodes
             # the kernel's own bytes: FP32 values (packed, padding included),
-            # packed block columns, row offsets, R, x read and q written in FP64
+            # packed block columns, row offsets, C, x read and q written in FP64
             own = 4 * s.nnz + 4 * s.n_blocks + 4 * (m.n_nodes + 1) + 72 * m.n_nodes + 16 * n
             ach = sb32 / (pus * 1e-6) / 1e9
             out["roofline_f32_tf"] = {
-                "kernel": "k_cg_spmv<float, double, 8, 24>", "bound": "hbm", "achieved": ach,
+                "kernel": "k_cg_spmv<float, double, 8, 72>", "bound": "hbm", "achieved": ach,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": read_traffic("cg_spmv_f32_tf_c2"), "bytes_per_launch": sb32,
                 "bytes_note": "scalar CSR FP32 SpMV count: 8 nnz + 4 (n+1) + 8 n",

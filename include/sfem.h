@@ -211,9 +211,12 @@ int sfem_spmv(sfem_ctx* ctx, const double* x, double* y, int ptr_kind);
  *                      of the values only meets neighbour differences of p
  *                      and perturbs the smooth, slowly converging modes far
  *                      less than a plain FP32 product; the recurrence runs
- *                      to rtol without a restart.  With f32_from the first
- *                      part of the solve uses FP64 products.  Needs
- *                      SFEM_ASM_F32_COPY.
+ *                      to rtol without a restart.  The kernels compute the
+ *                      same value as sum_J K32_IJ p_J + C_I p_I with C_I =
+ *                      sum_J (K_IJ - K32_IJ) (FP64, made once per
+ *                      assembly), so the rows are plain FP32 products.
+ *                      With f32_from the first part of the solve uses FP64
+ *                      products.  Needs SFEM_ASM_F32_COPY.
  *   SFEM_MODE_F32_RR : PCG with FP64 vectors and dots and FP32-matrix
  *                      products, the residual replaced every check_every
  *                      iterations by the FP64 residual f - K u, until the

@@ -375,7 +375,7 @@ int sfem_assemble(sfem_ctx* h, int flags) {
     c.have_learned = false;
     c.gnn.reset();
     c.packed64 = c.packed32 = false;
-    c.have_rsum = false;
+    c.have_rsum = c.have_rcorr = false;
     const int64_t nnz = 9 * c.topo.nb;
     c.val.reserve(nnz);
     SFEM_REQUIRE((flags & ~(SFEM_ASM_F32_COPY | SFEM_ASM_F32_ARITH)) == 0, SFEM_EINVAL,

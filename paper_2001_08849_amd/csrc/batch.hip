@@ -98,11 +98,14 @@ struct Work {
 //   EPI 1: residual replacement Y = F - K X, Z = dinv Y, partials (y.y),
 //          (y.z) per load case.
 // Partials: part[w][k][2].
-// DIFF: the translation form, Y_I = sum_J K_IJ (X_J - X_I) + R_I X_I with
-// rsum = R (the FP64 block row sums): the FP32 values' rounding then meets
+// CORR: the translation form's value in the corrected form, Y_I = sum_J
+// K32_IJ X_J + C_I X_I with rsum = C = R - R32 (R the FP64 block row sums,
+// R32 those of the FP32 values): the FP32 values' rounding then meets
 // neighbour differences only (see the single-system product).
-template <typename VT, int LPR, int EPI, bool DIFF = false>
-__global__ void __launch_bounds__(kBThreads)
+// 128 VGPRs at most: 4 waves per SIMD (the 8-lane FP32 form otherwise
+// takes 130 and 3 waves).
+template <typename VT, int LPR, int EPI, bool CORR = false>
+__global__ void __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4)))
     k_bspmm(Work wk, const int2* __restrict__ wr, const int32_t* __restrict__ wmesh,
             const BScal* __restrict__ sc, const int32_t* __restrict__ bptr,
             const int32_t* __restrict__ bcol, const VT* __restrict__ val,
@@ -132,12 +135,6 @@ __global__ void __launch_bounds__(kBThreads)
       for (int a = 0; a < 3; ++a)
   #pragma unroll
         for (int k = 0; k < kNR; ++k) acc[a][k] = 0.0;
-      double xi[3][kNR];  // X_I (DIFF)
-  #pragma unroll
-      for (int cc = 0; cc < 3; ++cc)
-  #pragma unroll
-        for (int k = 0; k < kNR; ++k)
-          xi[cc][k] = (DIFF && valid) ? X[(3 * int64_t(I) + cc) * kNR + k] : 0.0;
       // kCU columns per step (masked past the row), so each lane keeps kCU
       // columns' loads in flight
       for (int c0 = sub; c0 < td; c0 += kCU * LPR) {
@@ -151,12 +148,7 @@ __global__ void __launch_bounds__(kBThreads)
           const int64_t col = 3 * int64_t(bcol[rb + jj]) + comp;
           const double2 xa = *reinterpret_cast<const double2*>(X + col * kNR);
           const double2 xb = *reinterpret_cast<const double2*>(X + col * kNR + 2);
-          double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
-          if constexpr (DIFF) {
-  #pragma unroll
-            for (int k = 0; k < kNR; ++k)
-              x4[k] -= comp == 0 ? xi[0][k] : (comp == 1 ? xi[1][k] : xi[2][k]);
-          }
+          const double x4[kNR] = {xa.x, xa.y, xb.x, xb.y};
           const double m = in ? 1.0 : 0.0;
           const double a3[3] = {m * double(v[cc]), m * double(v[td + cc]),
                                 m * double(v[2 * td + cc])};
@@ -171,13 +163,16 @@ __global__ void __launch_bounds__(kBThreads)
   #pragma unroll
         for (int k = 0; k < kNR; ++k) acc[a][k] = gsum<LPR>(acc[a][k]);
       if (valid && sub == 0) {
-        if constexpr (DIFF) {
-          const double* R = rsum + 9 * int64_t(I);
+        if constexpr (CORR) {
+          const double* C = rsum + 9 * int64_t(I);
   #pragma unroll
-          for (int a = 0; a < 3; ++a)
+          for (int k = 0; k < kNR; ++k) {
+            const double x0 = X[(3 * int64_t(I)) * kNR + k];
+            const double x1 = X[(3 * int64_t(I) + 1) * kNR + k];
+            const double x2 = X[(3 * int64_t(I) + 2) * kNR + k];
   #pragma unroll
-            for (int k = 0; k < kNR; ++k)
-              acc[a][k] += R[3 * a] * xi[0][k] + R[3 * a + 1] * xi[1][k] + R[3 * a + 2] * xi[2][k];
+            for (int a = 0; a < 3; ++a) acc[a][k] += C[3 * a] * x0 + C[3 * a + 1] * x1 + C[3 * a + 2] * x2;
+          }
         }
   #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -692,16 +687,16 @@ void bspmm(Ctx& c, BatchState& b, bool f32, const double* X, const double* F, do
   k_bspmm<VT, LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                \
       wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(),     \
       c.topo.bcol.get(), VAL, X, F, Y, Z, c.dinv.get(), b.part.get())
-  // FP32 values: the translation form (R made with the assembly)
+  // FP32 values: the corrected form (C made with the assembly)
 #define T_(LPR)                                                                             \
   k_bspmm<float, LPR, EPI, true><<<grid, kBThreads, 0, c.stream>>>(                       \
       wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.topo.bptr.get(),     \
-      c.topo.bcol.get(), c.val32.get(), X, F, Y, Z, c.dinv.get(), b.part.get(), c.rsum.get())
+      c.topo.bcol.get(), c.val32.get(), X, F, Y, Z, c.dinv.get(), b.part.get(), c.rcorr.get())
 #define P_(LPR)                                                                              \
   k_bspmm_p<LPR, EPI><<<grid, kBThreads, 0, c.stream>>>(                                    \
       wk, b.wr.get(), b.wmesh.get(), use_sc ? b.sc.get() : nullptr, c.ptr4.get(),           \
       c.col4.get(), c.valp.get(), X, F, Y, Z, c.dinv.get(), b.part.get())
-    if (f32) SFEM_REQUIRE(c.have_rsum, SFEM_ESTATE, "block row sums of K missing");
+    if (f32) SFEM_REQUIRE(c.have_rcorr, SFEM_ESTATE, "row sums of the FP32 rounding missing");
     if (f32 && b.packed[bk]) {
       T_(16);  // FP32 values keep the CSR order
     } else if (b.packed[bk]) {
@@ -1192,7 +1187,7 @@ int sfem_batch_build(sfem_batch* h, int flags) {
     check(b, sfem_assemble(ch, flags));
     sfem::Ctx& c = ch->c;
     sfem::ensure_csr64(c);  // the batched products read the CSR order
-    if (c.have_f32) sfem::ensure_rowsum(c);  // FP32 products in the translation form
+    if (c.have_f32) sfem::ensure_rowcorr(c);  // FP32 products in the corrected form
     sfem::BatchState& s = *b.st;
     s.n_meshes = int(b.meshes.size());
     s.node0 = node0;

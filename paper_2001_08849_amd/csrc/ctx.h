@@ -150,6 +150,12 @@ struct Ctx {
   // (valid while have_rsum, remade after every assembly)
   DBuf<double> rsum;
   bool have_rsum = false;
+  // [N][9] C_I = sum_J (K_bc_IJ - K32_IJ), the block row sums of the FP32
+  // copy's rounding (valid while have_rcorr, remade after every assembly):
+  // sum_J K32_IJ x_J + C_I x_I is the translation form's value with plain
+  // FP32 rows
+  DBuf<double> rcorr;
+  bool have_rcorr = false;
 
   // learned preconditioner M = diag(msqrt) (I + S') diag(msqrt), S' in the
   // scalar-CSR value layout of K
@@ -242,6 +248,7 @@ bool ensure_lds_tables(Ctx& c);  // window tables of schedule 17; false: unavail
 // one forced: variant 0 rows, 1 LDS-staged; -1 time both).
 void tune_mapply(Ctx& c, int variant = -1);
 void ensure_rowsum(Ctx& c);      // block row sums R of K_bc (once per assembly)
+void ensure_rowcorr(Ctx& c);     // C = R - R32 of the FP32 copy (once per assembly)
 // diag(K_bc) from whichever copy of K is current
 void matrix_diagonal(Ctx& c, double* diag);
 void pack_values_f32(Ctx& c, const float* csr, float* packed);

@@ -14,8 +14,10 @@
 // the fastest.  The learned M's apply has the same two forms (k_mapply,
 // k_mapply_lds), the faster kept per mesh.  Grids are XCD-banded (for_rows).  The translation form
 // (row3p's DIFF) multiplies neighbour differences x_J - x_I and adds
-// R_I x_I, the FP64 block row sum: the true residual of every solve and the
-// products of SFEM_MODE_F32_TF use it.
+// R_I x_I, the FP64 block row sum: the true residual of every solve uses it.
+// The FP32 products of SFEM_MODE_F32_TF take the same value in the
+// corrected form: plain FP32 rows plus C_I x_I, C_I = sum_J (K_IJ - K32_IJ)
+// (MODE bit 6).
 //
 // PCG: x0 = 0; each iteration is
 //   p = z + beta p;   q = K p with (p.q) -> alpha;   x, r, z updates with
@@ -414,11 +416,21 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double* partials
 }
 
 // y += R_I x_I: the translation part of K x in the translation form
-// (MODE bit 4); rsum holds R_I row-major per node.
+// (MODE bit 4; rsum holds R_I row-major per node), or y += C_I x_I in the
+// corrected form (MODE bit 6; rsum holds C_I).
+//
+// The corrected form: sum_J K32_IJ (x_J - x_I) + R_I x_I equals
+// sum_J K32_IJ x_J + C_I x_I with C_I = R_I - sum_J K32_IJ = sum_J (K_IJ -
+// K32_IJ), the row sum of the FP32 values' rounding.  In exact arithmetic
+// both are K x + sum_J (K32_IJ - K_IJ)(x_J - x_I): the FP32 rounding still
+// meets only neighbour differences.  The rows then run as plain FP32
+// products (no x_I held, no subtractions); what changes is the FP64
+// accumulation's own rounding, now relative to |K||x| as in an FP64
+// product.
 template <int MODE, typename P>
 __device__ __forceinline__ void add_translation(int I, const double* __restrict__ rsum,
                                                 const P* __restrict__ x, double (&y)[3]) {
-  if constexpr ((MODE & 16) != 0) {
+  if constexpr ((MODE & (16 | 64)) != 0) {
     const double* R = rsum + 9 * int64_t(I);
     const double x0 = double(x[3 * int64_t(I)]), x1 = double(x[3 * int64_t(I) + 1]),
                  x2 = double(x[3 * int64_t(I) + 2]);
@@ -451,7 +463,8 @@ __global__ void __launch_bounds__(kVecThreads)
     p[i] = z[i] + beta * p[i];
 }
 
-// q = K p, partial (p.q).  MODE bit 4: the translation form (rsum: R).
+// q = K p, partial (p.q).  MODE bit 4: the translation form (rsum: R);
+// bit 6: the corrected form (rsum: C).
 template <typename VT, typename P, int LPR, int MODE>
 __global__ void __launch_bounds__(kRowWaves * kWave)
     k_cg_spmv(int64_t N, const int32_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
@@ -565,13 +578,13 @@ __global__ void __launch_bounds__(256)
 
 // The three sums of node row I against the LDS window xs ([window][3],
 // FP64): as row3p, with each lane's 4 block columns given by one 8-byte
-// load of window indices.  DIFF: the translation form (xi: x_I).
-template <typename VT, int LPR, bool DIFF>
+// load of window indices.
+template <typename VT, int LPR>
 __device__ __forceinline__ void row3p_lds(int I, bool valid, int sub,
                                           const int32_t* __restrict__ ptr4,
                                           const uint16_t* __restrict__ lcol4,
                                           const VT* __restrict__ valp, const double* xs,
-                                          const double (&xi)[3], double (&y)[3]) {
+                                          double (&y)[3]) {
   int r4 = 0, d4 = 0;
   if (valid) {
     r4 = ptr4[I];
@@ -588,12 +601,7 @@ __device__ __forceinline__ void row3p_lds(int I, bool valid, int sub,
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double* xj = xs + 3 * Js[t];
-      double x0 = xj[0], x1 = xj[1], x2 = xj[2];
-      if constexpr (DIFF) {
-        x0 -= xi[0];
-        x1 -= xi[1];
-        x2 -= xi[2];
-      }
+      const double x0 = xj[0], x1 = xj[1], x2 = xj[2];
       a0 += m[0][t] * x0 + m[1][t] * x1 + m[2][t] * x2;
       a1 += m[3][t] * x0 + m[4][t] * x1 + m[5][t] * x2;
       a2 += m[6][t] * x0 + m[7][t] * x1 + m[8][t] * x2;
@@ -606,11 +614,11 @@ __device__ __forceinline__ void row3p_lds(int I, bool valid, int sub,
 
 // q = K p, partial (p.q), with p staged in LDS per chunk of rows (schedule
 // 17).  Chunks are dealt to the XCDs in contiguous ranges (workgroup b runs
-// on XCD b mod 8), so neighbouring windows share an L2.  DIFF: the
-// translation form (rsum: R).
+// on XCD b mod 8), so neighbouring windows share an L2.  CORR: the
+// corrected form (rsum: C).
 constexpr int kLdsThreads = 256;
 
-template <typename VT, typename P, int LPR, bool DIFF>
+template <typename VT, typename P, int LPR, bool CORR>
 __global__ void __launch_bounds__(kLdsThreads)
     k_cg_spmv_lds(int64_t N, const int32_t* __restrict__ ptr4,
                   const uint16_t* __restrict__ lcol4, const VT* __restrict__ valp,
@@ -642,20 +650,16 @@ __global__ void __launch_bounds__(kLdsThreads)
       const int64_t I = r0 + rr + g;
       const bool valid = I < N;
       const int Ii = valid ? int(I) : 0;
-      double xi[3] = {0.0, 0.0, 0.0};
-      if (DIFF && valid) {
-        xi[0] = double(p[3 * int64_t(Ii)]);
-        xi[1] = double(p[3 * int64_t(Ii) + 1]);
-        xi[2] = double(p[3 * int64_t(Ii) + 2]);
-      }
       double y[3];
-      row3p_lds<VT, LPR, DIFF>(Ii, valid, sub, ptr4, lcol4, valp, xs, xi, y);
+      row3p_lds<VT, LPR>(Ii, valid, sub, ptr4, lcol4, valp, xs, y);
       if (valid && sub == 0) {
-        if constexpr (DIFF) {
-          const double* R = rsum + 9 * int64_t(Ii);
+        if constexpr (CORR) {
+          const double* C = rsum + 9 * int64_t(Ii);
+          const double xi[3] = {double(p[3 * int64_t(Ii)]), double(p[3 * int64_t(Ii) + 1]),
+                                double(p[3 * int64_t(Ii) + 2])};
 #pragma unroll
           for (int a = 0; a < 3; ++a)
-            y[a] += R[3 * a] * xi[0] + R[3 * a + 1] * xi[1] + R[3 * a + 2] * xi[2];
+            y[a] += C[3 * a] * xi[0] + C[3 * a + 1] * xi[1] + C[3 * a + 2] * xi[2];
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -693,7 +697,6 @@ __global__ void __launch_bounds__(kLdsThreads)
   const int64_t c_lo = xcd * span;
   const int64_t c_hi = c_lo + span < n_chunks ? c_lo + span : n_chunks;
   double v[3] = {0.0, 0.0, 0.0};
-  const double none[3] = {0.0, 0.0, 0.0};
   for (int64_t ch = c_lo + blockIdx.x / kXcds; ch < c_hi; ch += per_xcd) {
     const int cnt = wcnt[ch];
     const int32_t* W = wcol + ch * kWindow;
@@ -708,7 +711,7 @@ __global__ void __launch_bounds__(kLdsThreads)
       const bool valid = I < N;
       const int Ii = valid ? int(I) : 0;
       double y[3];
-      row3p_lds<__bf16, LPR, false>(Ii, valid, sub, ptr4, lcol4, mvalp, xs, none, y);
+      row3p_lds<__bf16, LPR>(Ii, valid, sub, ptr4, lcol4, mvalp, xs, y);
       if (valid && sub == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1035,6 +1038,13 @@ int row_grid(int64_t N, const RowSched& rs) {
     case 16: LAUNCH(16, 24); break; \
     default: LAUNCH(8, 24); break;  \
   }
+// The same schedules in the corrected form (packed layout, MODE bit 6).
+#define SFEM_CF_SWITCH(lpr, LAUNCH) \
+  switch (lpr) {                    \
+    case 4: LAUNCH(4, 72); break;   \
+    case 16: LAUNCH(16, 72); break; \
+    default: LAUNCH(8, 72); break;  \
+  }
 
 // The schedule the translation form runs with: rs itself if it is a packed
 // schedule, else the packed one with 8 lanes per row (same grid cap).
@@ -1045,18 +1055,22 @@ RowSched tf_sched(const RowSched& rs) {
 // R_I = sum_J K_IJ per node row, one thread per (I, q = 3a + c): the
 // row's d4 packed values of component q (the padding adds zeros),
 // Neumaier-compensated (exact to one rounding of R plus O(deg eps^2)
-// sum |K_IJ|).
+// sum |K_IJ|).  CORR: C_I = sum_J (K_IJ - K32_IJ) from the packed FP32
+// copy v32 (each difference is exact when K32 is K rounded to FP32).
+template <bool CORR>
 __global__ void k_rowsum(int64_t N, const int32_t* __restrict__ ptr4,
-                         const double* __restrict__ valp, double* __restrict__ rsum) {
+                         const double* __restrict__ valp, const float* __restrict__ valp32,
+                         double* __restrict__ rsum) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= 9 * N) return;
   const int64_t I = t / 9;
   const int q = int(t - 9 * I);
   const int r4 = ptr4[I], d4 = ptr4[I + 1] - r4;
-  const double* v = valp + 9 * int64_t(r4) + int64_t(q) * d4;
+  const int64_t off = 9 * int64_t(r4) + int64_t(q) * d4;
+  const double* v = valp + off;
   double sum = 0.0, comp = 0.0;
   for (int j = 0; j < d4; ++j) {
-    const double x = v[j];
+    const double x = CORR ? v[j] - double(valp32[off + j]) : v[j];
     const double t2 = sum + x;
     comp += fabs(sum) >= fabs(x) ? (sum - t2) + x : (x - t2) + sum;
     sum = t2;
@@ -1147,7 +1161,7 @@ struct CgBuffers {
   const int32_t* mcol4 = nullptr;
   const void* msq = nullptr;          // its diag(K)^-1/2, typed like the vectors
   void* rh = nullptr;                 // s r, typed like the vectors
-  const double* rsum = nullptr;       // set: products in the translation form
+  const double* rsum = nullptr;       // set (FP32 values only): C of the corrected form
 };
 
 // Grid of the LDS-staged product: one workgroup per chunk up to the cap,
@@ -1165,10 +1179,23 @@ void ensure_rowsum(Ctx& c) {
   if (c.have_rsum) return;
   ensure_packed64(c);
   c.rsum.reserve(9 * c.N);
-  k_rowsum<<<div_up(9 * c.N, 256), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.valp.get(),
-                                                        c.rsum.get());
+  k_rowsum<false><<<div_up(9 * c.N, 256), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.valp.get(),
+                                                               nullptr, c.rsum.get());
   SFEM_HIP(hipGetLastError());
   c.have_rsum = true;
+}
+
+// C = R - R32, the block row sums of the FP32 copy's rounding (once per
+// assembly).
+void ensure_rowcorr(Ctx& c) {
+  if (c.have_rcorr) return;
+  ensure_packed64(c);
+  ensure_packed32(c);
+  c.rcorr.reserve(9 * c.N);
+  k_rowsum<true><<<div_up(9 * c.N, 256), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.valp.get(),
+                                                              c.valp32.get(), c.rcorr.get());
+  SFEM_HIP(hipGetLastError());
+  c.have_rcorr = true;
 }
 
 namespace {
@@ -1246,7 +1273,12 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
             N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
             c.sc.get(), c.partials.get(), nullptr);
     } else if (B.rsum) {
-      SFEM_TF_SWITCH(kSched[rt.variant].lpr, L_)
+      static_assert(sizeof(VT) == 4 || sizeof(VT) == 8, "FP32 or FP64 values");
+      if constexpr (sizeof(VT) == 4) {
+        SFEM_CF_SWITCH(kSched[rt.variant].lpr, L_)
+      } else {
+        throw Error{SFEM_ESTATE, "the corrected form is for FP32 values"};
+      }
     } else {
       SFEM_SCHED_SWITCH(rs.variant, L_)
     }
@@ -1546,7 +1578,7 @@ void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
   for (int prec = 0; prec < (c.have_f32 ? 2 : 1); ++prec) {
     double best = 1e30;
     RowSched pick = prec ? c.sched32 : keep64;
-    if (prec == 1) ensure_rowsum(c);
+    if (prec == 1) ensure_rowcorr(c);
     for (int v = 0; v < kNumSched; ++v)
       for (int cap : caps) {
         if ((kSched[v].mode & 32) && !ensure_lds_tables(c)) continue;
@@ -1557,7 +1589,7 @@ void autotune_rows(Ctx& c, int reps, double* best_us64, double* best_us32) {
         CgBuffers B{prec == 0 ? (const void*)c.val.get() : (const void*)c.val32.get(),
                     c.val.get(), c.dinv.get(), c.w.get(), c.x.get(), c.r.get(),
                     c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
-        if (prec == 1) B.rsum = c.rsum.get();
+        if (prec == 1) B.rsum = c.rcorr.get();
         const int vg = vec_grid(n);
         k_cg_start<double><<<vg, kVecThreads, 0, c.stream>>>(
             n, c.w.get(), 1.0, nullptr, c.x.get(), c.r.get(), c.z.get(), c.p.get(), c.p2.get(),
@@ -1658,6 +1690,7 @@ static int refine64(Ctx& c, const CgBuffers& B, double tol_abs, int max_iter, in
   CgBuffers J = B;
   J.val = c.val.get();
   J.val_true = c.val.get();
+  J.rsum = nullptr;  // plain FP64 products
   J.b = c.w.get();
   const int its = pcg<double, double>(c, J, c.w.get(), 1.0, tol_abs, max_iter, check_every, met,
                                       brk);
@@ -1677,6 +1710,7 @@ static int jacobi_fallback(Ctx& c, const CgBuffers& B, double tol_abs, int max_i
   CgBuffers J = B;
   J.val = c.val.get();
   J.val_true = c.val.get();
+  J.rsum = nullptr;  // plain FP64 products
   J.mval = nullptr;
   J.b = c.w.get();
   bool brk = false;
@@ -1727,7 +1761,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
     // is the refinement step and the convergence test.
     // F32_TF: the same with the K32 products in the translation form,
     // q_I = sum_J K32_IJ (p_J - p_I) + R_I p_I (R_I the FP64 block row
-    // sums of K64), to the end: no restart.
+    // sums of K64), to the end: no restart.  The kernels compute it as
+    // sum_J K32_IJ p_J + C_I p_I (the corrected form, C = R - R32).
     const bool rr = o.mode == SFEM_MODE_F32_RR;
     const bool tf = o.mode == SFEM_MODE_F32_TF;
     SFEM_REQUIRE(!(rr || tf) || c.have_f32, SFEM_ESTATE,
@@ -1737,8 +1772,8 @@ int solve(Ctx& c, const sfem_solve_opts& o, sfem_solve_info& info) {
                 c.val.get(), c.dinv.get(), c.f_bc.get(), c.x.get(), c.r.get(),
                 c.z.get(), c.p.get(), c.p2.get(), c.q.get()};
     if (tf) {
-      ensure_rowsum(c);
-      B.rsum = c.rsum.get();
+      ensure_rowcorr(c);
+      B.rsum = c.rcorr.get();
     }
     if (learned) {
       B.mval = c.mvalp.get();

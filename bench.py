@@ -708,6 +708,9 @@ def main():
     ap.add_argument("--profile-command", default="", help="command line recorded in summaries")
     ap.add_argument("--schedule", default="", metavar="VARIANT,GRID_CAP",
                     help="pin the FP64 row schedule instead of autotuning it")
+    ap.add_argument("--precond-kernel", type=int, default=-1, metavar="VARIANT",
+                    help="pin the learned M's apply kernel (0: rows, 1: LDS-staged) instead of "
+                         "the one timed fastest (counter runs, whose timings are distorted)")
     ap.add_argument("--tf-solve", action="store_true",
                     help="after the timed steps, one Jacobi solve with FP32 translation-form "
                          "products (profiling; the full leg is --no-mixed's)")
@@ -836,6 +839,8 @@ def main():
             # the last solve times every launch (eager), for the M-apply roofline
             last = k == max(1, args.steps)
             ms_inf = net.apply(ctx)
+            if args.precond_kernel >= 0:
+                ctx.set_precond_kernel(args.precond_kernel)
             _, info = ctx.solve(rtol=1e-8, out=u, precond=sfem.PRECOND_LEARNED, profile=last)
             info["ms_inference"] = ms_inf
             if last:

@@ -1253,6 +1253,8 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
       c.prof_ev.push_back(e);
     }
   (void)parity;
+  // the corrected form's C belongs to the FP32 copy
+  SFEM_REQUIRE(!B.rsum || sizeof(VT) == 4, SFEM_ESTATE, "the corrected form is for FP32 values");
   P* p = (P*)B.p0;
   const RowSched rt = tf_sched(rs);
   const Lay<VT> LY = lay<VT>(c, B.rsum ? rt : rs, (const VT*)B.val);
@@ -1264,21 +1266,22 @@ void cg_iterations(Ctx& c, const CgBuffers& B, int iters, int& parity) {
                                                                 p, (P*)B.q, c.sc.get(),  \
                                                                 c.partials.get(), B.rsum)
     if (lds) {
-      if (B.rsum)
-        k_cg_spmv_lds<VT, P, 8, true><<<rg, kLdsThreads, 0, s>>>(
-            N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
-            c.sc.get(), c.partials.get(), B.rsum);
-      else
+      if constexpr (sizeof(VT) == 4) {
+        if (B.rsum)
+          k_cg_spmv_lds<VT, P, 8, true><<<rg, kLdsThreads, 0, s>>>(
+              N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
+              c.sc.get(), c.partials.get(), B.rsum);
+        else
+          k_cg_spmv_lds<VT, P, 8, false><<<rg, kLdsThreads, 0, s>>>(
+              N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
+              c.sc.get(), c.partials.get(), nullptr);
+      } else {
         k_cg_spmv_lds<VT, P, 8, false><<<rg, kLdsThreads, 0, s>>>(
             N, LY.ptr, c.lcol4.get(), LY.val, c.wcol.get(), c.wcnt.get(), p, (P*)B.q,
             c.sc.get(), c.partials.get(), nullptr);
-    } else if (B.rsum) {
-      static_assert(sizeof(VT) == 4 || sizeof(VT) == 8, "FP32 or FP64 values");
-      if constexpr (sizeof(VT) == 4) {
-        SFEM_CF_SWITCH(kSched[rt.variant].lpr, L_)
-      } else {
-        throw Error{SFEM_ESTATE, "the corrected form is for FP32 values"};
       }
+    } else if (B.rsum) {
+      if constexpr (sizeof(VT) == 4) SFEM_CF_SWITCH(kSched[rt.variant].lpr, L_)
     } else {
       SFEM_SCHED_SWITCH(rs.variant, L_)
     }

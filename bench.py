@@ -78,6 +78,7 @@ KERNEL_SOURCES = {
     "assemble_c2": ("k_assemble<false, false>", "paper_2001_08849_amd/csrc/assemble.hip"),
     "mapply_c2": ("k_mapply<double>", "paper_2001_08849_amd/csrc/solve.hip"),
     "mapply_lds_c2": ("k_mapply_lds<double>", "paper_2001_08849_amd/csrc/solve.hip"),
+    "mapply_grp_c2": ("k_mapply_grp<double>", "paper_2001_08849_amd/csrc/solve.hip"),
 }
 # instruction and stall counters summarised per kernel (one rocprofv3 pass:
 # at most 8 SQ counters)
@@ -910,14 +911,17 @@ def main():
             mb = mapply_bytes(m.n_nodes, s.nnz, s.n_blocks)
             ach_m = mb / (mms * 1e-3) / 1e9 if mms > 0 else None
             mk = ctx.precond_kernel()
+            kname, ktag = [("k_mapply<double>", "mapply_c2"),
+                           ("k_mapply_lds<double>", "mapply_lds_c2"),
+                           ("k_mapply_grp<double>", "mapply_grp_c2")][mk["variant"]]
             out["roofline_mapply"] = {
-                "kernel": "k_mapply_lds<double>" if mk["variant"] else "k_mapply<double>",
-                "bound": "hbm", "achieved": ach_m,
+                "kernel": kname, "bound": "hbm", "achieved": ach_m,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach_m / HBM_PEAK_GBS if ach_m else None,
-                "traffic": read_traffic("mapply_lds_c2" if mk["variant"] else "mapply_c2"),
+                "traffic": read_traffic(ktag),
                 "bytes_per_launch": mb, "us_per_launch": mms * 1e3,
-                "kernel_choice_us": {"rows": mk["us_rows"], "lds_staged": mk["us_lds"]}}
+                "kernel_choice_us": {"rows": mk["us_rows"], "lds_staged": mk["us_lds"],
+                                     "grouped": mk["us_grouped"]}}
             out["learned"] = {
                 "solver": "flexible PCG, K FP64, learned M (S' BF16 in the padded node-row layout, network BF16-MFMA), "
                           "FP64 vectors and dots, true relres <= 1e-8",

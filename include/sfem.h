@@ -280,7 +280,7 @@ int sfem_face_stress(sfem_ctx* ctx, const double* u, double* strain, double* str
 int sfem_get_timings(sfem_ctx* ctx, double* ms_topology, double* ms_assemble);
 
 /* Row-kernel schedules (SpMV, residual and CG product kernels; the learned
- * M's apply has its own two kernels, see sfem_set_precond_kernel):
+ * M's apply has its own three kernels, see sfem_set_precond_kernel):
  * `variant` in [0, SFEM_NUM_SCHEDULES) picks lanes per node row and a loop
  * shape:
  *   0-3   8/16/32/64 lanes, one row per lane group and step;
@@ -417,16 +417,21 @@ int sfem_get_precond_info(sfem_ctx* ctx, double* theta, double* lambda_min, doub
  * preconditioned solve; the network only fills S): variant 0 walks node rows
  * of the packed BF16 copy of theta S gathering r_hat = D^-1/2 r from HBM; 1
  * stages r_hat in LDS per chunk of 128 rows (the window tables of row
- * schedule 17; unavailable when a chunk gathers more than 1,024 nodes).
- * The first sfem_gnn_apply on a mesh times both (10 applies each, after
- * its own timed inference) and keeps the faster.
- * set: variant 0 or 1 forces one (times it), -1 times both again; errors
- * SFEM_EINVAL (unknown variant, or 1 unavailable), SFEM_ESTATE (no M).
- * get: the variant in use and both times in microseconds (0: not timed).
- * Both give the same z = M r bit for bit; the dot products of the learned
- * solve are grouped per workgroup differently. */
+ * schedule 17; unavailable when a chunk gathers more than 1,024 nodes); 2
+ * walks node rows of a grouped copy in which each 4 blocks of a row are one
+ * 80-byte record (36 BF16 values, then the 4 column offsets J - I as int16;
+ * made with every M, unavailable when some |J - I| > 32767).
+ * The first sfem_gnn_apply on a mesh times each available one (10 applies
+ * each, after its own timed inference) and keeps the fastest.
+ * set: variant 0, 1 or 2 forces one (times it), -1 times them again;
+ * errors SFEM_EINVAL (unknown variant, or one unavailable), SFEM_ESTATE (no
+ * M).  get: the variant in use and the three times in microseconds (0: not
+ * timed); pointers may be NULL.
+ * All give the same z = M r bit for bit; the dot products of the learned
+ * solve are grouped per workgroup differently under variant 1. */
 int sfem_set_precond_kernel(sfem_ctx* ctx, int variant);
-int sfem_get_precond_kernel(sfem_ctx* ctx, int* variant, double* us_rows, double* us_lds);
+int sfem_get_precond_kernel(sfem_ctx* ctx, int* variant, double* us_rows, double* us_lds,
+                            double* us_grouped);
 
 /* The learned preconditioner of a context: the correction theta S (float32
  * [nnz], in the order of sfem_get_csr's values; the solver applies these

@@ -113,8 +113,9 @@ void reset_problem(Ctx& c) {
   c.have_learned = false;
   c.nb4 = 0;
   c.lds_tables = 0;
-  c.mapply_lds = c.mapply_tuned = false;
-  c.mapply_us[0] = c.mapply_us[1] = 0.0;
+  c.mapply_kernel = 0;
+  c.mapply_tuned = c.mgrp_ok = false;
+  c.mapply_us[0] = c.mapply_us[1] = c.mapply_us[2] = 0.0;
   c.gnn.reset();
   c.have_material = false;
   c.per_tet = false;
@@ -986,12 +987,14 @@ int sfem_set_precond_kernel(sfem_ctx* h, int variant) {
   });
 }
 
-int sfem_get_precond_kernel(sfem_ctx* h, int* variant, double* us_rows, double* us_lds) {
+int sfem_get_precond_kernel(sfem_ctx* h, int* variant, double* us_rows, double* us_lds,
+                            double* us_grouped) {
   return guarded(h, [&](Ctx& c) {
     SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "call sfem_gnn_apply first");
-    if (variant) *variant = c.mapply_lds ? 1 : 0;
+    if (variant) *variant = c.mapply_kernel;
     if (us_rows) *us_rows = c.mapply_us[0];
     if (us_lds) *us_lds = c.mapply_us[1];
+    if (us_grouped) *us_grouped = c.mapply_us[2];
     return SFEM_OK;
   });
 }

@@ -164,11 +164,18 @@ struct Ctx {
   DBuf<float> mval;
   DBuf<__bf16> mvalp;            // the same values, BF16, in the packed layout
   DBuf<double> msqrt;
-  // M apply kernel: rows (k_mapply) or rh staged in LDS per chunk of rows
-  // (k_mapply_lds, needs the window tables); chosen by timing both after the
-  // first M of a mesh is built (mapply_us: their times, 0 if not timed)
-  bool mapply_lds = false, mapply_tuned = false;
-  double mapply_us[2] = {0.0, 0.0};
+  // S' again in the grouped layout: per node row, one 80-byte group per 4
+  // packed blocks, the 36 BF16 values [q][t] then the 4 int16 column
+  // offsets J - I (mgrp_ok: every offset fits; remade with each M)
+  DBuf<uint4> mgrp;
+  bool mgrp_ok = false;
+  // M apply kernel: 0 rows (k_mapply), 1 rh staged in LDS per chunk of rows
+  // (k_mapply_lds, needs the window tables), 2 the grouped layout
+  // (k_mapply_grp, needs mgrp_ok); chosen by timing each after the first M
+  // of a mesh is built (mapply_us: their times, 0 if not timed)
+  int mapply_kernel = 0;
+  bool mapply_tuned = false;
+  double mapply_us[3] = {0.0, 0.0, 0.0};
   DBuf<float> msqrt32;
   std::shared_ptr<GnnWork> gnn;  // features, activations and training pairs
 
@@ -247,6 +254,7 @@ bool ensure_lds_tables(Ctx& c);  // window tables of schedule 17; false: unavail
 // Times both M apply kernels on the current M and keeps the faster (or the
 // one forced: variant 0 rows, 1 LDS-staged; -1 time both).
 void tune_mapply(Ctx& c, int variant = -1);
+void build_mgroups(Ctx& c);  // S' in the grouped layout, after each new packed M
 void ensure_rowsum(Ctx& c);      // block row sums R of K_bc (once per assembly)
 void ensure_rowcorr(Ctx& c);     // C = R - R32 of the FP32 copy (once per assembly)
 // diag(K_bc) from whichever copy of K is current

@@ -1143,6 +1143,7 @@ void gnn_precondition(Ctx& c, Gnn& g) {
   pack_pattern(c);
   c.mvalp.reserve(9 * c.nb4);
   pack_values_bf16(c, c.mval.get(), c.mvalp.get());
+  build_mgroups(c);
   SFEM_HIP(hipStreamSynchronize(s));
   c.have_learned = true;
 }

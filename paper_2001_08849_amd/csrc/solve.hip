@@ -815,6 +815,121 @@ __global__ void __launch_bounds__(kRowWaves * kWave) __attribute__((amdgpu_waves
   store_partials<3>(v, partials);
 }
 
+// The three sums of node row I of S' in the grouped layout: a lane takes
+// one group (4 blocks) per step with five 16-byte loads, the 36 BF16
+// values [q][t] and the 4 int16 offsets J - I (the packed layout needs
+// nine 8-byte value loads and a 16-byte column load for as many).  The
+// sums are row3p's on the packed copy, term for term in the same order.
+template <int LPR, class XF>
+__device__ __forceinline__ void row3g(int I, bool valid, int sub, const int32_t* __restrict__ ptr4,
+                                      const uint4* __restrict__ grp, const XF& x, double& y0,
+                                      double& y1, double& y2) {
+  int g0 = 0, ng = 0;
+  if (valid) {
+    const int r4 = ptr4[I];
+    g0 = r4 >> 2;
+    ng = (ptr4[I + 1] - r4) >> 2;
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int g = sub; g < ng; g += LPR) {
+    const uint4* G = grp + 5 * (int64_t(g0) + g);
+    uint32_t w[20];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const uint4 t = G[k];
+      w[4 * k] = t.x;
+      w[4 * k + 1] = t.y;
+      w[4 * k + 2] = t.z;
+      w[4 * k + 3] = t.w;
+    }
+    double m[9][4];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) {
+      // BF16 i is the low (even i) or high half of word i / 2
+      const uint32_t bits = (i & 1) ? (w[i >> 1] & 0xffff0000u) : (w[i >> 1] << 16);
+      m[i >> 2][i & 3] = double(__uint_as_float(bits));
+    }
+    const int Js[4] = {I + int(int16_t(w[18] & 0xffffu)), I + int(int16_t(w[18] >> 16)),
+                       I + int(int16_t(w[19] & 0xffffu)), I + int(int16_t(w[19] >> 16))};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t j3 = 3 * int64_t(Js[t]);
+      const double x0 = double(x(j3)), x1 = double(x(j3 + 1)), x2 = double(x(j3 + 2));
+      a0 += m[0][t] * x0 + m[1][t] * x1 + m[2][t] * x2;
+      a1 += m[3][t] * x0 + m[4][t] * x1 + m[5][t] * x2;
+      a2 += m[6][t] * x0 + m[7][t] * x1 + m[8][t] * x2;
+    }
+  }
+  y0 = group_sum<LPR>(a0);
+  y1 = group_sum<LPR>(a1);
+  y2 = group_sum<LPR>(a2);
+}
+
+// The learned M apply of k_mapply from the grouped layout (same sums, same
+// order, same epilogue).
+template <typename P>
+__global__ void __launch_bounds__(kRowWaves * kWave) __attribute__((amdgpu_waves_per_eu(4)))
+    k_mapply_grp(int64_t N, const int32_t* __restrict__ ptr4, const uint4* __restrict__ grp,
+                 const P* __restrict__ s, const P* __restrict__ r, const P* __restrict__ rh,
+                 P* __restrict__ z, const CgScalars* __restrict__ sc,
+                 double* __restrict__ partials) {
+  if (sc && sc->converged) return;
+  const PlainX<P> xf{rh};
+  double v[3] = {0.0, 0.0, 0.0};
+  for_rows<kMLanes>(N, [&](int I, bool valid, int sub) {
+    double y[3];
+    row3g<kMLanes>(I, valid, sub, ptr4, grp, xf, y[0], y[1], y[2]);
+    if (valid && sub == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = 3 * int64_t(I) + a;
+        const double ri = double(r[i]);
+        const P zi = P(double(s[i]) * (double(rh[i]) + y[a]));
+        v[0] += ri * double(zi);
+        v[1] += ri * ri;
+        v[2] += ri * double(z[i]);
+        z[i] = zi;
+      }
+    }
+  });
+  store_partials<3>(v, partials);
+}
+
+// Packed BF16 S' and block columns -> the grouped layout, one thread per
+// node row; bad is set if an offset J - I does not fit in int16.
+__global__ void k_mgroup(int64_t N, const int32_t* __restrict__ ptr4,
+                         const int32_t* __restrict__ col4, const __bf16* __restrict__ mvalp,
+                         uint4* __restrict__ grp, int* __restrict__ bad) {
+  const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int r4 = ptr4[I], d4 = ptr4[I + 1] - r4;
+  const uint16_t* v = reinterpret_cast<const uint16_t*>(mvalp) + 9 * int64_t(r4);
+  for (int jb = 0; jb < d4; jb += 4) {
+    uint32_t w[20];
+#pragma unroll
+    for (int i = 0; i < 36; i += 2) {
+      const int q = i >> 2, t = i & 3;  // t is 0 or 2: (q, t) and (q, t + 1)
+      const int64_t o = int64_t(q) * d4 + jb + t;
+      w[i >> 1] = uint32_t(v[o]) | (uint32_t(v[o + 1]) << 16);
+    }
+    uint32_t off[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      int d = col4[r4 + jb + t] - int(I);
+      if (d < -32768 || d > 32767) {
+        atomicOr(bad, 1);
+        d = 0;
+      }
+      off[t] = uint32_t(d) & 0xffffu;
+    }
+    w[18] = off[0] | (off[1] << 16);
+    w[19] = off[2] | (off[3] << 16);
+    uint4* G = grp + 5 * (int64_t(r4 + jb) >> 2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) G[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+  }
+}
+
 // Residual replacement: r = b - K x, z = dinv r; partials (r.r), (r.z).
 // MODE bit 4: K x in the translation form (rsum: R).
 template <typename VT, typename P, int LPR, int MODE>
@@ -1203,7 +1318,7 @@ namespace {
 int lds_grid(Ctx& c, const RowSched& rs);
 
 int mapply_parts(Ctx& c) {
-  if (c.mapply_lds) return lds_grid(c, RowSched{17, kRowGridMax});
+  if (c.mapply_kernel == 1) return lds_grid(c, RowSched{17, kRowGridMax});
   const RowSched rs{0, kRowGridMax};
   const int64_t rows_per_block = int64_t(kRowWaves) * (kWave / kMLanes);
   int g = div_up(c.N, rows_per_block);
@@ -1222,10 +1337,14 @@ void mapply(Ctx& c, const CgBuffers& B, const P* r, P* z, bool guarded, bool fre
     k_rh<P><<<div_up(n, 256), 256, 0, c.stream>>>(n, (const P*)B.msq, r, (P*)B.rh);
     SFEM_HIP(hipGetLastError());
   }
-  if (c.mapply_lds) {
+  if (c.mapply_kernel == 1) {
     k_mapply_lds<P><<<mapply_parts(c), kLdsThreads, 0, c.stream>>>(
         c.N, B.mptr4, c.lcol4.get(), B.mval, c.wcol.get(), c.wcnt.get(), (const P*)B.msq, r,
         (const P*)B.rh, z, guarded ? c.sc.get() : nullptr, partials ? partials : c.partials.get());
+  } else if (c.mapply_kernel == 2) {
+    k_mapply_grp<P><<<mapply_parts(c), kRowWaves * kWave, 0, c.stream>>>(
+        c.N, B.mptr4, c.mgrp.get(), (const P*)B.msq, r, (const P*)B.rh, z,
+        guarded ? c.sc.get() : nullptr, partials ? partials : c.partials.get());
   } else {
     k_mapply<P><<<mapply_parts(c), kRowWaves * kWave, 0, c.stream>>>(
         c.N, B.mptr4, B.mcol4, B.mval, (const P*)B.msq, r, (const P*)B.rh, z,
@@ -1324,7 +1443,7 @@ void cg_period(Ctx& c, const CgBuffers& B, int iters, int& parity, bool eager) {
       reinterpret_cast<const void*>(intptr_t(c.N)), reinterpret_cast<const void*>(intptr_t(iters)),
       reinterpret_cast<const void*>(intptr_t(rs.variant * 100000 + rs.grid_cap)),
       reinterpret_cast<const void*>(intptr_t(sizeof(VT) * 16 + sizeof(P))),
-      reinterpret_cast<const void*>(intptr_t(c.mapply_lds))};
+      reinterpret_cast<const void*>(intptr_t(c.mapply_kernel)), c.mgrp.get()};
   if (!c.cg_exec || c.cg_key != key) {
     c.drop_cg_graph();
     SFEM_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
@@ -2082,10 +2201,13 @@ void learned_apply_into(Ctx& c, const double* r, double* z, double* rh, double* 
 
 void tune_mapply(Ctx& c, int variant) {
   SFEM_REQUIRE(c.have_learned, SFEM_ESTATE, "no learned preconditioner on this context");
-  SFEM_REQUIRE(variant >= -1 && variant <= 1, SFEM_EINVAL, "M apply variant must be -1, 0 or 1");
+  SFEM_REQUIRE(variant >= -1 && variant <= 2, SFEM_EINVAL,
+               "M apply variant must be -1, 0, 1 or 2");
   const bool lds_ok = ensure_lds_tables(c);
   SFEM_REQUIRE(variant != 1 || lds_ok, SFEM_EINVAL,
                "a chunk of rows gathers more than the LDS window holds");
+  SFEM_REQUIRE(variant != 2 || c.mgrp_ok, SFEM_EINVAL,
+               "a block column lies beyond the grouped layout's int16 offsets");
   ensure_work(c, false);
   const int64_t n = c.n_dof();
   CgBuffers B{};
@@ -2096,12 +2218,12 @@ void tune_mapply(Ctx& c, int variant) {
   B.rh = c.rh.get();
   k_ones<<<div_up(n, 256), 256, 0, c.stream>>>(n, c.r.get());
   SFEM_HIP(hipGetLastError());
-  c.mapply_us[0] = c.mapply_us[1] = 0.0;
+  c.mapply_us[0] = c.mapply_us[1] = c.mapply_us[2] = 0.0;
   constexpr int kReps = 10;
-  for (int v = 0; v < 2; ++v) {
-    if (v == 1 && !lds_ok) break;
+  for (int v = 0; v < 3; ++v) {
+    if ((v == 1 && !lds_ok) || (v == 2 && !c.mgrp_ok)) continue;
     if (variant >= 0 && v != variant) continue;
-    c.mapply_lds = v == 1;
+    c.mapply_kernel = v;
     mapply<double>(c, B, c.r.get(), c.z.get(), false, true);  // warm
     SFEM_HIP(hipEventRecord(c.ev0, c.stream));
     for (int k = 0; k < kReps; ++k) mapply<double>(c, B, c.r.get(), c.z.get(), false, false);
@@ -2111,8 +2233,34 @@ void tune_mapply(Ctx& c, int variant) {
     SFEM_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
     c.mapply_us[v] = 1e3 * ms / kReps;
   }
-  c.mapply_lds = variant >= 0 ? variant == 1
-                              : (c.mapply_us[1] > 0.0 && c.mapply_us[1] < c.mapply_us[0]);
+  if (variant >= 0) {
+    c.mapply_kernel = variant;
+  } else {
+    c.mapply_kernel = 0;
+    for (int v = 1; v < 3; ++v)
+      if (c.mapply_us[v] > 0.0 && c.mapply_us[v] < c.mapply_us[c.mapply_kernel])
+        c.mapply_kernel = v;
+  }
+}
+
+// S' in the grouped layout (after every new packed copy of M).
+void build_mgroups(Ctx& c) {
+  c.mgrp.reserve(c.nb4 > 0 ? 5 * int64_t(c.nb4 / 4) : 1);
+  DBuf<int> bad;
+  bad.reserve(1);
+  SFEM_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), c.stream));
+  k_mgroup<<<div_up(c.N, 256), 256, 0, c.stream>>>(c.N, c.ptr4.get(), c.col4.get(),
+                                                   c.mvalp.get(), c.mgrp.get(), bad.get());
+  SFEM_HIP(hipGetLastError());
+  int b = 0;
+  SFEM_HIP(hipMemcpyAsync(&b, bad.get(), sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  SFEM_HIP(hipStreamSynchronize(c.stream));
+  c.mgrp_ok = b == 0;
+  // a kernel chosen on the previous M stays valid only if this one fits
+  if (!c.mgrp_ok && c.mapply_kernel == 2) {
+    c.mapply_kernel = 0;
+    c.mapply_tuned = false;
+  }
 }
 
 void learned_apply(Ctx& c, const double* r, double* z) {

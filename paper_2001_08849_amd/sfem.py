@@ -144,7 +144,7 @@ def lib() -> C.CDLL:
             "sfem_get_precond_info": (i32, [vp] + [C.POINTER(dbl)] * 3),
             "sfem_set_precond_kernel": (i32, [vp, i32]),
             "sfem_get_precond_kernel": (i32, [vp, C.POINTER(i32), C.POINTER(dbl),
-                                              C.POINTER(dbl)]),
+                                              C.POINTER(dbl), C.POINTER(dbl)]),
             "sfem_face_stress": (i32, [vp, vp, vp, vp, i32, C.POINTER(dbl)]),
             "sfem_batch_create": (i32, [C.POINTER(vp), i32]),
             "sfem_batch_destroy": (None, [vp]),
@@ -461,14 +461,17 @@ class Context:
         return {"theta": t.value, "lambda_min": a.value, "lambda_max": b.value}
 
     def set_precond_kernel(self, variant: int):
-        """M apply kernel: 0 rows, 1 rh staged in LDS, -1 time both and keep the faster."""
+        """M apply kernel: 0 rows, 1 rh staged in LDS, 2 grouped layout, -1 time
+        each and keep the fastest."""
         self._check(self._L.sfem_set_precond_kernel(self._h, int(variant)))
 
     def precond_kernel(self):
-        """{'variant', 'us_rows', 'us_lds'}: the M apply kernel in use and both timings."""
-        v, a, b = C.c_int(), C.c_double(), C.c_double()
-        self._check(self._L.sfem_get_precond_kernel(self._h, C.byref(v), C.byref(a), C.byref(b)))
-        return {"variant": v.value, "us_rows": a.value, "us_lds": b.value}
+        """{'variant', 'us_rows', 'us_lds', 'us_grouped'}: the M apply kernel in use
+        and the timings (0: not timed)."""
+        v, a, b, g = C.c_int(), C.c_double(), C.c_double(), C.c_double()
+        self._check(self._L.sfem_get_precond_kernel(self._h, C.byref(v), C.byref(a), C.byref(b),
+                                                    C.byref(g)))
+        return {"variant": v.value, "us_rows": a.value, "us_lds": b.value, "us_grouped": g.value}
 
     def precond_apply(self, r):
         z = np.empty(self.sizes().n_rows, dtype=np.float64)

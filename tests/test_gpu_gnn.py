@@ -391,10 +391,12 @@ def test_weights_file_round_trip(S, small, tmp_path):
         b.load(tmp_path / "missing.sfgn")
 
 
-def test_lds_staged_m_apply(S):
-    """The M apply with r_hat staged in LDS per chunk of rows gives z = M r
-    bit for bit as the row kernel; learned solves under either reach the
-    oracle's u; sfem_gnn_apply timed both."""
+def test_m_apply_kernels(S):
+    """The M apply with r_hat staged in LDS per chunk of rows and the one on
+    the grouped layout give z = M r bit for bit as the row kernel; learned
+    solves under each reach the oracle's u (the grouped kernel's solve is
+    the row kernel's, bit for bit: same sums, same partials); sfem_gnn_apply
+    timed all three."""
     p = mg.learned_small(2, grid=(40, 6, 6))
     ctx = S.Context(0)
     S.setup_problem(ctx, p)
@@ -405,21 +407,58 @@ def test_lds_staged_m_apply(S):
     net.set_params(flat)
     net.apply(ctx)
     info = ctx.precond_kernel()
-    assert info["variant"] in (0, 1) and info["us_rows"] > 0 and info["us_lds"] > 0
+    assert info["variant"] in (0, 1, 2)
+    assert info["us_rows"] > 0 and info["us_lds"] > 0 and info["us_grouped"] > 0
     r = np.random.default_rng(4).standard_normal(Kb.shape[0])
     out = {}
-    for v in (0, 1):
+    for v in (0, 1, 2):
         ctx.set_precond_kernel(v)
         assert ctx.precond_kernel()["variant"] == v
         z = ctx.precond_apply(r)
         u, i = ctx.solve(rtol=1e-10, precond=S.PRECOND_LEARNED)
         err = np.linalg.norm(u - ub) / np.linalg.norm(ub)
-        out[v] = (z, i["iters"], err)
+        out[v] = (z, i["iters"], err, u)
         assert i["converged"] and not i["fell_back"] and err <= 1e-8
-    print(f"M apply: rows {info['us_rows']:.1f} us, LDS-staged {info['us_lds']:.1f} us "
-          f"(picked {info['variant']}); learned solve iterations {out[0][1]} / {out[1][1]}, "
-          f"u error vs banded {out[0][2]:.1e} / {out[1][2]:.1e}")
+    print(f"M apply: rows {info['us_rows']:.1f} us, LDS-staged {info['us_lds']:.1f} us, "
+          f"grouped {info['us_grouped']:.1f} us (picked {info['variant']}); learned solve "
+          f"iterations {out[0][1]} / {out[1][1]} / {out[2][1]}, u error vs banded "
+          f"{out[0][2]:.1e} / {out[1][2]:.1e} / {out[2][2]:.1e}")
     assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][0], out[2][0])
+    assert out[2][1] == out[0][1] and np.array_equal(out[2][3], out[0][3])
     assert abs(out[0][1] - out[1][1]) <= 0.05 * out[0][1] + 5
     with pytest.raises(S.SfemError, match="EINVAL"):
+        ctx.set_precond_kernel(3)
+
+
+def test_grouped_m_apply_needs_int16_offsets(S):
+    """With shuffled node ids on a mesh of more than 32,768 nodes some block
+    column lies beyond an int16 offset: the grouped M apply is neither timed
+    nor accepted, and the row kernel applies M."""
+    p = mg.learned_small(2, grid=(80, 20, 20))
+    m = p.mesh
+    assert m.n_nodes > 32768
+    sh = np.random.default_rng(5).permutation(m.n_nodes)
+    inv = np.empty_like(sh)
+    inv[sh] = np.arange(m.n_nodes)
+    ctx = S.Context(0)
+    ctx.set_mesh(m.xyz[sh], inv[m.tets].astype(np.int32))
+    ctx.set_material(p.E, p.nu)
+    fd = np.asarray(p.fixed_dofs())
+    ctx.set_dirichlet(3 * inv[fd // 3] + fd % 3)
+    ctx.add_traction(inv[m.end_tris].astype(np.int32),
+                     np.asarray(p.traction, dtype=np.float64).reshape(-1)[:3])
+    ctx.assemble()
+    flat, _ = fp32_params(S, random_params(3, 0.3))
+    net = S.Gnn(0, seed=1)
+    net.set_params(flat)
+    net.apply(ctx)
+    info = ctx.precond_kernel()
+    print(f"shuffled {m.n_nodes} nodes: M apply kernel {info['variant']}, "
+          f"us {info['us_rows']:.1f} / {info['us_lds']:.1f} / {info['us_grouped']:.1f}")
+    assert info["us_grouped"] == 0.0 and info["variant"] in (0, 1)
+    with pytest.raises(S.SfemError, match="EINVAL"):
         ctx.set_precond_kernel(2)
+    r = np.random.default_rng(6).standard_normal(3 * m.n_nodes)
+    z = ctx.precond_apply(r)
+    assert np.all(np.isfinite(z)) and np.array_equal(z, ctx.precond_apply(r))

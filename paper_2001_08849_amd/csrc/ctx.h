@@ -164,7 +164,7 @@ struct Ctx {
   DBuf<float> mval;
   DBuf<__bf16> mvalp;            // the same values, BF16, in the packed layout
   DBuf<double> msqrt;
-  // S' again in the grouped layout: per node row, one 80-byte group per 4
+  // S' also in the grouped layout: per node row, one 80-byte group per 4
   // packed blocks, the 36 BF16 values [q][t] then the 4 int16 column
   // offsets J - I (mgrp_ok: every offset fits; remade with each M)
   DBuf<uint4> mgrp;
@@ -251,8 +251,9 @@ void pack_pattern(Ctx& c);
 void pack_values64(Ctx& c);  // packed copy of the FP64 K (once per assembly)
 void ensure_csr64(Ctx& c);   // CSR-order FP64 K from the packed copy, if stale
 bool ensure_lds_tables(Ctx& c);  // window tables of schedule 17; false: unavailable
-// Times both M apply kernels on the current M and keeps the faster (or the
-// one forced: variant 0 rows, 1 LDS-staged; -1 time both).
+// Times the available M apply kernels on the current M and keeps the
+// fastest (or the one forced: variant 0 rows, 1 LDS-staged, 2 grouped; -1
+// time them all).
 void tune_mapply(Ctx& c, int variant = -1);
 void build_mgroups(Ctx& c);  // S' in the grouped layout, after each new packed M
 void ensure_rowsum(Ctx& c);      // block row sums R of K_bc (once per assembly)

@@ -404,8 +404,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
         const int c = r - 3 * jj;
         v = bc_value(v, 3 * I + a, 3 * bcol[b0 + rb + jj] + c, fixed, penalty);
       }
-      if (val) val[gbase + k] = v;
-      if (val32) val32[gbase + k] = float(v);
+      if (val) __builtin_nontemporal_store(v, val + gbase + k);
+      if (val32) __builtin_nontemporal_store(float(v), val32 + gbase + k);
     }
     if (!valp && !valp32) continue;
     // the same row in the packed layout: entry (q = 3a + c, block j) at
@@ -422,8 +422,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
         v = double((long long)sval[9 * rb + a * three_deg + 3 * j + c]) * u;
         if (rbc) v = bc_value(v, 3 * I + a, 3 * bcol[b0 + rb + j] + c, fixed, penalty);
       }
-      if (valp) valp[pbase + kp] = v;
-      if (valp32) valp32[pbase + kp] = float(v);
+      if (valp) __builtin_nontemporal_store(v, valp + pbase + kp);
+      if (valp32) __builtin_nontemporal_store(float(v), valp32 + pbase + kp);
     }
   }
 }

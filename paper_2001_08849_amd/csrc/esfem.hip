@@ -425,8 +425,8 @@ __global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_e
           v = 0.0;
         }
       }
-      val[gbase + k] = v;
-      if (val32) val32[gbase + k] = float(v);
+      __builtin_nontemporal_store(v, val + gbase + k);
+      if (val32) __builtin_nontemporal_store(float(v), val32 + gbase + k);
     }
   }
 }

@@ -319,12 +319,7 @@ __device__ __forceinline__ void row3p(int I, bool valid, int sub, const int32_t*
   }
   const VT* w = valp + 9 * int64_t(r4);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
-    const int4 J = *reinterpret_cast<const int4*>(col4 + r4 + jb);
-    double m[9][4];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) load4(w + q * d4 + jb, m[q]);
-    const int Js[4] = {J.x, J.y, J.z, J.w};
+  const auto blocks = [&](const int (&Js)[4], const double (&m)[9][4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t j3 = 3 * int64_t(Js[t]);
@@ -337,6 +332,41 @@ __device__ __forceinline__ void row3p(int I, bool valid, int sub, const int32_t*
       a0 += m[0][t] * x0 + m[1][t] * x1 + m[2][t] * x2;
       a1 += m[3][t] * x0 + m[4][t] * x1 + m[5][t] * x2;
       a2 += m[6][t] * x0 + m[7][t] * x1 + m[8][t] * x2;
+    }
+  };
+  if constexpr (sizeof(VT) == 8) {
+    // FP64: four blocks are 32 bytes per component, two 16-byte loads.  A
+    // lane takes the block pairs (jb, jb + 1) and (jb + 2 LPR, jb + 2 LPR +
+    // 1), so that in each load the group's lanes read one contiguous run
+    // (16 bytes apart) instead of every other 16 bytes of it.
+    for (int jb = 2 * sub; jb < d4; jb += 4 * LPR) {
+      const int jc = jb + 2 * LPR;
+      const bool two = jc < d4;
+      const int2 Ja = *reinterpret_cast<const int2*>(col4 + r4 + jb);
+      int2 Jc = make_int2(I, I);  // no second pair: column I with zero values
+      if (two) Jc = *reinterpret_cast<const int2*>(col4 + r4 + jc);
+      double m[9][4];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const double2 a = *reinterpret_cast<const double2*>(w + q * d4 + jb);
+        double2 b = make_double2(0.0, 0.0);
+        if (two) b = *reinterpret_cast<const double2*>(w + q * d4 + jc);
+        m[q][0] = a.x;
+        m[q][1] = a.y;
+        m[q][2] = b.x;
+        m[q][3] = b.y;
+      }
+      const int Js[4] = {Ja.x, Ja.y, Jc.x, Jc.y};
+      blocks(Js, m);
+    }
+  } else {
+    for (int jb = 4 * sub; jb < d4; jb += 4 * LPR) {
+      const int4 J = *reinterpret_cast<const int4*>(col4 + r4 + jb);
+      double m[9][4];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) load4(w + q * d4 + jb, m[q]);
+      const int Js[4] = {J.x, J.y, J.z, J.w};
+      blocks(Js, m);
     }
   }
   y0 = group_sum<LPR>(a0);
